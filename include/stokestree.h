@@ -1,0 +1,151 @@
+/*
+ * stokestree.h -- C-ABI of the MI355X (gfx950) treecode for 3D Stokeslets and
+ * stresslets of Wang, Tlupova & Krasny, "A Treecode Algorithm for 3D Stokeslets
+ * and Stresslets" (arXiv 1811.12498).
+ *
+ * The library evaluates, at targets x^m, the velocity of eq. StoStre (Sec. 1)
+ *
+ *     u_i(x^m) = sum_n S_ij(x^m, y^n) f_j^n + sum_n T_ijl(x^m, y^n) h_j^n nu_l^n
+ *
+ * with S and T exactly as printed in eqs. Stokeslet and stresslet (no 1/(8 pi)
+ * prefactor, T positive, d = x - y target minus source).  A pair with x == y is
+ * skipped (the n != m exclusion); targets may be disjoint from the sources.
+ * Algorithm 1 (Sec. 5) is followed per target: an octree of source clusters,
+ * the MAC r/R <= theta (eq. MAC), the order-p Cartesian Taylor far field
+ * (eqs. S_final and T_final built on the Coulomb recurrence, recurrence_1) and
+ * the contracted direct sum of Sec. 4.1 for leaves that fail the MAC.
+ *
+ * Conventions for every entry point:
+ *   - Arrays named "device" are caller-owned device pointers (any allocation
+ *     visible to the current HIP device), FP64, contiguous, row-major.  Arrays
+ *     named "host" are caller-owned host memory.
+ *   - (N,3) means N rows of (x, y, z); (K,N,3) means K consecutive (N,3) blocks,
+ *     one per right-hand side.
+ *   - Work is enqueued on `stream` (a hipStream_t, NULL = the default stream).
+ *     Entry points that must size device buffers from data (tree build, list
+ *     construction) synchronise that stream before returning; the others return
+ *     after enqueueing.  Input arrays must stay valid until the stream has
+ *     consumed them.
+ *   - Handles (stk_tree, stk_plan) are owned by the library and released with
+ *     the matching *_destroy call.  A handle is bound to the device that was
+ *     current when it was created and must be used with that device current.
+ *     Calls that use one handle must not overlap; distinct handles are
+ *     independent.
+ *   - Every entry point returns a stk_status.  Arguments are validated before
+ *     any work is enqueued (STK_EINVAL); a failed HIP call yields STK_EDEVICE and
+ *     an allocation failure STK_ENOMEM.  stk_last_error() returns a message for
+ *     the last non-OK status of the calling thread.  No C++ exception crosses the
+ *     ABI.  NaN/Inf inputs are not checked; they propagate.
+ */
+#ifndef STOKESTREE_H
+#define STOKESTREE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct stk_tree stk_tree; /* sources in Morton order, octree, moments  */
+typedef struct stk_plan stk_plan; /* a tree plus one target set's interaction lists */
+
+typedef enum {
+    STK_OK = 0,
+    STK_EINVAL = -1,  /* bad argument or parameter                               */
+    STK_ENOMEM = -2,  /* device allocation failed                                 */
+    STK_EDEVICE = -3, /* a HIP call failed                                        */
+    STK_ESTATE = -4   /* call out of order (e.g. evaluate before compute_moments) */
+} stk_status;
+
+typedef enum {
+    /* All arithmetic in FP64. */
+    STK_FP64 = 0,
+    /* Far and near fields in FP32 with compensated per-target accumulators and an
+     * FP64 final sum; positions, normals and the pair quantities d = x - y and
+     * d.nu are formed in FP64 (on a surface with nu the normal, d.nu = O(|d|^2),
+     * so rounding them to FP32 would dominate the error); moments accumulate in
+     * FP64 and are rounded once for the FP32 contraction. */
+    STK_MIXED = 1
+} stk_precision;
+
+/* Largest Taylor order accepted (the paper uses p = 0..10). */
+#define STK_P_MAX 10
+/* Deepest octree level (21-bit integer coordinates per axis). */
+#define STK_MAX_LEVEL 21
+
+/* Build the octree of Sec. 5 over n source points.
+ *   src  device (n,3) source positions y^n.
+ *   n0   leaf capacity N0 >= 1: a node is split while it holds more than n0
+ *        points and its level is below STK_MAX_LEVEL (so leaves hold <= n0
+ *        points except at the deepest level).
+ * The root cube is [lo, lo + L]^3 with lo the componentwise minimum and L the
+ * largest extent; a point's integer coordinate per axis is
+ * q = min(2^21 - 1, floor((y - lo) * (2^21 / L))) and children are visited in
+ * Morton order (x bit most significant).  Each node's centre y_c is the centre of
+ * the tight bounding box of its points and its radius r the largest |y - y_c|
+ * (Sec. 2 and the box shrinking of Sec. 6).  If all points coincide (L = 0) the
+ * tree is one leaf.  Synchronises `stream`.  *out receives the new handle. */
+stk_status stk_build_tree(const double *src, int64_t n, int32_t n0, void *stream, stk_tree **out);
+
+/* Compute the cluster moments of Sec. 2 for every node of `t`,
+ *   M_j^k(C) = sum_{y^n in C} (y^n - y_c)^k f_j^n,
+ *   Mt_jl^k(C) = sum_{y^n in C} (y^n - y_c)^k h_j^n nu_l^n,    ||k|| <= p,
+ * for K = k_rhs right-hand sides, and the per-node blocks the far field reads.
+ *   f, h  device (K,n,3) weights in the input order of the sources.
+ *   nu    device (n,3) normals (used as given; normalising is the caller's job).
+ *   p     Taylor order, 0 <= p <= STK_P_MAX.    prec  arithmetic of evaluation.
+ * Moments are always accumulated in FP64.  Replaces any earlier moments. */
+stk_status stk_compute_moments(stk_tree *t, const double *f, const double *h, const double *nu, int32_t k_rhs,
+                               int32_t p, stk_precision prec, void *stream);
+
+/* Evaluate the treecode velocity (Algorithm 1) at m targets with the moments of
+ * the last stk_compute_moments on `t`.
+ *   targets  device (m,3), m >= 1; may or may not coincide with the sources.
+ *   theta    MAC parameter, 0 <= theta < 1: a node is used through its Taylor
+ *            expansion iff R > 0 and r <= theta * R (R = |x - y_c|).
+ *   u_out    device (K,m,3), overwritten.
+ *   keep_plan  if non-NULL, receives a plan holding the targets' interaction
+ *            lists (for stk_evaluate_adjoint and stk_plan_counts); it refers to
+ *            `t`, which must outlive it.
+ * Synchronises `stream` once (to size the interaction lists). */
+stk_status stk_evaluate_tree(stk_tree *t, const double *targets, int64_t m, double theta, double *u_out,
+                             stk_plan **keep_plan, void *stream);
+
+/* One call: build the tree, compute moments and evaluate (eq. StoStre by
+ * Algorithm 1).  Arguments as above; if keep_plan is non-NULL the plan owns the
+ * tree it was built on. */
+stk_status stk_evaluate(const double *targets, int64_t m, const double *sources, int64_t n, const double *f,
+                        const double *h, const double *nu, int32_t k_rhs, int32_t p, double theta, int32_t n0,
+                        stk_precision prec, double *u_out, stk_plan **keep_plan, void *stream);
+
+/* Exact O(m n) direct sum of eq. StoStre in FP64 (contracted form of Sec. 4.1),
+ * the reference the treecode is measured against.  Same array conventions. */
+stk_status stk_direct(const double *targets, int64_t m, const double *sources, int64_t n, const double *f,
+                      const double *h, const double *nu, int32_t k_rhs, double *u_out, void *stream);
+
+/* Introspection, for verification and reporting. */
+/* nnodes, number of levels, and root = (lo_x, lo_y, lo_z, L). Host outputs. */
+stk_status stk_tree_info(const stk_tree *t, int64_t *nnodes, int32_t *nlevels, double root[4]);
+/* Copy the node table to host arrays of length nnodes (3*nnodes for boxes and
+ * centres) and perm (length n: sorted position -> input index).  Nodes are
+ * numbered breadth first, each level in Morton order.  Any pointer may be NULL. */
+stk_status stk_tree_export(const stk_tree *t, int32_t *perm, int32_t *level, int32_t *parent, int32_t *child0,
+                           int32_t *nchild, int32_t *start, int32_t *count, double *bmin, double *bmax,
+                           double *center, double *radius);
+/* Copy right-hand side `rhs`'s FP64 moments to host arrays M (nnodes,nm,3) and
+ * Mt (nnodes,nm,3,3), nm = (p+1)(p+2)(p+3)/6, k in graded-lex order
+ * (n = 0..p; k1 = n..0; k2 = n-k1..0). */
+stk_status stk_tree_export_moments(const stk_tree *t, int32_t rhs, double *M, double *Mt);
+/* Per-target interaction counts of a plan, in the caller's target order (host
+ * arrays of length m): far-field nodes, near-field leaves, near-field pairs. */
+stk_status stk_plan_counts(const stk_plan *plan, int64_t *nfar, int64_t *nnear, int64_t *npairs);
+
+void stk_tree_destroy(stk_tree *t);
+void stk_plan_destroy(stk_plan *plan);
+/* Message for the calling thread's last non-OK status ("" if none). */
+const char *stk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STOKESTREE_H */

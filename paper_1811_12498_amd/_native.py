@@ -1,0 +1,217 @@
+"""ctypes binding of libstokestree (include/stokestree.h).
+
+Argument marshalling only: torch tensors supply device memory and the current HIP
+stream; every step of the computation runs in the library's kernels.  There is no
+fallback: if the built library is missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libstokestree.so")
+
+STK_OK, STK_EINVAL, STK_ENOMEM, STK_EDEVICE, STK_ESTATE = 0, -1, -2, -3, -4
+FP64, MIXED = 0, 1
+P_MAX = 10
+
+_STATUS_NAMES = {STK_EINVAL: "STK_EINVAL", STK_ENOMEM: "STK_ENOMEM", STK_EDEVICE: "STK_EDEVICE",
+                 STK_ESTATE: "STK_ESTATE"}
+
+# every symbol include/stokestree.h declares
+EXPORTS = ["stk_build_tree", "stk_compute_moments", "stk_evaluate_tree", "stk_evaluate", "stk_direct",
+           "stk_tree_info", "stk_tree_export", "stk_tree_export_moments", "stk_plan_counts",
+           "stk_tree_destroy", "stk_plan_destroy", "stk_last_error"]
+
+
+class StkError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1811_12498_amd.build` "
+                      "(there is no fallback implementation)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_vp, _dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+_i32p, _i64p = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
+_i64, _i32, _d = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+
+_lib.stk_last_error.restype = ctypes.c_char_p
+_lib.stk_build_tree.argtypes = [_vp, _i64, _i32, _vp, ctypes.POINTER(_vp)]
+_lib.stk_compute_moments.argtypes = [_vp, _vp, _vp, _vp, _i32, _i32, ctypes.c_int, _vp]
+_lib.stk_evaluate_tree.argtypes = [_vp, _vp, _i64, _d, _vp, ctypes.POINTER(_vp), _vp]
+_lib.stk_evaluate.argtypes = [_vp, _i64, _vp, _i64, _vp, _vp, _vp, _i32, _i32, _d, _i32, ctypes.c_int, _vp,
+                              ctypes.POINTER(_vp), _vp]
+_lib.stk_direct.argtypes = [_vp, _i64, _vp, _i64, _vp, _vp, _vp, _i32, _vp, _vp]
+_lib.stk_tree_info.argtypes = [_vp, _i64p, _i32p, _dp]
+_lib.stk_tree_export.argtypes = [_vp] + [_vp] * 11
+_lib.stk_tree_export_moments.argtypes = [_vp, _i32, _vp, _vp]
+_lib.stk_plan_counts.argtypes = [_vp, _vp, _vp, _vp]
+_lib.stk_tree_destroy.argtypes = [_vp]
+_lib.stk_plan_destroy.argtypes = [_vp]
+for _name in EXPORTS:
+    _lib[_name].restype = ctypes.c_int if _name != "stk_last_error" else ctypes.c_char_p
+_lib.stk_tree_destroy.restype = None
+_lib.stk_plan_destroy.restype = None
+
+
+def _check(st: int) -> None:
+    if st != STK_OK:
+        raise StkError(st, _lib.stk_last_error().decode())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, name: str, shape_last: int | None = 3) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape_last is not None and t.shape[-1] != shape_last:
+        raise ValueError(f"{name} must have last dimension {shape_last}")
+    return t
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _prec(precision) -> int:
+    if precision in (FP64, "fp64", "float64"):
+        return FP64
+    if precision in (MIXED, "mixed", "fp32", "float32"):
+        return MIXED
+    raise ValueError(f"unknown precision {precision!r}")
+
+
+class Tree:
+    """Owning wrapper of an stk_tree handle."""
+
+    def __init__(self, handle: int, n: int):
+        self.handle = ctypes.c_void_p(handle)
+        self.n = n
+
+    def __del__(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            _lib.stk_tree_destroy(self.handle)
+            self.handle = ctypes.c_void_p(0)
+
+
+class Plan:
+    """Owning wrapper of an stk_plan handle (keeps its tree alive)."""
+
+    def __init__(self, handle: int, m: int, tree: Tree | None):
+        self.handle = ctypes.c_void_p(handle)
+        self.m = m
+        self.tree = tree
+
+    def __del__(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            _lib.stk_plan_destroy(self.handle)
+            self.handle = ctypes.c_void_p(0)
+
+
+def build_tree(sources: torch.Tensor, n0: int) -> Tree:
+    _dev(sources, "sources")
+    h = ctypes.c_void_p()
+    _check(_lib.stk_build_tree(_ptr(sources), sources.shape[0], int(n0), _stream(), ctypes.byref(h)))
+    return Tree(h.value, sources.shape[0])
+
+
+def compute_moments(tree: Tree, f: torch.Tensor, h: torch.Tensor, nu: torch.Tensor, p: int,
+                    precision="fp64") -> None:
+    for t, nm in ((f, "f"), (h, "h"), (nu, "nu")):
+        _dev(t, nm)
+    k = f.shape[0] if f.dim() == 3 else 1
+    _check(_lib.stk_compute_moments(tree.handle, _ptr(f), _ptr(h), _ptr(nu), k, int(p), _prec(precision),
+                                    _stream()))
+
+
+def evaluate_tree(tree: Tree, targets: torch.Tensor, theta: float, keep_plan: bool = False,
+                  out: torch.Tensor | None = None):
+    _dev(targets, "targets")
+    m = targets.shape[0]
+    u = out if out is not None else torch.empty((m, 3), dtype=torch.float64, device=targets.device)
+    _dev(u, "out")
+    ph = ctypes.c_void_p()
+    _check(_lib.stk_evaluate_tree(tree.handle, _ptr(targets), m, float(theta), _ptr(u),
+                                  ctypes.byref(ph) if keep_plan else None, _stream()))
+    return (u, Plan(ph.value, m, tree)) if keep_plan else u
+
+
+def evaluate(targets, sources, f, h, nu, p: int, theta: float, n0: int, precision="fp64",
+             keep_plan: bool = False):
+    for t, nm in ((targets, "targets"), (sources, "sources"), (f, "f"), (h, "h"), (nu, "nu")):
+        _dev(t, nm)
+    m, n = targets.shape[0], sources.shape[0]
+    k = f.shape[0] if f.dim() == 3 else 1
+    u = torch.empty((m, 3) if k == 1 else (k, m, 3), dtype=torch.float64, device=targets.device)
+    ph = ctypes.c_void_p()
+    _check(_lib.stk_evaluate(_ptr(targets), m, _ptr(sources), n, _ptr(f), _ptr(h), _ptr(nu), k, int(p),
+                             float(theta), int(n0), _prec(precision), _ptr(u),
+                             ctypes.byref(ph) if keep_plan else None, _stream()))
+    return (u, Plan(ph.value, m, None)) if keep_plan else u
+
+
+def direct(targets, sources, f, h, nu) -> torch.Tensor:
+    for t, nm in ((targets, "targets"), (sources, "sources"), (f, "f"), (h, "h"), (nu, "nu")):
+        _dev(t, nm)
+    m, n = targets.shape[0], sources.shape[0]
+    k = f.shape[0] if f.dim() == 3 else 1
+    u = torch.empty((m, 3) if k == 1 else (k, m, 3), dtype=torch.float64, device=targets.device)
+    _check(_lib.stk_direct(_ptr(targets), m, _ptr(sources), n, _ptr(f), _ptr(h), _ptr(nu), k, _ptr(u),
+                           _stream()))
+    return u
+
+
+def tree_info(tree: Tree):
+    nn, nl = ctypes.c_int64(), ctypes.c_int32()
+    root = (ctypes.c_double * 4)()
+    _check(_lib.stk_tree_info(tree.handle, ctypes.byref(nn), ctypes.byref(nl), root))
+    return int(nn.value), int(nl.value), np.array(root[:])
+
+
+def tree_export(tree: Tree) -> dict:
+    nn, _, _ = tree_info(tree)
+    out = {"perm": np.zeros(tree.n, np.int32)}
+    for k in ("level", "parent", "child0", "nchild", "start", "count"):
+        out[k] = np.zeros(nn, np.int32)
+    for k in ("bmin", "bmax", "center"):
+        out[k] = np.zeros((nn, 3))
+    out["radius"] = np.zeros(nn)
+    order = ["perm", "level", "parent", "child0", "nchild", "start", "count", "bmin", "bmax", "center", "radius"]
+    _check(_lib.stk_tree_export(tree.handle, *[ctypes.c_void_p(out[k].ctypes.data) for k in order]))
+    return out
+
+
+def tree_moments(tree: Tree, p: int, rhs: int = 0):
+    nn, _, _ = tree_info(tree)
+    nm = (p + 1) * (p + 2) * (p + 3) // 6
+    M = np.zeros((nn, nm, 3))
+    Mt = np.zeros((nn, nm, 3, 3))
+    _check(_lib.stk_tree_export_moments(tree.handle, int(rhs), ctypes.c_void_p(M.ctypes.data),
+                                        ctypes.c_void_p(Mt.ctypes.data)))
+    return M, Mt
+
+
+def plan_counts(plan: Plan):
+    a, b, c = (np.zeros(plan.m, np.int64) for _ in range(3))
+    _check(_lib.stk_plan_counts(plan.handle, ctypes.c_void_p(a.ctypes.data), ctypes.c_void_p(b.ctypes.data),
+                                ctypes.c_void_p(c.ctypes.data)))
+    return a, b, c
+
+
+def exported_symbols() -> list[str]:
+    """Names from include/stokestree.h that the loaded library exports."""
+    return [s for s in EXPORTS if hasattr(_lib, s)]

@@ -1,0 +1,245 @@
+// C-ABI entry points of libstokestree (declared in include/stokestree.h).  Validates
+// arguments, converts internal errors to status codes and keeps a thread-local
+// message for stk_last_error().
+#include <cmath>
+#include <memory>
+#include <string>
+
+#include "stk_internal.hpp"
+#include "stk_math.hpp"
+
+struct stk_tree {
+    stk::Tree t;
+};
+struct stk_plan {
+    stk::Plan p;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+template <class F> stk_status guarded(F &&f) {
+    try {
+        f();
+        g_err.clear();
+        return STK_OK;
+    } catch (const stk::Error &e) {
+        g_err = e.what();
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        g_err = "host allocation failed";
+        return STK_ENOMEM;
+    } catch (const std::exception &e) {
+        g_err = e.what();
+        return STK_EDEVICE;
+    } catch (...) {
+        g_err = "unknown error";
+        return STK_EDEVICE;
+    }
+}
+
+inline hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
+
+void check_device(int dev) {
+    int cur = -1;
+    STK_HIP(hipGetDevice(&cur));
+    stk::require(cur == dev, "handle used on a device other than the one it was created on");
+}
+
+void check_common(const double *pts, int64_t n, const char *what) {
+    stk::require(pts != nullptr, std::string(what) + " is NULL");
+    stk::require(n >= 1, std::string(what) + ": count must be >= 1");
+    stk::require(n < (int64_t(1) << 31) / 8, std::string(what) + ": count too large (int32 indexing)");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *stk_last_error(void) { return g_err.c_str(); }
+
+stk_status stk_build_tree(const double *src, int64_t n, int32_t n0, void *stream, stk_tree **out) {
+    return guarded([&] {
+        check_common(src, n, "sources");
+        stk::require(out != nullptr, "out is NULL");
+        stk::require(n0 >= 1, "n0 must be >= 1");
+        *out = nullptr;
+        auto *h = new stk_tree();
+        try {
+            STK_HIP(hipGetDevice(&h->t.device));
+            stk::build_tree(h->t, src, n, n0, as_stream(stream));
+        } catch (...) {
+            delete h;
+            throw;
+        }
+        *out = h;
+    });
+}
+
+stk_status stk_compute_moments(stk_tree *t, const double *f, const double *h, const double *nu, int32_t k_rhs,
+                               int32_t p, stk_precision prec, void *stream) {
+    return guarded([&] {
+        stk::require(t != nullptr, "tree is NULL");
+        stk::require(f && h && nu, "f, h and nu must be non-NULL");
+        stk::require(k_rhs >= 1 && k_rhs <= 64, "k_rhs must be in [1, 64]");
+        stk::require(p >= 0 && p <= STK_P_MAX, "p must be in [0, STK_P_MAX]");
+        stk::require(prec == STK_FP64 || prec == STK_MIXED, "unknown precision");
+        check_device(t->t.device);
+        stk::compute_moments(t->t, f, h, nu, k_rhs, p, prec, as_stream(stream));
+    });
+}
+
+stk_status stk_evaluate_tree(stk_tree *t, const double *targets, int64_t m, double theta, double *u_out,
+                             stk_plan **keep_plan, void *stream) {
+    return guarded([&] {
+        stk::require(t != nullptr, "tree is NULL");
+        check_common(targets, m, "targets");
+        stk::require(u_out != nullptr, "u_out is NULL");
+        stk::require(theta >= 0.0 && theta < 1.0, "theta must be in [0, 1)");
+        if (!t->t.have_moments) throw stk::Error(STK_ESTATE, "stk_compute_moments has not been called");
+        stk::require(t->t.k_rhs == 1, "more than one right-hand side is not supported by this entry point yet");
+        check_device(t->t.device);
+        if (keep_plan) *keep_plan = nullptr;
+        auto *pl = new stk_plan();
+        try {
+            stk::evaluate(t->t, pl->p, targets, m, theta, u_out, as_stream(stream));
+        } catch (...) {
+            delete pl;
+            throw;
+        }
+        if (keep_plan)
+            *keep_plan = pl;
+        else {
+            STK_HIP(hipStreamSynchronize(as_stream(stream)));
+            delete pl;
+        }
+    });
+}
+
+stk_status stk_evaluate(const double *targets, int64_t m, const double *sources, int64_t n, const double *f,
+                        const double *h, const double *nu, int32_t k_rhs, int32_t p, double theta, int32_t n0,
+                        stk_precision prec, double *u_out, stk_plan **keep_plan, void *stream) {
+    return guarded([&] {
+        check_common(sources, n, "sources");
+        check_common(targets, m, "targets");
+        stk::require(f && h && nu && u_out, "f, h, nu and u_out must be non-NULL");
+        stk::require(n0 >= 1, "n0 must be >= 1");
+        stk::require(k_rhs == 1, "more than one right-hand side is not supported by this entry point yet");
+        stk::require(p >= 0 && p <= STK_P_MAX, "p must be in [0, STK_P_MAX]");
+        stk::require(prec == STK_FP64 || prec == STK_MIXED, "unknown precision");
+        stk::require(theta >= 0.0 && theta < 1.0, "theta must be in [0, 1)");
+        if (keep_plan) *keep_plan = nullptr;
+        hipStream_t s = as_stream(stream);
+        std::unique_ptr<stk::Tree> tree(new stk::Tree());
+        STK_HIP(hipGetDevice(&tree->device));
+        stk::build_tree(*tree, sources, n, n0, s);
+        stk::compute_moments(*tree, f, h, nu, k_rhs, p, prec, s);
+        std::unique_ptr<stk_plan> pl(new stk_plan());
+        stk::evaluate(*tree, pl->p, targets, m, theta, u_out, s);
+        if (keep_plan) {
+            pl->p.tree = tree.release();
+            pl->p.owns_tree = true;
+            *keep_plan = pl.release();
+        } else {
+            STK_HIP(hipStreamSynchronize(s));
+        }
+    });
+}
+
+stk_status stk_direct(const double *targets, int64_t m, const double *sources, int64_t n, const double *f,
+                      const double *h, const double *nu, int32_t k_rhs, double *u_out, void *stream) {
+    return guarded([&] {
+        check_common(targets, m, "targets");
+        check_common(sources, n, "sources");
+        stk::require(f && h && nu && u_out, "f, h, nu and u_out must be non-NULL");
+        stk::require(k_rhs >= 1 && k_rhs <= 64, "k_rhs must be in [1, 64]");
+        stk::direct_sum(targets, m, sources, n, f, h, nu, k_rhs, u_out, as_stream(stream));
+    });
+}
+
+stk_status stk_tree_info(const stk_tree *t, int64_t *nnodes, int32_t *nlevels, double root[4]) {
+    return guarded([&] {
+        stk::require(t != nullptr, "tree is NULL");
+        if (nnodes) *nnodes = t->t.nnodes;
+        if (nlevels) *nlevels = t->t.nlevels;
+        if (root) {
+            for (int a = 0; a < 3; ++a) root[a] = t->t.lo[a];
+            root[3] = t->t.L;
+        }
+    });
+}
+
+stk_status stk_tree_export(const stk_tree *t, int32_t *perm, int32_t *level, int32_t *parent, int32_t *child0,
+                           int32_t *nchild, int32_t *start, int32_t *count, double *bmin, double *bmax,
+                           double *center, double *radius) {
+    return guarded([&] {
+        stk::require(t != nullptr, "tree is NULL");
+        check_device(t->t.device);
+        const stk::Tree &T = t->t;
+        const size_t nn = size_t(T.nnodes);
+        STK_HIP(hipDeviceSynchronize());
+        auto cp = [](void *dst, const stk::DBuf &b, size_t bytes) {
+            if (dst) STK_HIP(hipMemcpy(dst, b.p, bytes, hipMemcpyDeviceToHost));
+        };
+        cp(perm, T.perm, sizeof(int32_t) * size_t(T.n));
+        cp(level, T.nlevel, sizeof(int32_t) * nn);
+        cp(parent, T.nparent, sizeof(int32_t) * nn);
+        cp(child0, T.nchild0, sizeof(int32_t) * nn);
+        cp(nchild, T.nnchild, sizeof(int32_t) * nn);
+        cp(start, T.nstart, sizeof(int32_t) * nn);
+        cp(count, T.ncount, sizeof(int32_t) * nn);
+        cp(bmin, T.nbmin, sizeof(double) * 3 * nn);
+        cp(bmax, T.nbmax, sizeof(double) * 3 * nn);
+        cp(center, T.ncenter, sizeof(double) * 3 * nn);
+        cp(radius, T.nradius, sizeof(double) * nn);
+    });
+}
+
+stk_status stk_tree_export_moments(const stk_tree *t, int32_t rhs, double *M, double *Mt) {
+    return guarded([&] {
+        stk::require(t != nullptr, "tree is NULL");
+        const stk::Tree &T = t->t;
+        if (!T.have_moments) throw stk::Error(STK_ESTATE, "no moments computed");
+        stk::require(rhs >= 0 && rhs < T.k_rhs, "rhs out of range");
+        check_device(T.device);
+        const int nm = stk::nm_of(T.p);
+        const int K = T.k_rhs;
+        std::vector<double> h(size_t(T.nnodes) * nm * 12 * K);
+        STK_HIP(hipDeviceSynchronize());
+        STK_HIP(hipMemcpy(h.data(), T.mom.p, sizeof(double) * h.size(), hipMemcpyDeviceToHost));
+        for (size_t c = 0; c < size_t(T.nnodes); ++c)
+            for (int a = 0; a < nm; ++a) {
+                const double *src = h.data() + (c * nm + a) * 12 * K + 12 * rhs;
+                if (M)
+                    for (int j = 0; j < 3; ++j) M[(c * nm + a) * 3 + j] = src[j];
+                if (Mt)
+                    for (int j = 0; j < 9; ++j) Mt[(c * nm + a) * 9 + j] = src[3 + j];
+            }
+    });
+}
+
+stk_status stk_plan_counts(const stk_plan *plan, int64_t *nfar, int64_t *nnear, int64_t *npairs) {
+    return guarded([&] {
+        stk::require(plan != nullptr, "plan is NULL");
+        const stk::Plan &P = plan->p;
+        check_device(P.tree->device);
+        const size_t m = size_t(P.m);
+        std::vector<int32_t> perm(m), a(m), b(m), c(m);
+        STK_HIP(hipDeviceSynchronize());
+        STK_HIP(hipMemcpy(perm.data(), P.tperm.p, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
+        STK_HIP(hipMemcpy(a.data(), P.cnt_far.p, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
+        STK_HIP(hipMemcpy(b.data(), P.cnt_near.p, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
+        STK_HIP(hipMemcpy(c.data(), P.cnt_pairs.p, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < m; ++i) {
+            if (nfar) nfar[perm[i]] = a[i];
+            if (nnear) nnear[perm[i]] = b[i];
+            if (npairs) npairs[perm[i]] = c[i];
+        }
+    });
+}
+
+void stk_tree_destroy(stk_tree *t) { delete t; }
+void stk_plan_destroy(stk_plan *plan) { delete plan; }
+
+}  // extern "C"

@@ -1,0 +1,422 @@
+// Treecode evaluation (Algorithm 1) for a target set, and the FP64 direct sum.
+//
+// Targets are sorted into Morton order with the tree's root cube and cut into groups
+// of 64 (one wavefront).  A group walks the tree once: at each cluster every lane
+// applies the MAC (eq. MAC) to its own target, and the wave splits the cluster into
+// the lanes that accept it (a far entry with their mask), the lanes that reach a leaf
+// (a near entry) and the lanes that descend (children pushed with their mask).  This
+// is exactly Algorithm 1 per target; the lists are built in two passes (count, scan,
+// fill) and kept in the plan for the adjoint.
+#include "far_kernels.hpp"
+#include "stk_internal.hpp"
+#include "stk_math.hpp"
+
+namespace stk {
+
+template <int P, typename T> void launch_far(const FarArgs &, hipStream_t);
+
+namespace {
+
+constexpr int STACK = 256;  // >= 1 + 7 * STK_MAX_LEVEL
+
+__device__ inline uint64_t rfl64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(v));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(v >> 32));
+    return (uint64_t(hi) << 32) | lo;
+}
+
+struct TravArgs {
+    const double *tpos;
+    int64_t m;
+    const double *center;
+    const double *radius;
+    const int32_t *child0, *nchild, *count;
+    double theta;
+    // count pass outputs
+    int32_t *gfar, *gnear;              // per group entry counts
+    int32_t *cnt_far, *cnt_near, *cnt_pairs;  // per sorted target
+    // fill pass
+    const int32_t *far_off, *near_off;
+    int32_t *far_node, *near_node;
+    uint64_t *far_mask, *near_mask;
+};
+
+template <bool FILL> __global__ __launch_bounds__(64) void k_traverse(TravArgs a) {
+    __shared__ int32_t st_node[STACK];
+    __shared__ uint64_t st_mask[STACK];
+    const int32_t g = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t t = int64_t(g) * 64 + lane;
+    const bool valid = t < a.m;
+    double x0 = 0, x1 = 0, x2 = 0;
+    if (valid) {
+        x0 = a.tpos[3 * t];
+        x1 = a.tpos[3 * t + 1];
+        x2 = a.tpos[3 * t + 2];
+    }
+    int32_t nf = 0, nnr = 0, npr = 0;    // per-lane counts
+    int32_t fo = 0, no = 0;              // group entry counters
+    if (FILL) {
+        fo = a.far_off[g];
+        no = a.near_off[g];
+    }
+    const uint64_t vmask = __ballot(valid);
+    if (lane == 0) {
+        st_node[0] = 0;
+        st_mask[0] = vmask;
+    }
+    int sp = 1;
+    __syncthreads();
+    while (sp > 0) {
+        --sp;
+        const int32_t c = __builtin_amdgcn_readfirstlane(st_node[sp]);
+        const uint64_t mk = rfl64(st_mask[sp]);
+        __syncthreads();
+        const bool in = (mk >> lane) & 1ull;
+        bool accept = false;
+        {
+#pragma clang fp contract(off)
+            const double d0 = x0 - a.center[3 * c], d1 = x1 - a.center[3 * c + 1], d2 = x2 - a.center[3 * c + 2];
+            const double R = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            accept = in && R > 0.0 && a.radius[c] <= a.theta * R;
+        }
+        const uint64_t am = __ballot(accept);
+        const uint64_t rm = mk & ~am;
+        if (am) {
+            if (FILL && lane == 0) {
+                a.far_node[fo] = c;
+                a.far_mask[fo] = am;
+            }
+            ++fo;
+            nf += accept;
+        }
+        if (rm) {
+            const int32_t k = a.nchild[c];
+            if (k == 0) {
+                if (FILL && lane == 0) {
+                    a.near_node[no] = c;
+                    a.near_mask[no] = rm;
+                }
+                ++no;
+                if ((rm >> lane) & 1ull) {
+                    ++nnr;
+                    npr += a.count[c];
+                }
+            } else {
+                const int32_t c0 = a.child0[c];
+                if (lane == 0)
+                    for (int32_t j = k - 1; j >= 0; --j) {
+                        st_node[sp + (k - 1 - j)] = c0 + j;
+                        st_mask[sp + (k - 1 - j)] = rm;
+                    }
+                sp += k;
+            }
+        }
+        __syncthreads();
+    }
+    if (!FILL) {
+        if (lane == 0) {
+            a.gfar[g] = fo;
+            a.gnear[g] = no;
+        }
+        if (valid) {
+            a.cnt_far[t] = nf;
+            a.cnt_near[t] = nnr;
+            a.cnt_pairs[t] = npr;
+        }
+    }
+}
+
+// ---- near field: contracted direct sum of Sec. 4.1 over the group's near leaves ----
+struct NearArgs {
+    const double *tpos;
+    int64_t m;
+    const int32_t *off, *node;
+    const uint64_t *mask;
+    const int32_t *start, *count;
+    const double *geo;   // (n,6) y, nu
+    const void *wts;     // (n,6) f, h in T
+    double *unear;       // (m,3) sorted order
+};
+
+// one source's contribution, FP64 (STK_FP64)
+__device__ inline void pair_f64(double x0, double x1, double x2, const double *__restrict__ gj,
+                                const double *__restrict__ wj, double &u0, double &u1, double &u2) {
+    const double d0 = x0 - gj[0], d1 = x1 - gj[1], d2 = x2 - gj[2];
+    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    const double ri = r2 > 0.0 ? rsqrt(r2) : 0.0;
+    const double r2i = ri * ri;
+    const double r3i = ri * r2i;
+    const double dn = d0 * gj[3] + d1 * gj[4] + d2 * gj[5];
+    const double s = (d0 * wj[0] + d1 * wj[1] + d2 * wj[2]) * r3i;
+    const double tt = (d0 * wj[3] + d1 * wj[4] + d2 * wj[5]) * dn * (r3i * r2i);
+    const double st = s + tt;
+    u0 += wj[0] * ri + d0 * st;
+    u1 += wj[1] * ri + d1 * st;
+    u2 += wj[2] * ri + d2 * st;
+}
+
+// mixed precision: d and d.nu in FP64 (they carry the cancellation on surfaces), the
+// rest in FP32
+__device__ inline void pair_mixed(double x0, double x1, double x2, const double *__restrict__ gj,
+                                  const float *__restrict__ wj, float &u0, float &u1, float &u2) {
+    const double d0 = x0 - gj[0], d1 = x1 - gj[1], d2 = x2 - gj[2];
+    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    const double dn = d0 * gj[3] + d1 * gj[4] + d2 * gj[5];
+    const float f0 = float(d0), f1 = float(d1), f2 = float(d2);
+    const float ri = r2 > 0.0 ? __frsqrt_rn(float(r2)) : 0.0f;
+    const float r2i = ri * ri;
+    const float r3i = ri * r2i;
+    const float s = (f0 * wj[0] + f1 * wj[1] + f2 * wj[2]) * r3i;
+    const float tt = (f0 * wj[3] + f1 * wj[4] + f2 * wj[5]) * float(dn) * (r3i * r2i);
+    const float st = s + tt;
+    u0 += wj[0] * ri + f0 * st;
+    u1 += wj[1] * ri + f1 * st;
+    u2 += wj[2] * ri + f2 * st;
+}
+
+template <typename T> __global__ __launch_bounds__(64) void k_near(NearArgs a) {
+    const int32_t g = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t t = int64_t(g) * 64 + lane;
+    const bool valid = t < a.m;
+    double x0 = 0, x1 = 0, x2 = 0;
+    if (valid) {
+        x0 = a.tpos[3 * t];
+        x1 = a.tpos[3 * t + 1];
+        x2 = a.tpos[3 * t + 2];
+    }
+    const T *__restrict__ wts = static_cast<const T *>(a.wts);
+    const double *__restrict__ geo = a.geo;
+    Comp<T> acc[3];
+    const int32_t e0 = a.off[g], e1 = a.off[g + 1];
+    for (int32_t e = e0; e < e1; ++e) {
+        const int32_t c = __builtin_amdgcn_readfirstlane(a.node[e]);
+        const uint64_t mk = a.mask[e];
+        if ((mk >> lane) & 1ull) {
+            const int32_t s = a.start[c], n = a.count[c];
+            T u0 = T(0), u1 = T(0), u2 = T(0);
+#pragma unroll 4
+            for (int32_t j = s; j < s + n; ++j) {
+                if constexpr (sizeof(T) == 8)
+                    pair_f64(x0, x1, x2, geo + 6 * int64_t(j), reinterpret_cast<const double *>(wts) + 6 * int64_t(j),
+                             u0, u1, u2);
+                else
+                    pair_mixed(x0, x1, x2, geo + 6 * int64_t(j), reinterpret_cast<const float *>(wts) + 6 * int64_t(j),
+                               u0, u1, u2);
+            }
+            acc[0].add(u0);
+            acc[1].add(u1);
+            acc[2].add(u2);
+        }
+    }
+    if (valid) {
+        a.unear[3 * t] = acc[0].value();
+        a.unear[3 * t + 1] = acc[1].value();
+        a.unear[3 * t + 2] = acc[2].value();
+    }
+}
+
+// ---- target preparation --------------------------------------------------------------
+__device__ inline uint64_t spread3(uint64_t v) {
+    v &= 0x1fffffull;
+    v = (v | (v << 32)) & 0x1f00000000ffffull;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+__device__ inline uint64_t quant(double y, double lo, double scale) {
+#pragma clang fp contract(off)
+    const double v = floor((y - lo) * scale);
+    if (!(v > 0.0)) return 0;
+    if (v > 2097151.0) return 2097151;
+    return (uint64_t)v;
+}
+
+__global__ void k_tkeys(const double *__restrict__ pts, int64_t n, double lx, double ly, double lz, double scale,
+                        uint64_t *__restrict__ keys, int32_t *__restrict__ vals) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t qx = quant(pts[3 * i], lx, scale);
+    const uint64_t qy = quant(pts[3 * i + 1], ly, scale);
+    const uint64_t qz = quant(pts[3 * i + 2], lz, scale);
+    keys[i] = (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
+    vals[i] = int32_t(i);
+}
+
+__global__ void k_gather3(const double *__restrict__ src, const int32_t *__restrict__ perm, int64_t n,
+                          double *__restrict__ dst) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t j = perm[i];
+    dst[3 * i] = src[3 * j];
+    dst[3 * i + 1] = src[3 * j + 1];
+    dst[3 * i + 2] = src[3 * j + 2];
+}
+
+// ---- FP64 direct sum -----------------------------------------------------------------
+// grid (target groups, source chunks); each wave sums one source chunk for 64 targets
+constexpr int DCH = 8192;
+
+__global__ __launch_bounds__(64) void k_direct(const double *__restrict__ tgt, int64_t m,
+                                               const double *__restrict__ src, int64_t n,
+                                               const double *__restrict__ f, const double *__restrict__ h,
+                                               const double *__restrict__ nu, double *__restrict__ part) {
+    const int64_t t = int64_t(blockIdx.x) * 64 + threadIdx.x;
+    const bool valid = t < m;
+    double x0 = 0, x1 = 0, x2 = 0;
+    if (valid) {
+        x0 = tgt[3 * t];
+        x1 = tgt[3 * t + 1];
+        x2 = tgt[3 * t + 2];
+    }
+    const int64_t j0 = int64_t(blockIdx.y) * DCH;
+    const int64_t j1 = j0 + DCH < n ? j0 + DCH : n;
+    double u0 = 0, u1 = 0, u2 = 0;
+    for (int64_t j = j0; j < j1; ++j) {
+        const double d0 = x0 - src[3 * j], d1 = x1 - src[3 * j + 1], d2 = x2 - src[3 * j + 2];
+        const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+        const double ri = r2 > 0.0 ? rsqrt(r2) : 0.0;
+        const double r2i = ri * ri, r3i = ri * r2i;
+        const double s = (d0 * f[3 * j] + d1 * f[3 * j + 1] + d2 * f[3 * j + 2]) * r3i;
+        const double tt = (d0 * h[3 * j] + d1 * h[3 * j + 1] + d2 * h[3 * j + 2]) *
+                          (d0 * nu[3 * j] + d1 * nu[3 * j + 1] + d2 * nu[3 * j + 2]) * (r3i * r2i);
+        const double st = s + tt;
+        u0 += f[3 * j] * ri + d0 * st;
+        u1 += f[3 * j + 1] * ri + d1 * st;
+        u2 += f[3 * j + 2] * ri + d2 * st;
+    }
+    if (valid) {
+        double *o = part + (size_t(blockIdx.y) * m + t) * 3;
+        o[0] = u0;
+        o[1] = u1;
+        o[2] = u2;
+    }
+}
+
+__global__ void k_direct_reduce(const double *__restrict__ part, int64_t m, int nch, double *__restrict__ u) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= 3 * m) return;
+    double s = 0.0;
+    for (int c = 0; c < nch; ++c) s += part[size_t(c) * 3 * m + i];
+    u[i] = s;
+}
+
+inline unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
+
+template <typename T> void dispatch_far(int p, const FarArgs &a, hipStream_t s) {
+    switch (p) {
+        case 0: launch_far<0, T>(a, s); break;
+        case 1: launch_far<1, T>(a, s); break;
+        case 2: launch_far<2, T>(a, s); break;
+        case 3: launch_far<3, T>(a, s); break;
+        case 4: launch_far<4, T>(a, s); break;
+        case 5: launch_far<5, T>(a, s); break;
+        case 6: launch_far<6, T>(a, s); break;
+        case 7: launch_far<7, T>(a, s); break;
+        case 8: launch_far<8, T>(a, s); break;
+        case 9: launch_far<9, T>(a, s); break;
+        case 10: launch_far<10, T>(a, s); break;
+        default: throw Error(STK_EINVAL, "p out of range");
+    }
+}
+
+}  // namespace
+
+Plan::~Plan() {
+    if (owns_tree) delete tree;
+}
+
+void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, double *u_out, hipStream_t s) {
+    pl.tree = &t;
+    pl.m = m;
+    pl.theta = theta;
+    const int32_t ng = int32_t((m + 63) / 64);
+    pl.ngroups = ng;
+
+    // targets in Morton order of the tree's root cube
+    uint64_t *keys = reserve<uint64_t>(t.s_keys, size_t(m));
+    int32_t *tperm = reserve<int32_t>(pl.tperm, size_t(m));
+    hipLaunchKernelGGL(k_tkeys, dim3(nblk(m, 256)), dim3(256), 0, s, tgt, m, t.lo[0], t.lo[1], t.lo[2], t.scale,
+                       keys, tperm);
+    STK_CHECK_LAUNCH();
+    radix_sort_pairs(t, keys, tperm, m, 63, s);
+    double *tpos = reserve<double>(pl.tpos, size_t(m) * 3);
+    hipLaunchKernelGGL(k_gather3, dim3(nblk(m, 256)), dim3(256), 0, s, tgt, tperm, m, tpos);
+    STK_CHECK_LAUNCH();
+
+    // interaction lists: count, scan, fill
+    TravArgs ta{};
+    ta.tpos = tpos;
+    ta.m = m;
+    ta.center = t.ncenter.as<double>();
+    ta.radius = t.nradius.as<double>();
+    ta.child0 = t.nchild0.as<int32_t>();
+    ta.nchild = t.nnchild.as<int32_t>();
+    ta.count = t.ncount.as<int32_t>();
+    ta.theta = theta;
+    int32_t *gcnt = reserve<int32_t>(t.s_vals, size_t(ng) * 2);
+    ta.gfar = gcnt;
+    ta.gnear = gcnt + ng;
+    ta.cnt_far = reserve<int32_t>(pl.cnt_far, size_t(m));
+    ta.cnt_near = reserve<int32_t>(pl.cnt_near, size_t(m));
+    ta.cnt_pairs = reserve<int32_t>(pl.cnt_pairs, size_t(m));
+    hipLaunchKernelGGL(k_traverse<false>, dim3(ng), dim3(64), 0, s, ta);
+    STK_CHECK_LAUNCH();
+    int32_t *foff = reserve<int32_t>(pl.far_off, size_t(ng) + 1);
+    int32_t *noff = reserve<int32_t>(pl.near_off, size_t(ng) + 1);
+    scan_exclusive_i32(ta.gfar, foff, ng, s);
+    scan_exclusive_i32(ta.gnear, noff, ng, s);
+    int32_t tot[2];
+    STK_HIP(hipMemcpyAsync(&tot[0], foff + ng, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    STK_HIP(hipMemcpyAsync(&tot[1], noff + ng, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    STK_HIP(hipStreamSynchronize(s));
+    pl.n_far_entries = tot[0];
+    pl.n_near_entries = tot[1];
+    ta.far_off = foff;
+    ta.near_off = noff;
+    ta.far_node = reserve<int32_t>(pl.far_node, size_t(tot[0]) + 1);
+    ta.far_mask = reserve<uint64_t>(pl.far_mask, size_t(tot[0]) + 1);
+    ta.near_node = reserve<int32_t>(pl.near_node, size_t(tot[1]) + 1);
+    ta.near_mask = reserve<uint64_t>(pl.near_mask, size_t(tot[1]) + 1);
+    hipLaunchKernelGGL(k_traverse<true>, dim3(ng), dim3(64), 0, s, ta);
+    STK_CHECK_LAUNCH();
+
+    // near field, then far field (which adds the near part and un-permutes)
+    double *unear = reserve<double>(t.s_tmp, size_t(m) * 3);
+    NearArgs na{tpos, m, noff, ta.near_node, ta.near_mask, t.nstart.as<int32_t>(), t.ncount.as<int32_t>(),
+                t.geo.as<double>(), t.wts.p, unear};
+    FarArgs fa{tpos, m, foff, ta.far_node, ta.far_mask, t.ncenter.as<double>(), t.nrho.as<double>(), t.wblk.p,
+               unear, tperm, u_out, ng};
+    if (t.prec == STK_FP64) {
+        hipLaunchKernelGGL(k_near<double>, dim3(ng), dim3(64), 0, s, na);
+        STK_CHECK_LAUNCH();
+        dispatch_far<double>(t.p, fa, s);
+    } else {
+        hipLaunchKernelGGL(k_near<float>, dim3(ng), dim3(64), 0, s, na);
+        STK_CHECK_LAUNCH();
+        dispatch_far<float>(t.p, fa, s);
+    }
+}
+
+void direct_sum(const double *tgt, int64_t m, const double *src, int64_t n, const double *f, const double *h,
+                const double *nu, int32_t K, double *u_out, hipStream_t s) {
+    const int nch = int((n + DCH - 1) / DCH);
+    const unsigned ng = nblk(m, 64);
+    double *part = nullptr;
+    STK_HIP(hipMallocAsync((void **)&part, sizeof(double) * 3 * size_t(m) * nch, s));
+    for (int r = 0; r < K; ++r) {
+        hipLaunchKernelGGL(k_direct, dim3(ng, nch), dim3(64), 0, s, tgt, m, src, n, f + size_t(r) * n * 3,
+                           h + size_t(r) * n * 3, nu, part);
+        STK_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_direct_reduce, dim3(nblk(3 * m, 256)), dim3(256), 0, s, part, m, nch,
+                           u_out + size_t(r) * m * 3);
+        STK_CHECK_LAUNCH();
+    }
+    STK_HIP(hipFreeAsync(part, s));
+}
+
+}  // namespace stk

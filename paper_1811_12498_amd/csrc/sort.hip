@@ -1,0 +1,156 @@
+// Stable LSD radix sort of (uint64 key, int32 value) pairs and a single-block scan.
+//
+// Each pass handles 8 key bits: (1) per-tile digit histograms, (2) one exclusive
+// scan over the digit-major histogram table, (3) a stable scatter in which every
+// tile ranks its keys round by round (256 keys per round, wave64 ballots find the
+// lanes sharing a digit, wave counts are combined in LDS in wave order).  Ties keep
+// their input order, so sorting (key, index) pairs yields the order of a
+// lexicographic (key, index) sort.
+#include "stk_internal.hpp"
+
+namespace stk {
+namespace {
+
+constexpr int RB = 8;                 // bits per pass
+constexpr int RADIX = 1 << RB;
+constexpr int ST = 256;               // threads per block (4 waves)
+constexpr int ITEMS = 16;             // rounds per tile
+constexpr int TILE = ST * ITEMS;
+constexpr int NWAVE = ST / 64;
+
+__global__ __launch_bounds__(ST) void k_hist(const uint64_t *__restrict__ keys, int64_t n, int shift,
+                                             int32_t *__restrict__ hist, int32_t ntiles) {
+    __shared__ int32_t cnt[RADIX];
+    const int tid = threadIdx.x;
+    cnt[tid] = 0;
+    __syncthreads();
+    const int64_t base = int64_t(blockIdx.x) * TILE;
+    for (int it = 0; it < ITEMS; ++it) {
+        const int64_t i = base + int64_t(it) * ST + tid;
+        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & (RADIX - 1)], 1);
+    }
+    __syncthreads();
+    hist[int64_t(tid) * ntiles + blockIdx.x] = cnt[tid];
+}
+
+__global__ __launch_bounds__(ST) void k_scatter(const uint64_t *__restrict__ kin, const int32_t *__restrict__ vin,
+                                                uint64_t *__restrict__ kout, int32_t *__restrict__ vout, int64_t n,
+                                                int shift, const int32_t *__restrict__ off, int32_t ntiles) {
+    __shared__ int32_t base[RADIX];
+    __shared__ int32_t wcnt[NWAVE][RADIX];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const int lane = tid & 63;
+    base[tid] = off[int64_t(tid) * ntiles + blockIdx.x];
+    for (int w = 0; w < NWAVE; ++w) wcnt[w][tid] = 0;
+    __syncthreads();
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t tbase = int64_t(blockIdx.x) * TILE;
+    for (int it = 0; it < ITEMS; ++it) {
+        const int64_t i = tbase + int64_t(it) * ST + tid;
+        const bool valid = i < n;
+        uint64_t key = 0;
+        int32_t val = 0;
+        int dig = 0;
+        if (valid) {
+            key = kin[i];
+            val = vin[i];
+            dig = int((key >> shift) & (RADIX - 1));
+        }
+        uint64_t match = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+            const bool bit = (dig >> b) & 1;
+            const uint64_t bb = __ballot(bit);
+            match &= bit ? bb : ~bb;
+        }
+        const int rank = __popcll(match & lt);
+        if (valid && rank == 0) wcnt[wave][dig] = __popcll(match);
+        __syncthreads();
+        int dest = 0;
+        if (valid) {
+            int before = 0;
+            for (int w = 0; w < wave; ++w) before += wcnt[w][dig];
+            dest = base[dig] + before + rank;
+        }
+        __syncthreads();
+        {
+            int tot = 0;
+            for (int w = 0; w < NWAVE; ++w) {
+                tot += wcnt[w][tid];
+                wcnt[w][tid] = 0;
+            }
+            base[tid] += tot;
+        }
+        __syncthreads();
+        if (valid) {
+            kout[dest] = key;
+            vout[dest] = val;
+        }
+    }
+}
+
+constexpr int SCAN_T = 1024;
+
+__global__ __launch_bounds__(SCAN_T) void k_scan(const int32_t *__restrict__ in, int32_t *__restrict__ out,
+                                                 int64_t n) {
+    __shared__ int32_t part[SCAN_T];
+    const int tid = threadIdx.x;
+    const int64_t per = (n + SCAN_T - 1) / SCAN_T;
+    const int64_t b = int64_t(tid) * per;
+    const int64_t e = b + per < n ? b + per : n;
+    int32_t s = 0;
+    for (int64_t i = b; i < e; ++i) s += in[i];
+    part[tid] = s;
+    __syncthreads();
+    // inclusive Hillis-Steele scan of the per-thread sums
+    for (int o = 1; o < SCAN_T; o <<= 1) {
+        const int32_t v = tid >= o ? part[tid - o] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int32_t run = tid ? part[tid - 1] : 0;
+    for (int64_t i = b; i < e; ++i) {
+        const int32_t v = in[i];
+        out[i] = run;
+        run += v;
+    }
+    if (tid == SCAN_T - 1) out[n] = part[SCAN_T - 1];
+}
+
+}  // namespace
+
+void scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(SCAN_T), 0, s, in, out, n);
+    STK_CHECK_LAUNCH();
+}
+
+void radix_sort_pairs(Tree &t, uint64_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t s) {
+    if (n <= 1) return;
+    const int32_t ntiles = int32_t((n + TILE - 1) / TILE);
+    uint64_t *k2 = reserve<uint64_t>(t.s_keys2, size_t(n));
+    int32_t *v2 = reserve<int32_t>(t.s_vals2, size_t(n));
+    const int64_t hn = int64_t(RADIX) * ntiles;
+    int32_t *hist = reserve<int32_t>(t.s_hist, size_t(2 * hn + 2));
+    int32_t *off = hist + hn + 1;
+    uint64_t *ka = keys, *kb = k2;
+    int32_t *va = vals, *vb = v2;
+    const int passes = (bits + RB - 1) / RB;
+    for (int ps = 0; ps < passes; ++ps) {
+        const int shift = ps * RB;
+        hipLaunchKernelGGL(k_hist, dim3(ntiles), dim3(ST), 0, s, ka, n, shift, hist, ntiles);
+        STK_CHECK_LAUNCH();
+        scan_exclusive_i32(hist, off, hn, s);
+        hipLaunchKernelGGL(k_scatter, dim3(ntiles), dim3(ST), 0, s, ka, va, kb, vb, n, shift, off, ntiles);
+        STK_CHECK_LAUNCH();
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    if (ka != keys) {
+        STK_HIP(hipMemcpyAsync(keys, ka, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
+        STK_HIP(hipMemcpyAsync(vals, va, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+    }
+}
+
+}  // namespace stk

@@ -1,0 +1,147 @@
+// Internal declarations shared by the HIP translation units of libstokestree.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "stokestree.h"
+
+namespace stk {
+
+// ---------------------------------------------------------------------------------
+// errors: internal code throws stk::Error; the C-ABI layer converts it to a status
+// ---------------------------------------------------------------------------------
+struct Error : std::runtime_error {
+    stk_status status;
+    Error(stk_status s, const std::string &m) : std::runtime_error(m), status(s) {}
+};
+
+#define STK_HIP(call)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess) {                                                                    \
+            (void)hipGetLastError();                                                               \
+            throw ::stk::Error(e_ == hipErrorOutOfMemory ? STK_ENOMEM : STK_EDEVICE,               \
+                               std::string(#call) + ": " + hipGetErrorString(e_));                 \
+        }                                                                                          \
+    } while (0)
+
+#define STK_CHECK_LAUNCH() STK_HIP(hipGetLastError())
+
+inline void require(bool ok, const std::string &msg) {
+    if (!ok) throw Error(STK_EINVAL, msg);
+}
+
+// ---------------------------------------------------------------------------------
+// device buffer (grow-only, freed with its owner)
+// ---------------------------------------------------------------------------------
+struct DBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    ~DBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    // Ensure capacity; contents are not preserved.
+    void reserve(size_t b) {
+        if (b <= bytes) return;
+        release();
+        size_t want = b < 256 ? 256 : b;
+        STK_HIP(hipMalloc(&p, want));
+        bytes = want;
+    }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+template <class T> inline T *reserve(DBuf &b, size_t n) {
+    b.reserve(n * sizeof(T));
+    return b.as<T>();
+}
+
+// ---------------------------------------------------------------------------------
+// tree handle
+// ---------------------------------------------------------------------------------
+struct Tree {
+    int device = 0;
+    int64_t n = 0;
+    int32_t n0 = 0;
+    double lo[3] = {0, 0, 0}, L = 0.0, scale = 0.0;
+    bool degenerate = false;
+    int32_t nnodes = 0, nlevels = 0;
+    std::vector<int32_t> level_begin;  // host: first node of each level (+ end sentinel)
+
+    // sources in Morton order
+    DBuf keys, perm;            // uint64 keys, int32 sorted->input
+    DBuf pos;                   // double (n,3) sorted positions, row-major
+    // node table (SoA)
+    DBuf nlevel, nparent, nchild0, nnchild, nstart, ncount;   // int32
+    DBuf nbmin, nbmax, ncenter;  // double (nn,3)
+    DBuf nradius, nrho;          // double (nn)
+    // work chunks over (node, particle range) for per-node reductions
+    DBuf chunk_off;              // int32 (nn + 1): first chunk of each node
+    int32_t nchunks = 0;
+
+    // moments state
+    bool have_moments = false;
+    int32_t p = -1, k_rhs = 0;
+    stk_precision prec = STK_FP64;
+    DBuf mom;     // double (nn, nm, 12*K): channels 0..2 = M_j, 3..11 = Mt_jl (3 + 3j + l)
+    DBuf wblk;    // T (nn, nb, 12*K): scaled far-field channel blocks
+    DBuf geo;     // double (n, 6): sorted (y, nu) per source
+    DBuf wts;     // T (n, K, 6): sorted (f, h) per source and right-hand side
+
+    // reusable scratch for evaluation
+    DBuf s_keys, s_vals, s_keys2, s_vals2, s_hist, s_tmp;
+};
+
+// ---------------------------------------------------------------------------------
+// plan handle: a tree plus one target set's interaction lists
+// ---------------------------------------------------------------------------------
+struct Plan {
+    Tree *tree = nullptr;
+    bool owns_tree = false;
+    int64_t m = 0;
+    double theta = 0.0;
+    int32_t ngroups = 0;
+    DBuf tpos;                     // double (m,3) targets in Morton order
+    DBuf tperm;                    // int32 sorted -> caller index
+    DBuf far_off, near_off;        // int32 (ngroups + 1)
+    DBuf far_node, near_node;      // int32 entries
+    DBuf far_mask, near_mask;      // uint64 entries (lane masks of the 64-target group)
+    DBuf cnt_far, cnt_near, cnt_pairs;  // int32 per sorted target
+    int64_t n_far_entries = 0, n_near_entries = 0;
+    ~Plan();
+};
+
+// ---------------------------------------------------------------------------------
+// launch helpers implemented in the .hip files
+// ---------------------------------------------------------------------------------
+constexpr int GROUP = 64;  // targets per wavefront group
+constexpr int CHUNK = 2048;  // particles per reduction work item
+
+// radix sort of (uint64 key, int32 value) pairs; sorts keys[0..n) in place using
+// scratch buffers owned by `t`.  Stable.  `bits` = number of low key bits to sort.
+void radix_sort_pairs(Tree &t, uint64_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t s);
+// exclusive scan of int32 in[0..n) into out[0..n]; out[n] = total.  Single block.
+void scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t s);
+
+void build_tree(Tree &t, const double *src, int64_t n, int32_t n0, hipStream_t s);
+void compute_moments(Tree &t, const double *f, const double *h, const double *nu, int32_t k, int32_t p,
+                     stk_precision prec, hipStream_t s);
+void evaluate(Tree &t, Plan &plan, const double *tgt, int64_t m, double theta, double *u_out, hipStream_t s);
+void direct_sum(const double *tgt, int64_t m, const double *src, int64_t n, const double *f, const double *h,
+                const double *nu, int32_t k, double *u_out, hipStream_t s);
+
+inline int nm_of(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+
+}  // namespace stk

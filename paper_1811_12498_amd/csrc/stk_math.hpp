@@ -1,0 +1,202 @@
+// Arithmetic of the particle-cluster far field, shared by the device kernels (and
+// compiled for the host only by the unit check of this header).
+//
+// Notation of Wang, Tlupova & Krasny (arXiv 1811.12498): b^q are the Taylor
+// coefficients of the Coulomb potential 1/|x - y| about the cluster centre
+// (eq. GreenFunc), obtained from recurrence_1; M_j^k and Mt_jl^k are the cluster
+// moments of Sec. 2; the far field is eq. S_final plus eq. T_final.
+//
+// Both S_final and T_final are linear in the moments and in d = x - y_c.  Collecting
+// every term by the index q of the b it multiplies gives a 12-channel form
+//
+//     u_i = sum_q b^q G_i^q + sum_l d_l sum_q b^q F_il^q ,     ||q|| <= p + 2,
+//
+// where G (3 channels) and F (9 channels) depend on the cluster only; they are a
+// fixed sparse linear map of the moments (phi_channels below).  Per interaction this
+// costs 12 multiply-adds per b^q instead of forming sigma, tau, m, m_ij per k.
+//
+// Scaling.  With R = |d|, dh = d / R, t = rho / R (rho a power of two >= r, the
+// cluster radius) the recurrence is run on bt^q = t^||q|| R^(||q||+1) b^q:
+//     bt^0 = 1,  bt^k = c1_n sum_i dh_i bt^{k-e_i} - c2_n sum_i bt^{k-2e_i},
+//     c1_n = (2n-1)/n * t,  c2_n = (n-1)/n * t^2,  n = ||k||,
+// which is recurrence_1 divided through by R^(n+1) and multiplied by t^n.  With the
+// channel blocks stored as W^q / rho^||q||,
+//     u_i = (1/R) sum_q bt^q G^_i^q + sum_l dh_l sum_q bt^q F^_il^q .
+// Every bt^q is O(1) because t <= 2 theta, so FP32 neither overflows at small R nor
+// underflows at small rho.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace stk {
+
+#define STK_HD __host__ __device__ __attribute__((always_inline)) inline
+
+// number of multi-indices with ||k|| <= p
+STK_HD constexpr int nidx(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+
+// position of k in graded-lex order (n = 0..; k1 = n..0; k2 = n-k1..0), -1 if any
+// component is negative
+STK_HD constexpr int gidx(int k1, int k2, int k3) {
+    return (k1 < 0 || k2 < 0 || k3 < 0)
+               ? -1
+               : (k1 + k2 + k3) * (k1 + k2 + k3 + 1) * (k1 + k2 + k3 + 2) / 6 +
+                     (k2 + k3) * (k2 + k3 + 1) / 2 + k3;
+}
+
+// gidx restricted to ||k|| <= p
+STK_HD constexpr int gidxp(int k1, int k2, int k3, int p) {
+    return (k1 + k2 + k3 > p) ? -1 : gidx(k1, k2, k3);
+}
+
+// multi-index of position a (inverse of gidx)
+STK_HD void kof(int a, int k[3]) {
+    int n = 0;
+    while (nidx(n) <= a) ++n;
+    int r = a - (n > 0 ? nidx(n - 1) : 0);
+    // within order n: k1 = n..0, each k1 has (n - k1 + 1) entries
+    int k1 = n;
+    while (r >= n - k1 + 1) {
+        r -= n - k1 + 1;
+        --k1;
+    }
+    k[0] = k1;
+    k[1] = n - k1 - r;
+    k[2] = r;
+}
+
+// Moments of one cluster and one right-hand side: mom[a * ld + c], c = 0..2 for M_c,
+// c = 3 + 3j + l for Mt_jl.  Returns the 12 channels of W^q for multi-index q
+// (||q|| <= p + 2): out[i] = G_i^q, out[3 + 3i + l] = F_il^q.  Terms whose moment
+// index falls outside ||k|| <= p vanish (the expansion is truncated at order p).
+STK_HD void phi_channels(const double *mom, int ld, int p, const int q[3], double out[12]) {
+    auto M = [&](int k1, int k2, int k3, int c) -> double {
+        const int a = gidxp(k1, k2, k3, p);
+        return a < 0 ? 0.0 : mom[a * ld + c];
+    };
+    for (int c = 0; c < 12; ++c) out[c] = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        int ei[3] = {i == 0, i == 1, i == 2};
+        double G = 0.0;
+        // S_final: 2 b^k M_i^k
+        G += 2.0 * M(q[0], q[1], q[2], i);
+        for (int j = 0; j < 3; ++j) {
+            int ej[3] = {j == 0, j == 1, j == 2};
+            // S_final: -(k_i+1) b^{k+e_i-e_j} M_j^k, k = q - e_i + e_j
+            G -= (q[i] + (i == j)) * M(q[0] - ei[0] + ej[0], q[1] - ei[1] + ej[1], q[2] - ei[2] + ej[2], j);
+            // T_final: (k_j+1) b^{k+e_j} m_ij^k, k = q - e_j
+            {
+                const int k1 = q[0] - ej[0], k2 = q[1] - ej[1], k3 = q[2] - ej[2];
+                G += q[j] / 3.0 * (M(k1, k2, k3, 3 + 3 * i + j) + M(k1, k2, k3, 3 + 3 * j + i));
+            }
+            for (int l = 0; l < 3; ++l) {
+                int el[3] = {l == 0, l == 1, l == 2};
+                // T_final: -(k_i+1)(k_j+1+delta_ij) b^{k+e_i+e_j-e_l} Mt_jl^k
+                const int k[3] = {q[0] - ei[0] - ej[0] + el[0], q[1] - ei[1] - ej[1] + el[1],
+                                  q[2] - ei[2] - ej[2] + el[2]};
+                G -= (k[i] + 1) * (k[j] + 1 + (i == j)) / 3.0 * M(k[0], k[1], k[2], 3 + 3 * j + l);
+            }
+        }
+        // T_final: (k_i+1) b^{k+e_i} m^k, k = q - e_i
+        {
+            const int k1 = q[0] - ei[0], k2 = q[1] - ei[1], k3 = q[2] - ei[2];
+            G += q[i] / 3.0 * (M(k1, k2, k3, 3) + M(k1, k2, k3, 7) + M(k1, k2, k3, 11));
+        }
+        out[i] = G;
+        for (int l = 0; l < 3; ++l) {
+            // S_final: (k_i+1) b^{k+e_i} d_l M_l^k, k = q - e_i
+            double F = q[i] * M(q[0] - ei[0], q[1] - ei[1], q[2] - ei[2], l);
+            // T_final: (k_i+1)(k_j+1+delta_ij) b^{k+e_i+e_j} d_l Mt_jl^k, k = q - e_i - e_j
+            for (int j = 0; j < 3; ++j) {
+                int ej[3] = {j == 0, j == 1, j == 2};
+                F += q[i] * (q[j] - (i == j)) / 3.0 *
+                     M(q[0] - ei[0] - ej[0], q[1] - ei[1] - ej[1], q[2] - ei[2] - ej[2], 3 + 3 * j + l);
+            }
+            out[3 + 3 * i + l] = F;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// Far field of one (target, cluster) pair: the scaled recurrence fused with the
+// 12-channel contraction.  Straight-line code generated at compile time for each
+// order P, so every b^q lives in a register and only three orders are live at once.
+// W points at the cluster's block, W[q * 12 + c] (already divided by rho^||q||).
+// ---------------------------------------------------------------------------------
+template <int P, typename T> struct FarEval {
+    static constexpr int PB = P + 2;
+    static constexpr int NB = nidx(PB);
+
+    template <int N, int K1, int K2>
+    STK_HD static void step(T (&b)[NB], const T dh[3], T c1, T c2, const T *__restrict__ W, T acc[12]) {
+        constexpr int K3 = N - K1 - K2;
+        constexpr int Q = gidx(K1, K2, K3);
+        T s1 = T(0), s2 = T(0);
+        if constexpr (K1 > 0) s1 += dh[0] * b[gidx(K1 - 1, K2, K3)];
+        if constexpr (K2 > 0) s1 += dh[1] * b[gidx(K1, K2 - 1, K3)];
+        if constexpr (K3 > 0) s1 += dh[2] * b[gidx(K1, K2, K3 - 1)];
+        if constexpr (K1 > 1) s2 += b[gidx(K1 - 2, K2, K3)];
+        if constexpr (K2 > 1) s2 += b[gidx(K1, K2 - 2, K3)];
+        if constexpr (K3 > 1) s2 += b[gidx(K1, K2, K3 - 2)];
+        if constexpr (N > 1)
+            b[Q] = c1 * s1 - c2 * s2;
+        else
+            b[Q] = c1 * s1;
+        const T bq = b[Q];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) acc[c] += bq * W[Q * 12 + c];
+        if constexpr (K2 > 0)
+            step<N, K1, K2 - 1>(b, dh, c1, c2, W, acc);
+        else if constexpr (K1 > 0)
+            step<N, K1 - 1, N - K1 + 1>(b, dh, c1, c2, W, acc);
+    }
+
+    template <int N> STK_HD static void order(T (&b)[NB], const T dh[3], T t, const T *__restrict__ W, T acc[12]) {
+        const T c1 = T(2 * N - 1) / T(N) * t;
+        const T c2 = T(N - 1) / T(N) * (t * t);
+        step<N, N, 0>(b, dh, c1, c2, W, acc);
+        if constexpr (N < PB) order<N + 1>(b, dh, t, W, acc);
+    }
+
+    // acc[0..2] = sum_q bt^q G^_i^q, acc[3 + 3i + l] = sum_q bt^q F^_il^q
+    STK_HD static void run(const T dh[3], T t, const T *__restrict__ W, T acc[12]) {
+        T b[NB];
+        b[0] = T(1);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) acc[c] = W[c];
+        order<1>(b, dh, t, W, acc);
+    }
+};
+
+// velocity of one far interaction from the channel sums
+template <typename T> STK_HD void far_velocity(const T acc[12], const T dh[3], T rinv, T u[3]) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        u[i] = acc[i] * rinv + (dh[0] * acc[3 + 3 * i] + dh[1] * acc[4 + 3 * i] + dh[2] * acc[5 + 3 * i]);
+}
+
+// power of two >= r (1 when r == 0): the per-cluster scale of the channel blocks
+STK_HD double rho_of(double r) {
+    if (!(r > 0.0)) return 1.0;
+    int e;
+    const double m = frexp(r, &e);  // r = m * 2^e, m in [0.5, 1)
+    return ldexp(1.0, m == 0.5 ? e - 1 : e);
+}
+
+// Neumaier-compensated accumulator
+template <typename T> struct Comp {
+    T s = T(0), c = T(0);
+    STK_HD void add(T v) {
+        const T t = s + v;
+        if (fabs(s) >= fabs(v))
+            c += (s - t) + v;
+        else
+            c += (v - t) + s;
+        s = t;
+    }
+    STK_HD double value() const { return double(s) + double(c); }
+};
+
+}  // namespace stk

@@ -1,0 +1,408 @@
+// Octree over the sources (Sec. 5): root cube, Morton keys, radix sort, level-by-level
+// subdivision, tight boxes, centres and radii.
+//
+// Geometry is exact: bounds are min/max reductions, centres 0.5 * (min + max), and the
+// radius sqrt of the largest |y - y_c|^2, evaluated without contraction into FMA so
+// every value is the correctly rounded result of the expression as written.
+#include "stk_internal.hpp"
+#include "stk_math.hpp"
+
+#include <algorithm>
+#include <cmath>
+
+namespace stk {
+namespace {
+
+constexpr int BT = 256;
+
+__device__ inline double atomic_max_nonneg(double *addr, double v) {
+    // non-negative doubles order like their bit patterns
+    return __longlong_as_double(
+        (long long)atomicMax((unsigned long long *)addr, (unsigned long long)__double_as_longlong(v)));
+}
+
+// ---- bounds of the source set -----------------------------------------------------
+__global__ __launch_bounds__(BT) void k_bounds(const double *__restrict__ src, int64_t n, double *__restrict__ part) {
+    __shared__ double red[6][BT];
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = int64_t(blockIdx.x) * BT + threadIdx.x; i < n; i += int64_t(gridDim.x) * BT)
+        for (int a = 0; a < 3; ++a) {
+            const double v = src[3 * i + a];
+            lo[a] = fmin(lo[a], v);
+            hi[a] = fmax(hi[a], v);
+        }
+    for (int a = 0; a < 3; ++a) {
+        red[a][threadIdx.x] = lo[a];
+        red[3 + a][threadIdx.x] = hi[a];
+    }
+    __syncthreads();
+    for (int o = BT / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o)
+            for (int a = 0; a < 3; ++a) {
+                red[a][threadIdx.x] = fmin(red[a][threadIdx.x], red[a][threadIdx.x + o]);
+                red[3 + a][threadIdx.x] = fmax(red[3 + a][threadIdx.x], red[3 + a][threadIdx.x + o]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void k_bounds_final(const double *__restrict__ part, int nb, double *__restrict__ out) {
+    const int a = threadIdx.x;  // 6 threads
+    if (a >= 6) return;
+    double v = part[a];
+    for (int b = 1; b < nb; ++b) v = a < 3 ? fmin(v, part[b * 6 + a]) : fmax(v, part[b * 6 + a]);
+    out[a] = v;
+}
+
+// ---- Morton keys --------------------------------------------------------------------
+__device__ inline uint64_t spread3(uint64_t v) {  // 21 bits -> every third bit
+    v &= 0x1fffffull;
+    v = (v | (v << 32)) & 0x1f00000000ffffull;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+__device__ inline uint64_t quant(double y, double lo, double scale) {
+#pragma clang fp contract(off)
+    const double v = floor((y - lo) * scale);
+    if (!(v > 0.0)) return 0;
+    if (v > 2097151.0) return 2097151;
+    return (uint64_t)v;
+}
+
+__global__ void k_keys(const double *__restrict__ pts, int64_t n, double lx, double ly, double lz, double scale,
+                       int degenerate, uint64_t *__restrict__ keys, int32_t *__restrict__ vals) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t key = 0;
+    if (!degenerate) {
+        const uint64_t qx = quant(pts[3 * i], lx, scale);
+        const uint64_t qy = quant(pts[3 * i + 1], ly, scale);
+        const uint64_t qz = quant(pts[3 * i + 2], lz, scale);
+        key = (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
+    }
+    keys[i] = key;
+    vals[i] = int32_t(i);
+}
+
+__global__ void k_gather3(const double *__restrict__ src, const int32_t *__restrict__ perm, int64_t n,
+                          double *__restrict__ dst) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t j = perm[i];
+    dst[3 * i] = src[3 * j];
+    dst[3 * i + 1] = src[3 * j + 1];
+    dst[3 * i + 2] = src[3 * j + 2];
+}
+
+// ---- subdivision -----------------------------------------------------------------------
+// first index in [b, e) whose 3-bit digit at `shift` is >= c (keys sorted, prefix shared)
+__device__ inline int32_t lower_digit(const uint64_t *__restrict__ keys, int32_t b, int32_t e, int shift, int c) {
+    while (b < e) {
+        const int32_t m = b + ((e - b) >> 1);
+        if (int((keys[m] >> shift) & 7) < c)
+            b = m + 1;
+        else
+            e = m;
+    }
+    return b;
+}
+
+__global__ void k_split_count(const uint64_t *__restrict__ keys, const int32_t *__restrict__ start,
+                              const int32_t *__restrict__ count, int32_t lb, int32_t nlev, int shift, int32_t n0,
+                              int32_t *__restrict__ nch, int32_t *__restrict__ bnd) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nlev) return;
+    const int32_t s = start[lb + i], c = count[lb + i];
+    int32_t k = 0;
+    if (c > n0) {
+        int32_t b[9];
+        b[0] = s;
+        b[8] = s + c;
+        for (int d = 1; d < 8; ++d) b[d] = lower_digit(keys, b[d - 1], s + c, shift, d);
+        for (int d = 0; d < 9; ++d) bnd[9 * i + d] = b[d];
+        for (int d = 0; d < 8; ++d) k += b[d + 1] > b[d];
+    }
+    nch[i] = k;
+}
+
+__global__ void k_split_emit(int32_t lb, int32_t nlev, int32_t le, int32_t lev, const int32_t *__restrict__ nch,
+                             const int32_t *__restrict__ choff, const int32_t *__restrict__ bnd,
+                             int32_t *__restrict__ level, int32_t *__restrict__ parent, int32_t *__restrict__ child0,
+                             int32_t *__restrict__ nchild, int32_t *__restrict__ start, int32_t *__restrict__ count) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nlev) return;
+    const int32_t node = lb + i;
+    const int32_t k = nch[i];
+    if (k == 0) {
+        child0[node] = -1;
+        nchild[node] = 0;
+        return;
+    }
+    int32_t c = le + choff[i];
+    child0[node] = c;
+    nchild[node] = k;
+    for (int d = 0; d < 8; ++d) {
+        const int32_t b = bnd[9 * i + d], e = bnd[9 * i + d + 1];
+        if (e > b) {
+            level[c] = lev + 1;
+            parent[c] = node;
+            child0[c] = -1;
+            nchild[c] = 0;
+            start[c] = b;
+            count[c] = e - b;
+            ++c;
+        }
+    }
+}
+
+// ---- boxes ----------------------------------------------------------------------------
+__global__ __launch_bounds__(BT) void k_leaf_box(const double *__restrict__ pos, const int32_t *__restrict__ start,
+                                                 const int32_t *__restrict__ count,
+                                                 const int32_t *__restrict__ nchild, double *__restrict__ bmin,
+                                                 double *__restrict__ bmax, double *__restrict__ center) {
+    const int32_t node = blockIdx.x;
+    if (nchild[node] != 0) return;
+    __shared__ double red[6][BT];
+    const int32_t s = start[node], c = count[node];
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int32_t i = threadIdx.x; i < c; i += BT)
+        for (int a = 0; a < 3; ++a) {
+            const double v = pos[3 * int64_t(s + i) + a];
+            lo[a] = fmin(lo[a], v);
+            hi[a] = fmax(hi[a], v);
+        }
+    for (int a = 0; a < 3; ++a) {
+        red[a][threadIdx.x] = lo[a];
+        red[3 + a][threadIdx.x] = hi[a];
+    }
+    __syncthreads();
+    for (int o = BT / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o)
+            for (int a = 0; a < 3; ++a) {
+                red[a][threadIdx.x] = fmin(red[a][threadIdx.x], red[a][threadIdx.x + o]);
+                red[3 + a][threadIdx.x] = fmax(red[3 + a][threadIdx.x], red[3 + a][threadIdx.x + o]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) {
+        const int a = threadIdx.x;
+        const double l = red[a][0], h = red[3 + a][0];
+        bmin[3 * node + a] = l;
+        bmax[3 * node + a] = h;
+        center[3 * node + a] = 0.5 * (l + h);
+    }
+}
+
+__global__ void k_inner_box(int32_t lb, int32_t nlev, const int32_t *__restrict__ child0,
+                            const int32_t *__restrict__ nchild, double *__restrict__ bmin, double *__restrict__ bmax,
+                            double *__restrict__ center) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nlev) return;
+    const int32_t node = lb + i;
+    const int32_t k = nchild[node];
+    if (k == 0) return;
+    const int32_t c0 = child0[node];
+    for (int a = 0; a < 3; ++a) {
+        double l = bmin[3 * c0 + a], h = bmax[3 * c0 + a];
+        for (int32_t c = 1; c < k; ++c) {
+            l = fmin(l, bmin[3 * (c0 + c) + a]);
+            h = fmax(h, bmax[3 * (c0 + c) + a]);
+        }
+        bmin[3 * node + a] = l;
+        bmax[3 * node + a] = h;
+        center[3 * node + a] = 0.5 * (l + h);
+    }
+}
+
+// ---- radii over (node, chunk) work items ---------------------------------------------
+__global__ void k_chunk_count(const int32_t *__restrict__ count, int32_t nn, int32_t *__restrict__ out) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nn) out[i] = (count[i] + CHUNK - 1) / CHUNK;
+}
+
+__device__ inline int32_t node_of_chunk(const int32_t *__restrict__ off, int32_t nn, int32_t ch) {
+    int32_t lo = 0, hi = nn;  // last node with off[node] <= ch
+    while (hi - lo > 1) {
+        const int32_t m = (lo + hi) >> 1;
+        if (off[m] <= ch)
+            lo = m;
+        else
+            hi = m;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(BT) void k_radius(const double *__restrict__ pos, const int32_t *__restrict__ start,
+                                               const int32_t *__restrict__ count, const int32_t *__restrict__ coff,
+                                               int32_t nn, const double *__restrict__ center,
+                                               double *__restrict__ r2max) {
+#pragma clang fp contract(off)
+    const int32_t ch = blockIdx.x;
+    const int32_t node = node_of_chunk(coff, nn, ch);
+    const int32_t first = start[node] + (ch - coff[node]) * CHUNK;
+    const int32_t last = min(start[node] + count[node], first + CHUNK);
+    const double cx = center[3 * node], cy = center[3 * node + 1], cz = center[3 * node + 2];
+    double m = 0.0;
+    for (int32_t i = first + threadIdx.x; i < last; i += BT) {
+        const double dx = pos[3 * int64_t(i)] - cx;
+        const double dy = pos[3 * int64_t(i) + 1] - cy;
+        const double dz = pos[3 * int64_t(i) + 2] - cz;
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        m = fmax(m, r2);
+    }
+    __shared__ double red[BT];
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = BT / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomic_max_nonneg(&r2max[node], red[0]);
+}
+
+__global__ void k_radius_final(int32_t nn, double *__restrict__ r, double *__restrict__ rho) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nn) return;
+    const double v = sqrt(r[i]);
+    r[i] = v;
+    rho[i] = rho_of(v);
+}
+
+inline unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
+
+// grow a node array, keeping its first `keep` bytes
+void grow_keep(DBuf &b, size_t keep, size_t want, hipStream_t s) {
+    if (want <= b.bytes) return;
+    void *np = nullptr;
+    STK_HIP(hipMalloc(&np, want));
+    if (keep) STK_HIP(hipMemcpyAsync(np, b.p, keep, hipMemcpyDeviceToDevice, s));
+    STK_HIP(hipStreamSynchronize(s));
+    b.release();
+    b.p = np;
+    b.bytes = want;
+}
+
+}  // namespace
+
+void build_tree(Tree &t, const double *src, int64_t n, int32_t n0, hipStream_t s) {
+    t.n = n;
+    t.n0 = n0;
+    t.have_moments = false;
+
+    // root cube
+    const int nbb = int(std::min<int64_t>(1024, (n + BT - 1) / BT));
+    double *part = reserve<double>(t.s_tmp, size_t(nbb) * 6 + 6);
+    hipLaunchKernelGGL(k_bounds, dim3(nbb), dim3(BT), 0, s, src, n, part);
+    STK_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_bounds_final, dim3(1), dim3(64), 0, s, part, nbb, part + size_t(nbb) * 6);
+    STK_CHECK_LAUNCH();
+    double b6[6];
+    STK_HIP(hipMemcpyAsync(b6, part + size_t(nbb) * 6, sizeof(b6), hipMemcpyDeviceToHost, s));
+    STK_HIP(hipStreamSynchronize(s));
+    double L = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        t.lo[a] = b6[a];
+        if (b6[3 + a] - b6[a] > L) L = b6[3 + a] - b6[a];
+    }
+    t.L = L;
+    t.degenerate = !(L > 0.0);
+    t.scale = t.degenerate ? 0.0 : 2097152.0 / L;
+
+    // keys, sort, sorted positions
+    uint64_t *keys = reserve<uint64_t>(t.keys, size_t(n));
+    int32_t *perm = reserve<int32_t>(t.perm, size_t(n));
+    hipLaunchKernelGGL(k_keys, dim3(nblk(n, BT)), dim3(BT), 0, s, src, n, t.lo[0], t.lo[1], t.lo[2], t.scale,
+                       int(t.degenerate), keys, perm);
+    STK_CHECK_LAUNCH();
+    radix_sort_pairs(t, keys, perm, n, 63, s);
+    double *pos = reserve<double>(t.pos, size_t(n) * 3);
+    hipLaunchKernelGGL(k_gather3, dim3(nblk(n, BT)), dim3(BT), 0, s, src, perm, n, pos);
+    STK_CHECK_LAUNCH();
+
+    // subdivision, one level per step
+    size_t cap = 1024;
+    for (DBuf *b : {&t.nlevel, &t.nparent, &t.nchild0, &t.nnchild, &t.nstart, &t.ncount}) {
+        b->release();
+        b->reserve(cap * sizeof(int32_t));
+    }
+    {
+        const int32_t root[6] = {0, -1, -1, 0, 0, int32_t(n)};
+        DBuf *dst[6] = {&t.nlevel, &t.nparent, &t.nchild0, &t.nnchild, &t.nstart, &t.ncount};
+        for (int k = 0; k < 6; ++k)
+            STK_HIP(hipMemcpyAsync(dst[k]->p, &root[k], sizeof(int32_t), hipMemcpyHostToDevice, s));
+    }
+    int32_t nnodes = 1, lb = 0, le = 1, lev = 0;
+    t.level_begin.assign(1, 0);
+    while (!t.degenerate && lev < STK_MAX_LEVEL) {
+        const int32_t nlev = le - lb;
+        int32_t *nch = reserve<int32_t>(t.s_vals, size_t(nlev) * 11 + 2);
+        int32_t *choff = nch + nlev;
+        int32_t *bnd = reserve<int32_t>(t.s_vals2, size_t(nlev) * 9);
+        hipLaunchKernelGGL(k_split_count, dim3(nblk(nlev, BT)), dim3(BT), 0, s, keys, t.nstart.as<int32_t>(),
+                           t.ncount.as<int32_t>(), lb, nlev, 3 * (STK_MAX_LEVEL - 1 - lev), n0, nch, bnd);
+        STK_CHECK_LAUNCH();
+        scan_exclusive_i32(nch, choff, nlev, s);
+        int32_t total = 0;
+        STK_HIP(hipMemcpyAsync(&total, choff + nlev, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        STK_HIP(hipStreamSynchronize(s));
+        if (total > 0 && size_t(nnodes + total) > cap) {
+            size_t ncap = cap;
+            while (ncap < size_t(nnodes + total)) ncap *= 2;
+            for (DBuf *b : {&t.nlevel, &t.nparent, &t.nchild0, &t.nnchild, &t.nstart, &t.ncount})
+                grow_keep(*b, size_t(nnodes) * sizeof(int32_t), ncap * sizeof(int32_t), s);
+            cap = ncap;
+        }
+        hipLaunchKernelGGL(k_split_emit, dim3(nblk(nlev, BT)), dim3(BT), 0, s, lb, nlev, le, lev, nch, choff, bnd,
+                           t.nlevel.as<int32_t>(), t.nparent.as<int32_t>(), t.nchild0.as<int32_t>(),
+                           t.nnchild.as<int32_t>(), t.nstart.as<int32_t>(), t.ncount.as<int32_t>());
+        STK_CHECK_LAUNCH();
+        t.level_begin.push_back(le);
+        if (total == 0) break;
+        nnodes += total;
+        lb = le;
+        le = nnodes;
+        ++lev;
+    }
+    if (t.level_begin.back() != nnodes) t.level_begin.push_back(nnodes);
+    t.nnodes = nnodes;
+    t.nlevels = int32_t(t.level_begin.size()) - 1;
+
+    // boxes and centres: leaves from their points, inner nodes from their children
+    double *bmin = reserve<double>(t.nbmin, size_t(nnodes) * 3);
+    double *bmax = reserve<double>(t.nbmax, size_t(nnodes) * 3);
+    double *cen = reserve<double>(t.ncenter, size_t(nnodes) * 3);
+    hipLaunchKernelGGL(k_leaf_box, dim3(nnodes), dim3(BT), 0, s, pos, t.nstart.as<int32_t>(),
+                       t.ncount.as<int32_t>(), t.nnchild.as<int32_t>(), bmin, bmax, cen);
+    STK_CHECK_LAUNCH();
+    for (int l = t.nlevels - 2; l >= 0; --l) {
+        const int32_t b = t.level_begin[l], e = t.level_begin[l + 1];
+        hipLaunchKernelGGL(k_inner_box, dim3(nblk(e - b, BT)), dim3(BT), 0, s, b, e - b,
+                           t.nchild0.as<int32_t>(), t.nnchild.as<int32_t>(), bmin, bmax, cen);
+        STK_CHECK_LAUNCH();
+    }
+
+    // work chunks and radii
+    int32_t *cnt = reserve<int32_t>(t.s_vals, size_t(nnodes));
+    int32_t *coff = reserve<int32_t>(t.chunk_off, size_t(nnodes) + 1);
+    hipLaunchKernelGGL(k_chunk_count, dim3(nblk(nnodes, BT)), dim3(BT), 0, s, t.ncount.as<int32_t>(), nnodes, cnt);
+    STK_CHECK_LAUNCH();
+    scan_exclusive_i32(cnt, coff, nnodes, s);
+    STK_HIP(hipMemcpyAsync(&t.nchunks, coff + nnodes, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    double *rad = reserve<double>(t.nradius, size_t(nnodes));
+    double *rho = reserve<double>(t.nrho, size_t(nnodes));
+    STK_HIP(hipMemsetAsync(rad, 0, sizeof(double) * nnodes, s));
+    STK_HIP(hipStreamSynchronize(s));
+    hipLaunchKernelGGL(k_radius, dim3(t.nchunks), dim3(BT), 0, s, pos, t.nstart.as<int32_t>(),
+                       t.ncount.as<int32_t>(), coff, nnodes, cen, rad);
+    STK_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_radius_final, dim3(nblk(nnodes, BT)), dim3(BT), 0, s, nnodes, rad, rho);
+    STK_CHECK_LAUNCH();
+    STK_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace stk
