@@ -1,0 +1,198 @@
+"""Benchmark: Stokeslet + stresslet treecode on one MI355X.
+
+Workload (the metric's configuration): N = 1,000,000 points on the unit sphere from
+normalised Gaussians (seed 3), nu = outward normal, f ~ U[-1,1]^3, h = f; p = 8,
+theta = 0.5, N0 = 1000; mixed FP32/FP64 arithmetic.  One step = the whole hot path
+through the C-ABI (stk_evaluate: tree build, moments, target sort, MAC traversal, near
+and far fields) for all N targets with inputs already resident in HBM.
+
+Prints one JSON line with the throughput (targets/s), the roofline of the dominant
+kernel (far field) measured with HIP events on the library's stream, the accuracy on
+2000 seeded sampled targets against the FP64 GPU direct sum, and the FP64 CPU
+oracle's throughput on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_VALU = 157.3e12   # MI355X published FP32 vector peak (packed FMA)
+PEAK_FP64_VALU = 78.6e12
+PEAK_HBM = 8.0e12
+
+
+def nb_of(p):
+    q = p + 2
+    return (q + 1) * (q + 2) * (q + 3) // 6
+
+
+def far_flops_per_interaction(p, k=1):
+    # recurrence ~11 flops per b^q, 12-channel contraction 2 flops x 12 x K per b^q, 21 for
+    # the per-interaction set-up and the final combination (algorithmic count)
+    nb = nb_of(p)
+    return 11 * nb + 24 * nb * k + 21
+
+
+NEAR_FLOPS_PER_PAIR = 48  # Stokeslet + stresslet contracted pair (Sec. 4.1)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, f, h, n_sample=2000, seed=99):
+    """The FP64 oracle on the host: tree + moments for all N, then Algorithm 1 at a
+    seeded sample of targets; extrapolated to whole-job targets/s."""
+    import oracle
+    oracle.build(force=False)
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(w.n, n_sample, replace=False))
+    t0 = time.perf_counter()
+    T = oracle.build_tree(w.src, w.n0)
+    M, Mt = oracle.moments(T, w.src, f, h, w.nu, w.p)
+    t1 = time.perf_counter()
+    oracle.treecode(T, w.src, f, h, w.nu, M, Mt, w.p, w.theta, w.src[idx])
+    t2 = time.perf_counter()
+    t_job = (t1 - t0) + (t2 - t1) * w.n / n_sample
+    return {"value": w.n / t_job, "unit": "targets/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"tree+moments for all {w.n} sources ({t1 - t0:.2f} s) + Algorithm 1 at {n_sample} "
+                      f"seeded targets ({t2 - t1:.2f} s), extrapolated to {w.n} targets"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the FP64 comparison runs")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain 256 MiB device copy (a reference for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the treecode would shard over targets with replicated sources; see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1811_12498_amd import native, workloads
+
+    w = workloads.c3_sphere_1m()
+    f, h = w.f[0], w.h[0]
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    X, F, H, NU = t(w.src), t(f), t(h), t(w.nu)
+    torch.cuda.synchronize()
+    log(f"workload {w.name}: N={w.n} p={w.p} theta={w.theta} N0={w.n0} precision={args.precision}")
+
+    def step(prec=args.precision):
+        return native.evaluate(X, X, F, H, NU, w.p, w.theta, w.n0, prec)
+
+    if args.copy_probe:
+        a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    for i in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    native.profile_read()  # discard warm-up timings
+
+    native.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        u = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    native.profile_enable(False)
+    prof = native.profile_read()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = w.n / (ms_per_step / 1e3)
+    log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, {value:.4g} targets/s")
+    phases = {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items() if v[1]}
+    log(f"phase ms/launch: {phases}")
+
+    # algorithmic work of one step (exact interaction counts from the lists)
+    _, plan = native.evaluate(X, X, F, H, NU, w.p, w.theta, w.n0, args.precision, keep_plan=True)
+    nfar, nnear, npairs = native.plan_counts(plan)
+    del plan
+    far_total = int(nfar.sum())
+    pairs_total = int(npairs.sum())
+    far_ms = prof["far"][0] / prof["far"][1]
+    near_ms = prof["near"][0] / prof["near"][1]
+    far_flops = far_total * far_flops_per_interaction(w.p)
+    near_flops = pairs_total * NEAR_FLOPS_PER_PAIR
+    peak = PEAK_FP32_VALU if args.precision == "mixed" else PEAK_FP64_VALU
+    far_tf = far_flops / (far_ms * 1e-3)
+    near_tf = near_flops / (near_ms * 1e-3)
+    roofline = {"bound": "alu", "achieved": round(far_tf / 1e12, 3), "peak": peak / 1e12, "unit": "TFLOP/s",
+                "frac": round(far_tf / peak, 4), "traffic": None, "kernel": f"k_far<{w.p},{'float' if args.precision == 'mixed' else 'double'}>",
+                "far_interactions_per_launch": far_total, "flops_per_interaction": far_flops_per_interaction(w.p),
+                "avg_launch_ms": round(far_ms, 4)}
+
+    # accuracy on the seeded sample against the FP64 GPU direct sum
+    S = w.sample
+    XS = X[torch.from_numpy(S).to(dev)].contiguous()
+    ud = native.direct(XS, X, F, H, NU)
+    torch.cuda.synchronize()
+    uS = u[torch.from_numpy(S).to(dev)]
+    rel = lambda a, b: float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+    acc = {"E_S_vs_fp64_direct": rel(uS, ud), "sample_targets": int(S.size)}
+    extras = {}
+    if not args.no_extras:
+        # FP64 treecode at equal (p, theta) and the FP64 direct sum, both on the GPU
+        u64 = step("fp64")
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for i in range(2):
+            u64 = step("fp64")
+        torch.cuda.synchronize()
+        t64 = (time.perf_counter() - ta) / 2
+        acc["E_S_fp64_treecode_vs_fp64_direct"] = rel(u64[torch.from_numpy(S).to(dev)], ud)
+        acc["E_vs_fp64_treecode_all_targets"] = rel(u, u64)
+        native.profile_enable(True)
+        ud = native.direct(XS, X, F, H, NU)
+        torch.cuda.synchronize()
+        native.profile_enable(False)
+        dprof = native.profile_read()["direct"]
+        extras = {"fp64_treecode_targets_per_s": w.n / t64,
+                  "fp64_direct_targets_per_s": S.size / (dprof[0] * 1e-3),
+                  "near_field": {"achieved_tflops": round(near_tf / 1e12, 3),
+                                 "frac_of_fp32_peak": round(near_tf / PEAK_FP32_VALU, 4),
+                                 "pairs_per_launch": pairs_total, "avg_launch_ms": round(near_ms, 4)},
+                  "phase_ms_per_step": phases}
+    log(f"accuracy: {acc}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the FP64 CPU oracle on a bounded sample ...")
+        cpu = cpu_baseline(w, f, h)
+        log(f"cpu baseline: {cpu}")
+
+    out = {"metric": "targets/s at N=1M, rel L2 err<=1e-5 vs FP64 direct; fwd+adjoint ms, FP32 vs FP64",
+           "value": value, "unit": "targets/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32" if args.precision == "mixed" else "f64", "data": "synthetic",
+           "config": {"workload": "sphere N=1e6 (normalised Gaussians), nu=normal, h=f, p=8, theta=0.5, N0=1000, "
+                                  f"{args.precision}", "n": w.n, "p": w.p, "theta": w.theta, "n0": w.n0,
+                      "precision": args.precision},
+           "roofline": roofline, "cpu_baseline": cpu, "accuracy": acc, **extras}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

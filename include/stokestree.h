@@ -140,6 +140,26 @@ stk_status stk_tree_export_moments(const stk_tree *t, int32_t rhs, double *M, do
  * arrays of length m): far-field nodes, near-field leaves, near-field pairs. */
 stk_status stk_plan_counts(const stk_plan *plan, int64_t *nfar, int64_t *nnear, int64_t *npairs);
 
+/* Phase timing, a tracing aid.  While enabled, every entry point records a HIP event
+ * on its stream when it starts and after each phase below; stk_profile_read waits for
+ * those events, returns the summed milliseconds and the number of timed intervals
+ * per phase since the last read (host arrays of STK_NPHASES entries; either may be
+ * NULL), and clears the record.  Timing is process-wide; calls on several streams
+ * at once are not separated. */
+#define STK_NPHASES 8
+enum {
+    STK_PHASE_TREE = 0,     /* root cube, Morton keys, sort, subdivision, boxes, radii */
+    STK_PHASE_MOMENTS = 1,  /* moments, channel blocks, near-field records            */
+    STK_PHASE_TARGETS = 2,  /* target keys and sort                                    */
+    STK_PHASE_LISTS = 3,    /* MAC traversal: counts, scan, interaction lists          */
+    STK_PHASE_NEAR = 4,     /* near-field kernel                                        */
+    STK_PHASE_FAR = 5,      /* far-field kernel                                         */
+    STK_PHASE_DIRECT = 6,   /* FP64 direct sum                                          */
+    STK_PHASE_ADJOINT = 7   /* adjoint kernels                                          */
+};
+stk_status stk_profile_enable(int on);
+stk_status stk_profile_read(double *ms, int64_t *count);
+
 void stk_tree_destroy(stk_tree *t);
 void stk_plan_destroy(stk_plan *plan);
 /* Message for the calling thread's last non-OK status ("" if none). */

@@ -25,7 +25,9 @@ _STATUS_NAMES = {STK_EINVAL: "STK_EINVAL", STK_ENOMEM: "STK_ENOMEM", STK_EDEVICE
 # every symbol include/stokestree.h declares
 EXPORTS = ["stk_build_tree", "stk_compute_moments", "stk_evaluate_tree", "stk_evaluate", "stk_direct",
            "stk_tree_info", "stk_tree_export", "stk_tree_export_moments", "stk_plan_counts",
-           "stk_tree_destroy", "stk_plan_destroy", "stk_last_error"]
+           "stk_profile_enable", "stk_profile_read", "stk_tree_destroy", "stk_plan_destroy", "stk_last_error"]
+
+PHASES = ["tree", "moments", "targets", "lists", "near", "far", "direct", "adjoint"]
 
 
 class StkError(RuntimeError):
@@ -54,6 +56,8 @@ _lib.stk_tree_info.argtypes = [_vp, _i64p, _i32p, _dp]
 _lib.stk_tree_export.argtypes = [_vp] + [_vp] * 11
 _lib.stk_tree_export_moments.argtypes = [_vp, _i32, _vp, _vp]
 _lib.stk_plan_counts.argtypes = [_vp, _vp, _vp, _vp]
+_lib.stk_profile_enable.argtypes = [ctypes.c_int]
+_lib.stk_profile_read.argtypes = [_vp, _vp]
 _lib.stk_tree_destroy.argtypes = [_vp]
 _lib.stk_plan_destroy.argtypes = [_vp]
 for _name in EXPORTS:
@@ -210,6 +214,18 @@ def plan_counts(plan: Plan):
     _check(_lib.stk_plan_counts(plan.handle, ctypes.c_void_p(a.ctypes.data), ctypes.c_void_p(b.ctypes.data),
                                 ctypes.c_void_p(c.ctypes.data)))
     return a, b, c
+
+
+def profile_enable(on: bool = True) -> None:
+    _check(_lib.stk_profile_enable(1 if on else 0))
+
+
+def profile_read() -> dict:
+    """{phase: (total ms, number of timed intervals)} since the last read; clears the record."""
+    ms = np.zeros(len(PHASES))
+    cnt = np.zeros(len(PHASES), np.int64)
+    _check(_lib.stk_profile_read(ctypes.c_void_p(ms.ctypes.data), ctypes.c_void_p(cnt.ctypes.data)))
+    return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(PHASES)}
 
 
 def exported_symbols() -> list[str]:

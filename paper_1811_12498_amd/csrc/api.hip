@@ -239,6 +239,14 @@ stk_status stk_plan_counts(const stk_plan *plan, int64_t *nfar, int64_t *nnear, 
     });
 }
 
+stk_status stk_profile_enable(int on) {
+    return guarded([&] { stk::prof_enable(on != 0); });
+}
+
+stk_status stk_profile_read(double *ms, int64_t *count) {
+    return guarded([&] { stk::prof_read(ms, count); });
+}
+
 void stk_tree_destroy(stk_tree *t) { delete t; }
 void stk_plan_destroy(stk_plan *plan) { delete plan; }
 

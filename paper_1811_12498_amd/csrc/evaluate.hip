@@ -336,6 +336,7 @@ void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, dou
     pl.theta = theta;
     const int32_t ng = int32_t((m + 63) / 64);
     pl.ngroups = ng;
+    prof_mark(-1, s);
 
     // targets in Morton order of the tree's root cube
     uint64_t *keys = reserve<uint64_t>(t.s_keys, size_t(m));
@@ -347,6 +348,7 @@ void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, dou
     double *tpos = reserve<double>(pl.tpos, size_t(m) * 3);
     hipLaunchKernelGGL(k_gather3, dim3(nblk(m, 256)), dim3(256), 0, s, tgt, tperm, m, tpos);
     STK_CHECK_LAUNCH();
+    prof_mark(STK_PHASE_TARGETS, s);
 
     // interaction lists: count, scan, fill
     TravArgs ta{};
@@ -384,6 +386,7 @@ void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, dou
     ta.near_mask = reserve<uint64_t>(pl.near_mask, size_t(tot[1]) + 1);
     hipLaunchKernelGGL(k_traverse<true>, dim3(ng), dim3(64), 0, s, ta);
     STK_CHECK_LAUNCH();
+    prof_mark(STK_PHASE_LISTS, s);
 
     // near field, then far field (which adds the near part and un-permutes)
     double *unear = reserve<double>(t.s_tmp, size_t(m) * 3);
@@ -394,12 +397,15 @@ void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, dou
     if (t.prec == STK_FP64) {
         hipLaunchKernelGGL(k_near<double>, dim3(ng), dim3(64), 0, s, na);
         STK_CHECK_LAUNCH();
+        prof_mark(STK_PHASE_NEAR, s);
         dispatch_far<double>(t.p, fa, s);
     } else {
         hipLaunchKernelGGL(k_near<float>, dim3(ng), dim3(64), 0, s, na);
         STK_CHECK_LAUNCH();
+        prof_mark(STK_PHASE_NEAR, s);
         dispatch_far<float>(t.p, fa, s);
     }
+    prof_mark(STK_PHASE_FAR, s);
 }
 
 void direct_sum(const double *tgt, int64_t m, const double *src, int64_t n, const double *f, const double *h,
@@ -407,6 +413,7 @@ void direct_sum(const double *tgt, int64_t m, const double *src, int64_t n, cons
     const int nch = int((n + DCH - 1) / DCH);
     const unsigned ng = nblk(m, 64);
     double *part = nullptr;
+    prof_mark(-1, s);
     STK_HIP(hipMallocAsync((void **)&part, sizeof(double) * 3 * size_t(m) * nch, s));
     for (int r = 0; r < K; ++r) {
         hipLaunchKernelGGL(k_direct, dim3(ng, nch), dim3(64), 0, s, tgt, m, src, n, f + size_t(r) * n * 3,
@@ -416,6 +423,7 @@ void direct_sum(const double *tgt, int64_t m, const double *src, int64_t n, cons
                            u_out + size_t(r) * m * 3);
         STK_CHECK_LAUNCH();
     }
+    prof_mark(STK_PHASE_DIRECT, s);
     STK_HIP(hipFreeAsync(part, s));
 }
 

@@ -162,6 +162,7 @@ void compute_moments(Tree &t, const double *f, const double *h, const double *nu
                      stk_precision prec, hipStream_t s) {
     const int nm = nidx(p), nb = nidx(p + 2);
     const int32_t nn = t.nnodes;
+    prof_mark(-1, s);
     double *part = reserve<double>(t.s_tmp, size_t(t.nchunks) * K * nm * 12);
     const size_t shm = sizeof(double) * STAGE * (3 * (p + 1) + 12);
     hipLaunchKernelGGL(k_moments, dim3(t.nchunks, K), dim3(MT), shm, s, t.pos.as<double>(), t.perm.as<int32_t>(),
@@ -189,6 +190,7 @@ void compute_moments(Tree &t, const double *f, const double *h, const double *nu
                            t.perm.as<int32_t>(), t.n, K, f, h, nu, t.geo.as<double>(), t.wts.as<float>());
     }
     STK_CHECK_LAUNCH();
+    prof_mark(STK_PHASE_MOMENTS, s);
     t.p = p;
     t.k_rhs = K;
     t.prec = prec;

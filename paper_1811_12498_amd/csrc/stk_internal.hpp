@@ -142,6 +142,11 @@ void evaluate(Tree &t, Plan &plan, const double *tgt, int64_t m, double theta, d
 void direct_sum(const double *tgt, int64_t m, const double *src, int64_t n, const double *f, const double *h,
                 const double *nu, int32_t k, double *u_out, hipStream_t s);
 
+// phase timing (profile.hip); phases are the STK_PHASE_* values of the public header
+void prof_mark(int phase, hipStream_t s);
+void prof_enable(bool on);
+void prof_read(double *ms, int64_t *count);
+
 inline int nm_of(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
 
 }  // namespace stk

@@ -293,6 +293,7 @@ void build_tree(Tree &t, const double *src, int64_t n, int32_t n0, hipStream_t s
     t.n = n;
     t.n0 = n0;
     t.have_moments = false;
+    prof_mark(-1, s);
 
     // root cube
     const int nbb = int(std::min<int64_t>(1024, (n + BT - 1) / BT));
@@ -402,6 +403,7 @@ void build_tree(Tree &t, const double *src, int64_t n, int32_t n0, hipStream_t s
     STK_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_radius_final, dim3(nblk(nnodes, BT)), dim3(BT), 0, s, nnodes, rad, rho);
     STK_CHECK_LAUNCH();
+    prof_mark(STK_PHASE_TREE, s);
     STK_HIP(hipStreamSynchronize(s));
 }
 
