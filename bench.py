@@ -129,6 +129,7 @@ def main():
     # algorithmic work of one step (exact interaction counts from the lists)
     _, plan = native.evaluate(X, X, F, H, NU, w.p, w.theta, w.n0, args.precision, keep_plan=True)
     nfar, nnear, npairs = native.plan_counts(plan)
+    pinfo = native.plan_info(plan)
     del plan
     far_total = int(nfar.sum())
     pairs_total = int(npairs.sum())
@@ -142,7 +143,8 @@ def main():
     roofline = {"bound": "alu", "achieved": round(far_tf / 1e12, 3), "peak": peak / 1e12, "unit": "TFLOP/s",
                 "frac": round(far_tf / peak, 4), "traffic": None, "kernel": f"k_far<{w.p},{'float' if args.precision == 'mixed' else 'double'}>",
                 "far_interactions_per_launch": far_total, "flops_per_interaction": far_flops_per_interaction(w.p),
-                "avg_launch_ms": round(far_ms, 4)}
+                "avg_launch_ms": round(far_ms, 4), "far_entries": pinfo["far_entries"],
+                "lane_utilisation": round(far_total / (64.0 * pinfo["far_entries"]), 4)}
 
     # accuracy on the seeded sample against the FP64 GPU direct sum
     S = w.sample

@@ -160,6 +160,10 @@ enum {
 stk_status stk_profile_enable(int on);
 stk_status stk_profile_read(double *ms, int64_t *count);
 
+/* Sizes of a plan's interaction lists: number of 64-target groups, far entries and near
+ * entries (each entry is one cluster applied to a subset of one group's targets). */
+stk_status stk_plan_info(const stk_plan *plan, int64_t *ngroups, int64_t *n_far_entries, int64_t *n_near_entries);
+
 void stk_tree_destroy(stk_tree *t);
 void stk_plan_destroy(stk_plan *plan);
 /* Message for the calling thread's last non-OK status ("" if none). */

@@ -24,7 +24,7 @@ _STATUS_NAMES = {STK_EINVAL: "STK_EINVAL", STK_ENOMEM: "STK_ENOMEM", STK_EDEVICE
 
 # every symbol include/stokestree.h declares
 EXPORTS = ["stk_build_tree", "stk_compute_moments", "stk_evaluate_tree", "stk_evaluate", "stk_direct",
-           "stk_tree_info", "stk_tree_export", "stk_tree_export_moments", "stk_plan_counts",
+           "stk_tree_info", "stk_tree_export", "stk_tree_export_moments", "stk_plan_counts", "stk_plan_info",
            "stk_profile_enable", "stk_profile_read", "stk_tree_destroy", "stk_plan_destroy", "stk_last_error"]
 
 PHASES = ["tree", "moments", "targets", "lists", "near", "far", "direct", "adjoint"]
@@ -56,6 +56,7 @@ _lib.stk_tree_info.argtypes = [_vp, _i64p, _i32p, _dp]
 _lib.stk_tree_export.argtypes = [_vp] + [_vp] * 11
 _lib.stk_tree_export_moments.argtypes = [_vp, _i32, _vp, _vp]
 _lib.stk_plan_counts.argtypes = [_vp, _vp, _vp, _vp]
+_lib.stk_plan_info.argtypes = [_vp, _i64p, _i64p, _i64p]
 _lib.stk_profile_enable.argtypes = [ctypes.c_int]
 _lib.stk_profile_read.argtypes = [_vp, _vp]
 _lib.stk_tree_destroy.argtypes = [_vp]
@@ -214,6 +215,12 @@ def plan_counts(plan: Plan):
     _check(_lib.stk_plan_counts(plan.handle, ctypes.c_void_p(a.ctypes.data), ctypes.c_void_p(b.ctypes.data),
                                 ctypes.c_void_p(c.ctypes.data)))
     return a, b, c
+
+
+def plan_info(plan: Plan) -> dict:
+    g, fe, ne = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.stk_plan_info(plan.handle, ctypes.byref(g), ctypes.byref(fe), ctypes.byref(ne)))
+    return {"groups": g.value, "far_entries": fe.value, "near_entries": ne.value}
 
 
 def profile_enable(on: bool = True) -> None:

@@ -239,6 +239,15 @@ stk_status stk_plan_counts(const stk_plan *plan, int64_t *nfar, int64_t *nnear, 
     });
 }
 
+stk_status stk_plan_info(const stk_plan *plan, int64_t *ngroups, int64_t *n_far_entries, int64_t *n_near_entries) {
+    return guarded([&] {
+        stk::require(plan != nullptr, "plan is NULL");
+        if (ngroups) *ngroups = plan->p.ngroups;
+        if (n_far_entries) *n_far_entries = plan->p.n_far_entries;
+        if (n_near_entries) *n_near_entries = plan->p.n_near_entries;
+    });
+}
+
 stk_status stk_profile_enable(int on) {
     return guarded([&] { stk::prof_enable(on != 0); });
 }

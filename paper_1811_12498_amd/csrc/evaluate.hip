@@ -176,7 +176,9 @@ __device__ inline void pair_mixed(double x0, double x1, double x2, const double 
 }
 
 template <typename T> __global__ __launch_bounds__(64) void k_near(NearArgs a) {
-    const int32_t g = blockIdx.x;
+    const int32_t ng = int32_t((a.m + 63) / 64);
+    const int32_t g = xcd_group(ng);
+    if (g >= ng) return;
     const int lane = threadIdx.x;
     const int64_t t = int64_t(g) * 64 + lane;
     const bool valid = t < a.m;
@@ -395,12 +397,12 @@ void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, dou
     FarArgs fa{tpos, m, foff, ta.far_node, ta.far_mask, t.ncenter.as<double>(), t.nrho.as<double>(), t.wblk.p,
                unear, tperm, u_out, ng};
     if (t.prec == STK_FP64) {
-        hipLaunchKernelGGL(k_near<double>, dim3(ng), dim3(64), 0, s, na);
+        hipLaunchKernelGGL(k_near<double>, dim3(xcd_blocks(ng)), dim3(64), 0, s, na);
         STK_CHECK_LAUNCH();
         prof_mark(STK_PHASE_NEAR, s);
         dispatch_far<double>(t.p, fa, s);
     } else {
-        hipLaunchKernelGGL(k_near<float>, dim3(ng), dim3(64), 0, s, na);
+        hipLaunchKernelGGL(k_near<float>, dim3(xcd_blocks(ng)), dim3(64), 0, s, na);
         STK_CHECK_LAUNCH();
         prof_mark(STK_PHASE_NEAR, s);
         dispatch_far<float>(t.p, fa, s);

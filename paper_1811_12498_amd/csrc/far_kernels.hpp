@@ -1,8 +1,10 @@
 // Far-field kernel: one wavefront per group of 64 Morton-consecutive targets walks the
 // group's far list of (cluster, lane mask) entries; lanes whose target accepted the
-// cluster (eq. MAC) evaluate eq. S_final + eq. T_final through the scaled 12-channel
-// recurrence of stk_math.hpp.  The cluster index is wave-uniform, so its channel
+// cluster (eq. MAC) evaluate eq. S_final + eq. T_final through the scaled recurrence
+// and the G/E contraction of stk_math.hpp.  The cluster index is wave-uniform, so its
 // block is read through the scalar cache and broadcast to the lanes as SGPR operands.
+// Workgroups are numbered so that each XCD (8 per chip, each with its own L2) runs a
+// contiguous range of groups, which share most of their clusters.
 #pragma once
 
 #include "stk_internal.hpp"
@@ -18,17 +20,25 @@ struct FarArgs {
     const uint64_t *mask;
     const double *center;    // (nn,3)
     const double *rho;       // (nn)
-    const void *wblk;        // (nn, nb, 12) in T
+    const void *wblk;        // (nn, 6 nG) in T: G block then E block
     const double *unear;     // (m,3) sorted near-field velocity
     const int32_t *tperm;    // sorted -> caller index
     double *u_out;           // (m,3) caller order
     int32_t ngroups;
 };
 
+// block index -> group: XCD x = blockIdx % 8 gets groups [x * per, (x + 1) * per)
+__device__ inline int32_t xcd_group(int32_t ngroups) {
+    const int32_t per = (ngroups + 7) >> 3;
+    return int32_t(blockIdx.x & 7) * per + int32_t(blockIdx.x >> 3);
+}
+inline unsigned xcd_blocks(int32_t ngroups) { return unsigned(((ngroups + 7) >> 3) << 3); }
+
 template <int P, typename T>
 __global__ __launch_bounds__(64) void k_far(FarArgs a) {
-    constexpr int NB = nidx(P + 2);
-    const int32_t g = blockIdx.x;
+    constexpr int NG = nidx(P + 1);
+    const int32_t g = xcd_group(a.ngroups);
+    if (g >= a.ngroups) return;
     const int lane = threadIdx.x;
     const int64_t t = int64_t(g) * 64 + lane;
     const bool valid = t < a.m;
@@ -50,10 +60,11 @@ __global__ __launch_bounds__(64) void k_far(FarArgs a) {
             const double rinv = 1.0 / sqrt(R2);
             const T dh[3] = {T(d0 * rinv), T(d1 * rinv), T(d2 * rinv)};
             const T tt = T(a.rho[c] * rinv);
-            T ch[12];
-            FarEval<P, T>::run(dh, tt, wb + size_t(c) * NB * 12, ch);
+            const T *blk = wb + size_t(c) * 6 * NG;
+            T accG[3], accF[3];
+            FarEval<P, T>::run(dh, tt, blk, blk + 3 * NG, accG, accF);
             T u[3];
-            far_velocity(ch, dh, T(rinv), u);
+            far_velocity(accG, accF, T(rinv), u);
             acc[0].add(u[0]);
             acc[1].add(u[1]);
             acc[2].add(u[2]);
@@ -69,7 +80,7 @@ __global__ __launch_bounds__(64) void k_far(FarArgs a) {
 
 template <int P, typename T> void launch_far(const FarArgs &a, hipStream_t s) {
     if (a.ngroups == 0) return;
-    hipLaunchKernelGGL((k_far<P, T>), dim3(a.ngroups), dim3(64), 0, s, a);
+    hipLaunchKernelGGL((k_far<P, T>), dim3(xcd_blocks(a.ngroups)), dim3(64), 0, s, a);
     STK_CHECK_LAUNCH();
 }
 

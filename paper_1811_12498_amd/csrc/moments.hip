@@ -115,23 +115,27 @@ __global__ __launch_bounds__(MT) void k_moments_reduce(const double *__restrict_
     }
 }
 
-// grid (nnodes, K): channel blocks W^q / rho^||q|| for ||q|| <= p + 2, stored as
-// wblk[(node * nb + q) * 12K + 12 r + c] in the evaluation precision
+// grid (nnodes, K): far-field blocks for ||a|| <= p + 1 in the evaluation precision,
+// wblk[(node * K + r) * 6 nG + 3a + i] = G_i^a / rho^||a||  and
+// wblk[(node * K + r) * 6 nG + 3 nG + 3a + l] = E_l^a / rho^(||a||+1)
 template <typename T>
 __global__ __launch_bounds__(MT) void k_channels(const double *__restrict__ mom, const double *__restrict__ rho, int p,
-                                                 int nm, int nb, T *__restrict__ wblk) {
+                                                 int nm, int ng, T *__restrict__ wblk) {
     const int32_t node = blockIdx.x;
     const int r = blockIdx.y, K = gridDim.y;
     const double inv = 1.0 / rho[node];  // a power of two: exact
-    for (int a = threadIdx.x; a < nb; a += MT) {
+    T *out = wblk + (size_t(node) * K + r) * 6 * ng;
+    for (int a = threadIdx.x; a < ng; a += MT) {
         int q[3];
         kof(a, q);
-        double ch[12];
-        phi_channels(mom + size_t(node) * nm * 12 * K + 12 * r, 12 * K, p, q, ch);
+        double ge[6];
+        phi_ge(mom + size_t(node) * nm * 12 * K + 12 * r, 12 * K, p, q, ge);
         double s = 1.0;
         for (int e = 0; e < q[0] + q[1] + q[2]; ++e) s *= inv;
-        T *out = wblk + (size_t(node) * nb + a) * 12 * K + 12 * r;
-        for (int c = 0; c < 12; ++c) out[c] = T(ch[c] * s);
+        for (int c = 0; c < 3; ++c) {
+            out[3 * a + c] = T(ge[c] * s);
+            out[3 * ng + 3 * a + c] = T(ge[3 + c] * s * inv);
+        }
     }
 }
 
@@ -160,7 +164,7 @@ inline unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
 
 void compute_moments(Tree &t, const double *f, const double *h, const double *nu, int32_t K, int32_t p,
                      stk_precision prec, hipStream_t s) {
-    const int nm = nidx(p), nb = nidx(p + 2);
+    const int nm = nidx(p), ng = nidx(p + 1);
     const int32_t nn = t.nnodes;
     prof_mark(-1, s);
     double *part = reserve<double>(t.s_tmp, size_t(t.nchunks) * K * nm * 12);
@@ -173,17 +177,17 @@ void compute_moments(Tree &t, const double *f, const double *h, const double *nu
     hipLaunchKernelGGL(k_moments_reduce, dim3(nn, K), dim3(MT), 0, s, part, t.chunk_off.as<int32_t>(), nm, mom);
     STK_CHECK_LAUNCH();
     const size_t esz = prec == STK_FP64 ? sizeof(double) : sizeof(float);
-    t.wblk.reserve(size_t(nn) * nb * 12 * K * esz);
+    t.wblk.reserve(size_t(nn) * ng * 6 * K * esz);
     t.geo.reserve(size_t(t.n) * 6 * sizeof(double));
     t.wts.reserve(size_t(t.n) * K * 6 * esz);
     if (prec == STK_FP64) {
-        hipLaunchKernelGGL(k_channels<double>, dim3(nn, K), dim3(MT), 0, s, mom, t.nrho.as<double>(), p, nm, nb,
+        hipLaunchKernelGGL(k_channels<double>, dim3(nn, K), dim3(MT), 0, s, mom, t.nrho.as<double>(), p, nm, ng,
                            t.wblk.as<double>());
         STK_CHECK_LAUNCH();
         hipLaunchKernelGGL(k_records<double>, dim3(nblk(t.n, 256)), dim3(256), 0, s, t.pos.as<double>(),
                            t.perm.as<int32_t>(), t.n, K, f, h, nu, t.geo.as<double>(), t.wts.as<double>());
     } else {
-        hipLaunchKernelGGL(k_channels<float>, dim3(nn, K), dim3(MT), 0, s, mom, t.nrho.as<double>(), p, nm, nb,
+        hipLaunchKernelGGL(k_channels<float>, dim3(nn, K), dim3(MT), 0, s, mom, t.nrho.as<double>(), p, nm, ng,
                            t.wblk.as<float>());
         STK_CHECK_LAUNCH();
         hipLaunchKernelGGL(k_records<float>, dim3(nblk(t.n, 256)), dim3(256), 0, s, t.pos.as<double>(),

@@ -7,23 +7,23 @@
 // moments of Sec. 2; the far field is eq. S_final plus eq. T_final.
 //
 // Both S_final and T_final are linear in the moments and in d = x - y_c.  Collecting
-// every term by the index q of the b it multiplies gives a 12-channel form
+// every term by the index q of the b it multiplies gives
 //
 //     u_i = sum_q b^q G_i^q + sum_l d_l sum_q b^q F_il^q ,     ||q|| <= p + 2,
 //
-// where G (3 channels) and F (9 channels) depend on the cluster only; they are a
-// fixed sparse linear map of the moments (phi_channels below).  Per interaction this
-// costs 12 multiply-adds per b^q instead of forming sigma, tau, m, m_ij per k.
+// where G and F depend on the cluster only and are a fixed sparse linear map of the
+// moments (phi_channels below).  F factors further (phi_ge), leaving 3 G and 3 E
+// values per multi-index of order <= p + 1, so an interaction costs about 9 multiply-
+// adds per multi-index on top of the recurrence, instead of forming sigma, tau, m,
+// m_ij per k.
 //
 // Scaling.  With R = |d|, dh = d / R, t = rho / R (rho a power of two >= r, the
 // cluster radius) the recurrence is run on bt^q = t^||q|| R^(||q||+1) b^q:
 //     bt^0 = 1,  bt^k = c1_n sum_i dh_i bt^{k-e_i} - c2_n sum_i bt^{k-2e_i},
 //     c1_n = (2n-1)/n * t,  c2_n = (n-1)/n * t^2,  n = ||k||,
 // which is recurrence_1 divided through by R^(n+1) and multiplied by t^n.  With the
-// channel blocks stored as W^q / rho^||q||,
-//     u_i = (1/R) sum_q bt^q G^_i^q + sum_l dh_l sum_q bt^q F^_il^q .
-// Every bt^q is O(1) because t <= 2 theta, so FP32 neither overflows at small R nor
-// underflows at small rho.
+// cluster blocks stored as G^q / rho^||q|| and E^k / rho^(||k||+1), every bt^q is O(1)
+// (t <= 2 theta), so FP32 neither overflows at small R nor underflows at small rho.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -119,18 +119,47 @@ STK_HD void phi_channels(const double *mom, int ld, int p, const int q[3], doubl
     }
 }
 
+// The F channels factor: F_il^q = q_i E_l^{q-e_i} with
+//     E_l^k = M_l^k + (1/3) sum_j k_j Mt_jl^{k-e_j},     ||k|| <= p + 1,
+// (substitute k = q - e_i in the two F terms above), so the F part of the far field is
+//     sum_l d_l sum_q b^q F_il^q = sum_k (k_i + 1) b^{k+e_i} (d . E^k).
+// G vanishes for ||q|| = p + 2.  A cluster therefore needs 3 G and 3 E values per
+// multi-index of order <= p + 1.  Returns G^a (out[0..2]) and E^a (out[3..5]).
+STK_HD void phi_ge(const double *mom, int ld, int p, const int a3[3], double out[6]) {
+    double ch[12];
+    phi_channels(mom, ld, p, a3, ch);
+    out[0] = ch[0];
+    out[1] = ch[1];
+    out[2] = ch[2];
+    auto M = [&](int k1, int k2, int k3, int c) -> double {
+        const int a = gidxp(k1, k2, k3, p);
+        return a < 0 ? 0.0 : mom[a * ld + c];
+    };
+    for (int l = 0; l < 3; ++l) {
+        double e = M(a3[0], a3[1], a3[2], l);
+        e += a3[0] / 3.0 * M(a3[0] - 1, a3[1], a3[2], 3 + l);
+        e += a3[1] / 3.0 * M(a3[0], a3[1] - 1, a3[2], 6 + l);
+        e += a3[2] / 3.0 * M(a3[0], a3[1], a3[2] - 1, 9 + l);
+        out[3 + l] = e;
+    }
+}
+
 // ---------------------------------------------------------------------------------
 // Far field of one (target, cluster) pair: the scaled recurrence fused with the
-// 12-channel contraction.  Straight-line code generated at compile time for each
-// order P, so every b^q lives in a register and only three orders are live at once.
-// W points at the cluster's block, W[q * 12 + c] (already divided by rho^||q||).
+// contraction.  Straight-line code generated at compile time for each order P, so
+// every b^q lives in a register and only three orders are live at once.
+//   G points at the cluster's Ghat block, G[3a + i] = G_i^a / rho^||a||,
+//   E points at its Ehat block,          E[3a + l] = E_l^a / rho^(||a||+1),
+// for a < nidx(P + 1).  With bt the scaled coefficients,
+//   u_i = (1/R) sum_q bt^q Ghat_i^q + sum_k (k_i + 1) bt^{k+e_i} (dh . Ehat^k).
 // ---------------------------------------------------------------------------------
 template <int P, typename T> struct FarEval {
     static constexpr int PB = P + 2;
     static constexpr int NB = nidx(PB);
 
+    // b^q for ||q|| = N, plus the G contraction of that order
     template <int N, int K1, int K2>
-    STK_HD static void step(T (&b)[NB], const T dh[3], T c1, T c2, const T *__restrict__ W, T acc[12]) {
+    STK_HD static void step(T (&b)[NB], const T dh[3], T c1, T c2, const T *__restrict__ G, T accG[3]) {
         constexpr int K3 = N - K1 - K2;
         constexpr int Q = gidx(K1, K2, K3);
         T s1 = T(0), s2 = T(0);
@@ -144,37 +173,61 @@ template <int P, typename T> struct FarEval {
             b[Q] = c1 * s1 - c2 * s2;
         else
             b[Q] = c1 * s1;
-        const T bq = b[Q];
-#pragma unroll
-        for (int c = 0; c < 12; ++c) acc[c] += bq * W[Q * 12 + c];
+        if constexpr (N <= P + 1) {
+            const T bq = b[Q];
+            accG[0] += bq * G[3 * Q];
+            accG[1] += bq * G[3 * Q + 1];
+            accG[2] += bq * G[3 * Q + 2];
+        }
         if constexpr (K2 > 0)
-            step<N, K1, K2 - 1>(b, dh, c1, c2, W, acc);
+            step<N, K1, K2 - 1>(b, dh, c1, c2, G, accG);
         else if constexpr (K1 > 0)
-            step<N, K1 - 1, N - K1 + 1>(b, dh, c1, c2, W, acc);
+            step<N, K1 - 1, N - K1 + 1>(b, dh, c1, c2, G, accG);
     }
 
-    template <int N> STK_HD static void order(T (&b)[NB], const T dh[3], T t, const T *__restrict__ W, T acc[12]) {
+    // the E contraction for every k of order N - 1 (needs b of order N)
+    template <int N, int K1, int K2>
+    STK_HD static void estep(const T (&b)[NB], const T dh[3], const T *__restrict__ E, T accF[3]) {
+        constexpr int M = N - 1;
+        constexpr int K3 = M - K1 - K2;
+        constexpr int A = gidx(K1, K2, K3);
+        const T sig = dh[0] * E[3 * A] + dh[1] * E[3 * A + 1] + dh[2] * E[3 * A + 2];
+        accF[0] += b[gidx(K1 + 1, K2, K3)] * (T(K1 + 1) * sig);
+        accF[1] += b[gidx(K1, K2 + 1, K3)] * (T(K2 + 1) * sig);
+        accF[2] += b[gidx(K1, K2, K3 + 1)] * (T(K3 + 1) * sig);
+        if constexpr (K2 > 0)
+            estep<N, K1, K2 - 1>(b, dh, E, accF);
+        else if constexpr (K1 > 0)
+            estep<N, K1 - 1, M - K1 + 1>(b, dh, E, accF);
+    }
+
+    template <int N>
+    STK_HD static void order(T (&b)[NB], const T dh[3], T t, const T *__restrict__ G, const T *__restrict__ E,
+                             T accG[3], T accF[3]) {
         const T c1 = T(2 * N - 1) / T(N) * t;
         const T c2 = T(N - 1) / T(N) * (t * t);
-        step<N, N, 0>(b, dh, c1, c2, W, acc);
-        if constexpr (N < PB) order<N + 1>(b, dh, t, W, acc);
+        step<N, N, 0>(b, dh, c1, c2, G, accG);
+        estep<N, N - 1, 0>(b, dh, E, accF);
+        if constexpr (N < PB) order<N + 1>(b, dh, t, G, E, accG, accF);
     }
 
-    // acc[0..2] = sum_q bt^q G^_i^q, acc[3 + 3i + l] = sum_q bt^q F^_il^q
-    STK_HD static void run(const T dh[3], T t, const T *__restrict__ W, T acc[12]) {
+    // u_i = accG_i / R + accF_i
+    STK_HD static void run(const T dh[3], T t, const T *__restrict__ G, const T *__restrict__ E, T accG[3],
+                           T accF[3]) {
         T b[NB];
         b[0] = T(1);
-#pragma unroll
-        for (int c = 0; c < 12; ++c) acc[c] = W[c];
-        order<1>(b, dh, t, W, acc);
+        accG[0] = G[0];
+        accG[1] = G[1];
+        accG[2] = G[2];
+        accF[0] = accF[1] = accF[2] = T(0);
+        order<1>(b, dh, t, G, E, accG, accF);
     }
 };
 
-// velocity of one far interaction from the channel sums
-template <typename T> STK_HD void far_velocity(const T acc[12], const T dh[3], T rinv, T u[3]) {
+// velocity of one far interaction from the two partial sums
+template <typename T> STK_HD void far_velocity(const T accG[3], const T accF[3], T rinv, T u[3]) {
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
-        u[i] = acc[i] * rinv + (dh[0] * acc[3 + 3 * i] + dh[1] * acc[4 + 3 * i] + dh[2] * acc[5 + 3 * i]);
+    for (int i = 0; i < 3; ++i) u[i] = accG[i] * rinv + accF[i];
 }
 
 // power of two >= r (1 when r == 0): the per-cluster scale of the channel blocks

@@ -8,9 +8,10 @@
 template <int P> static void run_p(const double *d, double rho, const double *W, double u[3]) {
     const double R = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     const double dh[3] = {d[0] / R, d[1] / R, d[2] / R};
-    double acc[12];
-    stk::FarEval<P, double>::run(dh, rho / R, W, acc);
-    stk::far_velocity(acc, dh, 1.0 / R, u);
+    const int ng = stk::nidx(P + 1);
+    double accG[3], accF[3];
+    stk::FarEval<P, double>::run(dh, rho / R, W, W + 3 * ng, accG, accF);
+    stk::far_velocity(accG, accF, 1.0 / R, u);
 }
 
 extern "C" {
@@ -20,16 +21,19 @@ double hc_rho(double r) { return stk::rho_of(r); }
 
 // mom: (nm, 12) moments of one cluster; d = x - y_c; r = cluster radius
 void hc_far(const double *mom, int p, const double *d, double r, double *u) {
-    const int nb = stk::nidx(p + 2);
+    const int ng = stk::nidx(p + 1);
     const double rho = stk::rho_of(r);
-    std::vector<double> W(nb * 12);
-    for (int a = 0; a < nb; ++a) {
+    std::vector<double> W(ng * 6);
+    for (int a = 0; a < ng; ++a) {
         int q[3];
         stk::kof(a, q);
-        double ch[12];
-        stk::phi_channels(mom, 12, p, q, ch);
+        double ge[6];
+        stk::phi_ge(mom, 12, p, q, ge);
         const double s = std::pow(rho, -(q[0] + q[1] + q[2]));
-        for (int c = 0; c < 12; ++c) W[a * 12 + c] = ch[c] * s;
+        for (int c = 0; c < 3; ++c) {
+            W[3 * a + c] = ge[c] * s;
+            W[3 * ng + 3 * a + c] = ge[3 + c] * s / rho;
+        }
     }
     switch (p) {
         case 0: run_p<0>(d, rho, W.data(), u); break;
