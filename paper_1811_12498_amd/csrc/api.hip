@@ -103,7 +103,7 @@ stk_status stk_evaluate_tree(stk_tree *t, const double *targets, int64_t m, doub
         if (keep_plan) *keep_plan = nullptr;
         auto *pl = new stk_plan();
         try {
-            stk::evaluate(t->t, pl->p, targets, m, theta, u_out, as_stream(stream));
+            stk::evaluate(t->t, pl->p, targets, m, theta, u_out, false, as_stream(stream));
         } catch (...) {
             delete pl;
             throw;
@@ -131,19 +131,35 @@ stk_status stk_evaluate(const double *targets, int64_t m, const double *sources,
         stk::require(theta >= 0.0 && theta < 1.0, "theta must be in [0, 1)");
         if (keep_plan) *keep_plan = nullptr;
         hipStream_t s = as_stream(stream);
+        int dev = 0;
+        STK_HIP(hipGetDevice(&dev));
+        const bool same = targets == sources && m == n;
+        if (!keep_plan) {
+            // One-shot call: reuse this thread's workspace so that steady-state calls do not
+            // allocate.  The workspace lives until the thread ends (never freed: its device
+            // memory is returned when the process exits).
+            thread_local stk::Tree *ws_tree = nullptr;
+            thread_local stk_plan *ws_plan = nullptr;
+            if (!ws_tree || ws_tree->device != dev) {
+                ws_tree = new stk::Tree();
+                ws_plan = new stk_plan();
+                ws_tree->device = dev;
+            }
+            stk::build_tree(*ws_tree, sources, n, n0, s);
+            stk::compute_moments(*ws_tree, f, h, nu, k_rhs, p, prec, s);
+            stk::evaluate(*ws_tree, ws_plan->p, targets, m, theta, u_out, same, s);
+            STK_HIP(hipStreamSynchronize(s));
+            return;
+        }
         std::unique_ptr<stk::Tree> tree(new stk::Tree());
-        STK_HIP(hipGetDevice(&tree->device));
+        tree->device = dev;
         stk::build_tree(*tree, sources, n, n0, s);
         stk::compute_moments(*tree, f, h, nu, k_rhs, p, prec, s);
         std::unique_ptr<stk_plan> pl(new stk_plan());
-        stk::evaluate(*tree, pl->p, targets, m, theta, u_out, s);
-        if (keep_plan) {
-            pl->p.tree = tree.release();
-            pl->p.owns_tree = true;
-            *keep_plan = pl.release();
-        } else {
-            STK_HIP(hipStreamSynchronize(s));
-        }
+        stk::evaluate(*tree, pl->p, targets, m, theta, u_out, same, s);
+        pl->p.tree = tree.release();
+        pl->p.owns_tree = true;
+        *keep_plan = pl.release();
     });
 }
 

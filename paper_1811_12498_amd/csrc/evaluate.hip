@@ -139,40 +139,41 @@ struct NearArgs {
     double *unear;       // (m,3) sorted order
 };
 
-// one source's contribution, FP64 (STK_FP64)
-__device__ inline void pair_f64(double x0, double x1, double x2, const double *__restrict__ gj,
-                                const double *__restrict__ wj, double &u0, double &u1, double &u2) {
-    const double d0 = x0 - gj[0], d1 = x1 - gj[1], d2 = x2 - gj[2];
+// One source's contribution (contracted pair of Sec. 4.1).  g = (y, nu) and w = (f, h)
+// are wave-uniform (held in SGPRs).
+__device__ inline void pair_f64(double x0, double x1, double x2, const double g[6], const double w[6], double &u0,
+                                double &u1, double &u2) {
+    const double d0 = x0 - g[0], d1 = x1 - g[1], d2 = x2 - g[2];
     const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
     const double ri = r2 > 0.0 ? rsqrt(r2) : 0.0;
     const double r2i = ri * ri;
     const double r3i = ri * r2i;
-    const double dn = d0 * gj[3] + d1 * gj[4] + d2 * gj[5];
-    const double s = (d0 * wj[0] + d1 * wj[1] + d2 * wj[2]) * r3i;
-    const double tt = (d0 * wj[3] + d1 * wj[4] + d2 * wj[5]) * dn * (r3i * r2i);
-    const double st = s + tt;
-    u0 += wj[0] * ri + d0 * st;
-    u1 += wj[1] * ri + d1 * st;
-    u2 += wj[2] * ri + d2 * st;
+    const double dn = d0 * g[3] + d1 * g[4] + d2 * g[5];
+    const double sv = (d0 * w[0] + d1 * w[1] + d2 * w[2]) * r3i;
+    const double tt = (d0 * w[3] + d1 * w[4] + d2 * w[5]) * dn * (r3i * r2i);
+    const double st = sv + tt;
+    u0 += w[0] * ri + d0 * st;
+    u1 += w[1] * ri + d1 * st;
+    u2 += w[2] * ri + d2 * st;
 }
 
-// mixed precision: d and d.nu in FP64 (they carry the cancellation on surfaces), the
-// rest in FP32
-__device__ inline void pair_mixed(double x0, double x1, double x2, const double *__restrict__ gj,
-                                  const float *__restrict__ wj, float &u0, float &u1, float &u2) {
-    const double d0 = x0 - gj[0], d1 = x1 - gj[1], d2 = x2 - gj[2];
-    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-    const double dn = d0 * gj[3] + d1 * gj[4] + d2 * gj[5];
+// Mixed precision: d = x - y and d.nu in FP64 (on a surface with nu the normal d.nu is
+// O(|d|^2), so its absolute rounding must stay at FP64 level), the rest in FP32.
+__device__ inline void pair_mixed(double x0, double x1, double x2, const double g[6], const float w[6], float &u0,
+                                  float &u1, float &u2) {
+    const double d0 = x0 - g[0], d1 = x1 - g[1], d2 = x2 - g[2];
+    const double dn = d0 * g[3] + d1 * g[4] + d2 * g[5];
     const float f0 = float(d0), f1 = float(d1), f2 = float(d2);
-    const float ri = r2 > 0.0 ? __frsqrt_rn(float(r2)) : 0.0f;
+    const float r2 = f0 * f0 + f1 * f1 + f2 * f2;
+    const float ri = r2 > 0.0f ? __frsqrt_rn(r2) : 0.0f;
     const float r2i = ri * ri;
     const float r3i = ri * r2i;
-    const float s = (f0 * wj[0] + f1 * wj[1] + f2 * wj[2]) * r3i;
-    const float tt = (f0 * wj[3] + f1 * wj[4] + f2 * wj[5]) * float(dn) * (r3i * r2i);
-    const float st = s + tt;
-    u0 += wj[0] * ri + f0 * st;
-    u1 += wj[1] * ri + f1 * st;
-    u2 += wj[2] * ri + f2 * st;
+    const float sv = (f0 * w[0] + f1 * w[1] + f2 * w[2]) * r3i;
+    const float tt = (f0 * w[3] + f1 * w[4] + f2 * w[5]) * float(dn) * (r3i * r2i);
+    const float st = sv + tt;
+    u0 += w[0] * ri + f0 * st;
+    u1 += w[1] * ri + f1 * st;
+    u2 += w[2] * ri + f2 * st;
 }
 
 template <typename T> __global__ __launch_bounds__(64) void k_near(NearArgs a) {
@@ -198,14 +199,39 @@ template <typename T> __global__ __launch_bounds__(64) void k_near(NearArgs a) {
         if ((mk >> lane) & 1ull) {
             const int32_t s = a.start[c], n = a.count[c];
             T u0 = T(0), u1 = T(0), u2 = T(0);
-#pragma unroll 4
-            for (int32_t j = s; j < s + n; ++j) {
+            // sources in batches of four: the four records are requested together (one
+            // wait on the scalar cache per batch), then their four pairs are evaluated
+            int32_t j = s;
+            for (; j + 4 <= s + n; j += 4) {
+                double gb[4][6];
+                T wb[4][6];
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) {
+                        gb[b][q] = geo[6 * int64_t(j + b) + q];
+                        wb[b][q] = wts[6 * int64_t(j + b) + q];
+                    }
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    if constexpr (sizeof(T) == 8)
+                        pair_f64(x0, x1, x2, gb[b], reinterpret_cast<const double *>(wb[b]), u0, u1, u2);
+                    else
+                        pair_mixed(x0, x1, x2, gb[b], reinterpret_cast<const float *>(wb[b]), u0, u1, u2);
+                }
+            }
+            for (; j < s + n; ++j) {
+                double gc[6];
+                T wc[6];
+#pragma unroll
+                for (int q = 0; q < 6; ++q) {
+                    gc[q] = geo[6 * int64_t(j) + q];
+                    wc[q] = wts[6 * int64_t(j) + q];
+                }
                 if constexpr (sizeof(T) == 8)
-                    pair_f64(x0, x1, x2, geo + 6 * int64_t(j), reinterpret_cast<const double *>(wts) + 6 * int64_t(j),
-                             u0, u1, u2);
+                    pair_f64(x0, x1, x2, gc, reinterpret_cast<const double *>(wc), u0, u1, u2);
                 else
-                    pair_mixed(x0, x1, x2, geo + 6 * int64_t(j), reinterpret_cast<const float *>(wts) + 6 * int64_t(j),
-                               u0, u1, u2);
+                    pair_mixed(x0, x1, x2, gc, reinterpret_cast<const float *>(wc), u0, u1, u2);
             }
             acc[0].add(u0);
             acc[1].add(u1);
@@ -332,7 +358,8 @@ Plan::~Plan() {
     if (owns_tree) delete tree;
 }
 
-void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, double *u_out, hipStream_t s) {
+void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, double *u_out, bool same_as_sources,
+              hipStream_t s) {
     pl.tree = &t;
     pl.m = m;
     pl.theta = theta;
@@ -341,15 +368,20 @@ void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, dou
     prof_mark(-1, s);
 
     // targets in Morton order of the tree's root cube
-    uint64_t *keys = reserve<uint64_t>(t.s_keys, size_t(m));
     int32_t *tperm = reserve<int32_t>(pl.tperm, size_t(m));
-    hipLaunchKernelGGL(k_tkeys, dim3(nblk(m, 256)), dim3(256), 0, s, tgt, m, t.lo[0], t.lo[1], t.lo[2], t.scale,
-                       keys, tperm);
-    STK_CHECK_LAUNCH();
-    radix_sort_pairs(t, keys, tperm, m, 63, s);
     double *tpos = reserve<double>(pl.tpos, size_t(m) * 3);
-    hipLaunchKernelGGL(k_gather3, dim3(nblk(m, 256)), dim3(256), 0, s, tgt, tperm, m, tpos);
-    STK_CHECK_LAUNCH();
+    if (same_as_sources) {
+        STK_HIP(hipMemcpyAsync(tperm, t.perm.p, sizeof(int32_t) * m, hipMemcpyDeviceToDevice, s));
+        STK_HIP(hipMemcpyAsync(tpos, t.pos.p, sizeof(double) * 3 * m, hipMemcpyDeviceToDevice, s));
+    } else {
+        uint64_t *keys = reserve<uint64_t>(t.s_keys, size_t(m));
+        hipLaunchKernelGGL(k_tkeys, dim3(nblk(m, 256)), dim3(256), 0, s, tgt, m, t.lo[0], t.lo[1], t.lo[2],
+                           t.scale, keys, tperm);
+        STK_CHECK_LAUNCH();
+        radix_sort_pairs(t, keys, tperm, m, 63, s);
+        hipLaunchKernelGGL(k_gather3, dim3(nblk(m, 256)), dim3(256), 0, s, tgt, tperm, m, tpos);
+        STK_CHECK_LAUNCH();
+    }
     prof_mark(STK_PHASE_TARGETS, s);
 
     // interaction lists: count, scan, fill

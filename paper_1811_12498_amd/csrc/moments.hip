@@ -12,8 +12,9 @@
 namespace stk {
 namespace {
 
-constexpr int MT = 256;    // threads per block
-constexpr int STAGE = 32;  // points staged in LDS per round
+constexpr int MT = 256;    // threads per block (reduction and block kernels)
+constexpr int STAGE = 16;  // points whose powers are tabulated in LDS per round
+constexpr int AMAX = 5;    // multi-indices per lane: 64 * AMAX >= nidx(STK_P_MAX)
 
 __device__ inline int32_t node_of_chunk(const int32_t *__restrict__ off, int32_t nn, int32_t ch) {
     int32_t lo = 0, hi = nn;
@@ -27,92 +28,99 @@ __device__ inline int32_t node_of_chunk(const int32_t *__restrict__ off, int32_t
     return lo;
 }
 
-// grid (nchunks, K).  part[((chunk * K + r) * nm + a) * 12 + c]
-__global__ __launch_bounds__(MT) void k_moments(const double *__restrict__ pos, const int32_t *__restrict__ perm,
-                                                const int32_t *__restrict__ start, const int32_t *__restrict__ count,
-                                                const int32_t *__restrict__ coff, int32_t nn,
-                                                const double *__restrict__ center, const double *__restrict__ f,
-                                                const double *__restrict__ h, const double *__restrict__ nu, int64_t n,
-                                                int p, int nm, double *__restrict__ part) {
-    extern __shared__ double sm[];
-    const int P1 = p + 1;
-    double *pw = sm;                      // [STAGE][3][P1] powers of y - y_c
-    double *wt = sm + STAGE * 3 * P1;     // [STAGE][12] f_j and h_j nu_l
+// One wavefront per (node, chunk of <= CHUNK points) and right-hand side r (grid
+// (nchunks, K)).  Lane L owns the multi-indices a = L + 64 j.  For each point the wave
+// reads its 12 weights (f_j, h_j nu_l; uniform, so through the scalar cache) and the
+// powers (y - y_c)_axis^e from a small LDS table, and each lane adds
+// (y - y_c)^k * weight to its 12 accumulators per multi-index.  Powers and the monomial
+// are formed by repeated multiplication in the same order as the oracle.
+// part[((chunk * K + r) * nm + a) * 12 + c]
+template <int A>
+__global__ __launch_bounds__(64) void k_moments(const double *__restrict__ pos, const int32_t *__restrict__ start,
+                                                const int32_t *__restrict__ count, const int32_t *__restrict__ coff,
+                                                int32_t nn, const double *__restrict__ center,
+                                                const double *__restrict__ w12, int p, int nm,
+                                                double *__restrict__ part) {
+    __shared__ double pw[STAGE][3][STK_P_MAX + 1];
     const int32_t ch = blockIdx.x;
     const int r = blockIdx.y;
     const int K = gridDim.y;
+    const int lane = threadIdx.x;
     const int32_t node = node_of_chunk(coff, nn, ch);
     const int32_t first = start[node] + (ch - coff[node]) * CHUNK;
     const int32_t last = min(start[node] + count[node], first + CHUNK);
-    const double cx = center[3 * node], cy = center[3 * node + 1], cz = center[3 * node + 2];
+    const double c3[3] = {center[3 * node], center[3 * node + 1], center[3 * node + 2]};
+    const int P1 = p + 1;
 
-    // each thread owns up to two multi-indices
-    int ka[2][3];
-    const int a0 = threadIdx.x, a1 = threadIdx.x + MT;
-    if (a0 < nm) kof(a0, ka[0]);
-    if (a1 < nm) kof(a1, ka[1]);
-    double acc[2][12];
-    for (int u = 0; u < 2; ++u)
-        for (int c = 0; c < 12; ++c) acc[u][c] = 0.0;
-
-    const double *fr = f + size_t(r) * n * 3;
-    const double *hr = h + size_t(r) * n * 3;
+    int e1[A], e2[A], e3[A];
+    double acc[A][12];
+#pragma unroll
+    for (int j = 0; j < A; ++j) {
+        int k[3] = {0, 0, 0};
+        if (lane + 64 * j < nm) kof(lane + 64 * j, k);
+        e1[j] = k[0];
+        e2[j] = k[1];
+        e3[j] = k[2];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) acc[j][c] = 0.0;
+    }
     for (int32_t b = first; b < last; b += STAGE) {
         const int cnt = min(STAGE, last - b);
         __syncthreads();
-        for (int q = threadIdx.x; q < cnt * 3; q += MT) {
-            const int j = q / 3, ax = q % 3;
-            const double c = ax == 0 ? cx : (ax == 1 ? cy : cz);
-            const double d = pos[3 * int64_t(b + j) + ax] - c;
-            double *row = pw + (j * 3 + ax) * P1;
+        for (int idx = lane; idx < cnt * 3 * P1; idx += 64) {
+            const int pt = idx / (3 * P1), rem = idx % (3 * P1), ax = rem / P1, e = rem % P1;
+            const double d = pos[3 * int64_t(b + pt) + ax] - c3[ax];
             double v = 1.0;
-            row[0] = 1.0;
-            for (int e = 1; e <= p; ++e) {
-                v *= d;
-                row[e] = v;
-            }
-        }
-        for (int q = threadIdx.x; q < cnt * 12; q += MT) {
-            const int j = q / 12, c = q % 12;
-            const int64_t src = perm[b + j];
-            double w;
-            if (c < 3)
-                w = fr[3 * src + c];
-            else
-                w = hr[3 * src + (c - 3) / 3] * nu[3 * src + (c - 3) % 3];
-            wt[j * 12 + c] = w;
+            for (int i = 0; i < e; ++i) v *= d;
+            pw[pt][ax][e] = v;
         }
         __syncthreads();
-        for (int u = 0; u < 2; ++u) {
-            if ((u == 0 ? a0 : a1) >= nm) continue;
-            const int k1 = ka[u][0], k2 = ka[u][1], k3 = ka[u][2];
-            for (int j = 0; j < cnt; ++j) {
-                const double mono = pw[(j * 3) * P1 + k1] * pw[(j * 3 + 1) * P1 + k2] * pw[(j * 3 + 2) * P1 + k3];
+        for (int pt = 0; pt < cnt; ++pt) {
+            const double *__restrict__ w = w12 + (size_t(b + pt) * K + r) * 12;
+            double wv[12];
 #pragma unroll
-                for (int c = 0; c < 12; ++c) acc[u][c] += mono * wt[j * 12 + c];
+            for (int c = 0; c < 12; ++c) wv[c] = w[c];
+#pragma unroll
+            for (int j = 0; j < A; ++j) {
+                const double mono = pw[pt][0][e1[j]] * pw[pt][1][e2[j]] * pw[pt][2][e3[j]];
+#pragma unroll
+                for (int c = 0; c < 12; ++c) acc[j][c] += mono * wv[c];
             }
         }
     }
     double *out = part + (size_t(ch) * K + r) * nm * 12;
-    for (int u = 0; u < 2; ++u) {
-        const int a = u == 0 ? a0 : a1;
-        if (a >= nm) continue;
-        for (int c = 0; c < 12; ++c) out[a * 12 + c] = acc[u][c];
+#pragma unroll
+    for (int j = 0; j < A; ++j) {
+        const int a = lane + 64 * j;
+        if (a < nm)
+#pragma unroll
+            for (int c = 0; c < 12; ++c) out[a * 12 + c] = acc[j][c];
     }
 }
 
-// grid (nnodes, K): mom[(node * nm + a) * 12K + 12 r + c] = sum over the node's chunks
+// grid (nnodes, K, ceil(12 nm / MT)): mom[(node * nm + a) * 12K + 12 r + c] = sum of the
+// node's chunk partials in chunk order
 __global__ __launch_bounds__(MT) void k_moments_reduce(const double *__restrict__ part, const int32_t *__restrict__ coff,
                                                        int nm, double *__restrict__ mom) {
     const int32_t node = blockIdx.x;
     const int r = blockIdx.y, K = gridDim.y;
+    const int q = blockIdx.z * MT + threadIdx.x;
+    if (q >= nm * 12) return;
     const int32_t c0 = coff[node], c1 = coff[node + 1];
-    for (int q = threadIdx.x; q < nm * 12; q += MT) {
-        double s = 0.0;
-        for (int32_t ch = c0; ch < c1; ++ch) s += part[(size_t(ch) * K + r) * nm * 12 + q];
-        const int a = q / 12, c = q % 12;
-        mom[(size_t(node) * nm + a) * 12 * K + 12 * r + c] = s;
+    const size_t stride = size_t(K) * nm * 12;
+    const double *src = part + (size_t(c0) * K + r) * nm * 12 + q;
+    double s = 0.0;
+    int32_t ch = c0;
+    for (; ch + 4 <= c1; ch += 4, src += 4 * stride) {
+        const double v0 = src[0], v1 = src[stride], v2 = src[2 * stride], v3 = src[3 * stride];
+        s += v0;
+        s += v1;
+        s += v2;
+        s += v3;
     }
+    for (; ch < c1; ++ch, src += stride) s += src[0];
+    const int a = q / 12, c = q % 12;
+    mom[(size_t(node) * nm + a) * 12 * K + 12 * r + c] = s;
 }
 
 // grid (nnodes, K): far-field blocks for ||a|| <= p + 1 in the evaluation precision,
@@ -139,60 +147,86 @@ __global__ __launch_bounds__(MT) void k_channels(const double *__restrict__ mom,
     }
 }
 
-// near-field source records in Morton order: geo = (y, nu) FP64; wts = (f, h) per RHS
+// per-source records in Morton order: geo = (y, nu) FP64 and wts = (f, h) per RHS in the
+// evaluation precision (near field); w12 = (f_j, h_j nu_l) per RHS in FP64 (moments)
 template <typename T>
 __global__ void k_records(const double *__restrict__ pos, const int32_t *__restrict__ perm, int64_t n, int K,
                           const double *__restrict__ f, const double *__restrict__ h, const double *__restrict__ nu,
-                          double *__restrict__ geo, T *__restrict__ wts) {
+                          double *__restrict__ geo, T *__restrict__ wts, double *__restrict__ w12) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t j = perm[i];
+    double nv[3];
     for (int a = 0; a < 3; ++a) {
+        nv[a] = nu[3 * j + a];
         geo[6 * i + a] = pos[3 * i + a];
-        geo[6 * i + 3 + a] = nu[3 * j + a];
+        geo[6 * i + 3 + a] = nv[a];
     }
-    for (int r = 0; r < K; ++r)
+    for (int r = 0; r < K; ++r) {
+        double fv[3], hv[3];
         for (int a = 0; a < 3; ++a) {
-            wts[(i * K + r) * 6 + a] = T(f[(size_t(r) * n + j) * 3 + a]);
-            wts[(i * K + r) * 6 + 3 + a] = T(h[(size_t(r) * n + j) * 3 + a]);
+            fv[a] = f[(size_t(r) * n + j) * 3 + a];
+            hv[a] = h[(size_t(r) * n + j) * 3 + a];
+            wts[(i * K + r) * 6 + a] = T(fv[a]);
+            wts[(i * K + r) * 6 + 3 + a] = T(hv[a]);
         }
+        double *w = w12 + (i * K + r) * 12;
+        for (int a = 0; a < 3; ++a) w[a] = fv[a];
+        for (int jj = 0; jj < 3; ++jj)
+            for (int l = 0; l < 3; ++l) w[3 + 3 * jj + l] = hv[jj] * nv[l];
+    }
 }
 
 inline unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
 
 }  // namespace
 
+template <int A>
+static void launch_moments(Tree &t, int K, int p, int nm, const double *w12, double *part, hipStream_t s) {
+    hipLaunchKernelGGL(k_moments<A>, dim3(t.nchunks, K), dim3(64), 0, s, t.pos.as<double>(), t.nstart.as<int32_t>(),
+                       t.ncount.as<int32_t>(), t.chunk_off.as<int32_t>(), t.nnodes, t.ncenter.as<double>(), w12, p, nm,
+                       part);
+    STK_CHECK_LAUNCH();
+}
+
 void compute_moments(Tree &t, const double *f, const double *h, const double *nu, int32_t K, int32_t p,
                      stk_precision prec, hipStream_t s) {
     const int nm = nidx(p), ng = nidx(p + 1);
     const int32_t nn = t.nnodes;
     prof_mark(-1, s);
-    double *part = reserve<double>(t.s_tmp, size_t(t.nchunks) * K * nm * 12);
-    const size_t shm = sizeof(double) * STAGE * (3 * (p + 1) + 12);
-    hipLaunchKernelGGL(k_moments, dim3(t.nchunks, K), dim3(MT), shm, s, t.pos.as<double>(), t.perm.as<int32_t>(),
-                       t.nstart.as<int32_t>(), t.ncount.as<int32_t>(), t.chunk_off.as<int32_t>(), nn,
-                       t.ncenter.as<double>(), f, h, nu, t.n, p, nm, part);
-    STK_CHECK_LAUNCH();
-    double *mom = reserve<double>(t.mom, size_t(nn) * nm * 12 * K);
-    hipLaunchKernelGGL(k_moments_reduce, dim3(nn, K), dim3(MT), 0, s, part, t.chunk_off.as<int32_t>(), nm, mom);
-    STK_CHECK_LAUNCH();
     const size_t esz = prec == STK_FP64 ? sizeof(double) : sizeof(float);
     t.wblk.reserve(size_t(nn) * ng * 6 * K * esz);
     t.geo.reserve(size_t(t.n) * 6 * sizeof(double));
     t.wts.reserve(size_t(t.n) * K * 6 * esz);
-    if (prec == STK_FP64) {
+    double *w12 = reserve<double>(t.w12, size_t(t.n) * K * 12);
+    if (prec == STK_FP64)
+        hipLaunchKernelGGL(k_records<double>, dim3(nblk(t.n, 256)), dim3(256), 0, s, t.pos.as<double>(),
+                           t.perm.as<int32_t>(), t.n, K, f, h, nu, t.geo.as<double>(), t.wts.as<double>(), w12);
+    else
+        hipLaunchKernelGGL(k_records<float>, dim3(nblk(t.n, 256)), dim3(256), 0, s, t.pos.as<double>(),
+                           t.perm.as<int32_t>(), t.n, K, f, h, nu, t.geo.as<double>(), t.wts.as<float>(), w12);
+    STK_CHECK_LAUNCH();
+
+    double *part = reserve<double>(t.s_tmp, size_t(t.nchunks) * K * nm * 12);
+    const int A = (nm + 63) / 64;
+    switch (A) {
+        case 1: launch_moments<1>(t, K, p, nm, w12, part, s); break;
+        case 2: launch_moments<2>(t, K, p, nm, w12, part, s); break;
+        case 3: launch_moments<3>(t, K, p, nm, w12, part, s); break;
+        case 4: launch_moments<4>(t, K, p, nm, w12, part, s); break;
+        case 5: launch_moments<5>(t, K, p, nm, w12, part, s); break;
+        default: throw Error(STK_EINVAL, "p too large for the moment kernel");
+    }
+    double *mom = reserve<double>(t.mom, size_t(nn) * nm * 12 * K);
+    hipLaunchKernelGGL(k_moments_reduce, dim3(nn, K, (nm * 12 + MT - 1) / MT), dim3(MT), 0, s, part,
+                       t.chunk_off.as<int32_t>(), nm, mom);
+    STK_CHECK_LAUNCH();
+    if (prec == STK_FP64)
         hipLaunchKernelGGL(k_channels<double>, dim3(nn, K), dim3(MT), 0, s, mom, t.nrho.as<double>(), p, nm, ng,
                            t.wblk.as<double>());
-        STK_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_records<double>, dim3(nblk(t.n, 256)), dim3(256), 0, s, t.pos.as<double>(),
-                           t.perm.as<int32_t>(), t.n, K, f, h, nu, t.geo.as<double>(), t.wts.as<double>());
-    } else {
+    else
         hipLaunchKernelGGL(k_channels<float>, dim3(nn, K), dim3(MT), 0, s, mom, t.nrho.as<double>(), p, nm, ng,
                            t.wblk.as<float>());
-        STK_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_records<float>, dim3(nblk(t.n, 256)), dim3(256), 0, s, t.pos.as<double>(),
-                           t.perm.as<int32_t>(), t.n, K, f, h, nu, t.geo.as<double>(), t.wts.as<float>());
-    }
     STK_CHECK_LAUNCH();
     prof_mark(STK_PHASE_MOMENTS, s);
     t.p = p;

@@ -1,7 +1,8 @@
 // Stable LSD radix sort of (uint64 key, int32 value) pairs and a single-block scan.
 //
-// Each pass handles 8 key bits: (1) per-tile digit histograms, (2) one exclusive
-// scan over the digit-major histogram table, (3) a stable scatter in which every
+// Each pass handles 8 key bits: (1) per-tile digit histograms, (2) an exclusive scan of
+// each digit's row of tile counts plus a scan of the digit totals, (3) a stable scatter
+// in which every
 // tile ranks its keys round by round (256 keys per round, wave64 ballots find the
 // lanes sharing a digit, wave counts are combined in LDS in wave order).  Ties keep
 // their input order, so sorting (key, index) pairs yields the order of a
@@ -35,13 +36,14 @@ __global__ __launch_bounds__(ST) void k_hist(const uint64_t *__restrict__ keys, 
 
 __global__ __launch_bounds__(ST) void k_scatter(const uint64_t *__restrict__ kin, const int32_t *__restrict__ vin,
                                                 uint64_t *__restrict__ kout, int32_t *__restrict__ vout, int64_t n,
-                                                int shift, const int32_t *__restrict__ off, int32_t ntiles) {
+                                                int shift, const int32_t *__restrict__ off, int32_t ntiles,
+                                                const int32_t *__restrict__ dbase) {
     __shared__ int32_t base[RADIX];
     __shared__ int32_t wcnt[NWAVE][RADIX];
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
-    base[tid] = off[int64_t(tid) * ntiles + blockIdx.x];
+    base[tid] = off[int64_t(tid) * ntiles + blockIdx.x] + dbase[tid];
     for (int w = 0; w < NWAVE; ++w) wcnt[w][tid] = 0;
     __syncthreads();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -90,33 +92,83 @@ __global__ __launch_bounds__(ST) void k_scatter(const uint64_t *__restrict__ kin
     }
 }
 
+// Exclusive scan of in[0..n) into out[0..n) by one block of NT threads, tiles of 4 NT
+// elements (each thread 4 consecutive), carrying the running total; returns the total.
+template <int NT>
+__device__ int32_t block_scan_excl(const int32_t *in, int32_t *out, int64_t n) {  // in may equal out
+    constexpr int NW = NT / 64;
+    __shared__ int32_t wsum[NW];
+    __shared__ int32_t tile_total;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int32_t carry = 0;
+    for (int64_t base = 0; base < n; base += int64_t(NT) * 4) {
+        const int64_t i0 = base + int64_t(tid) * 4;
+        int32_t v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = (i0 + j < n) ? in[i0 + j] : 0;
+        const int32_t tsum = v[0] + v[1] + v[2] + v[3];
+        int32_t x = tsum;  // inclusive scan over the wave
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[wave] = x;
+        __syncthreads();
+        if (tid == 0) {
+            int32_t run = 0;
+            for (int w = 0; w < NW; ++w) {
+                const int32_t t = wsum[w];
+                wsum[w] = run;
+                run += t;
+            }
+            tile_total = run;
+        }
+        __syncthreads();
+        int32_t e = carry + wsum[wave] + (x - tsum);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (i0 + j < n) out[i0 + j] = e;
+            e += v[j];
+        }
+        carry += tile_total;
+        __syncthreads();
+    }
+    return carry;
+}
+
 constexpr int SCAN_T = 1024;
 
 __global__ __launch_bounds__(SCAN_T) void k_scan(const int32_t *__restrict__ in, int32_t *__restrict__ out,
                                                  int64_t n) {
-    __shared__ int32_t part[SCAN_T];
-    const int tid = threadIdx.x;
-    const int64_t per = (n + SCAN_T - 1) / SCAN_T;
-    const int64_t b = int64_t(tid) * per;
-    const int64_t e = b + per < n ? b + per : n;
-    int32_t s = 0;
-    for (int64_t i = b; i < e; ++i) s += in[i];
-    part[tid] = s;
+    const int32_t tot = block_scan_excl<SCAN_T>(in, out, n);
+    if (threadIdx.x == 0) out[n] = tot;
+}
+
+// radix histogram table hist[digit * ntiles + tile]: block d scans row d in place and
+// writes the row total
+__global__ __launch_bounds__(256) void k_scan_rows(int32_t *__restrict__ hist, int32_t ntiles,
+                                                   int32_t *__restrict__ tot) {
+    int32_t *row = hist + int64_t(blockIdx.x) * ntiles;
+    const int32_t t = block_scan_excl<256>(row, row, ntiles);
+    if (threadIdx.x == 0) tot[blockIdx.x] = t;
+}
+
+// exclusive scan of the RADIX row totals, added to every row
+__global__ __launch_bounds__(RADIX) void k_scan_digits(int32_t *__restrict__ tot) {
+    __shared__ int32_t s[RADIX];
+    s[threadIdx.x] = tot[threadIdx.x];
     __syncthreads();
-    // inclusive Hillis-Steele scan of the per-thread sums
-    for (int o = 1; o < SCAN_T; o <<= 1) {
-        const int32_t v = tid >= o ? part[tid - o] : 0;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t run = 0;
+        for (int d = 0; d < RADIX; ++d) {
+            const int32_t t = s[d];
+            s[d] = run;
+            run += t;
+        }
     }
-    int32_t run = tid ? part[tid - 1] : 0;
-    for (int64_t i = b; i < e; ++i) {
-        const int32_t v = in[i];
-        out[i] = run;
-        run += v;
-    }
-    if (tid == SCAN_T - 1) out[n] = part[SCAN_T - 1];
+    __syncthreads();
+    tot[threadIdx.x] = s[threadIdx.x];
 }
 
 }  // namespace
@@ -132,8 +184,8 @@ void radix_sort_pairs(Tree &t, uint64_t *keys, int32_t *vals, int64_t n, int bit
     uint64_t *k2 = reserve<uint64_t>(t.s_keys2, size_t(n));
     int32_t *v2 = reserve<int32_t>(t.s_vals2, size_t(n));
     const int64_t hn = int64_t(RADIX) * ntiles;
-    int32_t *hist = reserve<int32_t>(t.s_hist, size_t(2 * hn + 2));
-    int32_t *off = hist + hn + 1;
+    int32_t *hist = reserve<int32_t>(t.s_hist, size_t(hn + RADIX));
+    int32_t *dbase = hist + hn;
     uint64_t *ka = keys, *kb = k2;
     int32_t *va = vals, *vb = v2;
     const int passes = (bits + RB - 1) / RB;
@@ -141,8 +193,11 @@ void radix_sort_pairs(Tree &t, uint64_t *keys, int32_t *vals, int64_t n, int bit
         const int shift = ps * RB;
         hipLaunchKernelGGL(k_hist, dim3(ntiles), dim3(ST), 0, s, ka, n, shift, hist, ntiles);
         STK_CHECK_LAUNCH();
-        scan_exclusive_i32(hist, off, hn, s);
-        hipLaunchKernelGGL(k_scatter, dim3(ntiles), dim3(ST), 0, s, ka, va, kb, vb, n, shift, off, ntiles);
+        hipLaunchKernelGGL(k_scan_rows, dim3(RADIX), dim3(256), 0, s, hist, ntiles, dbase);
+        STK_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_scan_digits, dim3(1), dim3(RADIX), 0, s, dbase);
+        STK_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_scatter, dim3(ntiles), dim3(ST), 0, s, ka, va, kb, vb, n, shift, hist, ntiles, dbase);
         STK_CHECK_LAUNCH();
         std::swap(ka, kb);
         std::swap(va, vb);

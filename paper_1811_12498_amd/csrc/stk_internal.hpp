@@ -99,6 +99,7 @@ struct Tree {
     DBuf wblk;    // T (nn, nb, 12*K): scaled far-field channel blocks
     DBuf geo;     // double (n, 6): sorted (y, nu) per source
     DBuf wts;     // T (n, K, 6): sorted (f, h) per source and right-hand side
+    DBuf w12;     // double (n, K, 12): sorted (f_j, h_j nu_l) for the moments
 
     // reusable scratch for evaluation
     DBuf s_keys, s_vals, s_keys2, s_vals2, s_hist, s_tmp;
@@ -138,7 +139,10 @@ void scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t 
 void build_tree(Tree &t, const double *src, int64_t n, int32_t n0, hipStream_t s);
 void compute_moments(Tree &t, const double *f, const double *h, const double *nu, int32_t k, int32_t p,
                      stk_precision prec, hipStream_t s);
-void evaluate(Tree &t, Plan &plan, const double *tgt, int64_t m, double theta, double *u_out, hipStream_t s);
+// same_as_sources: the targets are exactly the tree's sources (same array), so their
+// Morton order is the tree's and they are not sorted again
+void evaluate(Tree &t, Plan &plan, const double *tgt, int64_t m, double theta, double *u_out, bool same_as_sources,
+              hipStream_t s);
 void direct_sum(const double *tgt, int64_t m, const double *src, int64_t n, const double *f, const double *h,
                 const double *nu, int32_t k, double *u_out, hipStream_t s);
 

@@ -47,12 +47,21 @@ __global__ __launch_bounds__(BT) void k_bounds(const double *__restrict__ src, i
     if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-__global__ void k_bounds_final(const double *__restrict__ part, int nb, double *__restrict__ out) {
-    const int a = threadIdx.x;  // 6 threads
-    if (a >= 6) return;
-    double v = part[a];
-    for (int b = 1; b < nb; ++b) v = a < 3 ? fmin(v, part[b * 6 + a]) : fmax(v, part[b * 6 + a]);
-    out[a] = v;
+__global__ __launch_bounds__(BT) void k_bounds_final(const double *__restrict__ part, int nb, double *__restrict__ out) {
+    __shared__ double red[6][BT];
+    double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int b = threadIdx.x; b < nb; b += BT)
+        for (int a = 0; a < 6; ++a) v[a] = a < 3 ? fmin(v[a], part[b * 6 + a]) : fmax(v[a], part[b * 6 + a]);
+    for (int a = 0; a < 6; ++a) red[a][threadIdx.x] = v[a];
+    __syncthreads();
+    for (int o = BT / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o)
+            for (int a = 0; a < 6; ++a)
+                red[a][threadIdx.x] = a < 3 ? fmin(red[a][threadIdx.x], red[a][threadIdx.x + o])
+                                            : fmax(red[a][threadIdx.x], red[a][threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) out[threadIdx.x] = red[threadIdx.x][0];
 }
 
 // ---- Morton keys --------------------------------------------------------------------
@@ -300,7 +309,7 @@ void build_tree(Tree &t, const double *src, int64_t n, int32_t n0, hipStream_t s
     double *part = reserve<double>(t.s_tmp, size_t(nbb) * 6 + 6);
     hipLaunchKernelGGL(k_bounds, dim3(nbb), dim3(BT), 0, s, src, n, part);
     STK_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_bounds_final, dim3(1), dim3(64), 0, s, part, nbb, part + size_t(nbb) * 6);
+    hipLaunchKernelGGL(k_bounds_final, dim3(1), dim3(BT), 0, s, part, nbb, part + size_t(nbb) * 6);
     STK_CHECK_LAUNCH();
     double b6[6];
     STK_HIP(hipMemcpyAsync(b6, part + size_t(nbb) * 6, sizeof(b6), hipMemcpyDeviceToHost, s));
@@ -326,10 +335,12 @@ void build_tree(Tree &t, const double *src, int64_t n, int32_t n0, hipStream_t s
     STK_CHECK_LAUNCH();
 
     // subdivision, one level per step
-    size_t cap = 1024;
+    size_t cap = std::max<size_t>(1024, t.nlevel.bytes / sizeof(int32_t));
     for (DBuf *b : {&t.nlevel, &t.nparent, &t.nchild0, &t.nnchild, &t.nstart, &t.ncount}) {
-        b->release();
-        b->reserve(cap * sizeof(int32_t));
+        if (b->bytes < cap * sizeof(int32_t)) {
+            b->release();
+            b->reserve(cap * sizeof(int32_t));
+        }
     }
     {
         const int32_t root[6] = {0, -1, -1, 0, 0, int32_t(n)};
