@@ -20,7 +20,7 @@ struct FarArgs {
     const uint64_t *mask;
     const double *center;    // (nn,3)
     const double *rho;       // (nn)
-    const void *wblk;        // (nn, 6 nG) in T: G block then E block
+    const void *wblk;        // (nn, 6 nG) in T: each cluster's G/E stream
     const double *unear;     // (m,3) sorted near-field velocity
     const int32_t *tperm;    // sorted -> caller index
     double *u_out;           // (m,3) caller order
@@ -60,9 +60,8 @@ __global__ __launch_bounds__(64) void k_far(FarArgs a) {
             const double rinv = 1.0 / sqrt(R2);
             const T dh[3] = {T(d0 * rinv), T(d1 * rinv), T(d2 * rinv)};
             const T tt = T(a.rho[c] * rinv);
-            const T *blk = wb + size_t(c) * 6 * NG;
             T accG[3], accF[3];
-            FarEval<P, T>::run(dh, tt, blk, blk + 3 * NG, accG, accF);
+            FarEval<P, T>::run(dh, tt, wb + size_t(c) * 6 * NG, accG, accF);
             T u[3];
             far_velocity(accG, accF, T(rinv), u);
             acc[0].add(u[0]);

@@ -123,9 +123,8 @@ __global__ __launch_bounds__(MT) void k_moments_reduce(const double *__restrict_
     mom[(size_t(node) * nm + a) * 12 * K + 12 * r + c] = s;
 }
 
-// grid (nnodes, K): far-field blocks for ||a|| <= p + 1 in the evaluation precision,
-// wblk[(node * K + r) * 6 nG + 3a + i] = G_i^a / rho^||a||  and
-// wblk[(node * K + r) * 6 nG + 3 nG + 3a + l] = E_l^a / rho^(||a||+1)
+// grid (nnodes, K): each cluster's far-field stream (stk_math.hpp) in the evaluation
+// precision, wblk[(node * K + r) * 6 nG + pos], nG = nidx(p + 1)
 template <typename T>
 __global__ __launch_bounds__(MT) void k_channels(const double *__restrict__ mom, const double *__restrict__ rho, int p,
                                                  int nm, int ng, T *__restrict__ wblk) {
@@ -140,9 +139,11 @@ __global__ __launch_bounds__(MT) void k_channels(const double *__restrict__ mom,
         phi_ge(mom + size_t(node) * nm * 12 * K + 12 * r, 12 * K, p, q, ge);
         double s = 1.0;
         for (int e = 0; e < q[0] + q[1] + q[2]; ++e) s *= inv;
+        int pg, pe;
+        stream_pos(p, q, pg, pe);
         for (int c = 0; c < 3; ++c) {
-            out[3 * a + c] = T(ge[c] * s);
-            out[3 * ng + 3 * a + c] = T(ge[3 + c] * s * inv);
+            out[pg + c] = T(ge[c] * s);
+            out[pe + c] = T(ge[3 + c] * s * inv);
         }
     }
 }

@@ -145,82 +145,140 @@ STK_HD void phi_ge(const double *mom, int ld, int p, const int a3[3], double out
 }
 
 // ---------------------------------------------------------------------------------
-// Far field of one (target, cluster) pair: the scaled recurrence fused with the
-// contraction.  Straight-line code generated at compile time for each order P, so
-// every b^q lives in a register and only three orders are live at once.
-//   G points at the cluster's Ghat block, G[3a + i] = G_i^a / rho^||a||,
-//   E points at its Ehat block,          E[3a + l] = E_l^a / rho^(||a||+1),
-// for a < nidx(P + 1).  With bt the scaled coefficients,
-//   u_i = (1/R) sum_q bt^q Ghat_i^q + sum_k (k_i + 1) bt^{k+e_i} (dh . Ehat^k).
+// Far field of one (target, cluster) pair: the scaled recurrence fused with the G/E
+// contraction, as straight-line code generated at compile time for each order P (every
+// b^q lives in a register).
+//
+// G = 1/|x - y| is harmonic in y, so for every multi-index m
+//     sum_i (m_i + 1)(m_i + 2) b^{m + 2e_i} = 0.
+// Taking m = k - 2e_3 gives, for k_3 >= 2,
+//     k_3 (k_3 - 1) b^k = -(k_1 + 1)(k_1 + 2) b^{k + 2e_1 - 2e_3} - (k_2 + 1)(k_2 + 2) b^{k + 2e_2 - 2e_3},
+// two coefficients of the same order (the relation is homogeneous in the order, so it
+// holds for the scaled bt too).  recurrence_1 is therefore run only for the layers
+// k_3 = 0 and k_3 = 1, which read only those two layers of the two orders below; the
+// other layers are filled from the harmonic relation.  Within an order the layers are
+// produced in increasing k_3, and the E contraction of layer j of the previous order
+// runs as soon as layers j and j + 1 exist, so few coefficients are live at once.
+//
+// Cluster block ("stream"): G^0, then for n = 1 .. P + 2 and layer j = 0 .. n the chunk
+//   [ G^q for q of order n, k_3 = j   (if n <= P + 1) ]
+//   [ E^k for k of order n - 1, k_3 = j - 1   (if j >= 1) ]
+// with entries in decreasing k_1, three values each: the order in which the kernel
+// consumes them, so each chunk is one contiguous scalar-cache read.  Values are stored
+// as G^q / rho^||q|| and E^k / rho^(||k||+1).  Total 6 nidx(P + 1) values.
 // ---------------------------------------------------------------------------------
+STK_HD constexpr int stream_gpart(int p, int n, int j) { return n <= p + 1 ? 3 * (n - j + 1) : 0; }
+STK_HD constexpr int stream_epart(int n, int j) { return j >= 1 ? 3 * (n - j + 1) : 0; }
+STK_HD constexpr int stream_off(int p, int n, int j) {
+    int o = 3;
+    for (int m = 1; m < n; ++m)
+        for (int jj = 0; jj <= m; ++jj) o += stream_gpart(p, m, jj) + stream_epart(m, jj);
+    for (int jj = 0; jj < j; ++jj) o += stream_gpart(p, n, jj) + stream_epart(n, jj);
+    return o;
+}
+// stream positions of G^a and E^a for multi-index a (||a|| <= p + 1)
+STK_HD void stream_pos(int p, const int a[3], int &g, int &e) {
+    const int n = a[0] + a[1] + a[2], j = a[2], i = (n - j) - a[0];
+    g = n == 0 ? 0 : stream_off(p, n, j) + 3 * i;
+    e = stream_off(p, n + 1, j + 1) + stream_gpart(p, n + 1, j + 1) + 3 * i;
+}
+
 template <int P, typename T> struct FarEval {
     static constexpr int PB = P + 2;
     static constexpr int NB = nidx(PB);
 
-    // b^q for ||q|| = N, plus the G contraction of that order
-    template <int N, int K1, int K2>
-    STK_HD static void step(T (&b)[NB], const T dh[3], T c1, T c2, const T *__restrict__ G, T accG[3]) {
-        constexpr int K3 = N - K1 - K2;
-        constexpr int Q = gidx(K1, K2, K3);
-        T s1 = T(0), s2 = T(0);
-        if constexpr (K1 > 0) s1 += dh[0] * b[gidx(K1 - 1, K2, K3)];
-        if constexpr (K2 > 0) s1 += dh[1] * b[gidx(K1, K2 - 1, K3)];
-        if constexpr (K3 > 0) s1 += dh[2] * b[gidx(K1, K2, K3 - 1)];
-        if constexpr (K1 > 1) s2 += b[gidx(K1 - 2, K2, K3)];
-        if constexpr (K2 > 1) s2 += b[gidx(K1, K2 - 2, K3)];
-        if constexpr (K3 > 1) s2 += b[gidx(K1, K2, K3 - 2)];
-        if constexpr (N > 1)
-            b[Q] = c1 * s1 - c2 * s2;
-        else
-            b[Q] = c1 * s1;
+    template <int N, int I> STK_HD static void gterm(T bq, const T *__restrict__ G, T accG[3]) {
         if constexpr (N <= P + 1) {
-            const T bq = b[Q];
-            accG[0] += bq * G[3 * Q];
-            accG[1] += bq * G[3 * Q + 1];
-            accG[2] += bq * G[3 * Q + 2];
+            accG[0] += bq * G[3 * I];
+            accG[1] += bq * G[3 * I + 1];
+            accG[2] += bq * G[3 * I + 2];
         }
-        if constexpr (K2 > 0)
-            step<N, K1, K2 - 1>(b, dh, c1, c2, G, accG);
-        else if constexpr (K1 > 0)
-            step<N, K1 - 1, N - K1 + 1>(b, dh, c1, c2, G, accG);
     }
 
-    // the E contraction for every k of order N - 1 (needs b of order N)
-    template <int N, int K1, int K2>
-    STK_HD static void estep(const T (&b)[NB], const T dh[3], const T *__restrict__ E, T accF[3]) {
+    // all coefficients of order N in layer K3 (k1 = N - K3 .. 0), with their G terms;
+    // G points at the chunk (N, K3)
+    template <int N, int K3, int K1>
+    STK_HD static void layer(T (&b)[NB], const T dh[3], T c1, T c2, const T *__restrict__ G, T accG[3]) {
+        constexpr int K2 = N - K3 - K1;
+        constexpr int Q = gidx(K1, K2, K3);
+        if constexpr (K3 <= 1) {  // recurrence_1, scaled
+            T s1 = T(0), s2 = T(0);
+            if constexpr (K1 > 0) s1 += dh[0] * b[gidx(K1 - 1, K2, K3)];
+            if constexpr (K2 > 0) s1 += dh[1] * b[gidx(K1, K2 - 1, K3)];
+            if constexpr (K3 > 0) s1 += dh[2] * b[gidx(K1, K2, K3 - 1)];
+            if constexpr (K1 > 1) s2 += b[gidx(K1 - 2, K2, K3)];
+            if constexpr (K2 > 1) s2 += b[gidx(K1, K2 - 2, K3)];
+            if constexpr (N > 1)
+                b[Q] = c1 * s1 - c2 * s2;
+            else
+                b[Q] = c1 * s1;
+        } else {  // harmonic fill
+            constexpr double den = double(K3 * (K3 - 1));
+            constexpr double ca = -double((K1 + 1) * (K1 + 2)) / den;
+            constexpr double cb = -double((K2 + 1) * (K2 + 2)) / den;
+            b[Q] = T(ca) * b[gidx(K1 + 2, K2, K3 - 2)] + T(cb) * b[gidx(K1, K2 + 2, K3 - 2)];
+        }
+        gterm<N, (N - K3) - K1>(b[Q], G, accG);
+        if constexpr (K1 > 0) layer<N, K3, K1 - 1>(b, dh, c1, c2, G, accG);
+    }
+
+    // E contraction for the k of order N - 1 in layer K3 (needs layers K3, K3 + 1 of
+    // order N); E points at the E part of chunk (N, K3 + 1)
+    template <int N, int K3, int K1>
+    STK_HD static void elayer(const T (&b)[NB], const T dh[3], const T *__restrict__ E, T accF[3]) {
         constexpr int M = N - 1;
-        constexpr int K3 = M - K1 - K2;
-        constexpr int A = gidx(K1, K2, K3);
-        const T sig = dh[0] * E[3 * A] + dh[1] * E[3 * A + 1] + dh[2] * E[3 * A + 2];
+        constexpr int K2 = M - K3 - K1;
+        constexpr int I = (M - K3) - K1;
+        const T sig = dh[0] * E[3 * I] + dh[1] * E[3 * I + 1] + dh[2] * E[3 * I + 2];
         accF[0] += b[gidx(K1 + 1, K2, K3)] * (T(K1 + 1) * sig);
         accF[1] += b[gidx(K1, K2 + 1, K3)] * (T(K2 + 1) * sig);
         accF[2] += b[gidx(K1, K2, K3 + 1)] * (T(K3 + 1) * sig);
-        if constexpr (K2 > 0)
-            estep<N, K1, K2 - 1>(b, dh, E, accF);
-        else if constexpr (K1 > 0)
-            estep<N, K1 - 1, M - K1 + 1>(b, dh, E, accF);
+        if constexpr (K1 > 0) elayer<N, K3, K1 - 1>(b, dh, E, accF);
+    }
+
+    // returns 0 through an asm the optimiser cannot see into.  Adding it to the block
+    // pointer pins each chunk's scalar loads after the previous chunk's accumulations,
+    // instead of letting every load of the interaction be hoisted to the top (they do
+    // not fit in SGPRs); the asm touches no memory, so the loads stay scalar.
+    STK_HD static int fence(T dep) {
+        int z = 0;
+#if defined(__HIP_DEVICE_COMPILE__)
+        asm("" : "+s"(z) : "v"(dep));
+        z = __builtin_amdgcn_readfirstlane(z);
+#else
+        (void)dep;
+#endif
+        return z;
+    }
+
+    template <int N, int J>
+    STK_HD static void layers_from(T (&b)[NB], const T dh[3], T c1, T c2, const T *__restrict__ W, T accG[3],
+                                   T accF[3]) {
+        if constexpr (J <= N) {
+            const T *__restrict__ chunk = W + stream_off(P, N, J) + fence(accG[0] + accF[0]);
+            layer<N, J, N - J>(b, dh, c1, c2, chunk, accG);
+            if constexpr (J >= 1) elayer<N, J - 1, N - J>(b, dh, chunk + stream_gpart(P, N, J), accF);
+            layers_from<N, J + 1>(b, dh, c1, c2, W, accG, accF);
+        }
     }
 
     template <int N>
-    STK_HD static void order(T (&b)[NB], const T dh[3], T t, const T *__restrict__ G, const T *__restrict__ E,
-                             T accG[3], T accF[3]) {
+    STK_HD static void order(T (&b)[NB], const T dh[3], T t, const T *__restrict__ W, T accG[3], T accF[3]) {
         const T c1 = T(2 * N - 1) / T(N) * t;
         const T c2 = T(N - 1) / T(N) * (t * t);
-        step<N, N, 0>(b, dh, c1, c2, G, accG);
-        estep<N, N - 1, 0>(b, dh, E, accF);
-        if constexpr (N < PB) order<N + 1>(b, dh, t, G, E, accG, accF);
+        layers_from<N, 0>(b, dh, c1, c2, W, accG, accF);
+        if constexpr (N < PB) order<N + 1>(b, dh, t, W, accG, accF);
     }
 
-    // u_i = accG_i / R + accF_i
-    STK_HD static void run(const T dh[3], T t, const T *__restrict__ G, const T *__restrict__ E, T accG[3],
-                           T accF[3]) {
+    // W: the cluster's stream.  u_i = accG_i / R + accF_i
+    STK_HD static void run(const T dh[3], T t, const T *__restrict__ W, T accG[3], T accF[3]) {
         T b[NB];
         b[0] = T(1);
-        accG[0] = G[0];
-        accG[1] = G[1];
-        accG[2] = G[2];
+        accG[0] = W[0];
+        accG[1] = W[1];
+        accG[2] = W[2];
         accF[0] = accF[1] = accF[2] = T(0);
-        order<1>(b, dh, t, G, E, accG, accF);
+        order<1>(b, dh, t, W, accG, accF);
     }
 };
 

@@ -5,16 +5,51 @@
 #include <cmath>
 #include <vector>
 
-template <int P> static void run_p(const double *d, double rho, const double *W, double u[3]) {
+// variant: 0 = FP64, 1 = FP32
+template <int P, typename T>
+static void run_pt(const double *d, double rho, const double *W, double u[3]) {
     const double R = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    const double dh[3] = {d[0] / R, d[1] / R, d[2] / R};
+    const T dh[3] = {T(d[0] / R), T(d[1] / R), T(d[2] / R)};
     const int ng = stk::nidx(P + 1);
-    double accG[3], accF[3];
-    stk::FarEval<P, double>::run(dh, rho / R, W, W + 3 * ng, accG, accF);
-    stk::far_velocity(accG, accF, 1.0 / R, u);
+    std::vector<T> Wt(6 * ng);
+    for (int i = 0; i < 6 * ng; ++i) Wt[i] = T(W[i]);
+    T accG[3], accF[3], ut[3];
+    stk::FarEval<P, T>::run(dh, T(rho / R), Wt.data(), accG, accF);
+    stk::far_velocity(accG, accF, T(1.0 / R), ut);
+    for (int i = 0; i < 3; ++i) u[i] = double(ut[i]);
+}
+
+static int g_variant = 0;
+
+template <int P> static void run_p(const double *d, double rho, const double *W, double u[3]) {
+    switch (g_variant) {
+        case 0: run_pt<P, double>(d, rho, W, u); break;
+        default: run_pt<P, float>(d, rho, W, u); break;
+    }
 }
 
 extern "C" {
+void hc_set_variant(int v) { g_variant = v; }
+
+// 1 if the stream positions of G^a and E^a (||a|| <= p + 1) cover [0, 6 nidx(p + 1))
+// exactly once each
+int hc_stream_ok(int p) {
+    const int ng = stk::nidx(p + 1);
+    std::vector<int> seen(6 * ng, 0);
+    for (int a = 0; a < ng; ++a) {
+        int q[3], pg, pe;
+        stk::kof(a, q);
+        stk::stream_pos(p, q, pg, pe);
+        for (int c = 0; c < 3; ++c) {
+            if (pg + c < 0 || pg + c >= 6 * ng || pe + c < 0 || pe + c >= 6 * ng) return 0;
+            seen[pg + c]++;
+            seen[pe + c]++;
+        }
+    }
+    for (int v : seen)
+        if (v != 1) return 0;
+    return stk::stream_off(p, p + 3, 0) == 6 * ng;
+}
 int hc_gidx(int k1, int k2, int k3) { return stk::gidx(k1, k2, k3); }
 void hc_kof(int a, int *k) { stk::kof(a, k); }
 double hc_rho(double r) { return stk::rho_of(r); }
@@ -30,9 +65,11 @@ void hc_far(const double *mom, int p, const double *d, double r, double *u) {
         double ge[6];
         stk::phi_ge(mom, 12, p, q, ge);
         const double s = std::pow(rho, -(q[0] + q[1] + q[2]));
+        int pg, pe;
+        stk::stream_pos(p, q, pg, pe);
         for (int c = 0; c < 3; ++c) {
-            W[3 * a + c] = ge[c] * s;
-            W[3 * ng + 3 * a + c] = ge[3 + c] * s / rho;
+            W[pg + c] = ge[c] * s;
+            W[pe + c] = ge[3 + c] * s / rho;
         }
     }
     switch (p) {
