@@ -128,7 +128,7 @@ struct Plan {
 // launch helpers implemented in the .hip files
 // ---------------------------------------------------------------------------------
 constexpr int GROUP = 64;  // targets per wavefront group
-constexpr int CHUNK = 2048;  // particles per reduction work item
+constexpr int CHUNK = 512;   // particles per reduction work item
 
 // radix sort of (uint64 key, int32 value) pairs; sorts keys[0..n) in place using
 // scratch buffers owned by `t`.  Stable.  `bits` = number of low key bits to sort.
