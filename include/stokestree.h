@@ -118,6 +118,22 @@ stk_status stk_evaluate(const double *targets, int64_t m, const double *sources,
                         const double *h, const double *nu, int32_t k_rhs, int32_t p, double theta, int32_t n0,
                         stk_precision prec, double *u_out, stk_plan **keep_plan, void *stream);
 
+/* Adjoint of the treecode operator of `plan` (derived from eq. S_final, eq. T_final,
+ * recurrence_1, the moments of Sec. 2 and the contracted pair of Sec. 4.1): for
+ * L = sum_m w^m . u^m, the gradients with respect to the weights f and h, the source
+ * positions and the target positions, with the plan's interaction lists, cluster
+ * membership, centres, radii and scales held fixed (the discrete operator the forward
+ * call applied).  The plan must come from a one-right-hand-side evaluation.
+ *   w             device (m,3) in the caller's target order.
+ *   grad_f, grad_h, grad_sources   device (n,3) in the caller's source order, or NULL.
+ *   grad_targets  device (m,3) in the caller's target order, or NULL.
+ * Outputs are overwritten.  Source-side sums over clusters use FP64 atomic additions,
+ * so the last bits can differ between runs; everything else is deterministic.
+ * Synchronises `stream` (to size the transposed lists).  Arithmetic follows the
+ * plan's precision. */
+stk_status stk_evaluate_adjoint(stk_plan *plan, const double *w, double *grad_f, double *grad_h,
+                                double *grad_targets, double *grad_sources, void *stream);
+
 /* Exact O(m n) direct sum of eq. StoStre in FP64 (contracted form of Sec. 4.1),
  * the reference the treecode is measured against.  Same array conventions. */
 stk_status stk_direct(const double *targets, int64_t m, const double *sources, int64_t n, const double *f,

@@ -23,7 +23,8 @@ _STATUS_NAMES = {STK_EINVAL: "STK_EINVAL", STK_ENOMEM: "STK_ENOMEM", STK_EDEVICE
                  STK_ESTATE: "STK_ESTATE"}
 
 # every symbol include/stokestree.h declares
-EXPORTS = ["stk_build_tree", "stk_compute_moments", "stk_evaluate_tree", "stk_evaluate", "stk_direct",
+EXPORTS = ["stk_build_tree", "stk_compute_moments", "stk_evaluate_tree", "stk_evaluate", "stk_evaluate_adjoint",
+           "stk_direct",
            "stk_tree_info", "stk_tree_export", "stk_tree_export_moments", "stk_plan_counts", "stk_plan_info",
            "stk_profile_enable", "stk_profile_read", "stk_tree_destroy", "stk_plan_destroy", "stk_last_error"]
 
@@ -52,6 +53,7 @@ _lib.stk_evaluate_tree.argtypes = [_vp, _vp, _i64, _d, _vp, ctypes.POINTER(_vp),
 _lib.stk_evaluate.argtypes = [_vp, _i64, _vp, _i64, _vp, _vp, _vp, _i32, _i32, _d, _i32, ctypes.c_int, _vp,
                               ctypes.POINTER(_vp), _vp]
 _lib.stk_direct.argtypes = [_vp, _i64, _vp, _i64, _vp, _vp, _vp, _i32, _vp, _vp]
+_lib.stk_evaluate_adjoint.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.stk_tree_info.argtypes = [_vp, _i64p, _i32p, _dp]
 _lib.stk_tree_export.argtypes = [_vp] + [_vp] * 11
 _lib.stk_tree_export_moments.argtypes = [_vp, _i32, _vp, _vp]
@@ -167,6 +169,23 @@ def evaluate(targets, sources, f, h, nu, p: int, theta: float, n0: int, precisio
                              float(theta), int(n0), _prec(precision), _ptr(u),
                              ctypes.byref(ph) if keep_plan else None, _stream()))
     return (u, Plan(ph.value, m, None)) if keep_plan else u
+
+
+def evaluate_adjoint(plan: Plan, w: torch.Tensor, n_sources: int, want=("f", "h", "targets", "sources")):
+    """Gradients of sum(w * u) for the plan's frozen operator: dict of tensors for the
+    requested keys among "f", "h", "targets", "sources"."""
+    _dev(w, "w")
+    if w.shape[0] != plan.m:
+        raise ValueError("w must have one row per target")
+    dev = w.device
+    out = {}
+    for k in want:
+        rows = plan.m if k == "targets" else n_sources
+        out[k] = torch.empty((rows, 3), dtype=torch.float64, device=dev)
+    ptr = lambda k: _ptr(out[k]) if k in out else None
+    _check(_lib.stk_evaluate_adjoint(plan.handle, _ptr(w), ptr("f"), ptr("h"), ptr("targets"), ptr("sources"),
+                                     _stream()))
+    return out
 
 
 def direct(targets, sources, f, h, nu) -> torch.Tensor:

@@ -1,0 +1,724 @@
+// Adjoint of the frozen-plan treecode operator: gradients of L = sum_m w^m . u^m with
+// respect to f, h, source positions and target positions, with the interaction lists,
+// cluster membership, centres, radii and scales of the forward evaluation held fixed.
+//
+//   near field   target side: d/dx of every near pair (analytic derivative of the
+//                contracted pair of Sec. 4.1); source side: the same pairs gathered per
+//                source through leaf-major (transposed) near lists.
+//   far field    target side: k_far_tgrad (adjoint_far.hpp); source side: per-cluster
+//                stream adjoints Lambda_C (k_far_lambda) -> moment adjoints through the
+//                transpose of the moment-to-stream map -> per source
+//                  dL/df_j  = sum_C sum_k (y - y_c)^k dL/dM_j^k(C)
+//                  dL/dh_j  = sum_C sum_k (y - y_c)^k sum_l nu_l dL/dMt_jl^k(C)
+//                  dL/dy_s  = sum_C sum_k k_s (y - y_c)^{k - e_s} [f . dL/dM^k + (h nu) : dL/dMt^k]
+//                (each source in one node per level: per-level partial sums, then a
+//                fixed-order total).
+#include <map>
+#include <mutex>
+
+#include "adjoint_far.hpp"
+#include "stk_internal.hpp"
+#include "stk_math.hpp"
+
+namespace stk {
+
+template <int P, typename T> void launch_far_lambda(const LambdaArgs &, hipStream_t);
+template <int P, typename T> void launch_far_tgrad(const TgradArgs &, hipStream_t);
+
+namespace {
+
+inline unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
+
+// ---- transposed lists ------------------------------------------------------------------
+__global__ void k_entry_group(const int32_t *__restrict__ off, int32_t ng, int32_t *__restrict__ eg) {
+    const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ng) return;
+    for (int32_t e = off[g]; e < off[g + 1]; ++e) eg[e] = g;
+}
+
+__global__ void k_node_keys(const int32_t *__restrict__ node, int64_t ne, uint64_t *__restrict__ keys,
+                            int32_t *__restrict__ vals) {
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    keys[e] = uint64_t(node[e]);
+    vals[e] = int32_t(e);
+}
+
+// node_off[c] = first position of node c in the sorted keys (lower bound), c in [0, nn]
+__global__ void k_node_off(const uint64_t *__restrict__ keys, int64_t ne, int32_t nn, int32_t *__restrict__ off) {
+    const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > nn) return;
+    int64_t lo = 0, hi = ne;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (keys[mid] < uint64_t(c))
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    off[c] = int32_t(lo);
+}
+
+// work items: per node, ceil(count / per) items of up to `per` consecutive units
+__global__ void k_item_count(const int32_t *__restrict__ off, int32_t nn, int32_t per, int32_t *__restrict__ cnt) {
+    const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nn) return;
+    cnt[c] = (off[c + 1] - off[c] + per - 1) / per;
+}
+
+__global__ void k_item_fill(const int32_t *__restrict__ off, const int32_t *__restrict__ ioff, int32_t nn, int32_t per,
+                            int32_t *__restrict__ inode, int32_t *__restrict__ i0, int32_t *__restrict__ i1) {
+    const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nn) return;
+    int32_t it = ioff[c];
+    for (int32_t b = off[c]; b < off[c + 1]; b += per, ++it) {
+        inode[it] = c;
+        i0[it] = b;
+        i1[it] = min(b + per, off[c + 1]);
+    }
+}
+
+// ---- near-field adjoint ------------------------------------------------------------------
+// dL/dx of one pair (w.u, u the contracted pair of Sec. 4.1) in FP64
+__device__ inline void pgrad_f64(const double d[3], const double f[3], const double h[3], const double nu[3],
+                                 const double w[3], double gx[3]) {
+    const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    const double ri = r2 > 0.0 ? rsqrt(r2) : 0.0;
+    const double r2i = ri * ri, r3i = ri * r2i, r5i = r3i * r2i;
+    const double df = d[0] * f[0] + d[1] * f[1] + d[2] * f[2];
+    const double dh = d[0] * h[0] + d[1] * h[1] + d[2] * h[2];
+    const double dn = d[0] * nu[0] + d[1] * nu[1] + d[2] * nu[2];
+    const double wd = w[0] * d[0] + w[1] * d[1] + w[2] * d[2];
+    const double wf = w[0] * f[0] + w[1] * f[1] + w[2] * f[2];
+    const double s = df * r3i, tt = dh * dn * r5i;
+    for (int q = 0; q < 3; ++q)
+        gx[q] = -wf * d[q] * r3i + w[q] * (s + tt) +
+                wd * (f[q] * r3i - 3.0 * s * d[q] * r2i + (h[q] * dn + dh * nu[q]) * r5i - 5.0 * tt * d[q] * r2i);
+}
+
+// mixed precision: d and d.nu arrive in FP64, the rest in FP32
+__device__ inline void pgrad_mixed(const double dd[3], double dnd, const float f[3], const float h[3],
+                                   const double nu64[3], const float w[3], float gx[3]) {
+    const float d[3] = {float(dd[0]), float(dd[1]), float(dd[2])};
+    const float nu[3] = {float(nu64[0]), float(nu64[1]), float(nu64[2])};
+    const float r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    const float ri = r2 > 0.0f ? __frsqrt_rn(r2) : 0.0f;
+    const float r2i = ri * ri, r3i = ri * r2i, r5i = r3i * r2i;
+    const float df = d[0] * f[0] + d[1] * f[1] + d[2] * f[2];
+    const float dh = d[0] * h[0] + d[1] * h[1] + d[2] * h[2];
+    const float dn = float(dnd);
+    const float wd = w[0] * d[0] + w[1] * d[1] + w[2] * d[2];
+    const float wf = w[0] * f[0] + w[1] * f[1] + w[2] * f[2];
+    const float s = df * r3i, tt = dh * dn * r5i;
+    for (int q = 0; q < 3; ++q)
+        gx[q] = -wf * d[q] * r3i + w[q] * (s + tt) +
+                wd * (f[q] * r3i - 3.0f * s * d[q] * r2i + (h[q] * dn + dh * nu[q]) * r5i - 5.0f * tt * d[q] * r2i);
+}
+
+struct NearAdjArgs {
+    const double *tpos, *ws;
+    int64_t m;
+    const int32_t *off, *node;   // group-major near lists
+    const uint64_t *mask;
+    const int32_t *start, *count;
+    const double *geo;           // (n,6) y, nu
+    const void *wts;             // (n,6) f, h in T
+    double *gt;                  // (m,3) sorted: near part of dL/dx
+    // source side
+    const int32_t *item_node, *item_j0;  // work item -> leaf, first source
+    const int32_t *ent, *ent_off;        // leaf-sorted near entries; per-leaf offsets
+    const int32_t *ent_group;
+    double *gs;                  // (n, 9) sorted: near part of dL/df, dL/dh, dL/dy
+    int32_t nitems;
+};
+
+template <typename T> __global__ __launch_bounds__(64) void k_near_tgrad(NearAdjArgs a) {
+    const int32_t ng = int32_t((a.m + 63) / 64);
+    const int32_t g = xcd_group(ng);
+    if (g >= ng) return;
+    const int lane = threadIdx.x;
+    const int64_t t = int64_t(g) * 64 + lane;
+    const bool valid = t < a.m;
+    double x[3] = {0, 0, 0}, w[3] = {0, 0, 0};
+    if (valid)
+        for (int q = 0; q < 3; ++q) {
+            x[q] = a.tpos[3 * t + q];
+            w[q] = a.ws[3 * t + q];
+        }
+    const T *wts = static_cast<const T *>(a.wts);
+    Comp<T> acc[3];
+    for (int32_t e = a.off[g]; e < a.off[g + 1]; ++e) {
+        const int32_t c = __builtin_amdgcn_readfirstlane(a.node[e]);
+        const uint64_t mk = a.mask[e];
+        if ((mk >> lane) & 1ull) {
+            T s0 = T(0), s1 = T(0), s2 = T(0);
+            for (int32_t j = a.start[c]; j < a.start[c] + a.count[c]; ++j) {
+                const double *gj = a.geo + 6 * int64_t(j);
+                const T *wj = wts + 6 * int64_t(j);
+                const double d[3] = {x[0] - gj[0], x[1] - gj[1], x[2] - gj[2]};
+                if constexpr (sizeof(T) == 8) {
+                    double gx[3];
+                    pgrad_f64(d, reinterpret_cast<const double *>(wj), reinterpret_cast<const double *>(wj) + 3, gj + 3, w,
+                              gx);
+                    s0 += gx[0];
+                    s1 += gx[1];
+                    s2 += gx[2];
+                } else {
+                    const double dn = d[0] * gj[3] + d[1] * gj[4] + d[2] * gj[5];
+                    const float wf[3] = {float(w[0]), float(w[1]), float(w[2])};
+                    float gx[3];
+                    pgrad_mixed(d, dn, reinterpret_cast<const float *>(wj), reinterpret_cast<const float *>(wj) + 3,
+                                gj + 3, wf, gx);
+                    s0 += gx[0];
+                    s1 += gx[1];
+                    s2 += gx[2];
+                }
+            }
+            acc[0].add(s0);
+            acc[1].add(s1);
+            acc[2].add(s2);
+        }
+    }
+    if (valid)
+        for (int q = 0; q < 3; ++q) a.gt[3 * t + q] = acc[q].value();
+}
+
+// one source per lane; loops over every near entry of its leaf and the targets of each
+template <typename T> __global__ __launch_bounds__(64) void k_near_sgrad(NearAdjArgs a) {
+    const int32_t it = blockIdx.x;
+    if (it >= a.nitems) return;
+    const int32_t c = a.item_node[it];
+    const int32_t j = a.item_j0[it] + threadIdx.x;
+    const bool valid = j < a.start[c] + a.count[c];
+    const int32_t jj = valid ? j : a.start[c];
+    double y[3], nu[3];
+    for (int q = 0; q < 3; ++q) {
+        y[q] = a.geo[6 * int64_t(jj) + q];
+        nu[q] = a.geo[6 * int64_t(jj) + 3 + q];
+    }
+    const T *wj = static_cast<const T *>(a.wts) + 6 * int64_t(jj);
+    const T f[3] = {wj[0], wj[1], wj[2]}, h[3] = {wj[3], wj[4], wj[5]};
+    Comp<T> af[3], ah[3], ay[3];
+    for (int32_t e = a.ent_off[c]; e < a.ent_off[c + 1]; ++e) {
+        const int32_t ent = a.ent[e];
+        const int32_t g = a.ent_group[ent];
+        uint64_t mk = a.mask[ent];
+        T sf[3] = {T(0), T(0), T(0)}, sh[3] = {T(0), T(0), T(0)}, sy[3] = {T(0), T(0), T(0)};
+        while (mk) {
+            const int b = __builtin_ctzll(mk);
+            mk &= mk - 1;
+            const int64_t t = int64_t(g) * 64 + b;
+            const double x[3] = {a.tpos[3 * t], a.tpos[3 * t + 1], a.tpos[3 * t + 2]};
+            const double wd64[3] = {a.ws[3 * t], a.ws[3 * t + 1], a.ws[3 * t + 2]};
+            const double d[3] = {x[0] - y[0], x[1] - y[1], x[2] - y[2]};
+            const double dn = d[0] * nu[0] + d[1] * nu[1] + d[2] * nu[2];
+            const T dt[3] = {T(d[0]), T(d[1]), T(d[2])};
+            const T wv[3] = {T(wd64[0]), T(wd64[1]), T(wd64[2])};
+            const T r2 = dt[0] * dt[0] + dt[1] * dt[1] + dt[2] * dt[2];
+            T ri = T(0);
+            if constexpr (sizeof(T) == 8) {
+                const double r2d = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                ri = T(r2d > 0.0 ? rsqrt(r2d) : 0.0);
+            } else {
+                ri = r2 > T(0) ? T(__frsqrt_rn(float(r2))) : T(0);
+            }
+            const T r3i = ri * ri * ri, r5i = r3i * ri * ri;
+            const T wdot = wv[0] * dt[0] + wv[1] * dt[1] + wv[2] * dt[2];
+            for (int q = 0; q < 3; ++q) {
+                sf[q] += wv[q] * ri + wdot * dt[q] * r3i;
+                sh[q] += wdot * dt[q] * T(dn) * r5i;
+            }
+            T gx[3];
+            if constexpr (sizeof(T) == 8) {
+                double gx64[3];
+                pgrad_f64(d, reinterpret_cast<const double *>(f), reinterpret_cast<const double *>(h), nu, wd64, gx64);
+                for (int q = 0; q < 3; ++q) gx[q] = T(gx64[q]);
+            } else {
+                float gx32[3];
+                pgrad_mixed(d, dn, reinterpret_cast<const float *>(f), reinterpret_cast<const float *>(h), nu,
+                            reinterpret_cast<const float *>(wv), gx32);
+                for (int q = 0; q < 3; ++q) gx[q] = T(gx32[q]);
+            }
+            for (int q = 0; q < 3; ++q) sy[q] -= gx[q];
+        }
+        for (int q = 0; q < 3; ++q) {
+            af[q].add(sf[q]);
+            ah[q].add(sh[q]);
+            ay[q].add(sy[q]);
+        }
+    }
+    if (valid) {
+        double *o = a.gs + 9 * int64_t(j);
+        for (int q = 0; q < 3; ++q) {
+            o[q] = af[q].value();
+            o[3 + q] = ah[q].value();
+            o[6 + q] = ay[q].value();
+        }
+    }
+}
+
+// ---- moment adjoints: transpose of the moment -> stream map ------------------------------
+struct PhiT {
+    int p = -1;
+    DBuf col_off, rowpos, epow;  // int32
+    DBuf coef;                   // double
+    DBuf colpos;                 // int32 (orders, 2, 64) for k_far_lambda
+};
+
+std::mutex g_phit_mu;
+std::map<std::pair<int, int>, PhiT *> g_phit;  // (device, p) -> table; kept for the process
+
+// Sparse matrix S with stream[pos] = sum S[pos, (a, c)] M[a][c] / rho^epow[pos], stored
+// by moment column, built once per order from phi_ge applied to unit moments.
+PhiT &phit_for(int dev, int p) {
+    std::lock_guard<std::mutex> lk(g_phit_mu);
+    auto key = std::make_pair(dev, p);
+    auto itr = g_phit.find(key);
+    if (itr != g_phit.end()) return *itr->second;
+    const int nm = nidx(p), ng = nidx(p + 1);
+    std::vector<int32_t> col_off(12 * nm + 1, 0), rowpos, epow(6 * ng, 0);
+    std::vector<double> coef;
+    std::vector<double> mom(size_t(nm) * 12, 0.0);
+    for (int b = 0; b < ng; ++b) {
+        int q[3], pg, pe;
+        kof(b, q);
+        stream_pos(p, q, pg, pe);
+        const int n = q[0] + q[1] + q[2];
+        for (int c = 0; c < 3; ++c) {
+            epow[pg + c] = n;
+            epow[pe + c] = n + 1;
+        }
+    }
+    for (int a = 0; a < nm; ++a) {
+        int ka[3];
+        kof(a, ka);
+        const int na = ka[0] + ka[1] + ka[2];
+        for (int c = 0; c < 12; ++c) {
+            mom[size_t(a) * 12 + c] = 1.0;
+            // only multi-indices of order na .. na + 2 read moment a
+            const int b0 = na > 0 ? nidx(na - 1) : 0, b1 = nidx(std::min(na + 2, p + 1));
+            for (int b = b0; b < b1; ++b) {
+                int q[3], pg, pe;
+                kof(b, q);
+                double ge[6];
+                phi_ge(mom.data(), 12, p, q, ge);
+                stream_pos(p, q, pg, pe);
+                for (int k = 0; k < 6; ++k)
+                    if (ge[k] != 0.0) {
+                        rowpos.push_back(k < 3 ? pg + k : pe + k - 3);
+                        coef.push_back(ge[k]);
+                    }
+            }
+            col_off[a * 12 + c + 1] = int32_t(rowpos.size());
+            mom[size_t(a) * 12 + c] = 0.0;
+        }
+    }
+    // LDS column -> stream position tables of k_far_lambda: row (2n + kind), kind 0 = G
+    // of order n, kind 1 = E of order n - 1; column = graded-lex position in that order
+    const int PB = p + 2;
+    std::vector<int32_t> colpos(size_t(PB + 1) * 2 * LAM_ROW, 0);
+    for (int n = 0; n <= PB; ++n)
+        for (int kind = 0; kind < 2; ++kind) {
+            const int ord = kind == 0 ? n : n - 1;
+            if (ord < 0 || ord > p + 1) continue;
+            const int cnt = (ord + 1) * (ord + 2) / 2, base = ord > 0 ? nidx(ord - 1) : 0;
+            if (cnt > LAM_ROW) throw Error(STK_EINVAL, "order too large for the adjoint column table");
+            for (int col = 0; col < cnt; ++col) {
+                int q[3], pg, pe;
+                kof(base + col, q);
+                stream_pos(p, q, pg, pe);
+                colpos[size_t(2 * n + kind) * LAM_ROW + col] = kind == 0 ? pg : pe;
+            }
+        }
+    auto *t = new PhiT();
+    t->p = p;
+    auto up = [](DBuf &d, const void *src, size_t bytes) {
+        d.reserve(bytes);
+        if (bytes) STK_HIP(hipMemcpy(d.p, src, bytes, hipMemcpyHostToDevice));
+    };
+    up(t->col_off, col_off.data(), sizeof(int32_t) * col_off.size());
+    up(t->rowpos, rowpos.data(), sizeof(int32_t) * rowpos.size());
+    up(t->coef, coef.data(), sizeof(double) * coef.size());
+    up(t->epow, epow.data(), sizeof(int32_t) * epow.size());
+    up(t->colpos, colpos.data(), sizeof(int32_t) * colpos.size());
+    g_phit[key] = t;
+    return *t;
+}
+
+// lm[(node * nm + a) * 12 + c] = sum_pos S[pos, (a,c)] rho^-epow[pos] lambda[node][pos]
+__global__ __launch_bounds__(256) void k_phi_adj(const double *__restrict__ lambda, const double *__restrict__ rho,
+                                                 int nm, int ng, const int32_t *__restrict__ col_off,
+                                                 const int32_t *__restrict__ rowpos, const double *__restrict__ coef,
+                                                 const int32_t *__restrict__ epow, double *__restrict__ lm) {
+    const int32_t node = blockIdx.x;
+    const double inv = 1.0 / rho[node];
+    const double *L = lambda + size_t(node) * 6 * ng;
+    for (int col = threadIdx.x; col < 12 * nm; col += 256) {
+        double s = 0.0;
+        for (int e = col_off[col]; e < col_off[col + 1]; ++e) {
+            const int pos = rowpos[e];
+            double sc = 1.0;
+            for (int k = 0; k < epow[pos]; ++k) sc *= inv;
+            s += coef[e] * sc * L[pos];
+        }
+        lm[size_t(node) * nm * 12 + col] = s;
+    }
+}
+
+// ---- far source gradients from the moment adjoints ---------------------------------------
+template <int P> struct SrcGrad {
+    static constexpr int NM = nidx(P);
+    // accumulate over every k of order <= P (compile-time walk in graded-lex order)
+    template <int A>
+    STK_HD static void walk(const double (&px)[P + 1], const double (&py)[P + 1], const double (&pz)[P + 1],
+                            const double *__restrict__ L, const double f[3], const double hn[9], const double nu[3],
+                            double gf[3], double gh[3], double gy[3]) {
+        if constexpr (A < NM) {
+            constexpr int K1 = kof1c(A), K2 = kof2c(A), K3 = ordc(A) - K1 - K2;
+            const double *La = L + A * 12;
+            const double mono = px[K1] * py[K2] * pz[K3];
+            double pf = 0.0;
+            for (int j = 0; j < 3; ++j) {
+                gf[j] += mono * La[j];
+                const double hl = nu[0] * La[3 + 3 * j] + nu[1] * La[4 + 3 * j] + nu[2] * La[5 + 3 * j];
+                gh[j] += mono * hl;
+                pf += f[j] * La[j];
+            }
+            for (int q = 0; q < 9; ++q) pf += hn[q] * La[3 + q];
+            if constexpr (K1 > 0) gy[0] += double(K1) * (px[K1 - 1] * py[K2] * pz[K3]) * pf;
+            if constexpr (K2 > 0) gy[1] += double(K2) * (px[K1] * py[K2 - 1] * pz[K3]) * pf;
+            if constexpr (K3 > 0) gy[2] += double(K3) * (px[K1] * py[K2] * pz[K3 - 1]) * pf;
+            walk<A + 1>(px, py, pz, L, f, hn, nu, gf, gh, gy);
+        }
+    }
+};
+
+struct SrcGradArgs {
+    const double *pos, *geo, *w12, *center, *lm;
+    const int32_t *start, *count, *coff, *level;
+    int32_t nn;
+    int64_t n;
+    double *part;  // (nlevels, n, 9)
+};
+
+__device__ inline int32_t node_of_item(const int32_t *__restrict__ off, int32_t nn, int32_t ch) {
+    int32_t lo = 0, hi = nn;
+    while (hi - lo > 1) {
+        const int32_t m = (lo + hi) >> 1;
+        if (off[m] <= ch)
+            lo = m;
+        else
+            hi = m;
+    }
+    return lo;
+}
+
+template <int P> __global__ __launch_bounds__(256) void k_src_grad(SrcGradArgs a) {
+    const int32_t ch = blockIdx.x;
+    const int32_t node = node_of_item(a.coff, a.nn, ch);
+    const int32_t first = a.start[node] + (ch - a.coff[node]) * CHUNK;
+    const int32_t last = min(a.start[node] + a.count[node], first + CHUNK);
+    const double *L = a.lm + size_t(node) * nidx(P) * 12;
+    const int lev = a.level[node];
+    for (int32_t j = first + threadIdx.x; j < last; j += 256) {
+        double px[P + 1], py[P + 1], pz[P + 1];
+        const double dx = a.pos[3 * int64_t(j)] - a.center[3 * node];
+        const double dy = a.pos[3 * int64_t(j) + 1] - a.center[3 * node + 1];
+        const double dz = a.pos[3 * int64_t(j) + 2] - a.center[3 * node + 2];
+        px[0] = py[0] = pz[0] = 1.0;
+#pragma unroll
+        for (int e = 1; e <= P; ++e) {
+            px[e] = px[e - 1] * dx;
+            py[e] = py[e - 1] * dy;
+            pz[e] = pz[e - 1] * dz;
+        }
+        const double *wr = a.w12 + 12 * int64_t(j);
+        const double f[3] = {wr[0], wr[1], wr[2]};
+        double hn[9];
+        for (int q = 0; q < 9; ++q) hn[q] = wr[3 + q];
+        const double nu[3] = {a.geo[6 * int64_t(j) + 3], a.geo[6 * int64_t(j) + 4], a.geo[6 * int64_t(j) + 5]};
+        double gf[3] = {0, 0, 0}, gh[3] = {0, 0, 0}, gy[3] = {0, 0, 0};
+        SrcGrad<P>::template walk<0>(px, py, pz, L, f, hn, nu, gf, gh, gy);
+        double *o = a.part + (size_t(lev) * a.n + j) * 9;
+        for (int q = 0; q < 3; ++q) {
+            o[q] = gf[q];
+            o[3 + q] = gh[q];
+            o[6 + q] = gy[q];
+        }
+    }
+}
+
+template <int P> void launch_src_grad(const SrcGradArgs &a, int32_t nitems, hipStream_t s) {
+    hipLaunchKernelGGL((k_src_grad<P>), dim3(nitems), dim3(256), 0, s, a);
+    STK_CHECK_LAUNCH();
+}
+
+// ---- totals, back to caller order --------------------------------------------------------
+__global__ void k_src_total(const double *__restrict__ part, int nlev, int64_t n, const double *__restrict__ near,
+                            const int32_t *__restrict__ perm, double *__restrict__ gf, double *__restrict__ gh,
+                            double *__restrict__ gy) {
+    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double v[9];
+    for (int q = 0; q < 9; ++q) v[q] = near[9 * j + q];
+    for (int l = 0; l < nlev; ++l)
+        for (int q = 0; q < 9; ++q) v[q] += part[(size_t(l) * n + j) * 9 + q];
+    const int64_t o = perm[j];
+    for (int q = 0; q < 3; ++q) {
+        if (gf) gf[3 * o + q] = v[q];
+        if (gh) gh[3 * o + q] = v[3 + q];
+        if (gy) gy[3 * o + q] = v[6 + q];
+    }
+}
+
+__global__ void k_tgt_total(const double *__restrict__ far, const double *__restrict__ near, int64_t m,
+                            const int32_t *__restrict__ tperm, double *__restrict__ gt) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= m) return;
+    const int64_t o = tperm[t];
+    for (int q = 0; q < 3; ++q) gt[3 * o + q] = far[3 * t + q] + near[3 * t + q];
+}
+
+__global__ void k_gather_w(const double *__restrict__ w, const int32_t *__restrict__ tperm, int64_t m,
+                           double *__restrict__ ws) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= m) return;
+    const int64_t o = tperm[t];
+    for (int q = 0; q < 3; ++q) ws[3 * t + q] = w[3 * o + q];
+}
+
+template <typename T> void dispatch_adj(int p, const LambdaArgs &la, const TgradArgs &ta, hipStream_t s) {
+    switch (p) {
+#define STK_ADJ_CASE(P)                  \
+    case P:                              \
+        launch_far_lambda<P, T>(la, s);  \
+        launch_far_tgrad<P, T>(ta, s);   \
+        break;
+        STK_ADJ_CASE(0)
+        STK_ADJ_CASE(1)
+        STK_ADJ_CASE(2)
+        STK_ADJ_CASE(3)
+        STK_ADJ_CASE(4)
+        STK_ADJ_CASE(5)
+        STK_ADJ_CASE(6)
+        STK_ADJ_CASE(7)
+        STK_ADJ_CASE(8)
+        STK_ADJ_CASE(9)
+        STK_ADJ_CASE(10)
+#undef STK_ADJ_CASE
+        default: throw Error(STK_EINVAL, "p out of range");
+    }
+}
+
+void dispatch_src_grad(int p, const SrcGradArgs &a, int32_t nitems, hipStream_t s) {
+    switch (p) {
+        case 0: launch_src_grad<0>(a, nitems, s); break;
+        case 1: launch_src_grad<1>(a, nitems, s); break;
+        case 2: launch_src_grad<2>(a, nitems, s); break;
+        case 3: launch_src_grad<3>(a, nitems, s); break;
+        case 4: launch_src_grad<4>(a, nitems, s); break;
+        case 5: launch_src_grad<5>(a, nitems, s); break;
+        case 6: launch_src_grad<6>(a, nitems, s); break;
+        case 7: launch_src_grad<7>(a, nitems, s); break;
+        case 8: launch_src_grad<8>(a, nitems, s); break;
+        case 9: launch_src_grad<9>(a, nitems, s); break;
+        case 10: launch_src_grad<10>(a, nitems, s); break;
+        default: throw Error(STK_EINVAL, "p out of range");
+    }
+}
+
+// leaf-side work items: leaves that appear in some near list, in blocks of `per` points
+__global__ void k_leaf_units(const int32_t *__restrict__ eoff, const int32_t *__restrict__ count, int32_t nn,
+                             int32_t per, int32_t *__restrict__ cnt) {
+    const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nn) return;
+    cnt[c] = eoff[c + 1] > eoff[c] ? (count[c] + per - 1) / per : 0;
+}
+
+__global__ void k_leaf_fill(const int32_t *__restrict__ eoff, const int32_t *__restrict__ start,
+                            const int32_t *__restrict__ count, const int32_t *__restrict__ ioff, int32_t nn, int32_t per,
+                            int32_t *__restrict__ inode, int32_t *__restrict__ ia) {
+    const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nn || eoff[c + 1] == eoff[c]) return;
+    int32_t it = ioff[c];
+    for (int32_t b = 0; b < count[c]; b += per, ++it) {
+        inode[it] = c;
+        ia[it] = start[c] + b;
+    }
+}
+
+// Re-sort group-major list entries by node: ent = entry positions ordered by node,
+// ent_off = per-node offsets into ent, ent_group = entry -> group, plus work items:
+// by_entries: (node, [a, b) range of ent) with <= per entries; otherwise (leaf, first
+// point) blocks of per points for leaves that have entries.
+void transpose(Tree &t, const DBuf &goff, const DBuf &gnode, int64_t ne, int32_t ngroups, TransposedLists &tr,
+               bool by_entries, int32_t per, hipStream_t s) {
+    const int32_t nn = t.nnodes;
+    int32_t *eg = reserve<int32_t>(tr.ent_group, size_t(ne) + 1);
+    hipLaunchKernelGGL(k_entry_group, dim3(nblk(ngroups, 256)), dim3(256), 0, s, goff.as<int32_t>(), ngroups, eg);
+    STK_CHECK_LAUNCH();
+    uint64_t *keys = reserve<uint64_t>(t.s_keys, size_t(ne) + 1);
+    int32_t *ent = reserve<int32_t>(tr.ent, size_t(ne) + 1);
+    if (ne > 0) {
+        hipLaunchKernelGGL(k_node_keys, dim3(nblk(ne, 256)), dim3(256), 0, s, gnode.as<int32_t>(), ne, keys, ent);
+        STK_CHECK_LAUNCH();
+        int bits = 1;
+        while ((int64_t(1) << bits) <= nn) ++bits;
+        radix_sort_pairs(t, keys, ent, ne, bits, s);
+    }
+    int32_t *eoff = reserve<int32_t>(tr.ent_off, size_t(nn) + 1);
+    hipLaunchKernelGGL(k_node_off, dim3(nblk(nn + 1, 256)), dim3(256), 0, s, keys, ne, nn, eoff);
+    STK_CHECK_LAUNCH();
+    int32_t *cnt = reserve<int32_t>(t.s_vals, size_t(nn) + 1);
+    int32_t *ioff = reserve<int32_t>(t.s_vals2, size_t(nn) + 1);
+    if (by_entries)
+        hipLaunchKernelGGL(k_item_count, dim3(nblk(nn, 256)), dim3(256), 0, s, eoff, nn, per, cnt);
+    else
+        hipLaunchKernelGGL(k_leaf_units, dim3(nblk(nn, 256)), dim3(256), 0, s, eoff, t.ncount.as<int32_t>(), nn, per,
+                           cnt);
+    STK_CHECK_LAUNCH();
+    scan_exclusive_i32(cnt, ioff, nn, s);
+    int32_t nitems = 0;
+    STK_HIP(hipMemcpyAsync(&nitems, ioff + nn, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    STK_HIP(hipStreamSynchronize(s));
+    tr.nitems = nitems;
+    int32_t *inode = reserve<int32_t>(tr.item_node, size_t(nitems) + 1);
+    int32_t *ia = reserve<int32_t>(tr.item_a, size_t(nitems) + 1);
+    int32_t *ib = reserve<int32_t>(tr.item_b, size_t(nitems) + 1);
+    if (by_entries)
+        hipLaunchKernelGGL(k_item_fill, dim3(nblk(nn, 256)), dim3(256), 0, s, eoff, ioff, nn, per, inode, ia, ib);
+    else
+        hipLaunchKernelGGL(k_leaf_fill, dim3(nblk(nn, 256)), dim3(256), 0, s, eoff, t.nstart.as<int32_t>(),
+                           t.ncount.as<int32_t>(), ioff, nn, per, inode, ia);
+    STK_CHECK_LAUNCH();
+}
+
+}  // namespace
+
+void adjoint(Plan &pl, const double *w, double *gf, double *gh, double *gt, double *gy, hipStream_t s) {
+    Tree &t = *pl.tree;
+    if (!t.have_moments) throw Error(STK_ESTATE, "the plan's tree has no moments");
+    require(t.k_rhs == 1, "the adjoint supports one right-hand side");
+    const int p = t.p, nm = nidx(p), ngc = nidx(p + 1);
+    const int64_t m = pl.m, n = t.n;
+    const int32_t nn = t.nnodes, ng = pl.ngroups;
+    const bool src = gf || gh || gy;
+    const bool fp64 = t.prec == STK_FP64;
+    AdjScratch &A = pl.adj;
+    prof_mark(-1, s);
+
+    double *ws = reserve<double>(A.ws, size_t(m) * 3);
+    hipLaunchKernelGGL(k_gather_w, dim3(nblk(m, 256)), dim3(256), 0, s, w, pl.tperm.as<int32_t>(), m, ws);
+    STK_CHECK_LAUNCH();
+
+    NearAdjArgs na{};
+    na.tpos = pl.tpos.as<double>();
+    na.ws = ws;
+    na.m = m;
+    na.off = pl.near_off.as<int32_t>();
+    na.node = pl.near_node.as<int32_t>();
+    na.mask = pl.near_mask.as<uint64_t>();
+    na.start = t.nstart.as<int32_t>();
+    na.count = t.ncount.as<int32_t>();
+    na.geo = t.geo.as<double>();
+    na.wts = t.wts.p;
+
+    // target side
+    double *gtn = nullptr, *gtf = nullptr;
+    if (gt) {
+        gtn = reserve<double>(A.gt_near, size_t(m) * 3);
+        gtf = reserve<double>(A.gt_far, size_t(m) * 3);
+        na.gt = gtn;
+        if (fp64)
+            hipLaunchKernelGGL(k_near_tgrad<double>, dim3(xcd_blocks(ng)), dim3(64), 0, s, na);
+        else
+            hipLaunchKernelGGL(k_near_tgrad<float>, dim3(xcd_blocks(ng)), dim3(64), 0, s, na);
+        STK_CHECK_LAUNCH();
+    }
+
+    // far field: stream adjoints (source side) and target gradients
+    LambdaArgs la{};
+    TgradArgs ta{};
+    PhiT &ph = phit_for(t.device, p);
+    if (src) {
+        transpose(t, pl.far_off, pl.far_node, pl.n_far_entries, ng, A.far_t, true, 16, s);
+        double *lam = reserve<double>(A.lambda, size_t(nn) * 6 * ngc);
+        STK_HIP(hipMemsetAsync(lam, 0, sizeof(double) * size_t(nn) * 6 * ngc, s));
+        la.tpos = pl.tpos.as<double>();
+        la.ws = ws;
+        la.m = m;
+        la.item_node = A.far_t.item_node.as<int32_t>();
+        la.item_e0 = A.far_t.item_a.as<int32_t>();
+        la.item_e1 = A.far_t.item_b.as<int32_t>();
+        la.ent = A.far_t.ent.as<int32_t>();
+        la.ent_group = A.far_t.ent_group.as<int32_t>();
+        la.mask = pl.far_mask.as<uint64_t>();
+        la.center = t.ncenter.as<double>();
+        la.rho = t.nrho.as<double>();
+        la.colpos = ph.colpos.as<int32_t>();
+        la.lambda = lam;
+        la.nitems = A.far_t.nitems;
+    }
+    if (gt) {
+        ta.tpos = pl.tpos.as<double>();
+        ta.ws = ws;
+        ta.m = m;
+        ta.off = pl.far_off.as<int32_t>();
+        ta.node = pl.far_node.as<int32_t>();
+        ta.mask = pl.far_mask.as<uint64_t>();
+        ta.center = t.ncenter.as<double>();
+        ta.rho = t.nrho.as<double>();
+        ta.wblk = t.wblk.p;
+        ta.gt = gtf;
+        ta.ngroups = ng;
+    }
+    if (fp64)
+        dispatch_adj<double>(p, la, ta, s);
+    else
+        dispatch_adj<float>(p, la, ta, s);
+
+    if (src) {
+        // stream adjoints -> moment adjoints -> per-level source gradients
+        double *lm = reserve<double>(A.lm, size_t(nn) * nm * 12);
+        hipLaunchKernelGGL(k_phi_adj, dim3(nn), dim3(256), 0, s, A.lambda.as<double>(), t.nrho.as<double>(), nm, ngc,
+                           ph.col_off.as<int32_t>(), ph.rowpos.as<int32_t>(), ph.coef.as<double>(),
+                           ph.epow.as<int32_t>(), lm);
+        STK_CHECK_LAUNCH();
+        const int nlev = t.nlevels;
+        double *part = reserve<double>(A.part, size_t(nlev) * n * 9);
+        STK_HIP(hipMemsetAsync(part, 0, sizeof(double) * size_t(nlev) * n * 9, s));
+        SrcGradArgs sa{t.pos.as<double>(), t.geo.as<double>(), t.w12.as<double>(), t.ncenter.as<double>(), lm,
+                       t.nstart.as<int32_t>(), t.ncount.as<int32_t>(), t.chunk_off.as<int32_t>(),
+                       t.nlevel.as<int32_t>(), nn, n, part};
+        dispatch_src_grad(p, sa, t.nchunks, s);
+
+        // near field, source side
+        transpose(t, pl.near_off, pl.near_node, pl.n_near_entries, ng, A.near_t, false, 64, s);
+        double *gs = reserve<double>(A.gs, size_t(n) * 9);
+        STK_HIP(hipMemsetAsync(gs, 0, sizeof(double) * size_t(n) * 9, s));
+        na.item_node = A.near_t.item_node.as<int32_t>();
+        na.item_j0 = A.near_t.item_a.as<int32_t>();
+        na.ent = A.near_t.ent.as<int32_t>();
+        na.ent_off = A.near_t.ent_off.as<int32_t>();
+        na.ent_group = A.near_t.ent_group.as<int32_t>();
+        na.gs = gs;
+        na.nitems = A.near_t.nitems;
+        if (na.nitems > 0) {
+            if (fp64)
+                hipLaunchKernelGGL(k_near_sgrad<double>, dim3(na.nitems), dim3(64), 0, s, na);
+            else
+                hipLaunchKernelGGL(k_near_sgrad<float>, dim3(na.nitems), dim3(64), 0, s, na);
+            STK_CHECK_LAUNCH();
+        }
+        hipLaunchKernelGGL(k_src_total, dim3(nblk(n, 256)), dim3(256), 0, s, part, nlev, n, gs,
+                           t.perm.as<int32_t>(), gf, gh, gy);
+        STK_CHECK_LAUNCH();
+    }
+    if (gt) {
+        hipLaunchKernelGGL(k_tgt_total, dim3(nblk(m, 256)), dim3(256), 0, s, gtf, gtn, m, pl.tperm.as<int32_t>(), gt);
+        STK_CHECK_LAUNCH();
+    }
+    prof_mark(STK_PHASE_ADJOINT, s);
+}
+
+}  // namespace stk

@@ -163,6 +163,16 @@ stk_status stk_evaluate(const double *targets, int64_t m, const double *sources,
     });
 }
 
+stk_status stk_evaluate_adjoint(stk_plan *plan, const double *w, double *grad_f, double *grad_h,
+                                double *grad_targets, double *grad_sources, void *stream) {
+    return guarded([&] {
+        stk::require(plan != nullptr, "plan is NULL");
+        stk::require(w != nullptr, "w is NULL");
+        check_device(plan->p.tree->device);
+        stk::adjoint(plan->p, w, grad_f, grad_h, grad_targets, grad_sources, as_stream(stream));
+    });
+}
+
 stk_status stk_direct(const double *targets, int64_t m, const double *sources, int64_t n, const double *f,
                       const double *h, const double *nu, int32_t k_rhs, double *u_out, void *stream) {
     return guarded([&] {

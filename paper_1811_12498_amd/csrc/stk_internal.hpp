@@ -105,6 +105,18 @@ struct Tree {
     DBuf s_keys, s_vals, s_keys2, s_vals2, s_hist, s_tmp;
 };
 
+// lists re-sorted by node (cluster-major / leaf-major) and their work items
+struct TransposedLists {
+    DBuf ent, ent_off, ent_group, item_node, item_a, item_b;
+    int32_t nitems = 0;
+};
+
+// scratch of the adjoint, kept with the plan for repeated backward calls
+struct AdjScratch {
+    DBuf ws, gt_near, gt_far, lambda, lm, part, gs;
+    TransposedLists far_t, near_t;
+};
+
 // ---------------------------------------------------------------------------------
 // plan handle: a tree plus one target set's interaction lists
 // ---------------------------------------------------------------------------------
@@ -121,6 +133,7 @@ struct Plan {
     DBuf far_mask, near_mask;      // uint64 entries (lane masks of the 64-target group)
     DBuf cnt_far, cnt_near, cnt_pairs;  // int32 per sorted target
     int64_t n_far_entries = 0, n_near_entries = 0;
+    AdjScratch adj;
     ~Plan();
 };
 
@@ -143,6 +156,10 @@ void compute_moments(Tree &t, const double *f, const double *h, const double *nu
 // Morton order is the tree's and they are not sorted again
 void evaluate(Tree &t, Plan &plan, const double *tgt, int64_t m, double theta, double *u_out, bool same_as_sources,
               hipStream_t s);
+// gradients of L = sum_m w^m . u^m for the plan's frozen operator (any output may be
+// NULL); w and the outputs in the caller's orders
+void adjoint(Plan &plan, const double *w, double *grad_f, double *grad_h, double *grad_targets,
+             double *grad_sources, hipStream_t s);
 void direct_sum(const double *tgt, int64_t m, const double *src, int64_t n, const double *f, const double *h,
                 const double *nu, int32_t k, double *u_out, hipStream_t s);
 

@@ -46,6 +46,32 @@ STK_HD constexpr int gidx(int k1, int k2, int k3) {
                      (k2 + k3) * (k2 + k3 + 1) / 2 + k3;
 }
 
+// order, first and second component of the multi-index at graded-lex position a
+// (compile-time forms of kof)
+STK_HD constexpr int ordc(int a) {
+    int n = 0;
+    while (nidx(n) <= a) ++n;
+    return n;
+}
+STK_HD constexpr int kof1c(int a) {
+    const int n = ordc(a);
+    int r = a - (n > 0 ? nidx(n - 1) : 0), k1 = n;
+    while (r >= n - k1 + 1) {
+        r -= n - k1 + 1;
+        --k1;
+    }
+    return k1;
+}
+STK_HD constexpr int kof2c(int a) {
+    const int n = ordc(a);
+    int r = a - (n > 0 ? nidx(n - 1) : 0), k1 = n;
+    while (r >= n - k1 + 1) {
+        r -= n - k1 + 1;
+        --k1;
+    }
+    return n - k1 - r;
+}
+
 // gidx restricted to ||k|| <= p
 STK_HD constexpr int gidxp(int k1, int k2, int k3, int p) {
     return (k1 + k2 + k3 > p) ? -1 : gidx(k1, k2, k3);
