@@ -67,6 +67,41 @@ def cpu_baseline(w, f, h, n_sample=2000, seed=99):
                       f"seeded targets ({t2 - t1:.2f} s), extrapolated to {w.n} targets"}
 
 
+def fwd_adjoint_times(reps=3):
+    """Differentiable workload: N = 200,000 in the unit cube (seed 5), p = 8, theta = 0.5,
+    N0 = 2000, L = sum(w * u) with w ~ U[-1,1]^3; forward (plan kept) + adjoint for
+    dL/df, dL/dh and the positions (targets = sources), per precision, in ms."""
+    import torch
+
+    from paper_1811_12498_amd import native, workloads
+    w = workloads.c5_cube_adjoint()
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    X, F, H, NU, Wt = t(w.src), t(w.f[0]), t(w.h[0]), t(w.nu), t(w.w)
+    out = {"workload": "cube N=2e5, p=8, theta=0.5, N0=2000, L=sum(w.u)"}
+    for prec in ("mixed", "fp64"):
+        def run():
+            u, plan = native.evaluate(X, X, F, H, NU, w.p, w.theta, w.n0, prec, keep_plan=True)
+            native.evaluate_adjoint(plan, Wt, w.n)
+            return plan
+        run()
+        torch.cuda.synchronize()
+        native.profile_read()
+        native.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            run()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        native.profile_enable(False)
+        prof = native.profile_read()
+        fwd_ms = sum(prof[k][0] for k in ("tree", "moments", "targets", "lists", "near", "far")) / reps
+        out["fp32" if prec == "mixed" else "fp64"] = {"fwd_adjoint_ms": round(ms, 3),
+                                                      "forward_ms": round(fwd_ms, 3),
+                                                      "adjoint_ms": round(prof["adjoint"][0] / reps, 3)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +213,10 @@ def main():
                                  "pairs_per_launch": pairs_total, "avg_launch_ms": round(near_ms, 4)},
                   "phase_ms_per_step": phases}
     log(f"accuracy: {acc}")
+
+    if not args.no_extras:
+        extras["fwd_adjoint"] = fwd_adjoint_times()
+        log(f"fwd+adjoint: {extras['fwd_adjoint']}")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -98,3 +98,67 @@ def test_autograd_function(nat):
     assert torch.allclose(H.grad, g["h"], rtol=1e-12, atol=1e-12)
     # the same tensor as targets and sources: autograd adds both position gradients
     assert torch.allclose(X.grad, g["targets"] + g["sources"], rtol=1e-10, atol=1e-10)
+
+
+def test_finite_differences_full_size(nat):
+    """N = 200,000 in the unit cube, p = 8, theta = 0.5, N0 = 2000, L = sum w.u: the FP64
+    adjoint against central differences on 50 seeded coordinates (17 of f, 17 of h, 16
+    of positions; targets = sources, so a position's gradient is the target part plus
+    the source part).  L is linear in f and h, so their difference quotient is exact for
+    any step and a unit step keeps rounding out of it; positions use a step of 1e-6 and
+    a tolerance that adds the rounding of two evaluations of L (64 ulp of sum |w.u|)
+    divided by the step.  A position perturbation that moves a cluster box or changes
+    an interaction count leaves the frozen operator; such coordinates are replaced by
+    the next draw."""
+    import torch
+    w = W.c5_cube_adjoint()
+    rng = np.random.default_rng(55)
+    X, F, H, NU, Wt = (_t(a) for a in (w.src, w.f[0], w.h[0], w.nu, w.w))
+    args = (w.p, w.theta, w.n0, "fp64")
+    u, plan = nat.evaluate(X, X, F, H, NU, *args, keep_plan=True)
+    g = nat.evaluate_adjoint(plan, Wt, w.n)
+    counts0 = nat.plan_counts(plan)
+    tree0 = nat.tree_export(nat.build_tree(X, w.n0))
+    eps = 1e-6
+    noise = 64 * np.finfo(np.float64).eps * float(torch.sum(torch.abs(Wt * u))) / (2 * eps)
+
+    def loss(Xp, Fp, Hp):
+        return float(torch.sum(Wt * nat.evaluate(Xp, Xp, Fp, Hp, NU, *args)))
+
+    checked = {"f": 0, "h": 0, "x": 0}
+    want = {"f": 17, "h": 17, "x": 16}
+    while any(checked[k] < want[k] for k in want):
+        kind = next(k for k in ("f", "h", "x") if checked[k] < want[k])
+        j, ax = int(rng.integers(w.n)), int(rng.integers(3))
+        if kind == "x":
+            ok = True
+            for sgn in (1.0, -1.0):
+                Xp = X.clone()
+                Xp[j, ax] += sgn * eps
+                t1 = nat.tree_export(nat.build_tree(Xp, w.n0))
+                same = all(np.array_equal(t1[k], tree0[k]) for k in ("perm", "start", "count", "center", "radius"))
+                _, pl1 = nat.evaluate(Xp, Xp, F, H, NU, *args, keep_plan=True)
+                c1 = nat.plan_counts(pl1)
+                same = same and all(np.array_equal(a, b) for a, b in zip(c1, counts0))
+                ok = ok and same
+            if not ok:
+                continue
+            Xp, Xm = X.clone(), X.clone()
+            Xp[j, ax] += eps
+            Xm[j, ax] -= eps
+            fd = (loss(Xp, F, H) - loss(Xm, F, H)) / (2 * eps)
+            ad = float(g["targets"][j, ax] + g["sources"][j, ax])
+            tol = 1e-5 * abs(ad) + noise
+        else:
+            A = F if kind == "f" else H
+            Ap, Am = A.clone(), A.clone()
+            Ap[j, ax] += 1.0
+            Am[j, ax] -= 1.0
+            lp = loss(X, Ap, H) if kind == "f" else loss(X, F, Ap)
+            lm = loss(X, Am, H) if kind == "f" else loss(X, F, Am)
+            fd = (lp - lm) / 2.0
+            ad = float(g[kind][j, ax])
+            tol = 1e-9 * abs(ad) + noise * 2 * eps
+        print(kind, j, ax, fd, ad, tol, flush=True)
+        assert abs(fd - ad) <= tol, (kind, j, ax, fd, ad, tol)
+        checked[kind] += 1
