@@ -165,7 +165,13 @@ def main():
     _, plan = native.evaluate(X, X, F, H, NU, w.p, w.theta, w.n0, args.precision, keep_plan=True)
     nfar, nnear, npairs = native.plan_counts(plan)
     pinfo = native.plan_info(plan)
+    near_lists = native.plan_lists(plan, "near")
     del plan
+    leaf_count = native.tree_export(native.build_tree(X, w.n0))["count"].astype(np.int64)
+    # leaf-major items: each leaf's (target, leaf) incidences in waves of 64 lanes
+    inc = np.bincount(near_lists["node"], weights=np.bitwise_count(near_lists["mask"]),
+                      minlength=leaf_count.size).astype(np.int64)
+    near_slots = int((64 * ((inc + 63) // 64) * leaf_count).sum())
     far_total = int(nfar.sum())
     pairs_total = int(npairs.sum())
     far_ms = prof["far"][0] / prof["far"][1]
@@ -210,7 +216,8 @@ def main():
                   "fp64_direct_targets_per_s": S.size / (dprof[0] * 1e-3),
                   "near_field": {"achieved_tflops": round(near_tf / 1e12, 3),
                                  "frac_of_fp32_peak": round(near_tf / PEAK_FP32_VALU, 4),
-                                 "pairs_per_launch": pairs_total, "avg_launch_ms": round(near_ms, 4)},
+                                 "pairs_per_launch": pairs_total, "avg_launch_ms": round(near_ms, 4),
+                                 "lane_utilisation": round(pairs_total / near_slots, 4)},
                   "phase_ms_per_step": phases}
     log(f"accuracy: {acc}")
 

@@ -155,6 +155,16 @@ stk_status stk_tree_export_moments(const stk_tree *t, int32_t rhs, double *M, do
 /* Per-target interaction counts of a plan, in the caller's target order (host
  * arrays of length m): far-field nodes, near-field leaves, near-field pairs. */
 stk_status stk_plan_counts(const stk_plan *plan, int64_t *nfar, int64_t *nnear, int64_t *npairs);
+/* Copy a plan's interaction lists (Alg. 1: the clusters accepted by eq. MAC, or the
+ * leaves summed directly) to host arrays.  kind 0 = far field, 1 = near field.  Targets
+ * are processed in groups of 64 consecutive Morton-sorted targets; group g's entries
+ * are off[g] .. off[g+1]-1 (off has ngroups + 1 entries), entry e applies node[e]
+ * (numbered as in stk_tree_export) to the targets whose lane bit is set in mask[e]:
+ * bit l of mask[e] is sorted target 64 g + l, i.e. caller target tperm[64 g + l]
+ * (tperm has m entries).  node and mask hold stk_plan_info's entry count for the kind.
+ * Any pointer may be NULL.  EINVAL: kind not 0 or 1. */
+stk_status stk_plan_export_lists(const stk_plan *plan, int32_t kind, int32_t *off, int32_t *node, uint64_t *mask,
+                                 int32_t *tperm);
 
 /* Phase timing, a tracing aid.  While enabled, every entry point records a HIP event
  * on its stream when it starts and after each phase below; stk_profile_read waits for

@@ -26,6 +26,7 @@ _STATUS_NAMES = {STK_EINVAL: "STK_EINVAL", STK_ENOMEM: "STK_ENOMEM", STK_EDEVICE
 EXPORTS = ["stk_build_tree", "stk_compute_moments", "stk_evaluate_tree", "stk_evaluate", "stk_evaluate_adjoint",
            "stk_direct",
            "stk_tree_info", "stk_tree_export", "stk_tree_export_moments", "stk_plan_counts", "stk_plan_info",
+           "stk_plan_export_lists",
            "stk_profile_enable", "stk_profile_read", "stk_tree_destroy", "stk_plan_destroy", "stk_last_error"]
 
 PHASES = ["tree", "moments", "targets", "lists", "near", "far", "direct", "adjoint"]
@@ -57,6 +58,7 @@ _lib.stk_evaluate_adjoint.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.stk_tree_info.argtypes = [_vp, _i64p, _i32p, _dp]
 _lib.stk_tree_export.argtypes = [_vp] + [_vp] * 11
 _lib.stk_tree_export_moments.argtypes = [_vp, _i32, _vp, _vp]
+_lib.stk_plan_export_lists.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp]
 _lib.stk_plan_counts.argtypes = [_vp, _vp, _vp, _vp]
 _lib.stk_plan_info.argtypes = [_vp, _i64p, _i64p, _i64p]
 _lib.stk_profile_enable.argtypes = [ctypes.c_int]
@@ -240,6 +242,20 @@ def plan_info(plan: Plan) -> dict:
     g, fe, ne = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     _check(_lib.stk_plan_info(plan.handle, ctypes.byref(g), ctypes.byref(fe), ctypes.byref(ne)))
     return {"groups": g.value, "far_entries": fe.value, "near_entries": ne.value}
+
+
+def plan_lists(plan: Plan, kind: str) -> dict:
+    """A plan's group lists ("far" or "near"): off (ngroups+1), node, mask (uint64 lane
+    masks) and tperm (sorted target -> caller index), as host arrays."""
+    info = plan_info(plan)
+    k = {"far": 0, "near": 1}[kind]
+    ne = info["far_entries" if k == 0 else "near_entries"]
+    out = {"off": np.zeros(info["groups"] + 1, np.int32), "node": np.zeros(max(ne, 1), np.int32),
+           "mask": np.zeros(max(ne, 1), np.uint64), "tperm": np.zeros(max(plan.m, 1), np.int32)}
+    _check(_lib.stk_plan_export_lists(plan.handle, k, *[ctypes.c_void_p(out[n].ctypes.data)
+                                                        for n in ("off", "node", "mask", "tperm")]))
+    out["node"], out["mask"], out["tperm"] = out["node"][:ne], out["mask"][:ne], out["tperm"][:plan.m]
+    return out
 
 
 def profile_enable(on: bool = True) -> None:

@@ -17,6 +17,7 @@
 #include <mutex>
 
 #include "adjoint_far.hpp"
+#include "lists.hpp"
 #include "stk_internal.hpp"
 #include "stk_math.hpp"
 
@@ -28,55 +29,6 @@ template <int P, typename T> void launch_far_tgrad(const TgradArgs &, hipStream_
 namespace {
 
 inline unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
-
-// ---- transposed lists ------------------------------------------------------------------
-__global__ void k_entry_group(const int32_t *__restrict__ off, int32_t ng, int32_t *__restrict__ eg) {
-    const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ng) return;
-    for (int32_t e = off[g]; e < off[g + 1]; ++e) eg[e] = g;
-}
-
-__global__ void k_node_keys(const int32_t *__restrict__ node, int64_t ne, uint64_t *__restrict__ keys,
-                            int32_t *__restrict__ vals) {
-    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (e >= ne) return;
-    keys[e] = uint64_t(node[e]);
-    vals[e] = int32_t(e);
-}
-
-// node_off[c] = first position of node c in the sorted keys (lower bound), c in [0, nn]
-__global__ void k_node_off(const uint64_t *__restrict__ keys, int64_t ne, int32_t nn, int32_t *__restrict__ off) {
-    const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c > nn) return;
-    int64_t lo = 0, hi = ne;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (keys[mid] < uint64_t(c))
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    off[c] = int32_t(lo);
-}
-
-// work items: per node, ceil(count / per) items of up to `per` consecutive units
-__global__ void k_item_count(const int32_t *__restrict__ off, int32_t nn, int32_t per, int32_t *__restrict__ cnt) {
-    const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nn) return;
-    cnt[c] = (off[c + 1] - off[c] + per - 1) / per;
-}
-
-__global__ void k_item_fill(const int32_t *__restrict__ off, const int32_t *__restrict__ ioff, int32_t nn, int32_t per,
-                            int32_t *__restrict__ inode, int32_t *__restrict__ i0, int32_t *__restrict__ i1) {
-    const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nn) return;
-    int32_t it = ioff[c];
-    for (int32_t b = off[c]; b < off[c + 1]; b += per, ++it) {
-        inode[it] = c;
-        i0[it] = b;
-        i1[it] = min(b + per, off[c + 1]);
-    }
-}
 
 // ---- near-field adjoint ------------------------------------------------------------------
 // dL/dx of one pair (w.u, u the contracted pair of Sec. 4.1) in FP64
@@ -577,7 +529,7 @@ void transpose(Tree &t, const DBuf &goff, const DBuf &gnode, int64_t ne, int32_t
         hipLaunchKernelGGL(k_leaf_units, dim3(nblk(nn, 256)), dim3(256), 0, s, eoff, t.ncount.as<int32_t>(), nn, per,
                            cnt);
     STK_CHECK_LAUNCH();
-    scan_exclusive_i32(cnt, ioff, nn, s);
+    scan_exclusive_i32(cnt, ioff, nn, t.s_scan, s);
     int32_t nitems = 0;
     STK_HIP(hipMemcpyAsync(&nitems, ioff + nn, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     STK_HIP(hipStreamSynchronize(s));

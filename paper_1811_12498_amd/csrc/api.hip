@@ -274,6 +274,25 @@ stk_status stk_plan_info(const stk_plan *plan, int64_t *ngroups, int64_t *n_far_
     });
 }
 
+stk_status stk_plan_export_lists(const stk_plan *plan, int32_t kind, int32_t *off, int32_t *node, uint64_t *mask,
+                                 int32_t *tperm) {
+    return guarded([&] {
+        stk::require(plan != nullptr, "plan is NULL");
+        stk::require(kind == 0 || kind == 1, "kind must be 0 (far) or 1 (near)");
+        const stk::Plan &P = plan->p;
+        check_device(P.tree->device);
+        STK_HIP(hipDeviceSynchronize());
+        const size_t ne = size_t(kind == 0 ? P.n_far_entries : P.n_near_entries);
+        auto cp = [](void *dst, const stk::DBuf &b, size_t bytes) {
+            if (dst && bytes) STK_HIP(hipMemcpy(dst, b.p, bytes, hipMemcpyDeviceToHost));
+        };
+        cp(off, kind == 0 ? P.far_off : P.near_off, sizeof(int32_t) * size_t(P.ngroups + 1));
+        cp(node, kind == 0 ? P.far_node : P.near_node, sizeof(int32_t) * ne);
+        cp(mask, kind == 0 ? P.far_mask : P.near_mask, sizeof(uint64_t) * ne);
+        cp(tperm, P.tperm, sizeof(int32_t) * size_t(P.m));
+    });
+}
+
 stk_status stk_profile_enable(int on) {
     return guarded([&] { stk::prof_enable(on != 0); });
 }

@@ -127,124 +127,6 @@ template <bool FILL> __global__ __launch_bounds__(64) void k_traverse(TravArgs a
     }
 }
 
-// ---- near field: contracted direct sum of Sec. 4.1 over the group's near leaves ----
-struct NearArgs {
-    const double *tpos;
-    int64_t m;
-    const int32_t *off, *node;
-    const uint64_t *mask;
-    const int32_t *start, *count;
-    const double *geo;   // (n,6) y, nu
-    const void *wts;     // (n,6) f, h in T
-    double *unear;       // (m,3) sorted order
-};
-
-// One source's contribution (contracted pair of Sec. 4.1).  g = (y, nu) and w = (f, h)
-// are wave-uniform (held in SGPRs).
-__device__ inline void pair_f64(double x0, double x1, double x2, const double g[6], const double w[6], double &u0,
-                                double &u1, double &u2) {
-    const double d0 = x0 - g[0], d1 = x1 - g[1], d2 = x2 - g[2];
-    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-    const double ri = r2 > 0.0 ? rsqrt(r2) : 0.0;
-    const double r2i = ri * ri;
-    const double r3i = ri * r2i;
-    const double dn = d0 * g[3] + d1 * g[4] + d2 * g[5];
-    const double sv = (d0 * w[0] + d1 * w[1] + d2 * w[2]) * r3i;
-    const double tt = (d0 * w[3] + d1 * w[4] + d2 * w[5]) * dn * (r3i * r2i);
-    const double st = sv + tt;
-    u0 += w[0] * ri + d0 * st;
-    u1 += w[1] * ri + d1 * st;
-    u2 += w[2] * ri + d2 * st;
-}
-
-// Mixed precision: d = x - y and d.nu in FP64 (on a surface with nu the normal d.nu is
-// O(|d|^2), so its absolute rounding must stay at FP64 level), the rest in FP32.
-__device__ inline void pair_mixed(double x0, double x1, double x2, const double g[6], const float w[6], float &u0,
-                                  float &u1, float &u2) {
-    const double d0 = x0 - g[0], d1 = x1 - g[1], d2 = x2 - g[2];
-    const double dn = d0 * g[3] + d1 * g[4] + d2 * g[5];
-    const float f0 = float(d0), f1 = float(d1), f2 = float(d2);
-    const float r2 = f0 * f0 + f1 * f1 + f2 * f2;
-    const float ri = r2 > 0.0f ? __frsqrt_rn(r2) : 0.0f;
-    const float r2i = ri * ri;
-    const float r3i = ri * r2i;
-    const float sv = (f0 * w[0] + f1 * w[1] + f2 * w[2]) * r3i;
-    const float tt = (f0 * w[3] + f1 * w[4] + f2 * w[5]) * float(dn) * (r3i * r2i);
-    const float st = sv + tt;
-    u0 += w[0] * ri + f0 * st;
-    u1 += w[1] * ri + f1 * st;
-    u2 += w[2] * ri + f2 * st;
-}
-
-template <typename T> __global__ __launch_bounds__(64) void k_near(NearArgs a) {
-    const int32_t ng = int32_t((a.m + 63) / 64);
-    const int32_t g = xcd_group(ng);
-    if (g >= ng) return;
-    const int lane = threadIdx.x;
-    const int64_t t = int64_t(g) * 64 + lane;
-    const bool valid = t < a.m;
-    double x0 = 0, x1 = 0, x2 = 0;
-    if (valid) {
-        x0 = a.tpos[3 * t];
-        x1 = a.tpos[3 * t + 1];
-        x2 = a.tpos[3 * t + 2];
-    }
-    const T *__restrict__ wts = static_cast<const T *>(a.wts);
-    const double *__restrict__ geo = a.geo;
-    Comp<T> acc[3];
-    const int32_t e0 = a.off[g], e1 = a.off[g + 1];
-    for (int32_t e = e0; e < e1; ++e) {
-        const int32_t c = __builtin_amdgcn_readfirstlane(a.node[e]);
-        const uint64_t mk = a.mask[e];
-        if ((mk >> lane) & 1ull) {
-            const int32_t s = a.start[c], n = a.count[c];
-            T u0 = T(0), u1 = T(0), u2 = T(0);
-            // sources in batches of four: the four records are requested together (one
-            // wait on the scalar cache per batch), then their four pairs are evaluated
-            int32_t j = s;
-            for (; j + 4 <= s + n; j += 4) {
-                double gb[4][6];
-                T wb[4][6];
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-#pragma unroll
-                    for (int q = 0; q < 6; ++q) {
-                        gb[b][q] = geo[6 * int64_t(j + b) + q];
-                        wb[b][q] = wts[6 * int64_t(j + b) + q];
-                    }
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    if constexpr (sizeof(T) == 8)
-                        pair_f64(x0, x1, x2, gb[b], reinterpret_cast<const double *>(wb[b]), u0, u1, u2);
-                    else
-                        pair_mixed(x0, x1, x2, gb[b], reinterpret_cast<const float *>(wb[b]), u0, u1, u2);
-                }
-            }
-            for (; j < s + n; ++j) {
-                double gc[6];
-                T wc[6];
-#pragma unroll
-                for (int q = 0; q < 6; ++q) {
-                    gc[q] = geo[6 * int64_t(j) + q];
-                    wc[q] = wts[6 * int64_t(j) + q];
-                }
-                if constexpr (sizeof(T) == 8)
-                    pair_f64(x0, x1, x2, gc, reinterpret_cast<const double *>(wc), u0, u1, u2);
-                else
-                    pair_mixed(x0, x1, x2, gc, reinterpret_cast<const float *>(wc), u0, u1, u2);
-            }
-            acc[0].add(u0);
-            acc[1].add(u1);
-            acc[2].add(u2);
-        }
-    }
-    if (valid) {
-        a.unear[3 * t] = acc[0].value();
-        a.unear[3 * t + 1] = acc[1].value();
-        a.unear[3 * t + 2] = acc[2].value();
-    }
-}
-
 // ---- target preparation --------------------------------------------------------------
 __device__ inline uint64_t spread3(uint64_t v) {
     v &= 0x1fffffull;
@@ -404,8 +286,8 @@ void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, dou
     STK_CHECK_LAUNCH();
     int32_t *foff = reserve<int32_t>(pl.far_off, size_t(ng) + 1);
     int32_t *noff = reserve<int32_t>(pl.near_off, size_t(ng) + 1);
-    scan_exclusive_i32(ta.gfar, foff, ng, s);
-    scan_exclusive_i32(ta.gnear, noff, ng, s);
+    scan_exclusive_i32(ta.gfar, foff, ng, t.s_scan, s);
+    scan_exclusive_i32(ta.gnear, noff, ng, t.s_scan, s);
     int32_t tot[2];
     STK_HIP(hipMemcpyAsync(&tot[0], foff + ng, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     STK_HIP(hipMemcpyAsync(&tot[1], noff + ng, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -420,25 +302,17 @@ void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, dou
     ta.near_mask = reserve<uint64_t>(pl.near_mask, size_t(tot[1]) + 1);
     hipLaunchKernelGGL(k_traverse<true>, dim3(ng), dim3(64), 0, s, ta);
     STK_CHECK_LAUNCH();
-    prof_mark(STK_PHASE_LISTS, s);
 
-    // near field, then far field (which adds the near part and un-permutes)
+    // near field (its leaf-major lists close the lists phase), then far field (which adds
+    // the near part and un-permutes)
     double *unear = reserve<double>(t.s_tmp, size_t(m) * 3);
-    NearArgs na{tpos, m, noff, ta.near_node, ta.near_mask, t.nstart.as<int32_t>(), t.ncount.as<int32_t>(),
-                t.geo.as<double>(), t.wts.p, unear};
+    near_field(t, pl, unear, s);
     FarArgs fa{tpos, m, foff, ta.far_node, ta.far_mask, t.ncenter.as<double>(), t.nrho.as<double>(), t.wblk.p,
                unear, tperm, u_out, ng};
-    if (t.prec == STK_FP64) {
-        hipLaunchKernelGGL(k_near<double>, dim3(xcd_blocks(ng)), dim3(64), 0, s, na);
-        STK_CHECK_LAUNCH();
-        prof_mark(STK_PHASE_NEAR, s);
+    if (t.prec == STK_FP64)
         dispatch_far<double>(t.p, fa, s);
-    } else {
-        hipLaunchKernelGGL(k_near<float>, dim3(xcd_blocks(ng)), dim3(64), 0, s, na);
-        STK_CHECK_LAUNCH();
-        prof_mark(STK_PHASE_NEAR, s);
+    else
         dispatch_far<float>(t.p, fa, s);
-    }
     prof_mark(STK_PHASE_FAR, s);
 }
 

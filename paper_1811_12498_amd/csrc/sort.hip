@@ -95,12 +95,11 @@ __global__ __launch_bounds__(ST) void k_scatter(const uint64_t *__restrict__ kin
 // Exclusive scan of in[0..n) into out[0..n) by one block of NT threads, tiles of 4 NT
 // elements (each thread 4 consecutive), carrying the running total; returns the total.
 template <int NT>
-__device__ int32_t block_scan_excl(const int32_t *in, int32_t *out, int64_t n) {  // in may equal out
+__device__ int32_t block_scan_excl(const int32_t *in, int32_t *out, int64_t n, int32_t carry = 0) {  // in may equal out
     constexpr int NW = NT / 64;
     __shared__ int32_t wsum[NW];
     __shared__ int32_t tile_total;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    int32_t carry = 0;
     for (int64_t base = 0; base < n; base += int64_t(NT) * 4) {
         const int64_t i0 = base + int64_t(tid) * 4;
         int32_t v[4];
@@ -145,6 +144,37 @@ __global__ __launch_bounds__(SCAN_T) void k_scan(const int32_t *__restrict__ in,
     if (threadIdx.x == 0) out[n] = tot;
 }
 
+// device-wide scan for long inputs: tile sums, a single-block scan of them, then each
+// tile scanned from its offset
+constexpr int STILE_T = 256;
+constexpr int STILE = 4 * STILE_T;
+
+__global__ __launch_bounds__(STILE_T) void k_tile_sums(const int32_t *__restrict__ in, int64_t n,
+                                                       int32_t *__restrict__ sums) {
+    __shared__ int32_t ws[STILE_T / 64];
+    const int64_t base = int64_t(blockIdx.x) * STILE + int64_t(threadIdx.x) * 4;
+    int32_t v = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if (base + j < n) v += in[base + j];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t tot = 0;
+        for (int w = 0; w < STILE_T / 64; ++w) tot += ws[w];
+        sums[blockIdx.x] = tot;
+    }
+}
+
+__global__ __launch_bounds__(STILE_T) void k_tile_scan(const int32_t *__restrict__ in, int64_t n,
+                                                       const int32_t *__restrict__ offs, int32_t *__restrict__ out) {
+    const int64_t base = int64_t(blockIdx.x) * STILE;
+    const int64_t len = n - base < STILE ? n - base : STILE;
+    block_scan_excl<STILE_T>(in + base, out + base, len, offs[blockIdx.x]);
+}
+
 // radix histogram table hist[digit * ntiles + tile]: block d scans row d in place and
 // writes the row total
 __global__ __launch_bounds__(256) void k_scan_rows(int32_t *__restrict__ hist, int32_t ntiles,
@@ -173,9 +203,22 @@ __global__ __launch_bounds__(RADIX) void k_scan_digits(int32_t *__restrict__ tot
 
 }  // namespace
 
-void scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(SCAN_T), 0, s, in, out, n);
+void scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, DBuf &scratch, hipStream_t s) {
+    if (n <= 16 * 4 * SCAN_T) {
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(SCAN_T), 0, s, in, out, n);
+        STK_CHECK_LAUNCH();
+        return;
+    }
+    const int64_t ntiles = (n + STILE - 1) / STILE;
+    int32_t *sums = reserve<int32_t>(scratch, size_t(2 * ntiles + 1));
+    int32_t *offs = sums + ntiles;
+    hipLaunchKernelGGL(k_tile_sums, dim3(unsigned(ntiles)), dim3(STILE_T), 0, s, in, n, sums);
     STK_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(SCAN_T), 0, s, sums, offs, ntiles);  // offs[ntiles] = total
+    STK_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_tile_scan, dim3(unsigned(ntiles)), dim3(STILE_T), 0, s, in, n, offs, out);
+    STK_CHECK_LAUNCH();
+    STK_HIP(hipMemcpyAsync(out + n, offs + ntiles, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
 }
 
 void radix_sort_pairs(Tree &t, uint64_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t s) {

@@ -103,6 +103,7 @@ struct Tree {
 
     // reusable scratch for evaluation
     DBuf s_keys, s_vals, s_keys2, s_vals2, s_hist, s_tmp;
+    DBuf s_scan;                   // tile sums of scan_exclusive_i32
 };
 
 // lists re-sorted by node (cluster-major / leaf-major) and their work items
@@ -133,6 +134,20 @@ struct Plan {
     DBuf far_mask, near_mask;      // uint64 entries (lane masks of the 64-target group)
     DBuf cnt_far, cnt_near, cnt_pairs;  // int32 per sorted target
     int64_t n_far_entries = 0, n_near_entries = 0;
+    // leaf-major near field, built from the group-major near lists: incidences (one per
+    // (target, near leaf)) sorted by leaf, work items of up to 64 incidences of one leaf,
+    // and per target the slots of its incidences in the order of its near list
+    DBuf nl_keys, nl_ent;          // uint64 / int32 (near entries): entries sorted by leaf
+    DBuf nl_pc, nl_pos;            // int32: popcount of each sorted entry; sorted position of each entry
+    DBuf nl_incoff;                // int32 (near entries + 1): first incidence of each sorted entry
+    DBuf nl_eoff, nl_loff;         // int32 (nn + 1): first sorted entry / first incidence of each leaf
+    DBuf nl_icnt, nl_ioff;         // int32: items per leaf (nn), their offsets (nn + 1)
+    DBuf near_toff;                // int32 (m + 1): first slot of each sorted target
+    DBuf inc_tgt, inc_slot;        // int32 (incidences): sorted target and slot of each incidence
+    DBuf item_leaf, item_i0, item_i1;  // int32 (items)
+    DBuf near_part;                // T (incidences, 3): per (target, leaf) partial velocities
+    int64_t n_inc = 0;
+    int32_t n_near_items = 0;
     AdjScratch adj;
     ~Plan();
 };
@@ -146,8 +161,9 @@ constexpr int CHUNK = 512;   // particles per reduction work item
 // radix sort of (uint64 key, int32 value) pairs; sorts keys[0..n) in place using
 // scratch buffers owned by `t`.  Stable.  `bits` = number of low key bits to sort.
 void radix_sort_pairs(Tree &t, uint64_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t s);
-// exclusive scan of int32 in[0..n) into out[0..n]; out[n] = total.  Single block.
-void scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t s);
+// exclusive scan of int32 in[0..n) into out[0..n]; out[n] = total.  Long inputs use
+// `scratch` for per-tile sums (in and out must not overlap).
+void scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, DBuf &scratch, hipStream_t s);
 
 void build_tree(Tree &t, const double *src, int64_t n, int32_t n0, hipStream_t s);
 void compute_moments(Tree &t, const double *f, const double *h, const double *nu, int32_t k, int32_t p,
@@ -160,6 +176,8 @@ void evaluate(Tree &t, Plan &plan, const double *tgt, int64_t m, double theta, d
 // NULL); w and the outputs in the caller's orders
 void adjoint(Plan &plan, const double *w, double *grad_f, double *grad_h, double *grad_targets,
              double *grad_sources, hipStream_t s);
+// near field of a plan whose group-major near lists are filled: unear (m,3), sorted order
+void near_field(Tree &t, Plan &plan, double *unear, hipStream_t s);
 void direct_sum(const double *tgt, int64_t m, const double *src, int64_t n, const double *f, const double *h,
                 const double *nu, int32_t k, double *u_out, hipStream_t s);
 

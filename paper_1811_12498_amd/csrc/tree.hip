@@ -358,7 +358,7 @@ void build_tree(Tree &t, const double *src, int64_t n, int32_t n0, hipStream_t s
         hipLaunchKernelGGL(k_split_count, dim3(nblk(nlev, BT)), dim3(BT), 0, s, keys, t.nstart.as<int32_t>(),
                            t.ncount.as<int32_t>(), lb, nlev, 3 * (STK_MAX_LEVEL - 1 - lev), n0, nch, bnd);
         STK_CHECK_LAUNCH();
-        scan_exclusive_i32(nch, choff, nlev, s);
+        scan_exclusive_i32(nch, choff, nlev, t.s_scan, s);
         int32_t total = 0;
         STK_HIP(hipMemcpyAsync(&total, choff + nlev, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         STK_HIP(hipStreamSynchronize(s));
@@ -403,7 +403,7 @@ void build_tree(Tree &t, const double *src, int64_t n, int32_t n0, hipStream_t s
     int32_t *coff = reserve<int32_t>(t.chunk_off, size_t(nnodes) + 1);
     hipLaunchKernelGGL(k_chunk_count, dim3(nblk(nnodes, BT)), dim3(BT), 0, s, t.ncount.as<int32_t>(), nnodes, cnt);
     STK_CHECK_LAUNCH();
-    scan_exclusive_i32(cnt, coff, nnodes, s);
+    scan_exclusive_i32(cnt, coff, nnodes, t.s_scan, s);
     STK_HIP(hipMemcpyAsync(&t.nchunks, coff + nnodes, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     double *rad = reserve<double>(t.nradius, size_t(nnodes));
     double *rho = reserve<double>(t.nrho, size_t(nnodes));

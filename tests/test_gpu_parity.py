@@ -123,6 +123,57 @@ def test_treecode_fp64_matches_oracle(nat, orc, kind, n, seed, n0, p, theta, how
     assert orc.rel_l2(u.cpu().numpy(), ref.u) < 1e-12
 
 
+def _per_target(lists, m):
+    """Expand group lists (entries with 64-bit lane masks) into per-target sorted node arrays."""
+    off, node, mask, tperm = lists["off"], lists["node"], lists["mask"], lists["tperm"]
+    grp = np.repeat(np.arange(len(off) - 1), np.diff(off))
+    bits = ((mask[:, None] >> np.arange(64, dtype=np.uint64)[None, :]) & np.uint64(1)).astype(bool)
+    e_idx, lane = np.nonzero(bits)
+    sorted_t = grp[e_idx].astype(np.int64) * 64 + lane
+    assert np.all(sorted_t < m)
+    tgt = tperm[sorted_t]
+    order = np.lexsort((node[e_idx], tgt))
+    return tgt[order], node[e_idx][order]
+
+
+@pytest.mark.parametrize("kind,n,seed,n0,p,theta,how", [TC_CASES[i] for i in (0, 2, 4, 6)])
+def test_interaction_lists_match_oracle(nat, orc, kind, n, seed, n0, p, theta, how):
+    """Alg. 1: every target's far clusters and near leaves are the oracle's, as sets."""
+    w = _case(kind, n, seed, n0)
+    tg = _targets(w, how)
+    T = orc.build_tree(w.src, n0)
+    L = orc.lists(T, theta, tg)
+    _, plan = nat.evaluate(_t(tg), _t(w.src), _t(w.f[0]), _t(w.h[0]), _t(w.nu), p, theta, n0, "fp64",
+                           keep_plan=True)
+    m = tg.shape[0]
+    for kind_, ptr, nodes in (("far", L.far_ptr, L.far_nodes), ("near", L.near_ptr, L.near_nodes)):
+        t_gpu, n_gpu = _per_target(nat.plan_lists(plan, kind_), m)
+        t_ref = np.repeat(np.arange(m), np.diff(ptr))
+        n_ref = nodes[: int(ptr[-1])]
+        order = np.lexsort((n_ref, t_ref))
+        assert np.array_equal(t_gpu, t_ref[order]), kind_
+        assert np.array_equal(n_gpu, n_ref[order]), kind_
+
+
+def test_large_plan_matches_oracle(nat, orc):
+    """150,000 targets (= sources) with small leaves: the device-wide scans of the list
+    build take their multi-tile path (more than 65,536 entries); counts, lists and the
+    FP64 result still match the oracle."""
+    w = W.cube(150_000, seed=10, n0=64)
+    p, theta = 3, 0.5
+    ref = _oracle_tc(orc, w, p, theta, w.src)
+    u, plan = nat.evaluate(_t(w.src), _t(w.src), _t(w.f[0]), _t(w.h[0]), _t(w.nu), p, theta, 64, "fp64",
+                           keep_plan=True)
+    nf, nn, npair = nat.plan_counts(plan)
+    assert np.array_equal(nf, ref.nfar)
+    assert np.array_equal(nn, ref.nnear)
+    assert np.array_equal(npair, ref.npairs)
+    assert nat.plan_info(plan)["near_entries"] > 65536
+    t_gpu, n_gpu = _per_target(nat.plan_lists(plan, "near"), w.n)
+    assert np.array_equal(np.bincount(t_gpu, minlength=w.n), ref.nnear)
+    assert orc.rel_l2(u.cpu().numpy(), ref.u) < 1e-12
+
+
 @pytest.mark.parametrize("kind,n,seed,n0,p,theta,how", TC_CASES[:6])
 def test_treecode_mixed_close_to_fp64(nat, orc, kind, n, seed, n0, p, theta, how):
     w = _case(kind, n, seed, n0)
