@@ -103,7 +103,9 @@ stk_status stk_compute_moments(stk_tree *t, const double *f, const double *h, co
  *   targets  device (m,3), m >= 1; may or may not coincide with the sources.
  *   theta    MAC parameter, 0 <= theta < 1: a node is used through its Taylor
  *            expansion iff R > 0 and r <= theta * R (R = |x - y_c|).
- *   u_out    device (K,m,3), overwritten.
+ *   u_out    device (K,m,3), overwritten (K = the k_rhs of the moments).  The K
+ *            right-hand sides share the tree, the interaction lists and, for each
+ *            target-cluster pair, the Taylor coefficients of recurrence_1.
  *   keep_plan  if non-NULL, receives a plan holding the targets' interaction
  *            lists (for stk_evaluate_adjoint and stk_plan_counts); it refers to
  *            `t`, which must outlive it.

@@ -145,14 +145,19 @@ def compute_moments(tree: Tree, f: torch.Tensor, h: torch.Tensor, nu: torch.Tens
     k = f.shape[0] if f.dim() == 3 else 1
     _check(_lib.stk_compute_moments(tree.handle, _ptr(f), _ptr(h), _ptr(nu), k, int(p), _prec(precision),
                                     _stream()))
+    tree.k_rhs = k
 
 
 def evaluate_tree(tree: Tree, targets: torch.Tensor, theta: float, keep_plan: bool = False,
                   out: torch.Tensor | None = None):
     _dev(targets, "targets")
     m = targets.shape[0]
-    u = out if out is not None else torch.empty((m, 3), dtype=torch.float64, device=targets.device)
+    k = getattr(tree, "k_rhs", 1)
+    shape = (m, 3) if k == 1 else (k, m, 3)
+    u = out if out is not None else torch.empty(shape, dtype=torch.float64, device=targets.device)
     _dev(u, "out")
+    if u.numel() != k * m * 3:
+        raise ValueError(f"out must hold {k} x {m} x 3 values")
     ph = ctypes.c_void_p()
     _check(_lib.stk_evaluate_tree(tree.handle, _ptr(targets), m, float(theta), _ptr(u),
                                   ctypes.byref(ph) if keep_plan else None, _stream()))

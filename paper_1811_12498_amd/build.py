@@ -8,9 +8,12 @@ from __future__ import annotations
 
 import concurrent.futures as cf
 import glob
+import json
 import os
+import re
 import subprocess
 import sys
+import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -24,23 +27,44 @@ FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Xclang", "-ta
          "-packed-fp32-ops", "-I", CSRC, "-I", os.path.join(ROOT, "include"), "-Wno-unused-result"]
 
 
-def _compile(src: str) -> str:
+TIMES = os.path.join(ROOT, "_build", "compile_seconds.json")
+
+
+def _compile(src: str) -> tuple[str, float]:
     obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
     cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    t0 = time.perf_counter()
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr[-4000:]}")
-    return obj
+    return obj, time.perf_counter() - t0
+
+
+def _order_key(path: str, times: dict) -> tuple:
+    """Longest compile first (last build's times; else the Taylor order in the name)."""
+    name = os.path.basename(path)
+    if name in times:
+        return (-times[name], name)
+    m = re.search(r"_p(\d+)\.hip$", name)
+    return (-(1000 + int(m.group(1))) if m else 0.0, name)
 
 
 def build(jobs: int | None = None, verbose: bool = False) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
-    # the far-field orders dominate compile time: start them first
-    srcs.sort(key=lambda p: (0 if "far_p" in p else 1, p))
+    srcs = glob.glob(os.path.join(CSRC, "*.hip"))
+    try:
+        with open(TIMES) as fh:
+            times = json.load(fh)
+    except (OSError, ValueError):
+        times = {}
+    srcs.sort(key=lambda p: _order_key(p, times))
     jobs = jobs or min(16, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        res = list(ex.map(_compile, srcs))
+    objs = [o for o, _ in res]
+    times.update({os.path.basename(sp): round(dt, 1) for sp, (_, dt) in zip(srcs, res)})
+    with open(TIMES, "w") as fh:
+        json.dump(times, fh, indent=0, sort_keys=True)
     tmp = OUT + f".tmp{os.getpid()}"
     r = subprocess.run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs],
                        capture_output=True, text=True)

@@ -1,9 +1,9 @@
-// Far-field adjoint kernels for Taylor order p = 1 (both precisions).
-#include "adjoint_far.hpp"
+// Far-field adjoint for Taylor order p = 1: cluster stream adjoints (both precisions) and
+// the per-source gradients from the moment adjoints.
+#include "adjoint_far_impl.hpp"
 
 namespace stk {
 template void launch_far_lambda<1, float>(const LambdaArgs &, hipStream_t);
 template void launch_far_lambda<1, double>(const LambdaArgs &, hipStream_t);
-template void launch_far_tgrad<1, float>(const TgradArgs &, hipStream_t);
-template void launch_far_tgrad<1, double>(const TgradArgs &, hipStream_t);
+template void launch_src_grad<1>(const SrcGradArgs &, int32_t, hipStream_t);
 }  // namespace stk

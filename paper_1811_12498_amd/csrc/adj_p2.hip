@@ -1,9 +1,9 @@
-// Far-field adjoint kernels for Taylor order p = 2 (both precisions).
-#include "adjoint_far.hpp"
+// Far-field adjoint for Taylor order p = 2: cluster stream adjoints (both precisions) and
+// the per-source gradients from the moment adjoints.
+#include "adjoint_far_impl.hpp"
 
 namespace stk {
 template void launch_far_lambda<2, float>(const LambdaArgs &, hipStream_t);
 template void launch_far_lambda<2, double>(const LambdaArgs &, hipStream_t);
-template void launch_far_tgrad<2, float>(const TgradArgs &, hipStream_t);
-template void launch_far_tgrad<2, double>(const TgradArgs &, hipStream_t);
+template void launch_src_grad<2>(const SrcGradArgs &, int32_t, hipStream_t);
 }  // namespace stk

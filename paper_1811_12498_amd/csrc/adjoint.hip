@@ -23,8 +23,6 @@
 
 namespace stk {
 
-template <int P, typename T> void launch_far_lambda(const LambdaArgs &, hipStream_t);
-template <int P, typename T> void launch_far_tgrad(const TgradArgs &, hipStream_t);
 
 namespace {
 
@@ -315,94 +313,6 @@ __global__ __launch_bounds__(256) void k_phi_adj(const double *__restrict__ lamb
         }
         lm[size_t(node) * nm * 12 + col] = s;
     }
-}
-
-// ---- far source gradients from the moment adjoints ---------------------------------------
-template <int P> struct SrcGrad {
-    static constexpr int NM = nidx(P);
-    // accumulate over every k of order <= P (compile-time walk in graded-lex order)
-    template <int A>
-    STK_HD static void walk(const double (&px)[P + 1], const double (&py)[P + 1], const double (&pz)[P + 1],
-                            const double *__restrict__ L, const double f[3], const double hn[9], const double nu[3],
-                            double gf[3], double gh[3], double gy[3]) {
-        if constexpr (A < NM) {
-            constexpr int K1 = kof1c(A), K2 = kof2c(A), K3 = ordc(A) - K1 - K2;
-            const double *La = L + A * 12;
-            const double mono = px[K1] * py[K2] * pz[K3];
-            double pf = 0.0;
-            for (int j = 0; j < 3; ++j) {
-                gf[j] += mono * La[j];
-                const double hl = nu[0] * La[3 + 3 * j] + nu[1] * La[4 + 3 * j] + nu[2] * La[5 + 3 * j];
-                gh[j] += mono * hl;
-                pf += f[j] * La[j];
-            }
-            for (int q = 0; q < 9; ++q) pf += hn[q] * La[3 + q];
-            if constexpr (K1 > 0) gy[0] += double(K1) * (px[K1 - 1] * py[K2] * pz[K3]) * pf;
-            if constexpr (K2 > 0) gy[1] += double(K2) * (px[K1] * py[K2 - 1] * pz[K3]) * pf;
-            if constexpr (K3 > 0) gy[2] += double(K3) * (px[K1] * py[K2] * pz[K3 - 1]) * pf;
-            walk<A + 1>(px, py, pz, L, f, hn, nu, gf, gh, gy);
-        }
-    }
-};
-
-struct SrcGradArgs {
-    const double *pos, *geo, *w12, *center, *lm;
-    const int32_t *start, *count, *coff, *level;
-    int32_t nn;
-    int64_t n;
-    double *part;  // (nlevels, n, 9)
-};
-
-__device__ inline int32_t node_of_item(const int32_t *__restrict__ off, int32_t nn, int32_t ch) {
-    int32_t lo = 0, hi = nn;
-    while (hi - lo > 1) {
-        const int32_t m = (lo + hi) >> 1;
-        if (off[m] <= ch)
-            lo = m;
-        else
-            hi = m;
-    }
-    return lo;
-}
-
-template <int P> __global__ __launch_bounds__(256) void k_src_grad(SrcGradArgs a) {
-    const int32_t ch = blockIdx.x;
-    const int32_t node = node_of_item(a.coff, a.nn, ch);
-    const int32_t first = a.start[node] + (ch - a.coff[node]) * CHUNK;
-    const int32_t last = min(a.start[node] + a.count[node], first + CHUNK);
-    const double *L = a.lm + size_t(node) * nidx(P) * 12;
-    const int lev = a.level[node];
-    for (int32_t j = first + threadIdx.x; j < last; j += 256) {
-        double px[P + 1], py[P + 1], pz[P + 1];
-        const double dx = a.pos[3 * int64_t(j)] - a.center[3 * node];
-        const double dy = a.pos[3 * int64_t(j) + 1] - a.center[3 * node + 1];
-        const double dz = a.pos[3 * int64_t(j) + 2] - a.center[3 * node + 2];
-        px[0] = py[0] = pz[0] = 1.0;
-#pragma unroll
-        for (int e = 1; e <= P; ++e) {
-            px[e] = px[e - 1] * dx;
-            py[e] = py[e - 1] * dy;
-            pz[e] = pz[e - 1] * dz;
-        }
-        const double *wr = a.w12 + 12 * int64_t(j);
-        const double f[3] = {wr[0], wr[1], wr[2]};
-        double hn[9];
-        for (int q = 0; q < 9; ++q) hn[q] = wr[3 + q];
-        const double nu[3] = {a.geo[6 * int64_t(j) + 3], a.geo[6 * int64_t(j) + 4], a.geo[6 * int64_t(j) + 5]};
-        double gf[3] = {0, 0, 0}, gh[3] = {0, 0, 0}, gy[3] = {0, 0, 0};
-        SrcGrad<P>::template walk<0>(px, py, pz, L, f, hn, nu, gf, gh, gy);
-        double *o = a.part + (size_t(lev) * a.n + j) * 9;
-        for (int q = 0; q < 3; ++q) {
-            o[q] = gf[q];
-            o[3 + q] = gh[q];
-            o[6 + q] = gy[q];
-        }
-    }
-}
-
-template <int P> void launch_src_grad(const SrcGradArgs &a, int32_t nitems, hipStream_t s) {
-    hipLaunchKernelGGL((k_src_grad<P>), dim3(nitems), dim3(256), 0, s, a);
-    STK_CHECK_LAUNCH();
 }
 
 // ---- totals, back to caller order --------------------------------------------------------

@@ -1,0 +1,377 @@
+// Far-field adjoint kernel bodies (instantiated per Taylor order in adj_p*.hip and
+// adjt_p*.hip); the operator they apply is described in adjoint_far.hpp.
+#pragma once
+
+#include "adjoint_far.hpp"
+
+namespace stk {
+
+// ---------------------------------------------------------------------------------
+// coefficients bt^q of one (target, cluster) pair up to order PB in registers: the
+// scaled recurrence_1 for layers k3 <= 1 and the harmonic fill for k3 >= 2 (the same
+// arithmetic as FarEval), calling Visit::coef<Q, N>(bq) as each coefficient is formed
+// and Visit::order_done<N>(b) after each order
+// ---------------------------------------------------------------------------------
+template <int PB, typename T, class Visit> struct Coefs {
+    static constexpr int NB = nidx(PB);
+
+    template <int N, int K3, int K1> STK_HD static void layer(T (&b)[NB], const T dh[3], T c1, T c2, Visit &v) {
+        constexpr int K2 = N - K3 - K1;
+        constexpr int Q = gidx(K1, K2, K3);
+        if constexpr (K3 <= 1) {
+            T s1 = T(0), s2 = T(0);
+            if constexpr (K1 > 0) s1 += dh[0] * b[gidx(K1 - 1, K2, K3)];
+            if constexpr (K2 > 0) s1 += dh[1] * b[gidx(K1, K2 - 1, K3)];
+            if constexpr (K3 > 0) s1 += dh[2] * b[gidx(K1, K2, K3 - 1)];
+            if constexpr (K1 > 1) s2 += b[gidx(K1 - 2, K2, K3)];
+            if constexpr (K2 > 1) s2 += b[gidx(K1, K2 - 2, K3)];
+            if constexpr (N > 1)
+                b[Q] = c1 * s1 - c2 * s2;
+            else
+                b[Q] = c1 * s1;
+        } else {
+            constexpr double den = double(K3 * (K3 - 1));
+            constexpr double ca = -double((K1 + 1) * (K1 + 2)) / den;
+            constexpr double cb = -double((K2 + 1) * (K2 + 2)) / den;
+            b[Q] = T(ca) * b[gidx(K1 + 2, K2, K3 - 2)] + T(cb) * b[gidx(K1, K2 + 2, K3 - 2)];
+        }
+        v.template coef<Q, N>(b[Q]);
+        if constexpr (K1 > 0) layer<N, K3, K1 - 1>(b, dh, c1, c2, v);
+    }
+
+    template <int N, int J> STK_HD static void layers(T (&b)[NB], const T dh[3], T c1, T c2, Visit &v) {
+        if constexpr (J <= N) {
+            layer<N, J, N - J>(b, dh, c1, c2, v);
+            layers<N, J + 1>(b, dh, c1, c2, v);
+        }
+    }
+
+    template <int N> STK_HD static void order(T (&b)[NB], const T dh[3], T t, Visit &v) {
+        const T c1 = T(2 * N - 1) / T(N) * t;
+        const T c2 = T(N - 1) / T(N) * (t * t);
+        layers<N, 0>(b, dh, c1, c2, v);
+        v.template order_done<N>(b);
+        if constexpr (N < PB) order<N + 1>(b, dh, t, v);
+    }
+
+    STK_HD static void run(T (&b)[NB], const T dh[3], T t, Visit &v) {
+        b[0] = T(1);
+        v.template coef<0, 0>(b[0]);
+        v.template order_done<0>(b);
+        order<1>(b, dh, t, v);
+    }
+};
+
+template <int P, typename T> struct LambdaVisit {
+    T *cols;       // [col][LPITCH]
+    const T *cw;   // [3][64] w_i / R per target (0 for lanes outside the mask)
+    const T *dw;   // [3][64] dh_l per target (0 outside the mask)
+    double *acc;   // [6 nG] LDS accumulator in stream order
+    const int32_t *colpos;
+    T wl[3];       // this lane's w
+    int lane;
+
+    template <int Q, int N> STK_HD void coef(T bq) {
+        if constexpr (N <= P + 1) cols[(Q - (N > 0 ? nidx(N - 1) : 0)) * LPITCH + lane] = bq;
+    }
+
+    // reduce columns [0, nc) of the LDS table over the 64 targets with weights wt
+    STK_HD void reduce(int nc, const T *wt, const int32_t *pos) {
+        __syncthreads();
+        for (int col = lane; col < nc; col += 64) {
+            T a0 = T(0), a1 = T(0), a2 = T(0);
+            const T *row = cols + col * LPITCH;
+#pragma unroll 4
+            for (int mm = 0; mm < 64; ++mm) {
+                const T v = row[mm];
+                a0 += wt[mm] * v;
+                a1 += wt[64 + mm] * v;
+                a2 += wt[128 + mm] * v;
+            }
+            const int p0 = pos[col];
+            acc[p0] += double(a0);
+            acc[p0 + 1] += double(a1);
+            acc[p0 + 2] += double(a2);
+        }
+        __syncthreads();
+    }
+
+    template <int N> STK_HD void order_done(const T (&b)[nidx(P + 2)]) {
+        // G columns of order N (already written by coef)
+        if constexpr (N <= P + 1) reduce(lam_ncol_g<P>(N), cw, colpos + (2 * N) * LAM_ROW);
+        // E columns: zh^k for k of order N - 1
+        if constexpr (N >= 1) {
+            constexpr int M = N - 1;
+            ecol<N, M, 0>(b);
+            reduce(lam_ncol_e<P>(N), dw, colpos + (2 * N + 1) * LAM_ROW);
+        }
+    }
+
+    // zh^k = sum_i w_i (k_i+1) bt^{k+e_i} for every k of order M, in graded-lex order
+    template <int N, int M, int A> STK_HD void ecol(const T (&b)[nidx(P + 2)]) {
+        if constexpr (A < (M + 1) * (M + 2) / 2) {
+            constexpr int Q = (M > 0 ? nidx(M - 1) : 0) + A;
+            constexpr int K1 = kof1c(Q), K2 = kof2c(Q), K3 = M - K1 - K2;
+            const T z = wl[0] * (T(K1 + 1) * b[gidx(K1 + 1, K2, K3)]) + wl[1] * (T(K2 + 1) * b[gidx(K1, K2 + 1, K3)]) +
+                        wl[2] * (T(K3 + 1) * b[gidx(K1, K2, K3 + 1)]);
+            cols[A * LPITCH + lane] = z;
+            ecol<N, M, A + 1>(b);
+        }
+    }
+
+};
+
+template <int P, typename T> __global__ __launch_bounds__(64) void k_far_lambda(LambdaArgs a) {
+    constexpr int NG = nidx(P + 1);
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    double *acc = reinterpret_cast<double *>(lds_raw);
+    T *cols = reinterpret_cast<T *>(acc + 6 * NG);
+    T *cw = cols + lam_maxcol<P>() * LPITCH;
+    T *dw = cw + 192;
+    const int lane = threadIdx.x;
+    const int32_t it = blockIdx.x;
+    if (it >= a.nitems) return;
+    const int32_t c = a.item_node[it];
+    for (int q = lane; q < 6 * NG; q += 64) acc[q] = 0.0;
+    const double c0 = a.center[3 * c], c1 = a.center[3 * c + 1], c2 = a.center[3 * c + 2];
+    const double rho = a.rho[c];
+    for (int32_t e = a.item_e0[it]; e < a.item_e1[it]; ++e) {
+        const int32_t ent = a.ent[e];
+        const int32_t g = a.ent_group[ent];
+        const uint64_t mk = a.mask[ent];
+        const int64_t t = int64_t(g) * 64 + lane;
+        const bool in = ((mk >> lane) & 1ull) && t < a.m;
+        T dh[3] = {T(1), T(0), T(0)}, tt = T(0), wl[3] = {T(0), T(0), T(0)}, ri = T(0);
+        if (in) {
+            const double d0 = a.tpos[3 * t] - c0, d1 = a.tpos[3 * t + 1] - c1, d2 = a.tpos[3 * t + 2] - c2;
+            const double rinv = 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            dh[0] = T(d0 * rinv);
+            dh[1] = T(d1 * rinv);
+            dh[2] = T(d2 * rinv);
+            tt = T(rho * rinv);
+            ri = T(rinv);
+            wl[0] = T(a.ws[3 * t]);
+            wl[1] = T(a.ws[3 * t + 1]);
+            wl[2] = T(a.ws[3 * t + 2]);
+        }
+        __syncthreads();
+        for (int i = 0; i < 3; ++i) {
+            cw[64 * i + lane] = wl[i] * ri;
+            dw[64 * i + lane] = in ? dh[i] : T(0);
+        }
+        LambdaVisit<P, T> v{cols, cw, dw, acc, a.colpos, {wl[0], wl[1], wl[2]}, lane};
+        T b[nidx(P + 2)];
+        Coefs<P + 2, T, LambdaVisit<P, T>>::run(b, dh, tt, v);
+    }
+    __syncthreads();
+    double *out = a.lambda + size_t(c) * 6 * NG;
+    for (int q = lane; q < 6 * NG; q += 64) atomicAdd(out + q, acc[q]);
+}
+
+template <int P, typename T> struct TgradVisit {
+    const T *W;   // cluster stream
+    T dh[3], wl[3];
+    T a1[3], a2[3], a3[3];
+
+    template <int Q, int N> STK_HD void coef(T) {}
+
+    // at order N (coefficients 0..N exist):
+    //  term 1 for q of order N-1 (<= P+1): (w.Ghat^q) (q_s+1) bt^{q+e_s}
+    //  term 3 for k of order N-1 (<= P+1): Ehat_s^k zh^k
+    //  term 2 for k of order N-2 (<= P+1): (dh.Ehat^k) sum_i w_i (k_i+1)(k_s+1+delta_is) bt^{k+e_i+e_s}
+    template <int N> STK_HD void order_done(const T (&b)[nidx(P + 3)]) {
+        // the fence pins this order's scalar loads after the previous order's sums
+        const T *__restrict__ Wf = W + FarEval<P, T>::fence(a1[0] + a2[0] + a3[0]);
+        if constexpr (N >= 1 && N - 1 <= P + 1) walk13<N - 1, 0>(b, Wf);
+        if constexpr (N >= 2 && N - 2 <= P + 1) walk2<N - 2, 0>(b, Wf);
+    }
+
+    template <int M, int A> STK_HD void walk13(const T (&b)[nidx(P + 3)], const T *__restrict__ W) {
+        if constexpr (A < (M + 1) * (M + 2) / 2) {
+            constexpr int Q = (M > 0 ? nidx(M - 1) : 0) + A;
+            constexpr int K1 = kof1c(Q), K2 = kof2c(Q), K3 = M - K1 - K2;
+            constexpr int kk[3] = {K1, K2, K3};
+            int pg = 0, pe = 0;
+            stream_pos_c(kk, pg, pe);
+            const T g = wl[0] * W[pg] + wl[1] * W[pg + 1] + wl[2] * W[pg + 2];
+            const T bx = b[gidx(K1 + 1, K2, K3)], by = b[gidx(K1, K2 + 1, K3)], bz = b[gidx(K1, K2, K3 + 1)];
+            a1[0] += g * (T(K1 + 1) * bx);
+            a1[1] += g * (T(K2 + 1) * by);
+            a1[2] += g * (T(K3 + 1) * bz);
+            const T z = wl[0] * (T(K1 + 1) * bx) + wl[1] * (T(K2 + 1) * by) + wl[2] * (T(K3 + 1) * bz);
+            a3[0] += W[pe] * z;
+            a3[1] += W[pe + 1] * z;
+            a3[2] += W[pe + 2] * z;
+            walk13<M, A + 1>(b, W);
+        }
+    }
+
+    template <int M, int A> STK_HD void walk2(const T (&b)[nidx(P + 3)], const T *__restrict__ W) {
+        if constexpr (A < (M + 1) * (M + 2) / 2) {
+            constexpr int Q = (M > 0 ? nidx(M - 1) : 0) + A;
+            constexpr int K1 = kof1c(Q), K2 = kof2c(Q), K3 = M - K1 - K2;
+            constexpr int kk[3] = {K1, K2, K3};
+            int pg = 0, pe = 0;
+            stream_pos_c(kk, pg, pe);
+            const T sig = dh[0] * W[pe] + dh[1] * W[pe + 1] + dh[2] * W[pe + 2];
+            // h_s = sum_i w_i (k_i+1)(k_s+1+delta_is) bt^{k+e_i+e_s}
+            const T w0 = wl[0] * T(K1 + 1), w1 = wl[1] * T(K2 + 1), w2 = wl[2] * T(K3 + 1);
+            const T hx = w0 * T(K1 + 2) * b[gidx(K1 + 2, K2, K3)] + w1 * T(K1 + 1) * b[gidx(K1 + 1, K2 + 1, K3)] +
+                         w2 * T(K1 + 1) * b[gidx(K1 + 1, K2, K3 + 1)];
+            const T hy = w0 * T(K2 + 1) * b[gidx(K1 + 1, K2 + 1, K3)] + w1 * T(K2 + 2) * b[gidx(K1, K2 + 2, K3)] +
+                         w2 * T(K2 + 1) * b[gidx(K1, K2 + 1, K3 + 1)];
+            const T hz = w0 * T(K3 + 1) * b[gidx(K1 + 1, K2, K3 + 1)] + w1 * T(K3 + 1) * b[gidx(K1, K2 + 1, K3 + 1)] +
+                         w2 * T(K3 + 2) * b[gidx(K1, K2, K3 + 2)];
+            a2[0] += sig * hx;
+            a2[1] += sig * hy;
+            a2[2] += sig * hz;
+            walk2<M, A + 1>(b, W);
+        }
+    }
+
+    STK_HD static constexpr void stream_pos_c(const int (&k)[3], int &g, int &e) {
+        const int n = k[0] + k[1] + k[2], j = k[2], i = (n - j) - k[0];
+        g = n == 0 ? 0 : stream_off(P, n, j) + 3 * i;
+        e = stream_off(P, n + 1, j + 1) + stream_gpart(P, n + 1, j + 1) + 3 * i;
+    }
+};
+
+template <int P, typename T> __global__ __launch_bounds__(64) void k_far_tgrad(TgradArgs a) {
+    constexpr int NG = nidx(P + 1);
+    const int32_t g = xcd_group(a.ngroups);
+    if (g >= a.ngroups) return;
+    const int lane = threadIdx.x;
+    const int64_t t = int64_t(g) * 64 + lane;
+    const bool valid = t < a.m;
+    double x0 = 0, x1 = 0, x2 = 0, w0 = 0, w1 = 0, w2 = 0;
+    if (valid) {
+        x0 = a.tpos[3 * t];
+        x1 = a.tpos[3 * t + 1];
+        x2 = a.tpos[3 * t + 2];
+        w0 = a.ws[3 * t];
+        w1 = a.ws[3 * t + 1];
+        w2 = a.ws[3 * t + 2];
+    }
+    const T *wb = static_cast<const T *>(a.wblk);
+    Comp<T> acc[3];
+    for (int32_t e = a.off[g]; e < a.off[g + 1]; ++e) {
+        const int32_t c = __builtin_amdgcn_readfirstlane(a.node[e]);
+        const uint64_t mk = a.mask[e];
+        if ((mk >> lane) & 1ull) {
+            const double d0 = x0 - a.center[3 * c], d1 = x1 - a.center[3 * c + 1], d2 = x2 - a.center[3 * c + 2];
+            const double rinv = 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            const double rho = a.rho[c];
+            TgradVisit<P, T> v{wb + size_t(c) * 6 * NG,
+                               {T(d0 * rinv), T(d1 * rinv), T(d2 * rinv)},
+                               {T(w0), T(w1), T(w2)},
+                               {T(0), T(0), T(0)},
+                               {T(0), T(0), T(0)},
+                               {T(0), T(0), T(0)}};
+            T b[nidx(P + 3)];
+            Coefs<P + 3, T, TgradVisit<P, T>>::run(b, v.dh, T(rho * rinv), v);
+            const T f1 = T(-rinv / rho), f2 = T(-1.0 / rho), f3 = T(rinv);
+            for (int s = 0; s < 3; ++s) acc[s].add(f1 * v.a1[s] + f2 * v.a2[s] + f3 * v.a3[s]);
+        }
+    }
+    if (valid) {
+        a.gt[3 * t] = acc[0].value();
+        a.gt[3 * t + 1] = acc[1].value();
+        a.gt[3 * t + 2] = acc[2].value();
+    }
+}
+
+template <int P, typename T> void launch_far_lambda(const LambdaArgs &a, hipStream_t s) {
+    if (a.nitems == 0) return;
+    hipLaunchKernelGGL((k_far_lambda<P, T>), dim3(a.nitems), dim3(64), (lam_lds_bytes<P, T>()), s, a);
+    STK_CHECK_LAUNCH();
+}
+
+template <int P, typename T> void launch_far_tgrad(const TgradArgs &a, hipStream_t s) {
+    if (a.ngroups == 0) return;
+    hipLaunchKernelGGL((k_far_tgrad<P, T>), dim3(xcd_blocks(a.ngroups)), dim3(64), 0, s, a);
+    STK_CHECK_LAUNCH();
+}
+
+// ---- far source gradients from the moment adjoints ---------------------------------------
+template <int P> struct SrcGrad {
+    static constexpr int NM = nidx(P);
+    // accumulate over every k of order <= P (compile-time walk in graded-lex order)
+    template <int A>
+    STK_HD static void walk(const double (&px)[P + 1], const double (&py)[P + 1], const double (&pz)[P + 1],
+                            const double *__restrict__ L, const double f[3], const double hn[9], const double nu[3],
+                            double gf[3], double gh[3], double gy[3]) {
+        if constexpr (A < NM) {
+            constexpr int K1 = kof1c(A), K2 = kof2c(A), K3 = ordc(A) - K1 - K2;
+            const double *La = L + A * 12;
+            const double mono = px[K1] * py[K2] * pz[K3];
+            double pf = 0.0;
+            for (int j = 0; j < 3; ++j) {
+                gf[j] += mono * La[j];
+                const double hl = nu[0] * La[3 + 3 * j] + nu[1] * La[4 + 3 * j] + nu[2] * La[5 + 3 * j];
+                gh[j] += mono * hl;
+                pf += f[j] * La[j];
+            }
+            for (int q = 0; q < 9; ++q) pf += hn[q] * La[3 + q];
+            if constexpr (K1 > 0) gy[0] += double(K1) * (px[K1 - 1] * py[K2] * pz[K3]) * pf;
+            if constexpr (K2 > 0) gy[1] += double(K2) * (px[K1] * py[K2 - 1] * pz[K3]) * pf;
+            if constexpr (K3 > 0) gy[2] += double(K3) * (px[K1] * py[K2] * pz[K3 - 1]) * pf;
+            walk<A + 1>(px, py, pz, L, f, hn, nu, gf, gh, gy);
+        }
+    }
+};
+
+
+__device__ inline int32_t node_of_item(const int32_t *__restrict__ off, int32_t nn, int32_t ch) {
+    int32_t lo = 0, hi = nn;
+    while (hi - lo > 1) {
+        const int32_t m = (lo + hi) >> 1;
+        if (off[m] <= ch)
+            lo = m;
+        else
+            hi = m;
+    }
+    return lo;
+}
+
+template <int P> __global__ __launch_bounds__(256) void k_src_grad(SrcGradArgs a) {
+    const int32_t ch = blockIdx.x;
+    const int32_t node = node_of_item(a.coff, a.nn, ch);
+    const int32_t first = a.start[node] + (ch - a.coff[node]) * CHUNK;
+    const int32_t last = min(a.start[node] + a.count[node], first + CHUNK);
+    const double *L = a.lm + size_t(node) * nidx(P) * 12;
+    const int lev = a.level[node];
+    for (int32_t j = first + threadIdx.x; j < last; j += 256) {
+        double px[P + 1], py[P + 1], pz[P + 1];
+        const double dx = a.pos[3 * int64_t(j)] - a.center[3 * node];
+        const double dy = a.pos[3 * int64_t(j) + 1] - a.center[3 * node + 1];
+        const double dz = a.pos[3 * int64_t(j) + 2] - a.center[3 * node + 2];
+        px[0] = py[0] = pz[0] = 1.0;
+#pragma unroll
+        for (int e = 1; e <= P; ++e) {
+            px[e] = px[e - 1] * dx;
+            py[e] = py[e - 1] * dy;
+            pz[e] = pz[e - 1] * dz;
+        }
+        const double *wr = a.w12 + 12 * int64_t(j);
+        const double f[3] = {wr[0], wr[1], wr[2]};
+        double hn[9];
+        for (int q = 0; q < 9; ++q) hn[q] = wr[3 + q];
+        const double nu[3] = {a.geo[6 * int64_t(j) + 3], a.geo[6 * int64_t(j) + 4], a.geo[6 * int64_t(j) + 5]};
+        double gf[3] = {0, 0, 0}, gh[3] = {0, 0, 0}, gy[3] = {0, 0, 0};
+        SrcGrad<P>::template walk<0>(px, py, pz, L, f, hn, nu, gf, gh, gy);
+        double *o = a.part + (size_t(lev) * a.n + j) * 9;
+        for (int q = 0; q < 3; ++q) {
+            o[q] = gf[q];
+            o[3 + q] = gh[q];
+            o[6 + q] = gy[q];
+        }
+    }
+}
+
+template <int P> void launch_src_grad(const SrcGradArgs &a, int32_t nitems, hipStream_t s) {
+    hipLaunchKernelGGL((k_src_grad<P>), dim3(nitems), dim3(256), 0, s, a);
+    STK_CHECK_LAUNCH();
+}
+
+
+}  // namespace stk

@@ -98,7 +98,6 @@ stk_status stk_evaluate_tree(stk_tree *t, const double *targets, int64_t m, doub
         stk::require(u_out != nullptr, "u_out is NULL");
         stk::require(theta >= 0.0 && theta < 1.0, "theta must be in [0, 1)");
         if (!t->t.have_moments) throw stk::Error(STK_ESTATE, "stk_compute_moments has not been called");
-        stk::require(t->t.k_rhs == 1, "more than one right-hand side is not supported by this entry point yet");
         check_device(t->t.device);
         if (keep_plan) *keep_plan = nullptr;
         auto *pl = new stk_plan();
@@ -125,7 +124,7 @@ stk_status stk_evaluate(const double *targets, int64_t m, const double *sources,
         check_common(targets, m, "targets");
         stk::require(f && h && nu && u_out, "f, h, nu and u_out must be non-NULL");
         stk::require(n0 >= 1, "n0 must be >= 1");
-        stk::require(k_rhs == 1, "more than one right-hand side is not supported by this entry point yet");
+        stk::require(k_rhs >= 1 && k_rhs <= 64, "k_rhs must be in [1, 64]");
         stk::require(p >= 0 && p <= STK_P_MAX, "p must be in [0, STK_P_MAX]");
         stk::require(prec == STK_FP64 || prec == STK_MIXED, "unknown precision");
         stk::require(theta >= 0.0 && theta < 1.0, "theta must be in [0, 1)");

@@ -13,7 +13,6 @@
 
 namespace stk {
 
-template <int P, typename T> void launch_far(const FarArgs &, hipStream_t);
 
 namespace {
 
@@ -217,19 +216,19 @@ __global__ void k_direct_reduce(const double *__restrict__ part, int64_t m, int 
 
 inline unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
 
-template <typename T> void dispatch_far(int p, const FarArgs &a, hipStream_t s) {
+template <typename T, int KB> void dispatch_far(int p, const FarArgs &a, hipStream_t s) {
     switch (p) {
-        case 0: launch_far<0, T>(a, s); break;
-        case 1: launch_far<1, T>(a, s); break;
-        case 2: launch_far<2, T>(a, s); break;
-        case 3: launch_far<3, T>(a, s); break;
-        case 4: launch_far<4, T>(a, s); break;
-        case 5: launch_far<5, T>(a, s); break;
-        case 6: launch_far<6, T>(a, s); break;
-        case 7: launch_far<7, T>(a, s); break;
-        case 8: launch_far<8, T>(a, s); break;
-        case 9: launch_far<9, T>(a, s); break;
-        case 10: launch_far<10, T>(a, s); break;
+        case 0: launch_far<0, T, KB>(a, s); break;
+        case 1: launch_far<1, T, KB>(a, s); break;
+        case 2: launch_far<2, T, KB>(a, s); break;
+        case 3: launch_far<3, T, KB>(a, s); break;
+        case 4: launch_far<4, T, KB>(a, s); break;
+        case 5: launch_far<5, T, KB>(a, s); break;
+        case 6: launch_far<6, T, KB>(a, s); break;
+        case 7: launch_far<7, T, KB>(a, s); break;
+        case 8: launch_far<8, T, KB>(a, s); break;
+        case 9: launch_far<9, T, KB>(a, s); break;
+        case 10: launch_far<10, T, KB>(a, s); break;
         default: throw Error(STK_EINVAL, "p out of range");
     }
 }
@@ -303,16 +302,26 @@ void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, dou
     hipLaunchKernelGGL(k_traverse<true>, dim3(ng), dim3(64), 0, s, ta);
     STK_CHECK_LAUNCH();
 
+    // right-hand sides per kernel pass (FP64: one)
+    const int K = t.k_rhs;
+    const int kb = t.prec == STK_FP64 ? 1 : (K % 4 == 0 ? 4 : (K % 2 == 0 ? 2 : 1));
+    pl.far_kb = kb;
+    pl.near_kb = kb;
+
     // near field (its leaf-major lists close the lists phase), then far field (which adds
     // the near part and un-permutes)
-    double *unear = reserve<double>(t.s_tmp, size_t(m) * 3);
+    double *unear = reserve<double>(t.s_tmp, size_t(m) * K * 3);
     near_field(t, pl, unear, s);
     FarArgs fa{tpos, m, foff, ta.far_node, ta.far_mask, t.ncenter.as<double>(), t.nrho.as<double>(), t.wblk.p,
-               unear, tperm, u_out, ng};
+               unear, tperm, u_out, ng, K};
     if (t.prec == STK_FP64)
-        dispatch_far<double>(t.p, fa, s);
+        dispatch_far<double, 1>(t.p, fa, s);
+    else if (kb == 4)
+        dispatch_far<float, 4>(t.p, fa, s);
+    else if (kb == 2)
+        dispatch_far<float, 2>(t.p, fa, s);
     else
-        dispatch_far<float>(t.p, fa, s);
+        dispatch_far<float, 1>(t.p, fa, s);
     prof_mark(STK_PHASE_FAR, s);
 }
 

@@ -1,0 +1,73 @@
+// Far-field kernel body (instantiated per Taylor order in far_p*.hip and fark_p*.hip).
+#pragma once
+
+#include "far_kernels.hpp"
+
+namespace stk {
+
+// right-hand sides in blocks of KB: each block walks the far list once and shares each
+// interaction's recurrence between its KB streams
+template <int P, typename T, int KB>
+__global__ __launch_bounds__(64) void k_far(FarArgs a) {
+    constexpr int WS = 6 * nidx(P + 1);
+    const int32_t g = xcd_group(a.ngroups);
+    if (g >= a.ngroups) return;
+    const int lane = threadIdx.x;
+    const int64_t t = int64_t(g) * 64 + lane;
+    const bool valid = t < a.m;
+    double x0 = 0, x1 = 0, x2 = 0;
+    if (valid) {
+        x0 = a.tpos[3 * t];
+        x1 = a.tpos[3 * t + 1];
+        x2 = a.tpos[3 * t + 2];
+    }
+    // FP64 streams are read through the constant address space: the double u_out stores
+    // between right-hand-side blocks would otherwise turn their uniform loads into vector
+    // loads (FP32 streams cannot alias them)
+    constexpr bool CAS = sizeof(T) == 8;
+    using Eval = FarEval<P, T, KB, CAS>;
+    const typename Eval::Ptr __restrict__ wb = (typename Eval::Ptr)(a.wblk);
+    const int32_t e0 = a.off[g], e1 = a.off[g + 1];
+    const int K = a.K;
+    for (int r0 = 0; r0 < K; r0 += KB) {
+        Comp<T> acc[KB][3];
+        for (int32_t e = e0; e < e1; ++e) {
+            const int32_t c = __builtin_amdgcn_readfirstlane(a.node[e]);
+            const uint64_t mk = a.mask[e];
+            if ((mk >> lane) & 1ull) {
+                const double d0 = x0 - a.center[3 * c], d1 = x1 - a.center[3 * c + 1], d2 = x2 - a.center[3 * c + 2];
+                const double R2 = d0 * d0 + d1 * d1 + d2 * d2;
+                const double rinv = 1.0 / sqrt(R2);
+                const T dh[3] = {T(d0 * rinv), T(d1 * rinv), T(d2 * rinv)};
+                const T tt = T(a.rho[c] * rinv);
+                T accG[KB][3], accF[KB][3];
+                Eval::run(dh, tt, wb + (size_t(c) * K + r0) * WS, accG, accF);
+#pragma unroll
+                for (int r = 0; r < KB; ++r) {
+                    T u[3];
+                    far_velocity(accG[r], accF[r], T(rinv), u);
+                    acc[r][0].add(u[0]);
+                    acc[r][1].add(u[1]);
+                    acc[r][2].add(u[2]);
+                }
+            }
+        }
+        if (valid) {
+            const int64_t o = a.tperm[t];
+#pragma unroll
+            for (int r = 0; r < KB; ++r)
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+                    a.u_out[(size_t(r0 + r) * a.m + o) * 3 + i] =
+                        acc[r][i].value() + a.unear[(size_t(t) * K + r0 + r) * 3 + i];
+        }
+    }
+}
+
+template <int P, typename T, int KB> void launch_far(const FarArgs &a, hipStream_t s) {
+    if (a.ngroups == 0) return;
+    hipLaunchKernelGGL((k_far<P, T, KB>), dim3(xcd_blocks(a.ngroups)), dim3(64), 0, s, a);
+    STK_CHECK_LAUNCH();
+}
+
+}  // namespace stk

@@ -1,7 +1,7 @@
-// Far-field kernels for Taylor order p = 10 (both precisions).
-#include "far_kernels.hpp"
+// Far-field kernels for Taylor order p = 10, one right-hand side per pass (both precisions).
+#include "far_impl.hpp"
 
 namespace stk {
-template void launch_far<10, float>(const FarArgs &, hipStream_t);
-template void launch_far<10, double>(const FarArgs &, hipStream_t);
+template void launch_far<10, float, 1>(const FarArgs &, hipStream_t);
+template void launch_far<10, double, 1>(const FarArgs &, hipStream_t);
 }  // namespace stk

@@ -1,7 +1,7 @@
-// Far-field kernels for Taylor order p = 7 (both precisions).
-#include "far_kernels.hpp"
+// Far-field kernels for Taylor order p = 7, one right-hand side per pass (both precisions).
+#include "far_impl.hpp"
 
 namespace stk {
-template void launch_far<7, float>(const FarArgs &, hipStream_t);
-template void launch_far<7, double>(const FarArgs &, hipStream_t);
+template void launch_far<7, float, 1>(const FarArgs &, hipStream_t);
+template void launch_far<7, double, 1>(const FarArgs &, hipStream_t);
 }  // namespace stk

@@ -23,32 +23,36 @@ inline unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
 
 // One source's contribution (contracted pair of Sec. 4.1), arranged as
 //   u_i += (1/r) (f_i + d_i s),   s = (d.f + (d.h)(d.nu)/r^2) / r^2,
-// which is f_i/r + d_i (d.f)/r^3 + d_i (d.h)(d.nu)/r^5, in two FMAs per component.
-// g = (y, nu) and w = (f, h) are wave-uniform (held in SGPRs).  CHECK: a pair with
-// r = 0 may occur (the coincident source is skipped, Sec. 2); without it the caller
-// has shown that every pair of the leaf is at distance > 1e-15.
-template <bool CHECK>
-__device__ inline void pair_f64(double x0, double x1, double x2, const double g[6], const double w[6], double &u0,
-                                double &u1, double &u2) {
+// which is f_i/r + d_i (d.f)/r^3 + d_i (d.h)(d.nu)/r^5, in two FMAs per component,
+// for KB right-hand sides that share the geometry (d, r, d.nu).  g = (y, nu) and
+// w[r] = (f, h) are wave-uniform (held in SGPRs).  CHECK: a pair with r = 0 may occur
+// (the coincident source is skipped, Sec. 2); without it the caller has shown that
+// every pair of the leaf is at distance > 1e-15.
+template <bool CHECK, int KB>
+__device__ inline void pair_f64(double x0, double x1, double x2, const double g[6], const double (*w)[6],
+                                double (*u)[3]) {
     const double d0 = x0 - g[0], d1 = x1 - g[1], d2 = x2 - g[2];
     const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
     double ri = rsqrt(r2);
     if constexpr (CHECK) ri = r2 > 0.0 ? ri : 0.0;
     const double r2i = ri * ri;
     const double dn = d0 * g[3] + d1 * g[4] + d2 * g[5];
-    const double df = d0 * w[0] + d1 * w[1] + d2 * w[2];
-    const double dh = d0 * w[3] + d1 * w[4] + d2 * w[5];
-    const double sc = fma(dh, dn * r2i, df) * r2i;
-    u0 = fma(ri, fma(d0, sc, w[0]), u0);
-    u1 = fma(ri, fma(d1, sc, w[1]), u1);
-    u2 = fma(ri, fma(d2, sc, w[2]), u2);
+#pragma unroll
+    for (int r = 0; r < KB; ++r) {
+        const double df = d0 * w[r][0] + d1 * w[r][1] + d2 * w[r][2];
+        const double dh = d0 * w[r][3] + d1 * w[r][4] + d2 * w[r][5];
+        const double sc = fma(dh, dn * r2i, df) * r2i;
+        u[r][0] = fma(ri, fma(d0, sc, w[r][0]), u[r][0]);
+        u[r][1] = fma(ri, fma(d1, sc, w[r][1]), u[r][1]);
+        u[r][2] = fma(ri, fma(d2, sc, w[r][2]), u[r][2]);
+    }
 }
 
 // Mixed precision: d = x - y and d.nu in FP64 (on a surface with nu the normal d.nu is
 // O(|d|^2), so its absolute rounding must stay at FP64 level), the rest in FP32.
-template <bool CHECK>
-__device__ inline void pair_mixed(double x0, double x1, double x2, const double g[6], const float w[6], float &u0,
-                                  float &u1, float &u2) {
+template <bool CHECK, int KB>
+__device__ inline void pair_mixed(double x0, double x1, double x2, const double g[6], const float (*w)[6],
+                                  float (*u)[3]) {
     const double d0 = x0 - g[0], d1 = x1 - g[1], d2 = x2 - g[2];
     const double dn = d0 * g[3] + d1 * g[4] + d2 * g[5];
     const float f0 = float(d0), f1 = float(d1), f2 = float(d2);
@@ -56,50 +60,67 @@ __device__ inline void pair_mixed(double x0, double x1, double x2, const double 
     float ri = __frsqrt_rn(r2);
     if constexpr (CHECK) ri = r2 > 0.0f ? ri : 0.0f;
     const float r2i = ri * ri;
-    const float df = f0 * w[0] + f1 * w[1] + f2 * w[2];
-    const float dh = f0 * w[3] + f1 * w[4] + f2 * w[5];
-    const float sc = fmaf(dh, float(dn) * r2i, df) * r2i;
-    u0 = fmaf(ri, fmaf(f0, sc, w[0]), u0);
-    u1 = fmaf(ri, fmaf(f1, sc, w[1]), u1);
-    u2 = fmaf(ri, fmaf(f2, sc, w[2]), u2);
+    const float q = float(dn) * r2i;
+#pragma unroll
+    for (int r = 0; r < KB; ++r) {
+        const float df = f0 * w[r][0] + f1 * w[r][1] + f2 * w[r][2];
+        const float dh = f0 * w[r][3] + f1 * w[r][4] + f2 * w[r][5];
+        const float sc = fmaf(dh, q, df) * r2i;
+        u[r][0] = fmaf(ri, fmaf(f0, sc, w[r][0]), u[r][0]);
+        u[r][1] = fmaf(ri, fmaf(f1, sc, w[r][1]), u[r][1]);
+        u[r][2] = fmaf(ri, fmaf(f2, sc, w[r][2]), u[r][2]);
+    }
 }
 
-// sum over sources [s, s + n) of one leaf; records are read four at a time (one wait on
-// the scalar cache per batch of four)
-template <typename T, bool CHECK>
-__device__ inline void near_leaf(const double *__restrict__ geo, const T *__restrict__ wts, int32_t s, int32_t n,
-                                 double x0, double x1, double x2, T &u0, T &u1, T &u2) {
+// sum over sources [s, s + n) of one leaf for KB right-hand sides; wr points at source
+// 0's weights of the first of them and ws is the per-source stride (both wave-uniform);
+// records are read NBATCH at a time (one wait on the scalar cache per batch)
+template <typename T, bool CHECK, int KB>
+__device__ inline void near_leaf(const double *__restrict__ geo_g, const T *__restrict__ wr_g, int ws, int32_t s,
+                                 int32_t n, double x0, double x1, double x2, T (*u)[3]) {
+    constexpr int NBATCH = KB == 1 ? 4 : (KB == 2 ? 2 : 1);
+    // the records are not written while the kernel runs: read them as constant memory, so
+    // the partial stores between right-hand-side blocks do not turn them into vector loads
+    const STK_CONST_AS double *geo = (const STK_CONST_AS double *)(geo_g);
+    const STK_CONST_AS T *wr = (const STK_CONST_AS T *)(wr_g);
     int32_t j = s;
-    for (; j + 4 <= s + n; j += 4) {
-        double gb[4][6];
-        T wb[4][6];
+    for (; j + NBATCH <= s + n; j += NBATCH) {
+        double gb[NBATCH][6];
+        T wb[NBATCH][KB][6];
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
+        for (int b = 0; b < NBATCH; ++b) {
 #pragma unroll
-            for (int q = 0; q < 6; ++q) {
-                gb[b][q] = geo[6 * int64_t(j + b) + q];
-                wb[b][q] = wts[6 * int64_t(j + b) + q];
-            }
+            for (int q = 0; q < 6; ++q) gb[b][q] = geo[6 * int64_t(j + b) + q];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
+            for (int r = 0; r < KB; ++r)
+#pragma unroll
+                for (int q = 0; q < 6; ++q) wb[b][r][q] = wr[int64_t(j + b) * ws + 6 * r + q];
+        }
+#pragma unroll
+        for (int b = 0; b < NBATCH; ++b) {
             if constexpr (sizeof(T) == 8)
-                pair_f64<CHECK>(x0, x1, x2, gb[b], reinterpret_cast<const double *>(wb[b]), u0, u1, u2);
+                pair_f64<CHECK, KB>(x0, x1, x2, gb[b], reinterpret_cast<const double(*)[6]>(wb[b]),
+                                    reinterpret_cast<double(*)[3]>(u));
             else
-                pair_mixed<CHECK>(x0, x1, x2, gb[b], reinterpret_cast<const float *>(wb[b]), u0, u1, u2);
+                pair_mixed<CHECK, KB>(x0, x1, x2, gb[b], reinterpret_cast<const float(*)[6]>(wb[b]),
+                                      reinterpret_cast<float(*)[3]>(u));
         }
     }
     for (; j < s + n; ++j) {
         double gc[6];
-        T wc[6];
+        T wc[KB][6];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            gc[q] = geo[6 * int64_t(j) + q];
-            wc[q] = wts[6 * int64_t(j) + q];
-        }
+        for (int q = 0; q < 6; ++q) gc[q] = geo[6 * int64_t(j) + q];
+#pragma unroll
+        for (int r = 0; r < KB; ++r)
+#pragma unroll
+            for (int q = 0; q < 6; ++q) wc[r][q] = wr[int64_t(j) * ws + 6 * r + q];
         if constexpr (sizeof(T) == 8)
-            pair_f64<CHECK>(x0, x1, x2, gc, reinterpret_cast<const double *>(wc), u0, u1, u2);
+            pair_f64<CHECK, KB>(x0, x1, x2, gc, reinterpret_cast<const double(*)[6]>(wc),
+                                reinterpret_cast<double(*)[3]>(u));
         else
-            pair_mixed<CHECK>(x0, x1, x2, gc, reinterpret_cast<const float *>(wc), u0, u1, u2);
+            pair_mixed<CHECK, KB>(x0, x1, x2, gc, reinterpret_cast<const float(*)[6]>(wc),
+                                  reinterpret_cast<float(*)[3]>(u));
     }
 }
 
@@ -159,14 +180,16 @@ struct NearArgs {
     const int32_t *start, *count;          // leaf source ranges
     const double *bmin, *bmax;             // (nn,3) tight source boxes
     const double *geo;                     // (n,6) y, nu
-    const void *wts;                       // (n,6) f, h in T
-    void *part;                            // (incidences, 3) T
+    const void *wts;                       // (n,K,6) f, h in T
+    void *part;                            // (incidences, K, 3) T
     int32_t nitems;
+    int32_t K;                             // right-hand sides (a multiple of KB)
 };
 
-// one wave per item: the item's leaf against up to 64 of its targets.  Items of one leaf
-// are consecutive and go to one XCD, so the leaf's records are shared in its L2.
-template <typename T> __global__ __launch_bounds__(64) void k_near(NearArgs a) {
+// one wave per item: the item's leaf against up to 64 of its targets, for all right-hand
+// sides in blocks of KB.  Items of one leaf are consecutive and go to one XCD, so the
+// leaf's records are shared in its L2.
+template <typename T, int KB> __global__ __launch_bounds__(64) void k_near(NearArgs a) {
     const int32_t it = xcd_group(a.nitems);
     if (it >= a.nitems) return;
     const int lane = threadIdx.x;
@@ -186,36 +209,58 @@ template <typename T> __global__ __launch_bounds__(64) void k_near(NearArgs a) {
     // distance of the leaf's box: only then does the wave take the checked loop
     const bool close = on && box_dist2(x0, x1, x2, a.bmin + 3 * c, a.bmax + 3 * c) <= 1e-30;
     const bool any_close = __ballot(close) != 0;
-    if (on) {
-        const T *__restrict__ wts = static_cast<const T *>(a.wts);
-        const int32_t s = a.start[c], n = a.count[c];
-        T u0 = T(0), u1 = T(0), u2 = T(0);
+    // every lane runs the loops (lanes without a target use x = 0 and store nothing), so
+    // the source records stay wave-uniform scalar loads
+    const T *__restrict__ wts = static_cast<const T *>(a.wts);
+    const int32_t s = a.start[c], n = a.count[c];
+    const int K = a.K;
+    const int ws = __builtin_amdgcn_readfirstlane(6 * K);
+    for (int r0 = 0; r0 < K; r0 += KB) {
+        T u[KB][3];
+#pragma unroll
+        for (int r = 0; r < KB; ++r) u[r][0] = u[r][1] = u[r][2] = T(0);
+        const T *__restrict__ wr = wts + 6 * r0;
         if (any_close)
-            near_leaf<T, true>(a.geo, wts, s, n, x0, x1, x2, u0, u1, u2);
+            near_leaf<T, true, KB>(a.geo, wr, ws, s, n, x0, x1, x2, u);
         else
-            near_leaf<T, false>(a.geo, wts, s, n, x0, x1, x2, u0, u1, u2);
-        T *o = static_cast<T *>(a.part) + 3 * int64_t(slot);
-        o[0] = u0;
-        o[1] = u1;
-        o[2] = u2;
+            near_leaf<T, false, KB>(a.geo, wr, ws, s, n, x0, x1, x2, u);
+        if (on) {
+            T *o = static_cast<T *>(a.part) + (int64_t(slot) * K + r0) * 3;
+#pragma unroll
+            for (int r = 0; r < KB; ++r) {
+                o[3 * r] = u[r][0];
+                o[3 * r + 1] = u[r][1];
+                o[3 * r + 2] = u[r][2];
+            }
+        }
     }
 }
 
-// per target: its partials in near-list order, compensated, to FP64
+// per (target, right-hand side): its partials in near-list order, compensated, to FP64
 template <typename T>
-__global__ void k_near_reduce(const T *__restrict__ part, const int32_t *__restrict__ toff, int64_t m,
+__global__ void k_near_reduce(const T *__restrict__ part, const int32_t *__restrict__ toff, int64_t m, int K,
                               double *__restrict__ unear) {
-    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= m) return;
+    const int64_t id = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (id >= m * K) return;
+    const int64_t t = id / K;
+    const int r = int(id - t * K);
     Comp<T> acc[3];
     for (int32_t k = toff[t]; k < toff[t + 1]; ++k) {
-        acc[0].add(part[3 * int64_t(k)]);
-        acc[1].add(part[3 * int64_t(k) + 1]);
-        acc[2].add(part[3 * int64_t(k) + 2]);
+        const T *p = part + (int64_t(k) * K + r) * 3;
+        acc[0].add(p[0]);
+        acc[1].add(p[1]);
+        acc[2].add(p[2]);
     }
-    unear[3 * t] = acc[0].value();
-    unear[3 * t + 1] = acc[1].value();
-    unear[3 * t + 2] = acc[2].value();
+    unear[3 * id] = acc[0].value();
+    unear[3 * id + 1] = acc[1].value();
+    unear[3 * id + 2] = acc[2].value();
+}
+
+template <typename T, int KB> void launch_near(const NearArgs &na, hipStream_t s) {
+    if (na.nitems > 0) {
+        hipLaunchKernelGGL((k_near<T, KB>), dim3(xcd_blocks(na.nitems)), dim3(64), 0, s, na);
+        STK_CHECK_LAUNCH();
+    }
 }
 
 }  // namespace
@@ -283,29 +328,30 @@ void near_field(Tree &t, Plan &pl, double *unear, hipStream_t s) {
     }
     prof_mark(STK_PHASE_LISTS, s);
 
+    const int K = t.k_rhs;
     const size_t tsz = t.prec == STK_FP64 ? sizeof(double) : sizeof(float);
-    void *part = reserve<unsigned char>(pl.near_part, tsz * 3 * size_t(pl.n_inc) + tsz);
+    void *part = reserve<unsigned char>(pl.near_part, tsz * 3 * size_t(pl.n_inc) * K + tsz);
     NearArgs na{pl.tpos.as<double>(), ileaf, i0, i1, inc_tgt, inc_slot, t.nstart.as<int32_t>(),
                 t.ncount.as<int32_t>(), t.nbmin.as<double>(), t.nbmax.as<double>(), t.geo.as<double>(), t.wts.p,
-                part, pl.n_near_items};
+                part, pl.n_near_items, K};
+    const int64_t mk = m * K;
     if (t.prec == STK_FP64) {
-        if (na.nitems > 0) {
-            hipLaunchKernelGGL(k_near<double>, dim3(xcd_blocks(na.nitems)), dim3(64), 0, s, na);
-            STK_CHECK_LAUNCH();
-        }
-        if (m > 0) {
-            hipLaunchKernelGGL(k_near_reduce<double>, dim3(nblk(m, 256)), dim3(256), 0, s,
-                               static_cast<const double *>(part), toff, m, unear);
+        launch_near<double, 1>(na, s);
+        if (mk > 0) {
+            hipLaunchKernelGGL(k_near_reduce<double>, dim3(nblk(mk, 256)), dim3(256), 0, s,
+                               static_cast<const double *>(part), toff, m, K, unear);
             STK_CHECK_LAUNCH();
         }
     } else {
-        if (na.nitems > 0) {
-            hipLaunchKernelGGL(k_near<float>, dim3(xcd_blocks(na.nitems)), dim3(64), 0, s, na);
-            STK_CHECK_LAUNCH();
-        }
-        if (m > 0) {
-            hipLaunchKernelGGL(k_near_reduce<float>, dim3(nblk(m, 256)), dim3(256), 0, s,
-                               static_cast<const float *>(part), toff, m, unear);
+        if (pl.near_kb == 4)
+            launch_near<float, 4>(na, s);
+        else if (pl.near_kb == 2)
+            launch_near<float, 2>(na, s);
+        else
+            launch_near<float, 1>(na, s);
+        if (mk > 0) {
+            hipLaunchKernelGGL(k_near_reduce<float>, dim3(nblk(mk, 256)), dim3(256), 0, s,
+                               static_cast<const float *>(part), toff, m, K, unear);
             STK_CHECK_LAUNCH();
         }
     }

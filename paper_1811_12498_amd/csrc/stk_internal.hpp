@@ -148,6 +148,7 @@ struct Plan {
     DBuf near_part;                // T (incidences, 3): per (target, leaf) partial velocities
     int64_t n_inc = 0;
     int32_t n_near_items = 0;
+    int32_t far_kb = 1, near_kb = 1;  // right-hand sides per pass of the far / near kernels
     AdjScratch adj;
     ~Plan();
 };
@@ -176,7 +177,8 @@ void evaluate(Tree &t, Plan &plan, const double *tgt, int64_t m, double theta, d
 // NULL); w and the outputs in the caller's orders
 void adjoint(Plan &plan, const double *w, double *grad_f, double *grad_h, double *grad_targets,
              double *grad_sources, hipStream_t s);
-// near field of a plan whose group-major near lists are filled: unear (m,3), sorted order
+// near field of a plan whose group-major near lists are filled: unear (m,K,3), sorted
+// target order, K = the tree's right-hand sides
 void near_field(Tree &t, Plan &plan, double *unear, hipStream_t s);
 void direct_sum(const double *tgt, int64_t m, const double *src, int64_t n, const double *f, const double *h,
                 const double *nu, int32_t k, double *u_out, hipStream_t s);

@@ -26,6 +26,8 @@
 // (t <= 2 theta), so FP32 neither overflows at small R nor underflows at small rho.
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -209,22 +211,40 @@ STK_HD void stream_pos(int p, const int a[3], int &g, int &e) {
     e = stream_off(p, n + 1, j + 1) + stream_gpart(p, n + 1, j + 1) + 3 * i;
 }
 
-template <int P, typename T> struct FarEval {
+// KB right-hand sides share one recurrence: their streams follow each other at a
+// stride of WS values and each has its own pair of partial sums
+// read-only device data that no store of the running kernel can touch, read through the
+// constant address space: loads at wave-uniform addresses then stay scalar even where the
+// kernel stores elsewhere in between (the host build of the same code sees plain pointers)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define STK_CONST_AS __attribute__((address_space(4)))
+#else
+#define STK_CONST_AS
+#endif
+
+// CAS: read the streams through the constant address space (needed where the kernel
+// stores values of the stream's own type between interactions)
+template <int P, typename T, int KB = 1, bool CAS = false> struct FarEval {
+    using Ptr = std::conditional_t<CAS, const STK_CONST_AS T *, const T *>;
     static constexpr int PB = P + 2;
     static constexpr int NB = nidx(PB);
+    static constexpr int WS = 6 * nidx(P + 1);
 
-    template <int N, int I> STK_HD static void gterm(T bq, const T *__restrict__ G, T accG[3]) {
+    template <int N, int I> STK_HD static void gterm(T bq, Ptr __restrict__ G, T (*accG)[3]) {
         if constexpr (N <= P + 1) {
-            accG[0] += bq * G[3 * I];
-            accG[1] += bq * G[3 * I + 1];
-            accG[2] += bq * G[3 * I + 2];
+#pragma unroll
+            for (int r = 0; r < KB; ++r) {
+                accG[r][0] += bq * G[r * WS + 3 * I];
+                accG[r][1] += bq * G[r * WS + 3 * I + 1];
+                accG[r][2] += bq * G[r * WS + 3 * I + 2];
+            }
         }
     }
 
     // all coefficients of order N in layer K3 (k1 = N - K3 .. 0), with their G terms;
     // G points at the chunk (N, K3)
     template <int N, int K3, int K1>
-    STK_HD static void layer(T (&b)[NB], const T dh[3], T c1, T c2, const T *__restrict__ G, T accG[3]) {
+    STK_HD static void layer(T (&b)[NB], const T dh[3], T c1, T c2, Ptr __restrict__ G, T (*accG)[3]) {
         constexpr int K2 = N - K3 - K1;
         constexpr int Q = gidx(K1, K2, K3);
         if constexpr (K3 <= 1) {  // recurrence_1, scaled
@@ -251,14 +271,18 @@ template <int P, typename T> struct FarEval {
     // E contraction for the k of order N - 1 in layer K3 (needs layers K3, K3 + 1 of
     // order N); E points at the E part of chunk (N, K3 + 1)
     template <int N, int K3, int K1>
-    STK_HD static void elayer(const T (&b)[NB], const T dh[3], const T *__restrict__ E, T accF[3]) {
+    STK_HD static void elayer(const T (&b)[NB], const T dh[3], Ptr __restrict__ E, T (*accF)[3]) {
         constexpr int M = N - 1;
         constexpr int K2 = M - K3 - K1;
         constexpr int I = (M - K3) - K1;
-        const T sig = dh[0] * E[3 * I] + dh[1] * E[3 * I + 1] + dh[2] * E[3 * I + 2];
-        accF[0] += b[gidx(K1 + 1, K2, K3)] * (T(K1 + 1) * sig);
-        accF[1] += b[gidx(K1, K2 + 1, K3)] * (T(K2 + 1) * sig);
-        accF[2] += b[gidx(K1, K2, K3 + 1)] * (T(K3 + 1) * sig);
+#pragma unroll
+        for (int r = 0; r < KB; ++r) {
+            Ptr __restrict__ Er = E + r * WS;
+            const T sig = dh[0] * Er[3 * I] + dh[1] * Er[3 * I + 1] + dh[2] * Er[3 * I + 2];
+            accF[r][0] += b[gidx(K1 + 1, K2, K3)] * (T(K1 + 1) * sig);
+            accF[r][1] += b[gidx(K1, K2 + 1, K3)] * (T(K2 + 1) * sig);
+            accF[r][2] += b[gidx(K1, K2, K3 + 1)] * (T(K3 + 1) * sig);
+        }
         if constexpr (K1 > 0) elayer<N, K3, K1 - 1>(b, dh, E, accF);
     }
 
@@ -278,10 +302,10 @@ template <int P, typename T> struct FarEval {
     }
 
     template <int N, int J>
-    STK_HD static void layers_from(T (&b)[NB], const T dh[3], T c1, T c2, const T *__restrict__ W, T accG[3],
-                                   T accF[3]) {
+    STK_HD static void layers_from(T (&b)[NB], const T dh[3], T c1, T c2, Ptr __restrict__ W, T (*accG)[3],
+                                   T (*accF)[3]) {
         if constexpr (J <= N) {
-            const T *__restrict__ chunk = W + stream_off(P, N, J) + fence(accG[0] + accF[0]);
+            Ptr __restrict__ chunk = W + stream_off(P, N, J) + fence(accG[0][0] + accF[0][0]);
             layer<N, J, N - J>(b, dh, c1, c2, chunk, accG);
             if constexpr (J >= 1) elayer<N, J - 1, N - J>(b, dh, chunk + stream_gpart(P, N, J), accF);
             layers_from<N, J + 1>(b, dh, c1, c2, W, accG, accF);
@@ -289,22 +313,29 @@ template <int P, typename T> struct FarEval {
     }
 
     template <int N>
-    STK_HD static void order(T (&b)[NB], const T dh[3], T t, const T *__restrict__ W, T accG[3], T accF[3]) {
+    STK_HD static void order(T (&b)[NB], const T dh[3], T t, Ptr __restrict__ W, T (*accG)[3], T (*accF)[3]) {
         const T c1 = T(2 * N - 1) / T(N) * t;
         const T c2 = T(N - 1) / T(N) * (t * t);
         layers_from<N, 0>(b, dh, c1, c2, W, accG, accF);
         if constexpr (N < PB) order<N + 1>(b, dh, t, W, accG, accF);
     }
 
-    // W: the cluster's stream.  u_i = accG_i / R + accF_i
-    STK_HD static void run(const T dh[3], T t, const T *__restrict__ W, T accG[3], T accF[3]) {
+    // W: the first right-hand side's cluster stream.  u_i = accG[r][i] / R + accF[r][i]
+    STK_HD static void run(const T dh[3], T t, Ptr __restrict__ W, T (*accG)[3], T (*accF)[3]) {
         T b[NB];
         b[0] = T(1);
-        accG[0] = W[0];
-        accG[1] = W[1];
-        accG[2] = W[2];
-        accF[0] = accF[1] = accF[2] = T(0);
+#pragma unroll
+        for (int r = 0; r < KB; ++r) {
+            accG[r][0] = W[r * WS];
+            accG[r][1] = W[r * WS + 1];
+            accG[r][2] = W[r * WS + 2];
+            accF[r][0] = accF[r][1] = accF[r][2] = T(0);
+        }
         order<1>(b, dh, t, W, accG, accF);
+    }
+    // one right-hand side
+    STK_HD static void run(const T dh[3], T t, Ptr __restrict__ W, T accG[3], T accF[3]) {
+        run(dh, t, W, reinterpret_cast<T(*)[3]>(accG), reinterpret_cast<T(*)[3]>(accF));
     }
 };
 
