@@ -168,6 +168,40 @@ stk_status stk_plan_counts(const stk_plan *plan, int64_t *nfar, int64_t *nnear, 
 stk_status stk_plan_export_lists(const stk_plan *plan, int32_t kind, int32_t *off, int32_t *node, uint64_t *mask,
                                  int32_t *tperm);
 
+/* Kernel variants ("tiles") of the far and near fields, per (device architecture, p,
+ * K = k_rhs, precision).  Not part of the paper's method: they change only how the
+ * sums are scheduled on the GPU (and, for near_mfma, the FP32 summation order).
+ *   far_kb     right-hand sides per pass of the far-field kernel: 1, 2 or 4, dividing K
+ *              (FP64: 1).  Each pass shares one Taylor-coefficient recurrence.
+ *   near_kb    right-hand sides per pass of the VALU near-field kernel: 1, 2 or 4,
+ *              dividing K (FP64: 1).
+ *   near_mfma  1: near field on the matrix cores (FP32 mixed precision only), 16
+ *              right-hand sides per pass; near_kb is then unused. */
+typedef struct stk_tiles {
+    int32_t far_kb;
+    int32_t near_kb;
+    int32_t near_mfma;
+} stk_tiles;
+/* Record tiles for (current device's architecture, p, k_rhs, prec); NULL removes the
+ * entry.  EINVAL if the tiles do not fit k_rhs and prec. */
+stk_status stk_tiles_set(int32_t p, int32_t k_rhs, stk_precision prec, const stk_tiles *tiles);
+/* The tiles an evaluation with these parameters would use on the current device;
+ * *from_table (may be NULL) is 1 if they come from the table, 0 for the built-in rule. */
+stk_status stk_tiles_get(int32_t p, int32_t k_rhs, stk_precision prec, stk_tiles *out, int32_t *from_table);
+/* Time every candidate on a synthetic problem of n points uniform in the unit cube
+ * (generated on the device; theta and n0 as the caller will use them), record the
+ * fastest in the table and return it with its time in ms (either output may be NULL).
+ * Allocates and frees its own device memory; synchronises `stream`. */
+stk_status stk_autotune(int32_t p, int32_t k_rhs, stk_precision prec, int64_t n, double theta, int32_t n0,
+                        stk_tiles *best, double *best_ms, void *stream);
+/* Write the table to / merge it from a text file (one "arch p K precision far_kb
+ * near_kb near_mfma" line per entry).  Load is all-or-nothing: EINVAL on a malformed
+ * or invalid line, and nothing is merged. */
+stk_status stk_tiles_save(const char *path);
+stk_status stk_tiles_load(const char *path, int32_t *n_entries);
+/* The tiles a plan's evaluation used. */
+stk_status stk_plan_tiles(const stk_plan *plan, stk_tiles *out);
+
 /* Phase timing, a tracing aid.  While enabled, every entry point records a HIP event
  * on its stream when it starts and after each phase below; stk_profile_read waits for
  * those events, returns the summed milliseconds and the number of timed intervals

@@ -26,7 +26,8 @@ _STATUS_NAMES = {STK_EINVAL: "STK_EINVAL", STK_ENOMEM: "STK_ENOMEM", STK_EDEVICE
 EXPORTS = ["stk_build_tree", "stk_compute_moments", "stk_evaluate_tree", "stk_evaluate", "stk_evaluate_adjoint",
            "stk_direct",
            "stk_tree_info", "stk_tree_export", "stk_tree_export_moments", "stk_plan_counts", "stk_plan_info",
-           "stk_plan_export_lists",
+           "stk_plan_export_lists", "stk_tiles_set", "stk_tiles_get", "stk_autotune", "stk_tiles_save",
+           "stk_tiles_load", "stk_plan_tiles",
            "stk_profile_enable", "stk_profile_read", "stk_tree_destroy", "stk_plan_destroy", "stk_last_error"]
 
 PHASES = ["tree", "moments", "targets", "lists", "near", "far", "direct", "adjoint"]
@@ -59,6 +60,22 @@ _lib.stk_tree_info.argtypes = [_vp, _i64p, _i32p, _dp]
 _lib.stk_tree_export.argtypes = [_vp] + [_vp] * 11
 _lib.stk_tree_export_moments.argtypes = [_vp, _i32, _vp, _vp]
 _lib.stk_plan_export_lists.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp]
+
+
+class Tiles(ctypes.Structure):
+    """stk_tiles: kernel variants of the far and near fields."""
+    _fields_ = [("far_kb", ctypes.c_int32), ("near_kb", ctypes.c_int32), ("near_mfma", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {"far_kb": self.far_kb, "near_kb": self.near_kb, "near_mfma": bool(self.near_mfma)}
+
+
+_lib.stk_tiles_set.argtypes = [_i32, _i32, ctypes.c_int, ctypes.POINTER(Tiles)]
+_lib.stk_tiles_get.argtypes = [_i32, _i32, ctypes.c_int, ctypes.POINTER(Tiles), _i32p]
+_lib.stk_autotune.argtypes = [_i32, _i32, ctypes.c_int, _i64, _d, _i32, ctypes.POINTER(Tiles), _dp, _vp]
+_lib.stk_tiles_save.argtypes = [ctypes.c_char_p]
+_lib.stk_tiles_load.argtypes = [ctypes.c_char_p, _i32p]
+_lib.stk_plan_tiles.argtypes = [_vp, ctypes.POINTER(Tiles)]
 _lib.stk_plan_counts.argtypes = [_vp, _vp, _vp, _vp]
 _lib.stk_plan_info.argtypes = [_vp, _i64p, _i64p, _i64p]
 _lib.stk_profile_enable.argtypes = [ctypes.c_int]
@@ -112,7 +129,7 @@ class Tree:
         self.n = n
 
     def __del__(self):
-        if getattr(self, "handle", None) and self.handle.value:
+        if getattr(self, "handle", None) and self.handle.value and _lib is not None:
             _lib.stk_tree_destroy(self.handle)
             self.handle = ctypes.c_void_p(0)
 
@@ -126,7 +143,7 @@ class Plan:
         self.tree = tree
 
     def __del__(self):
-        if getattr(self, "handle", None) and self.handle.value:
+        if getattr(self, "handle", None) and self.handle.value and _lib is not None:
             _lib.stk_plan_destroy(self.handle)
             self.handle = ctypes.c_void_p(0)
 
@@ -261,6 +278,41 @@ def plan_lists(plan: Plan, kind: str) -> dict:
                                                         for n in ("off", "node", "mask", "tperm")]))
     out["node"], out["mask"], out["tperm"] = out["node"][:ne], out["mask"][:ne], out["tperm"][:plan.m]
     return out
+
+
+def tiles_set(p: int, k_rhs: int, precision: str, far_kb: int = 1, near_kb: int = 1, near_mfma: bool = False,
+              clear: bool = False) -> None:
+    t = Tiles(far_kb, near_kb, int(near_mfma))
+    _check(_lib.stk_tiles_set(int(p), int(k_rhs), _prec(precision), None if clear else ctypes.byref(t)))
+
+
+def tiles_get(p: int, k_rhs: int, precision: str) -> tuple[dict, bool]:
+    t, hit = Tiles(), ctypes.c_int32()
+    _check(_lib.stk_tiles_get(int(p), int(k_rhs), _prec(precision), ctypes.byref(t), ctypes.byref(hit)))
+    return t.as_dict(), bool(hit.value)
+
+
+def autotune(p: int, k_rhs: int, precision: str, n: int, theta: float, n0: int) -> tuple[dict, float]:
+    t, ms = Tiles(), ctypes.c_double()
+    _check(_lib.stk_autotune(int(p), int(k_rhs), _prec(precision), int(n), float(theta), int(n0), ctypes.byref(t),
+                             ctypes.byref(ms), _stream()))
+    return t.as_dict(), ms.value
+
+
+def tiles_save(path: str) -> None:
+    _check(_lib.stk_tiles_save(str(path).encode()))
+
+
+def tiles_load(path: str) -> int:
+    k = ctypes.c_int32()
+    _check(_lib.stk_tiles_load(str(path).encode(), ctypes.byref(k)))
+    return k.value
+
+
+def plan_tiles(plan: Plan) -> dict:
+    t = Tiles()
+    _check(_lib.stk_plan_tiles(plan.handle, ctypes.byref(t)))
+    return t.as_dict()
 
 
 def profile_enable(on: bool = True) -> None:

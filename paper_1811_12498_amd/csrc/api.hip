@@ -292,6 +292,80 @@ stk_status stk_plan_export_lists(const stk_plan *plan, int32_t kind, int32_t *of
     });
 }
 
+namespace {
+stk::Tiles from_abi(const stk_tiles &t) {
+    stk::Tiles r;
+    r.far_kb = t.far_kb;
+    r.near_kb = t.near_kb;
+    r.near_mfma = t.near_mfma != 0;
+    return r;
+}
+stk_tiles to_abi(const stk::Tiles &t) { return stk_tiles{t.far_kb, t.near_kb, t.near_mfma ? 1 : 0}; }
+void check_tile_key(int32_t p, int32_t k_rhs, stk_precision prec) {
+    stk::require(p >= 0 && p <= STK_P_MAX, "p must be in [0, STK_P_MAX]");
+    stk::require(k_rhs >= 1 && k_rhs <= 64, "k_rhs must be in [1, 64]");
+    stk::require(prec == STK_FP64 || prec == STK_MIXED, "unknown precision");
+}
+}  // namespace
+
+stk_status stk_tiles_set(int32_t p, int32_t k_rhs, stk_precision prec, const stk_tiles *tiles) {
+    return guarded([&] {
+        check_tile_key(p, k_rhs, prec);
+        if (!tiles) {
+            stk::tiles_set(p, k_rhs, prec, nullptr);
+            return;
+        }
+        const stk::Tiles t = from_abi(*tiles);
+        stk::require(stk::tiles_valid(t, k_rhs, prec), "tiles do not fit k_rhs and the precision");
+        stk::tiles_set(p, k_rhs, prec, &t);
+    });
+}
+
+stk_status stk_tiles_get(int32_t p, int32_t k_rhs, stk_precision prec, stk_tiles *out, int32_t *from_table) {
+    return guarded([&] {
+        check_tile_key(p, k_rhs, prec);
+        stk::require(out != nullptr, "out is NULL");
+        stk::Tiles t;
+        const bool hit = stk::tiles_lookup(p, k_rhs, prec, &t);
+        *out = to_abi(hit ? t : stk::default_tiles(k_rhs, prec));
+        if (from_table) *from_table = hit ? 1 : 0;
+    });
+}
+
+stk_status stk_autotune(int32_t p, int32_t k_rhs, stk_precision prec, int64_t n, double theta, int32_t n0,
+                        stk_tiles *best, double *best_ms, void *stream) {
+    return guarded([&] {
+        check_tile_key(p, k_rhs, prec);
+        stk::require(n >= 1 && n < (int64_t(1) << 31) / 8, "n out of range");
+        stk::require(theta >= 0.0 && theta < 1.0, "theta must be in [0, 1)");
+        stk::require(n0 >= 1, "n0 must be >= 1");
+        const stk::Tiles t = stk::autotune(p, k_rhs, prec, n, theta, n0, best_ms, as_stream(stream));
+        if (best) *best = to_abi(t);
+    });
+}
+
+stk_status stk_tiles_save(const char *path) {
+    return guarded([&] {
+        stk::require(path != nullptr, "path is NULL");
+        stk::tiles_save(path);
+    });
+}
+
+stk_status stk_tiles_load(const char *path, int32_t *n_entries) {
+    return guarded([&] {
+        stk::require(path != nullptr, "path is NULL");
+        const int k = stk::tiles_load(path);
+        if (n_entries) *n_entries = k;
+    });
+}
+
+stk_status stk_plan_tiles(const stk_plan *plan, stk_tiles *out) {
+    return guarded([&] {
+        stk::require(plan != nullptr && out != nullptr, "plan and out must be non-NULL");
+        *out = to_abi(plan->p.tiles);
+    });
+}
+
 stk_status stk_profile_enable(int on) {
     return guarded([&] { stk::prof_enable(on != 0); });
 }

@@ -302,11 +302,11 @@ void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, dou
     hipLaunchKernelGGL(k_traverse<true>, dim3(ng), dim3(64), 0, s, ta);
     STK_CHECK_LAUNCH();
 
-    // right-hand sides per kernel pass (FP64: one)
+    // kernel variants: right-hand sides per pass, matrix cores
     const int K = t.k_rhs;
-    const int kb = t.prec == STK_FP64 ? 1 : (K % 4 == 0 ? 4 : (K % 2 == 0 ? 2 : 1));
-    pl.far_kb = kb;
-    pl.near_kb = kb;
+    pl.tiles = pl.forced ? pl.force : tiles_for(t.p, K, t.prec);
+    if (!tiles_valid(pl.tiles, K, t.prec)) throw Error(STK_EINVAL, "kernel tiles do not fit this evaluation");
+    const int kb = pl.tiles.far_kb;
 
     // near field (its leaf-major lists close the lists phase), then far field (which adds
     // the near part and un-permutes)

@@ -5,8 +5,11 @@
 
 namespace stk {
 
-// right-hand sides in blocks of KB: each block walks the far list once and shares each
-// interaction's recurrence between its KB streams
+// right-hand sides in blocks of KB, one block per grid row (blockIdx.y): each wave
+// walks its group's far list once and shares each interaction's recurrence between the
+// block's KB streams.  All resident waves work on the same block, so the streams in use
+// at a time are KB per cluster (the cluster data of one block fits the XCD's L2 where
+// that of all K would not).
 template <int P, typename T, int KB>
 __global__ __launch_bounds__(64) void k_far(FarArgs a) {
     constexpr int WS = 6 * nidx(P + 1);
@@ -29,7 +32,8 @@ __global__ __launch_bounds__(64) void k_far(FarArgs a) {
     const typename Eval::Ptr __restrict__ wb = (typename Eval::Ptr)(a.wblk);
     const int32_t e0 = a.off[g], e1 = a.off[g + 1];
     const int K = a.K;
-    for (int r0 = 0; r0 < K; r0 += KB) {
+    {
+        const int r0 = int(blockIdx.y) * KB;
         Comp<T> acc[KB][3];
         for (int32_t e = e0; e < e1; ++e) {
             const int32_t c = __builtin_amdgcn_readfirstlane(a.node[e]);
@@ -66,7 +70,7 @@ __global__ __launch_bounds__(64) void k_far(FarArgs a) {
 
 template <int P, typename T, int KB> void launch_far(const FarArgs &a, hipStream_t s) {
     if (a.ngroups == 0) return;
-    hipLaunchKernelGGL((k_far<P, T, KB>), dim3(xcd_blocks(a.ngroups)), dim3(64), 0, s, a);
+    hipLaunchKernelGGL((k_far<P, T, KB>), dim3(xcd_blocks(a.ngroups), unsigned(a.K / KB)), dim3(64), 0, s, a);
     STK_CHECK_LAUNCH();
 }
 

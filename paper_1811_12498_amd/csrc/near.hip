@@ -236,6 +236,137 @@ template <typename T, int KB> __global__ __launch_bounds__(64) void k_near(NearA
     }
 }
 
+// Near field for K right-hand sides on the matrix cores (FP32 mixed precision).  With
+// the pair written as u_i = sum_j K_ij w_j over w = (f, h):
+//   K_ij = delta_ij / r + d_i d_j / r^3,   K_i(3+j) = d_i d_j (d.nu) / r^5,
+// an item (one leaf against up to 64 targets, in four blocks of 16) is a product of the
+// (target x source) kernel blocks with the (source x RHS) weights.  Per block of four
+// sources, lane l forms the 3x6 block of the pair (target 16 tb + l % 16, source
+// 4 yb + l / 16) and loads the six weights of (source 4 yb + l / 16, RHS r0 + l % 16);
+// v_mfma_f32_16x16x4_f32 then adds A[t][y] B[y][r] over the four sources for each
+// (i, j), so every lane supplies exactly the operand entries it computed (rows =
+// targets, depth = the four sources, columns = 16 right-hand sides).  d and d.nu are
+// FP64 as in the VALU kernel; the kernel entries and their sums are FP32.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <bool CHECK, bool TAIL>
+__device__ inline void near_mfma_block(const double (&xt)[4][3], const double gy[6], const float wj[6], bool yv,
+                                       f32x4 (&acc)[4][3]) {
+#pragma unroll
+    for (int tb = 0; tb < 4; ++tb) {
+        const double d0 = xt[tb][0] - gy[0], d1 = xt[tb][1] - gy[1], d2 = xt[tb][2] - gy[2];
+        const double dn = d0 * gy[3] + d1 * gy[4] + d2 * gy[5];
+        const float f[3] = {float(d0), float(d1), float(d2)};
+        const float r2 = f[0] * f[0] + f[1] * f[1] + f[2] * f[2];
+        float ri = __frsqrt_rn(r2);
+        if constexpr (CHECK) ri = r2 > 0.0f ? ri : 0.0f;
+        if constexpr (TAIL) ri = yv ? ri : 0.0f;  // padding source: a zero column (d is finite)
+        const float r2i = ri * ri;
+        const float a3 = ri * r2i;
+        const float a5 = float(dn) * (a3 * r2i);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const float pij = f[i] * f[j];
+                const float ks = i == j ? fmaf(pij, a3, ri) : pij * a3;
+                acc[tb][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(ks, wj[j], acc[tb][i], 0, 0, 0);
+                acc[tb][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(pij * a5, wj[3 + j], acc[tb][i], 0, 0, 0);
+            }
+        }
+    }
+}
+
+template <bool CHECK>
+__device__ inline void near_mfma_leaf(const double *__restrict__ geo, const float *__restrict__ wts, int K, int r,
+                                      bool rv, int32_t s, int32_t n, int q4, const double (&xt)[4][3],
+                                      f32x4 (&acc)[4][3]) {
+    int32_t y0 = s;
+    for (; y0 + 4 <= s + n; y0 += 4) {
+        const int64_t y = y0 + q4;
+        double gy[6];
+        float wj[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            gy[q] = geo[6 * y + q];
+            wj[q] = rv ? wts[(y * K + r) * 6 + q] : 0.0f;
+        }
+        near_mfma_block<CHECK, false>(xt, gy, wj, true, acc);
+    }
+    if (y0 < s + n) {  // last, partial block of four
+        const int64_t y = y0 + q4;
+        const bool yv = y < s + n;
+        double gy[6] = {0, 0, 0, 0, 0, 0};
+        float wj[6] = {0, 0, 0, 0, 0, 0};
+        if (yv) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                gy[q] = geo[6 * y + q];
+                wj[q] = rv ? wts[(y * K + r) * 6 + q] : 0.0f;
+            }
+        }
+        near_mfma_block<CHECK, true>(xt, gy, wj, yv, acc);
+    }
+}
+
+__global__ __launch_bounds__(64) void k_near_mfma(NearArgs a) {
+    const int32_t it = xcd_group(a.nitems);
+    if (it >= a.nitems) return;
+    const int lane = threadIdx.x;
+    const int tl = lane & 15, q4 = lane >> 4;
+    const int32_t c = a.item_leaf[it];
+    const int32_t i0 = a.item_i0[it];
+    const int32_t nt = a.item_i1[it] - i0;
+    // this lane's A rows: targets 16 tb + tl of the item (rows past nt compute unused
+    // values from x = 0 and are never stored)
+    double xt[4][3];
+    bool close = false;
+#pragma unroll
+    for (int tb = 0; tb < 4; ++tb) {
+        xt[tb][0] = xt[tb][1] = xt[tb][2] = 0.0;
+        if (16 * tb + tl < nt) {
+            const int64_t t = a.inc_tgt[i0 + 16 * tb + tl];
+            xt[tb][0] = a.tpos[3 * t];
+            xt[tb][1] = a.tpos[3 * t + 1];
+            xt[tb][2] = a.tpos[3 * t + 2];
+            close = close || box_dist2(xt[tb][0], xt[tb][1], xt[tb][2], a.bmin + 3 * c, a.bmax + 3 * c) <= 1e-30;
+        }
+    }
+    const bool any_close = __ballot(close) != 0;
+    const float *__restrict__ wts = static_cast<const float *>(a.wts);
+    const int32_t s = a.start[c], n = a.count[c];
+    const int K = a.K;
+    for (int r0 = 0; r0 < K; r0 += 16) {
+        const int r = r0 + tl;
+        const bool rv = r < K;
+        f32x4 acc[4][3];
+#pragma unroll
+        for (int tb = 0; tb < 4; ++tb)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) acc[tb][i] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        if (any_close)
+            near_mfma_leaf<true>(a.geo, wts, K, r, rv, s, n, q4, xt, acc);
+        else
+            near_mfma_leaf<false>(a.geo, wts, K, r, rv, s, n, q4, xt, acc);
+        // lane holds rows 4 q4 + v (v = 0..3) of each target block, column tl
+        if (rv) {
+            float *part = static_cast<float *>(a.part);
+#pragma unroll
+            for (int tb = 0; tb < 4; ++tb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int idx = 16 * tb + 4 * q4 + v;
+                    if (idx < nt) {
+                        float *o = part + (int64_t(a.inc_slot[i0 + idx]) * K + r) * 3;
+                        o[0] = acc[tb][0][v];
+                        o[1] = acc[tb][1][v];
+                        o[2] = acc[tb][2][v];
+                    }
+                }
+        }
+    }
+}
+
 // per (target, right-hand side): its partials in near-list order, compensated, to FP64
 template <typename T>
 __global__ void k_near_reduce(const T *__restrict__ part, const int32_t *__restrict__ toff, int64_t m, int K,
@@ -343,9 +474,14 @@ void near_field(Tree &t, Plan &pl, double *unear, hipStream_t s) {
             STK_CHECK_LAUNCH();
         }
     } else {
-        if (pl.near_kb == 4)
+        if (pl.tiles.near_mfma) {
+            if (na.nitems > 0) {
+                hipLaunchKernelGGL(k_near_mfma, dim3(xcd_blocks(na.nitems)), dim3(64), 0, s, na);
+                STK_CHECK_LAUNCH();
+            }
+        } else if (pl.tiles.near_kb == 4)
             launch_near<float, 4>(na, s);
-        else if (pl.near_kb == 2)
+        else if (pl.tiles.near_kb == 2)
             launch_near<float, 2>(na, s);
         else
             launch_near<float, 1>(na, s);

@@ -121,6 +121,13 @@ struct AdjScratch {
 // ---------------------------------------------------------------------------------
 // plan handle: a tree plus one target set's interaction lists
 // ---------------------------------------------------------------------------------
+// kernel variants of one evaluation (chosen per architecture, p, K and precision)
+struct Tiles {
+    int32_t far_kb = 1;      // right-hand sides per pass of the far-field kernel (1, 2, 4)
+    int32_t near_kb = 1;     // right-hand sides per pass of the VALU near-field kernel
+    bool near_mfma = false;  // near field on the matrix cores (FP32)
+};
+
 struct Plan {
     Tree *tree = nullptr;
     bool owns_tree = false;
@@ -148,7 +155,9 @@ struct Plan {
     DBuf near_part;                // T (incidences, 3): per (target, leaf) partial velocities
     int64_t n_inc = 0;
     int32_t n_near_items = 0;
-    int32_t far_kb = 1, near_kb = 1;  // right-hand sides per pass of the far / near kernels
+    Tiles tiles;                      // kernel variants used by the last evaluation
+    bool forced = false;              // use `force` instead of the table (autotuning)
+    Tiles force;
     AdjScratch adj;
     ~Plan();
 };
@@ -177,6 +186,16 @@ void evaluate(Tree &t, Plan &plan, const double *tgt, int64_t m, double theta, d
 // NULL); w and the outputs in the caller's orders
 void adjoint(Plan &plan, const double *w, double *grad_f, double *grad_h, double *grad_targets,
              double *grad_sources, hipStream_t s);
+// kernel-variant table (tiles.hip)
+Tiles default_tiles(int K, stk_precision prec);
+bool tiles_valid(const Tiles &t, int K, stk_precision prec);
+Tiles tiles_for(int p, int K, stk_precision prec);
+bool tiles_lookup(int p, int K, stk_precision prec, Tiles *out);
+void tiles_set(int p, int K, stk_precision prec, const Tiles *t);
+void tiles_save(const char *path);
+int tiles_load(const char *path);
+Tiles autotune(int p, int K, stk_precision prec, int64_t n, double theta, int32_t n0, double *best_ms, hipStream_t s);
+
 // near field of a plan whose group-major near lists are filled: unear (m,K,3), sorted
 // target order, K = the tree's right-hand sides
 void near_field(Tree &t, Plan &plan, double *unear, hipStream_t s);

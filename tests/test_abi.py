@@ -30,3 +30,30 @@ def test_library_exports_every_declared_symbol():
 def test_binding_lists_match_header():
     from paper_1811_12498_amd import native
     assert set(native.EXPORTS) == _declared()
+
+
+def test_tiles_file_round_trip(tmp_path):
+    """The kernel-variant table's text format: a valid file merges, save writes it back,
+    and a malformed or invalid line rejects the whole file (no device needed)."""
+    from paper_1811_12498_amd import native
+    good = tmp_path / "tiles.txt"
+    good.write_text("# arch p K precision far_kb near_kb near_mfma\n"
+                    "gfx950 8 16 1 4 4 1\n"
+                    "gfx950 6 1 0 1 1 0\n")
+    assert native.tiles_load(str(good)) == 2
+    out = tmp_path / "saved.txt"
+    native.tiles_save(str(out))
+    lines = {ln for ln in out.read_text().splitlines() if not ln.startswith("#")}
+    assert {"gfx950 8 16 1 4 4 1", "gfx950 6 1 0 1 1 0"} <= lines
+    for bad in ("gfx950 8 16 1 4 4\n",          # too few fields
+                "gfx950 8 16 0 4 1 0\n",        # FP64 with 4 right-hand sides per pass
+                "gfx950 8 6 1 4 1 0\n",         # 4 does not divide K = 6
+                "gfx950 8 16 7 1 1 0\n"):       # unknown precision
+        f = tmp_path / "bad.txt"
+        f.write_text(bad)
+        try:
+            native.tiles_load(str(f))
+        except native.StkError as e:
+            assert e.status == -1
+        else:
+            raise AssertionError(f"accepted {bad!r}")

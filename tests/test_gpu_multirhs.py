@@ -65,3 +65,43 @@ def test_multi_rhs_reused_tree(nat):
     u = nat.evaluate_tree(tree, X, 0.5)
     ref = nat.evaluate(X, X, _t(w.f), _t(w.h), _t(w.nu), 6, 0.5, 100, "mixed")
     assert torch.equal(u, ref)
+
+
+@pytest.mark.parametrize("K", [16, 20])
+def test_near_mfma_matches_valu(nat, K):
+    """The matrix-core near field (FP32 sums over 16 right-hand sides per pass; K = 20
+    leaves a partial pass) against the VALU kernels, per right-hand side, and against
+    the FP64 evaluation."""
+    w = W.cube(30_000, seed=60 + K, n0=300, k=K)
+    X = _t(w.src)
+    F, H, NU = _t(w.f), _t(w.h), _t(w.nu)
+    p, theta = 6, 0.5
+    try:
+        nat.tiles_set(p, K, "mixed", far_kb=4, near_kb=4, near_mfma=False)
+        u_valu = nat.evaluate(X, X, F, H, NU, p, theta, 300, "mixed")
+        nat.tiles_set(p, K, "mixed", far_kb=4, near_kb=4, near_mfma=True)
+        u_mfma, plan = nat.evaluate(X, X, F, H, NU, p, theta, 300, "mixed", keep_plan=True)
+        assert nat.plan_tiles(plan)["near_mfma"]
+    finally:
+        nat.tiles_set(p, K, "mixed", clear=True)
+    u64 = nat.evaluate(X, X, F, H, NU, p, theta, 300, "fp64")
+    for r in range(K):
+        e_v = float((u_mfma[r] - u_valu[r]).norm() / u_valu[r].norm())
+        e_64 = float((u_mfma[r] - u64[r]).norm() / u64[r].norm())
+        assert e_v < 1e-6 and e_64 < 1e-5, (r, e_v, e_64)
+
+
+def test_autotune_records_valid_tiles(nat):
+    K, p = 8, 5
+    best, ms = nat.autotune(p, K, "mixed", 20_000, 0.6, 200)
+    assert ms > 0
+    assert best["far_kb"] in (1, 2, 4) and K % best["far_kb"] == 0
+    got, hit = nat.tiles_get(p, K, "mixed")
+    assert hit and got == best
+    w = W.cube(20_000, seed=70, n0=200, k=K)
+    X = _t(w.src)
+    u, plan = nat.evaluate(X, X, _t(w.f), _t(w.h), _t(w.nu), p, 0.6, 200, "mixed", keep_plan=True)
+    assert nat.plan_tiles(plan) == best
+    u64 = nat.evaluate(X, X, _t(w.f), _t(w.h), _t(w.nu), p, 0.6, 200, "fp64")
+    assert float((u - u64).norm() / u64.norm()) < 1e-5
+    nat.tiles_set(p, K, "mixed", clear=True)
