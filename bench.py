@@ -102,6 +102,47 @@ def fwd_adjoint_times(reps=3):
     return out
 
 
+def multi_rhs_times(reps=3):
+    """Batched workload: N = 500,000 uniform in the unit cube (seed 4), K = 16 (f, h)
+    pairs sharing positions and nu, p = 8, theta = 0.6, N0 = 2000, mixed precision, with
+    the kernel variants chosen by the library's autotuner; compared with K one-RHS calls."""
+    import torch
+
+    from paper_1811_12498_amd import native, workloads
+    w = workloads.c4_cube_multirhs()
+    K = w.f.shape[0]
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    X, F, H, NU = t(w.src), t(w.f), t(w.h), t(w.nu)
+    tiles, tune_ms = native.autotune(w.p, K, "mixed", w.n, w.theta, w.n0)
+
+    def timed(f_, h_):
+        u = native.evaluate(X, X, f_, h_, NU, w.p, w.theta, w.n0, "mixed")
+        torch.cuda.synchronize()
+        native.profile_read()
+        native.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            u = native.evaluate(X, X, f_, h_, NU, w.p, w.theta, w.n0, "mixed")
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        native.profile_enable(False)
+        prof = native.profile_read()
+        return u, ms, {k: round(v[0] / max(v[1], 1), 3) for k, v in prof.items() if v[1]}
+
+    u, ms, phases = timed(F, H)
+    f0, h0 = F[0].contiguous(), H[0].contiguous()
+    _, ms1, _ = timed(f0, h0)
+    S = torch.from_numpy(w.sample).to(dev)
+    ud = native.direct(X[S].contiguous(), X, f0, h0, NU)
+    err = float(torch.linalg.norm(u[0][S] - ud) / torch.linalg.norm(ud))
+    return {"workload": f"cube N={w.n}, K={K}, p={w.p}, theta={w.theta}, N0={w.n0}, mixed",
+            "ms": round(ms, 3), "rhs_targets_per_s": K * w.n / (ms * 1e-3), "tiles": tiles,
+            "autotune_best_ms": round(tune_ms, 3), "one_rhs_ms": round(ms1, 3),
+            "batch_speedup_vs_K_calls": round(K * ms1 / ms, 3), "phase_ms": phases,
+            "E_S_rhs0_vs_fp64_direct": err, "sample_targets": int(w.sample.size)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -224,6 +265,8 @@ def main():
     if not args.no_extras:
         extras["fwd_adjoint"] = fwd_adjoint_times()
         log(f"fwd+adjoint: {extras['fwd_adjoint']}")
+        extras["multi_rhs"] = multi_rhs_times()
+        log(f"multi-rhs: {extras['multi_rhs']}")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -9,8 +9,9 @@ namespace stk {
 // ---------------------------------------------------------------------------------
 // coefficients bt^q of one (target, cluster) pair up to order PB in registers: the
 // scaled recurrence_1 for layers k3 <= 1 and the harmonic fill for k3 >= 2 (the same
-// arithmetic as FarEval), calling Visit::coef<Q, N>(bq) as each coefficient is formed
-// and Visit::order_done<N>(b) after each order
+// arithmetic as FarEval), calling Visit::coef<Q, N>(bq) as each coefficient is formed,
+// Visit::layer_done<N, J>(b) after layer k3 = J of order N and Visit::order_done<N>(b)
+// after each order
 // ---------------------------------------------------------------------------------
 template <int PB, typename T, class Visit> struct Coefs {
     static constexpr int NB = nidx(PB);
@@ -42,6 +43,7 @@ template <int PB, typename T, class Visit> struct Coefs {
     template <int N, int J> STK_HD static void layers(T (&b)[NB], const T dh[3], T c1, T c2, Visit &v) {
         if constexpr (J <= N) {
             layer<N, J, N - J>(b, dh, c1, c2, v);
+            v.template layer_done<N, J>(b);
             layers<N, J + 1>(b, dh, c1, c2, v);
         }
     }
@@ -95,6 +97,8 @@ template <int P, typename T> struct LambdaVisit {
         }
         __syncthreads();
     }
+
+    template <int N, int J> STK_HD void layer_done(const T (&)[nidx(P + 2)]) {}
 
     template <int N> STK_HD void order_done(const T (&b)[nidx(P + 2)]) {
         // G columns of order N (already written by coef)
@@ -174,59 +178,58 @@ template <int P, typename T> struct TgradVisit {
     T a1[3], a2[3], a3[3];
 
     template <int Q, int N> STK_HD void coef(T) {}
+    template <int N> STK_HD void order_done(const T (&)[nidx(P + 3)]) {}
 
-    // at order N (coefficients 0..N exist):
-    //  term 1 for q of order N-1 (<= P+1): (w.Ghat^q) (q_s+1) bt^{q+e_s}
-    //  term 3 for k of order N-1 (<= P+1): Ehat_s^k zh^k
-    //  term 2 for k of order N-2 (<= P+1): (dh.Ehat^k) sum_i w_i (k_i+1)(k_s+1+delta_is) bt^{k+e_i+e_s}
-    template <int N> STK_HD void order_done(const T (&b)[nidx(P + 3)]) {
-        // the fence pins this order's scalar loads after the previous order's sums
+    // after layer k3 = J of order N (layers 0..J of order N exist):
+    //  term 1 for q of order N-1 in layer J-1 (<= P+1): (w.Ghat^q) (q_s+1) bt^{q+e_s}
+    //  term 3 for k of order N-1 in layer J-1 (<= P+1): Ehat_s^k zh^k
+    //  term 2 for k of order N-2 in layer J-2 (<= P+1):
+    //      (dh.Ehat^k) sum_i w_i (k_i+1)(k_s+1+delta_is) bt^{k+e_i+e_s}
+    // so each layer of order N is last read two layers later and the coefficients alive
+    // at a time are three layers of the current order plus those the recurrence keeps
+    template <int N, int J> STK_HD void layer_done(const T (&b)[nidx(P + 3)]) {
+        // the fence pins this layer's scalar loads after the previous layer's sums
         const T *__restrict__ Wf = W + FarEval<P, T>::fence(a1[0] + a2[0] + a3[0]);
-        if constexpr (N >= 1 && N - 1 <= P + 1) walk13<N - 1, 0>(b, Wf);
-        if constexpr (N >= 2 && N - 2 <= P + 1) walk2<N - 2, 0>(b, Wf);
+        if constexpr (J >= 1 && N - 1 <= P + 1) walk13<N - 1, J - 1, N - J>(b, Wf);
+        if constexpr (J >= 2 && N - 2 <= P + 1) walk2<N - 2, J - 2, N - J>(b, Wf);
     }
 
-    template <int M, int A> STK_HD void walk13(const T (&b)[nidx(P + 3)], const T *__restrict__ W) {
-        if constexpr (A < (M + 1) * (M + 2) / 2) {
-            constexpr int Q = (M > 0 ? nidx(M - 1) : 0) + A;
-            constexpr int K1 = kof1c(Q), K2 = kof2c(Q), K3 = M - K1 - K2;
-            constexpr int kk[3] = {K1, K2, K3};
-            int pg = 0, pe = 0;
-            stream_pos_c(kk, pg, pe);
-            const T g = wl[0] * W[pg] + wl[1] * W[pg + 1] + wl[2] * W[pg + 2];
-            const T bx = b[gidx(K1 + 1, K2, K3)], by = b[gidx(K1, K2 + 1, K3)], bz = b[gidx(K1, K2, K3 + 1)];
-            a1[0] += g * (T(K1 + 1) * bx);
-            a1[1] += g * (T(K2 + 1) * by);
-            a1[2] += g * (T(K3 + 1) * bz);
-            const T z = wl[0] * (T(K1 + 1) * bx) + wl[1] * (T(K2 + 1) * by) + wl[2] * (T(K3 + 1) * bz);
-            a3[0] += W[pe] * z;
-            a3[1] += W[pe + 1] * z;
-            a3[2] += W[pe + 2] * z;
-            walk13<M, A + 1>(b, W);
-        }
+    // k of order M in layer k3 = K3, k1 = K1 .. 0
+    template <int M, int K3, int K1> STK_HD void walk13(const T (&b)[nidx(P + 3)], const T *__restrict__ W) {
+        constexpr int K2 = M - K3 - K1;
+        constexpr int kk[3] = {K1, K2, K3};
+        int pg = 0, pe = 0;
+        stream_pos_c(kk, pg, pe);
+        const T g = wl[0] * W[pg] + wl[1] * W[pg + 1] + wl[2] * W[pg + 2];
+        const T bx = b[gidx(K1 + 1, K2, K3)], by = b[gidx(K1, K2 + 1, K3)], bz = b[gidx(K1, K2, K3 + 1)];
+        a1[0] += g * (T(K1 + 1) * bx);
+        a1[1] += g * (T(K2 + 1) * by);
+        a1[2] += g * (T(K3 + 1) * bz);
+        const T z = wl[0] * (T(K1 + 1) * bx) + wl[1] * (T(K2 + 1) * by) + wl[2] * (T(K3 + 1) * bz);
+        a3[0] += W[pe] * z;
+        a3[1] += W[pe + 1] * z;
+        a3[2] += W[pe + 2] * z;
+        if constexpr (K1 > 0) walk13<M, K3, K1 - 1>(b, W);
     }
 
-    template <int M, int A> STK_HD void walk2(const T (&b)[nidx(P + 3)], const T *__restrict__ W) {
-        if constexpr (A < (M + 1) * (M + 2) / 2) {
-            constexpr int Q = (M > 0 ? nidx(M - 1) : 0) + A;
-            constexpr int K1 = kof1c(Q), K2 = kof2c(Q), K3 = M - K1 - K2;
-            constexpr int kk[3] = {K1, K2, K3};
-            int pg = 0, pe = 0;
-            stream_pos_c(kk, pg, pe);
-            const T sig = dh[0] * W[pe] + dh[1] * W[pe + 1] + dh[2] * W[pe + 2];
-            // h_s = sum_i w_i (k_i+1)(k_s+1+delta_is) bt^{k+e_i+e_s}
-            const T w0 = wl[0] * T(K1 + 1), w1 = wl[1] * T(K2 + 1), w2 = wl[2] * T(K3 + 1);
-            const T hx = w0 * T(K1 + 2) * b[gidx(K1 + 2, K2, K3)] + w1 * T(K1 + 1) * b[gidx(K1 + 1, K2 + 1, K3)] +
-                         w2 * T(K1 + 1) * b[gidx(K1 + 1, K2, K3 + 1)];
-            const T hy = w0 * T(K2 + 1) * b[gidx(K1 + 1, K2 + 1, K3)] + w1 * T(K2 + 2) * b[gidx(K1, K2 + 2, K3)] +
-                         w2 * T(K2 + 1) * b[gidx(K1, K2 + 1, K3 + 1)];
-            const T hz = w0 * T(K3 + 1) * b[gidx(K1 + 1, K2, K3 + 1)] + w1 * T(K3 + 1) * b[gidx(K1, K2 + 1, K3 + 1)] +
-                         w2 * T(K3 + 2) * b[gidx(K1, K2, K3 + 2)];
-            a2[0] += sig * hx;
-            a2[1] += sig * hy;
-            a2[2] += sig * hz;
-            walk2<M, A + 1>(b, W);
-        }
+    template <int M, int K3, int K1> STK_HD void walk2(const T (&b)[nidx(P + 3)], const T *__restrict__ W) {
+        constexpr int K2 = M - K3 - K1;
+        constexpr int kk[3] = {K1, K2, K3};
+        int pg = 0, pe = 0;
+        stream_pos_c(kk, pg, pe);
+        const T sig = dh[0] * W[pe] + dh[1] * W[pe + 1] + dh[2] * W[pe + 2];
+        // h_s = sum_i w_i (k_i+1)(k_s+1+delta_is) bt^{k+e_i+e_s}
+        const T w0 = wl[0] * T(K1 + 1), w1 = wl[1] * T(K2 + 1), w2 = wl[2] * T(K3 + 1);
+        const T hx = w0 * T(K1 + 2) * b[gidx(K1 + 2, K2, K3)] + w1 * T(K1 + 1) * b[gidx(K1 + 1, K2 + 1, K3)] +
+                     w2 * T(K1 + 1) * b[gidx(K1 + 1, K2, K3 + 1)];
+        const T hy = w0 * T(K2 + 1) * b[gidx(K1 + 1, K2 + 1, K3)] + w1 * T(K2 + 2) * b[gidx(K1, K2 + 2, K3)] +
+                     w2 * T(K2 + 1) * b[gidx(K1, K2 + 1, K3 + 1)];
+        const T hz = w0 * T(K3 + 1) * b[gidx(K1 + 1, K2, K3 + 1)] + w1 * T(K3 + 1) * b[gidx(K1, K2 + 1, K3 + 1)] +
+                     w2 * T(K3 + 2) * b[gidx(K1, K2, K3 + 2)];
+        a2[0] += sig * hx;
+        a2[1] += sig * hy;
+        a2[2] += sig * hz;
+        if constexpr (K1 > 0) walk2<M, K3, K1 - 1>(b, W);
     }
 
     STK_HD static constexpr void stream_pos_c(const int (&k)[3], int &g, int &e) {
