@@ -82,55 +82,86 @@ struct NearAdjArgs {
     int32_t nitems;
 };
 
-template <typename T> __global__ __launch_bounds__(64) void k_near_tgrad(NearAdjArgs a) {
-    const int32_t ng = int32_t((a.m + 63) / 64);
-    const int32_t g = xcd_group(ng);
-    if (g >= ng) return;
+// target side, leaf major (the forward plan's near work items): one wave per item, a
+// leaf against up to 64 of its targets; each incidence's partial gradient goes to its
+// slot in the target's near list, and k_slot_reduce adds the slots in list order (the
+// same sums, in the same order, as a walk of each target's own list)
+struct NearTgradArgs {
+    const double *tpos, *ws;
+    const int32_t *item_leaf, *item_i0, *item_i1;
+    const int32_t *inc_tgt, *inc_slot;
+    const int32_t *start, *count;
+    const double *geo;           // (n,6) y, nu
+    const void *wts;             // (n,6) f, h in T
+    void *part;                  // (incidences, 3) T
+    int32_t nitems;
+};
+
+template <typename T> __global__ __launch_bounds__(64) void k_near_tgrad(NearTgradArgs a) {
+    const int32_t it = xcd_group(a.nitems);
+    if (it >= a.nitems) return;
     const int lane = threadIdx.x;
-    const int64_t t = int64_t(g) * 64 + lane;
-    const bool valid = t < a.m;
+    const int32_t c = a.item_leaf[it];
+    const int32_t i0 = a.item_i0[it];
+    const bool on = lane < a.item_i1[it] - i0;
+    int32_t slot = 0;
     double x[3] = {0, 0, 0}, w[3] = {0, 0, 0};
-    if (valid)
+    if (on) {
+        const int64_t t = a.inc_tgt[i0 + lane];
+        slot = a.inc_slot[i0 + lane];
         for (int q = 0; q < 3; ++q) {
             x[q] = a.tpos[3 * t + q];
             w[q] = a.ws[3 * t + q];
         }
-    const T *wts = static_cast<const T *>(a.wts);
-    Comp<T> acc[3];
-    for (int32_t e = a.off[g]; e < a.off[g + 1]; ++e) {
-        const int32_t c = __builtin_amdgcn_readfirstlane(a.node[e]);
-        const uint64_t mk = a.mask[e];
-        if ((mk >> lane) & 1ull) {
-            T s0 = T(0), s1 = T(0), s2 = T(0);
-            for (int32_t j = a.start[c]; j < a.start[c] + a.count[c]; ++j) {
-                const double *gj = a.geo + 6 * int64_t(j);
-                const T *wj = wts + 6 * int64_t(j);
-                const double d[3] = {x[0] - gj[0], x[1] - gj[1], x[2] - gj[2]};
-                if constexpr (sizeof(T) == 8) {
-                    double gx[3];
-                    pgrad_f64(d, reinterpret_cast<const double *>(wj), reinterpret_cast<const double *>(wj) + 3, gj + 3, w,
-                              gx);
-                    s0 += gx[0];
-                    s1 += gx[1];
-                    s2 += gx[2];
-                } else {
-                    const double dn = d[0] * gj[3] + d[1] * gj[4] + d[2] * gj[5];
-                    const float wf[3] = {float(w[0]), float(w[1]), float(w[2])};
-                    float gx[3];
-                    pgrad_mixed(d, dn, reinterpret_cast<const float *>(wj), reinterpret_cast<const float *>(wj) + 3,
-                                gj + 3, wf, gx);
-                    s0 += gx[0];
-                    s1 += gx[1];
-                    s2 += gx[2];
-                }
-            }
-            acc[0].add(s0);
-            acc[1].add(s1);
-            acc[2].add(s2);
+    }
+    // read-only source records through the constant address space (scalar loads)
+    const STK_CONST_AS double *geo = (const STK_CONST_AS double *)(a.geo);
+    const STK_CONST_AS T *wts = (const STK_CONST_AS T *)(a.wts);
+    const float wf[3] = {float(w[0]), float(w[1]), float(w[2])};
+    T s0 = T(0), s1 = T(0), s2 = T(0);
+    const int32_t j0 = a.start[c], j1 = j0 + a.count[c];
+    for (int32_t j = j0; j < j1; ++j) {
+        double gj[6];
+        T wj[6];
+        for (int q = 0; q < 6; ++q) {
+            gj[q] = geo[6 * int64_t(j) + q];
+            wj[q] = wts[6 * int64_t(j) + q];
+        }
+        const double d[3] = {x[0] - gj[0], x[1] - gj[1], x[2] - gj[2]};
+        if constexpr (sizeof(T) == 8) {
+            double gx[3];
+            pgrad_f64(d, reinterpret_cast<const double *>(wj), reinterpret_cast<const double *>(wj) + 3, gj + 3, w, gx);
+            s0 += gx[0];
+            s1 += gx[1];
+            s2 += gx[2];
+        } else {
+            const double dn = d[0] * gj[3] + d[1] * gj[4] + d[2] * gj[5];
+            float gx[3];
+            pgrad_mixed(d, dn, reinterpret_cast<const float *>(wj), reinterpret_cast<const float *>(wj) + 3, gj + 3,
+                        wf, gx);
+            s0 += gx[0];
+            s1 += gx[1];
+            s2 += gx[2];
         }
     }
-    if (valid)
-        for (int q = 0; q < 3; ++q) a.gt[3 * t + q] = acc[q].value();
+    if (on) {
+        T *o = static_cast<T *>(a.part) + 3 * int64_t(slot);
+        o[0] = s0;
+        o[1] = s1;
+        o[2] = s2;
+    }
+}
+
+// per target: its slots in near-list order, compensated, to FP64 (m,3)
+template <typename T>
+__global__ void k_slot_reduce(const T *__restrict__ part, const int32_t *__restrict__ toff, int64_t m,
+                              double *__restrict__ out) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= m) return;
+    Comp<T> acc[3];
+    for (int32_t k = toff[t]; k < toff[t + 1]; ++k)
+        for (int q = 0; q < 3; ++q) acc[q].add(part[3 * int64_t(k) + q]);
+    for (int q = 0; q < 3; ++q) out[3 * t + q] = acc[q].value();
 }
 
 // one source per lane; loops over every near entry of its leaf and the targets of each
@@ -491,10 +522,26 @@ void adjoint(Plan &pl, const double *w, double *gf, double *gh, double *gt, doub
         gtn = reserve<double>(A.gt_near, size_t(m) * 3);
         gtf = reserve<double>(A.gt_far, size_t(m) * 3);
         na.gt = gtn;
-        if (fp64)
-            hipLaunchKernelGGL(k_near_tgrad<double>, dim3(xcd_blocks(ng)), dim3(64), 0, s, na);
-        else
-            hipLaunchKernelGGL(k_near_tgrad<float>, dim3(xcd_blocks(ng)), dim3(64), 0, s, na);
+        NearTgradArgs nt{pl.tpos.as<double>(), ws, pl.item_leaf.as<int32_t>(), pl.item_i0.as<int32_t>(),
+                         pl.item_i1.as<int32_t>(), pl.inc_tgt.as<int32_t>(), pl.inc_slot.as<int32_t>(),
+                         t.nstart.as<int32_t>(), t.ncount.as<int32_t>(), t.geo.as<double>(), t.wts.p,
+                         pl.near_part.p, pl.n_near_items};
+        const int32_t *toff = pl.near_toff.as<int32_t>();
+        if (fp64) {
+            if (nt.nitems > 0) {
+                hipLaunchKernelGGL(k_near_tgrad<double>, dim3(xcd_blocks(nt.nitems)), dim3(64), 0, s, nt);
+                STK_CHECK_LAUNCH();
+            }
+            hipLaunchKernelGGL(k_slot_reduce<double>, dim3(nblk(m, 256)), dim3(256), 0, s,
+                               static_cast<const double *>(nt.part), toff, m, gtn);
+        } else {
+            if (nt.nitems > 0) {
+                hipLaunchKernelGGL(k_near_tgrad<float>, dim3(xcd_blocks(nt.nitems)), dim3(64), 0, s, nt);
+                STK_CHECK_LAUNCH();
+            }
+            hipLaunchKernelGGL(k_slot_reduce<float>, dim3(nblk(m, 256)), dim3(256), 0, s,
+                               static_cast<const float *>(nt.part), toff, m, gtn);
+        }
         STK_CHECK_LAUNCH();
     }
 
