@@ -49,9 +49,23 @@ def _order_key(path: str, times: dict) -> tuple:
     return (-(1000 + int(m.group(1))) if m else 0.0, name)
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
+def _stale(src: str, newest_header: float) -> bool:
+    obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
+    if not os.path.exists(obj):
+        return True
+    return os.path.getmtime(obj) < max(os.path.getmtime(src), newest_header)
+
+
+def build(jobs: int | None = None, verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every .hip under csrc/ and link the library.  incremental=True recompiles
+    only sources older than their object or than any header (csrc/*.hpp, include/*.h)."""
     os.makedirs(OBJDIR, exist_ok=True)
     srcs = glob.glob(os.path.join(CSRC, "*.hip"))
+    all_srcs = sorted(srcs)
+    if incremental:
+        headers = glob.glob(os.path.join(CSRC, "*.hpp")) + glob.glob(os.path.join(ROOT, "include", "*.h"))
+        newest = max((os.path.getmtime(h) for h in headers), default=0.0)
+        srcs = [sp for sp in srcs if _stale(sp, newest)]
     try:
         with open(TIMES) as fh:
             times = json.load(fh)
@@ -61,7 +75,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     jobs = jobs or min(16, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(jobs) as ex:
         res = list(ex.map(_compile, srcs))
-    objs = [o for o, _ in res]
+    objs = [os.path.join(OBJDIR, os.path.basename(sp) + ".o") for sp in all_srcs]
     times.update({os.path.basename(sp): round(dt, 1) for sp, (_, dt) in zip(srcs, res)})
     with open(TIMES, "w") as fh:
         json.dump(times, fh, indent=0, sort_keys=True)

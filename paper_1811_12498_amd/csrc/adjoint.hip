@@ -243,7 +243,7 @@ struct PhiT {
     int p = -1;
     DBuf col_off, rowpos, epow;  // int32
     DBuf coef;                   // double
-    DBuf colpos;                 // int32 (orders, 2, 64) for k_far_lambda
+    DBuf cpos, ckind;            // int32 (batches, lam_tbl) for k_far_lambda
 };
 
 std::mutex g_phit_mu;
@@ -294,23 +294,22 @@ PhiT &phit_for(int dev, int p) {
             mom[size_t(a) * 12 + c] = 0.0;
         }
     }
-    // LDS column -> stream position tables of k_far_lambda: row (2n + kind), kind 0 = G
-    // of order n, kind 1 = E of order n - 1; column = graded-lex position in that order
-    const int PB = p + 2;
-    std::vector<int32_t> colpos(size_t(PB + 1) * 2 * LAM_ROW, 0);
-    for (int n = 0; n <= PB; ++n)
-        for (int kind = 0; kind < 2; ++kind) {
-            const int ord = kind == 0 ? n : n - 1;
-            if (ord < 0 || ord > p + 1) continue;
-            const int cnt = (ord + 1) * (ord + 2) / 2, base = ord > 0 ? nidx(ord - 1) : 0;
-            if (cnt > LAM_ROW) throw Error(STK_EINVAL, "order too large for the adjoint column table");
-            for (int col = 0; col < cnt; ++col) {
-                int q[3], pg, pe;
-                kof(base + col, q);
-                stream_pos(p, q, pg, pe);
-                colpos[size_t(2 * n + kind) * LAM_ROW + col] = kind == 0 ? pg : pe;
-            }
+    // LDS column -> stream position and weight kind of k_far_lambda, per column batch
+    const int TBL = lam_tbl(p), NBT = lam_nbatch(p);
+    std::vector<int32_t> cpos(size_t(NBT) * TBL, 0), ckind(size_t(NBT) * TBL, 0);
+    for (int g = 0; g < lam_ngroup(p); ++g) {
+        const int n = g >> 1, kind = g & 1, ord = kind ? n - 1 : n;
+        const int cnt = lam_gsize(p, g);
+        if (cnt == 0) continue;
+        const int base = ord > 0 ? nidx(ord - 1) : 0, bt = lam_batch(p, g), off = lam_off(p, g);
+        for (int col = 0; col < cnt; ++col) {
+            int q[3], pg, pe;
+            kof(base + col, q);
+            stream_pos(p, q, pg, pe);
+            cpos[size_t(bt) * TBL + off + col] = kind == 0 ? pg : pe;
+            ckind[size_t(bt) * TBL + off + col] = kind;
         }
+    }
     auto *t = new PhiT();
     t->p = p;
     auto up = [](DBuf &d, const void *src, size_t bytes) {
@@ -321,7 +320,8 @@ PhiT &phit_for(int dev, int p) {
     up(t->rowpos, rowpos.data(), sizeof(int32_t) * rowpos.size());
     up(t->coef, coef.data(), sizeof(double) * coef.size());
     up(t->epow, epow.data(), sizeof(int32_t) * epow.size());
-    up(t->colpos, colpos.data(), sizeof(int32_t) * colpos.size());
+    up(t->cpos, cpos.data(), sizeof(int32_t) * cpos.size());
+    up(t->ckind, ckind.data(), sizeof(int32_t) * ckind.size());
     g_phit[key] = t;
     return *t;
 }
@@ -564,7 +564,8 @@ void adjoint(Plan &pl, const double *w, double *gf, double *gh, double *gt, doub
         la.mask = pl.far_mask.as<uint64_t>();
         la.center = t.ncenter.as<double>();
         la.rho = t.nrho.as<double>();
-        la.colpos = ph.colpos.as<int32_t>();
+        la.cpos = ph.cpos.as<int32_t>();
+        la.ckind = ph.ckind.as<int32_t>();
         la.lambda = lam;
         la.nitems = A.far_t.nitems;
     }

@@ -36,28 +36,66 @@ struct LambdaArgs {
     const int32_t *ent_group;  // far entry -> group
     const uint64_t *mask;      // far entry -> lane mask
     const double *center, *rho;
-    const int32_t *colpos;     // (orders, 2, LAM_ROW): stream position of each LDS column
+    const int32_t *cpos;       // (batches, lam_tbl): stream position of each LDS column
+    const int32_t *ckind;      // (batches, lam_tbl): 0 = G column (weights w / R), 1 = E column (weights dh)
     double *lambda;            // (nn, 6 nG) adjoint of the cluster streams, accumulated
     int32_t nitems;
 };
 
 constexpr int LPITCH = 65;   // LDS row pitch (targets), padded against bank conflicts
-constexpr int LAM_ROW = 128; // entries per row of the column -> stream position table
 
-template <int P> __host__ __device__ constexpr int lam_ncol_g(int n) { return n <= P + 1 ? (n + 1) * (n + 2) / 2 : 0; }
-template <int P> __host__ __device__ constexpr int lam_ncol_e(int n) { return n >= 1 ? n * (n + 1) / 2 : 0; }
-template <int P> __host__ __device__ constexpr int lam_maxcol() {
-    int m = 1;
-    for (int n = 0; n <= P + 2; ++n) {
-        if (lam_ncol_g<P>(n) > m) m = lam_ncol_g<P>(n);
-        if (lam_ncol_e<P>(n) > m) m = lam_ncol_e<P>(n);
-    }
+// The LDS columns of k_far_lambda (one value per target lane), in the order they are
+// formed: group 2n = the G columns of order n (n <= p + 1), group 2n + 1 = the E columns
+// of order n - 1 (n = 1 .. p + 2).  Groups are packed greedily into batches of at most
+// lam_tbl(p) columns, and each batch is reduced over the 64 targets in one pass.
+__host__ __device__ constexpr int lam_gsize(int p, int g) {
+    const int n = g >> 1;
+    if (g & 1) return n >= 1 ? n * (n + 1) / 2 : 0;
+    return n <= p + 1 ? (n + 1) * (n + 2) / 2 : 0;
+}
+__host__ __device__ constexpr int lam_ngroup(int p) { return 2 * (p + 3); }
+__host__ __device__ constexpr int lam_tbl(int p) {
+    int m = 64;
+    for (int g = 0; g < lam_ngroup(p); ++g) m = lam_gsize(p, g) > m ? lam_gsize(p, g) : m;
     return m;
 }
-// LDS of one work item: the FP64 stream accumulator first (8-byte aligned), then the
+__host__ __device__ constexpr int lam_batch(int p, int g) {
+    int pend = 0, b = 0;
+    for (int x = 0; x <= g; ++x) {
+        const int sz = lam_gsize(p, x);
+        if (pend + sz > lam_tbl(p)) {
+            ++b;
+            pend = 0;
+        }
+        pend += sz;
+    }
+    return b;
+}
+// first column of group g within its batch
+__host__ __device__ constexpr int lam_off(int p, int g) {
+    int pend = 0;
+    for (int x = 0; x <= g; ++x) {
+        const int sz = lam_gsize(p, x);
+        if (pend + sz > lam_tbl(p)) pend = 0;
+        if (x == g) return pend;
+        pend += sz;
+    }
+    return 0;
+}
+__host__ __device__ constexpr int lam_nbatch(int p) { return lam_batch(p, lam_ngroup(p) - 1) + 1; }
+__host__ __device__ constexpr int lam_bcount(int p, int b) {
+    int c = 0;
+    for (int g = 0; g < lam_ngroup(p); ++g)
+        if (lam_batch(p, g) == b) c += lam_gsize(p, g);
+    return c;
+}
+__host__ __device__ constexpr bool lam_last_in_batch(int p, int g) {
+    return g == lam_ngroup(p) - 1 || lam_batch(p, g + 1) != lam_batch(p, g);
+}
+// LDS of one work item: the stream accumulator (evaluation precision) first, then the
 // column table and the two weight tables
 template <int P, typename T> __host__ __device__ constexpr size_t lam_lds_bytes() {
-    return sizeof(double) * 6 * nidx(P + 1) + sizeof(T) * (size_t(lam_maxcol<P>()) * LPITCH + 6 * 64);
+    return sizeof(T) * (6 * size_t(nidx(P + 1)) + size_t(lam_tbl(P)) * LPITCH + 6 * 64);
 }
 
 // ---------------------------------------------------------------------------------

@@ -65,22 +65,27 @@ template <int PB, typename T, class Visit> struct Coefs {
 };
 
 template <int P, typename T> struct LambdaVisit {
+    static constexpr int TBL = lam_tbl(P);
     T *cols;       // [col][LPITCH]
     const T *cw;   // [3][64] w_i / R per target (0 for lanes outside the mask)
     const T *dw;   // [3][64] dh_l per target (0 outside the mask)
-    double *acc;   // [6 nG] LDS accumulator in stream order
-    const int32_t *colpos;
+    T *acc;        // [6 nG] LDS accumulator in stream order
+    const int32_t *cpos, *ckind;
     T wl[3];       // this lane's w
     int lane;
 
     template <int Q, int N> STK_HD void coef(T bq) {
-        if constexpr (N <= P + 1) cols[(Q - (N > 0 ? nidx(N - 1) : 0)) * LPITCH + lane] = bq;
+        if constexpr (N <= P + 1) {
+            constexpr int COL = lam_off(P, 2 * N) + Q - (N > 0 ? nidx(N - 1) : 0);
+            cols[COL * LPITCH + lane] = bq;
+        }
     }
 
-    // reduce columns [0, nc) of the LDS table over the 64 targets with weights wt
-    STK_HD void reduce(int nc, const T *wt, const int32_t *pos) {
+    // reduce the nc columns of batch bt over the 64 targets, each with its weights
+    STK_HD void reduce(int nc, int bt) {
         __syncthreads();
         for (int col = lane; col < nc; col += 64) {
+            const T *wt = ckind[bt * TBL + col] ? dw : cw;
             T a0 = T(0), a1 = T(0), a2 = T(0);
             const T *row = cols + col * LPITCH;
 #pragma unroll 4
@@ -90,25 +95,28 @@ template <int P, typename T> struct LambdaVisit {
                 a1 += wt[64 + mm] * v;
                 a2 += wt[128 + mm] * v;
             }
-            const int p0 = pos[col];
-            acc[p0] += double(a0);
-            acc[p0 + 1] += double(a1);
-            acc[p0 + 2] += double(a2);
+            const int p0 = cpos[bt * TBL + col];
+            acc[p0] += a0;
+            acc[p0 + 1] += a1;
+            acc[p0 + 2] += a2;
         }
         __syncthreads();
+    }
+
+    // after group G is complete: reduce its batch if G closes it
+    template <int G> STK_HD void close_group() {
+        constexpr int BT = lam_batch(P, G);
+        constexpr int NC = lam_bcount(P, BT);
+        if constexpr (lam_last_in_batch(P, G) && NC > 0) reduce(NC, BT);
     }
 
     template <int N, int J> STK_HD void layer_done(const T (&)[nidx(P + 2)]) {}
 
     template <int N> STK_HD void order_done(const T (&b)[nidx(P + 2)]) {
-        // G columns of order N (already written by coef)
-        if constexpr (N <= P + 1) reduce(lam_ncol_g<P>(N), cw, colpos + (2 * N) * LAM_ROW);
+        close_group<2 * N>();  // the G columns of order N (written by coef)
         // E columns: zh^k for k of order N - 1
-        if constexpr (N >= 1) {
-            constexpr int M = N - 1;
-            ecol<N, M, 0>(b);
-            reduce(lam_ncol_e<P>(N), dw, colpos + (2 * N + 1) * LAM_ROW);
-        }
+        if constexpr (N >= 1) ecol<N, N - 1, 0>(b);
+        close_group<2 * N + 1>();
     }
 
     // zh^k = sum_i w_i (k_i+1) bt^{k+e_i} for every k of order M, in graded-lex order
@@ -118,25 +126,26 @@ template <int P, typename T> struct LambdaVisit {
             constexpr int K1 = kof1c(Q), K2 = kof2c(Q), K3 = M - K1 - K2;
             const T z = wl[0] * (T(K1 + 1) * b[gidx(K1 + 1, K2, K3)]) + wl[1] * (T(K2 + 1) * b[gidx(K1, K2 + 1, K3)]) +
                         wl[2] * (T(K3 + 1) * b[gidx(K1, K2, K3 + 1)]);
-            cols[A * LPITCH + lane] = z;
+            constexpr int COL = lam_off(P, 2 * N + 1) + A;
+            cols[COL * LPITCH + lane] = z;
             ecol<N, M, A + 1>(b);
         }
     }
-
 };
 
 template <int P, typename T> __global__ __launch_bounds__(64) void k_far_lambda(LambdaArgs a) {
     constexpr int NG = nidx(P + 1);
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    double *acc = reinterpret_cast<double *>(lds_raw);
-    T *cols = reinterpret_cast<T *>(acc + 6 * NG);
-    T *cw = cols + lam_maxcol<P>() * LPITCH;
+    T *acc = reinterpret_cast<T *>(lds_raw);
+    T *cols = acc + 6 * NG;
+    constexpr int TBL = lam_tbl(P);
+    T *cw = cols + TBL * LPITCH;
     T *dw = cw + 192;
     const int lane = threadIdx.x;
     const int32_t it = blockIdx.x;
     if (it >= a.nitems) return;
     const int32_t c = a.item_node[it];
-    for (int q = lane; q < 6 * NG; q += 64) acc[q] = 0.0;
+    for (int q = lane; q < 6 * NG; q += 64) acc[q] = T(0);
     const double c0 = a.center[3 * c], c1 = a.center[3 * c + 1], c2 = a.center[3 * c + 2];
     const double rho = a.rho[c];
     for (int32_t e = a.item_e0[it]; e < a.item_e1[it]; ++e) {
@@ -163,13 +172,13 @@ template <int P, typename T> __global__ __launch_bounds__(64) void k_far_lambda(
             cw[64 * i + lane] = wl[i] * ri;
             dw[64 * i + lane] = in ? dh[i] : T(0);
         }
-        LambdaVisit<P, T> v{cols, cw, dw, acc, a.colpos, {wl[0], wl[1], wl[2]}, lane};
+        LambdaVisit<P, T> v{cols, cw, dw, acc, a.cpos, a.ckind, {wl[0], wl[1], wl[2]}, lane};
         T b[nidx(P + 2)];
         Coefs<P + 2, T, LambdaVisit<P, T>>::run(b, dh, tt, v);
     }
     __syncthreads();
     double *out = a.lambda + size_t(c) * 6 * NG;
-    for (int q = lane; q < 6 * NG; q += 64) atomicAdd(out + q, acc[q]);
+    for (int q = lane; q < 6 * NG; q += 64) atomicAdd(out + q, double(acc[q]));
 }
 
 template <int P, typename T> struct TgradVisit {
