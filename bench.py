@@ -48,7 +48,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, f, h, n_sample=2000, seed=99):
+def cpu_baseline(w, f, h, n_sample=100_000, seed=99):
     """The FP64 oracle on the host: tree + moments for all N, then Algorithm 1 at a
     seeded sample of targets; extrapolated to whole-job targets/s."""
     import oracle
@@ -65,6 +65,26 @@ def cpu_baseline(w, f, h, n_sample=2000, seed=99):
     return {"value": w.n / t_job, "unit": "targets/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"tree+moments for all {w.n} sources ({t1 - t0:.2f} s) + Algorithm 1 at {n_sample} "
                       f"seeded targets ({t2 - t1:.2f} s), extrapolated to {w.n} targets"}
+
+
+def profiled_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (profiles/k_far_sphere1m_p8_mixed.md: FETCH_SIZE and WRITE_SIZE runs scaled by a plain
+    copy's readings), or None when the kernel's sources have changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_far_sphere1m_p8_mixed.md")
+    try:
+        text = open(path).read()
+        rec = json.loads(text.split("<!-- traffic-record ", 1)[1].split(" -->", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if rec.get("kernel") != kernel:
+        return None
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as fh:
+            h.update(fh.read())
+    return rec["bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
 
 
 def fwd_adjoint_times(reps=3):
@@ -153,6 +173,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 comparison runs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 256 MiB device copy (a reference for HBM counters)")
+    ap.add_argument("--only", choices=["fwd_adjoint", "multi_rhs"],
+                    help="run only this secondary measurement and print its JSON object (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -163,6 +185,11 @@ def main():
     import torch
 
     from paper_1811_12498_amd import native, workloads
+
+    if args.only:
+        res = fwd_adjoint_times() if args.only == "fwd_adjoint" else multi_rhs_times()
+        print(json.dumps(res), flush=True)
+        return
 
     w = workloads.c3_sphere_1m()
     f, h = w.f[0], w.h[0]
@@ -222,8 +249,10 @@ def main():
     peak = PEAK_FP32_VALU if args.precision == "mixed" else PEAK_FP64_VALU
     far_tf = far_flops / (far_ms * 1e-3)
     near_tf = near_flops / (near_ms * 1e-3)
+    kname = f"k_far<{w.p},{'float' if args.precision == 'mixed' else 'double'},1>"
+    traffic = profiled_traffic(kname) if (w.p == 8 and args.precision == "mixed") else None
     roofline = {"bound": "alu", "achieved": round(far_tf / 1e12, 3), "peak": peak / 1e12, "unit": "TFLOP/s",
-                "frac": round(far_tf / peak, 4), "traffic": None, "kernel": f"k_far<{w.p},{'float' if args.precision == 'mixed' else 'double'}>",
+                "frac": round(far_tf / peak, 4), "traffic": traffic, "kernel": kname,
                 "far_interactions_per_launch": far_total, "flops_per_interaction": far_flops_per_interaction(w.p),
                 "avg_launch_ms": round(far_ms, 4), "far_entries": pinfo["far_entries"],
                 "lane_utilisation": round(far_total / (64.0 * pinfo["far_entries"]), 4)}
