@@ -1,0 +1,89 @@
+"""Parity at the full workload sizes, in the launch configuration the bench times
+(stk_evaluate with targets = sources), on sampled outputs the oracle computes one by one.
+
+The oracle builds the same tree and moments and runs Algorithm 1 only at the seeded sample
+targets; per-target interaction counts must be equal and the FP64 velocities agree to
+1e-12 (relative L2 over the sample), the mixed path to 1e-5 of FP64.  The errors against the
+FP64 direct sum at the sample are the paper's accuracy measure (Sec. 6) and are checked
+against the bound of the FP64 treecode itself."""
+import numpy as np
+import pytest
+
+from paper_1811_12498_amd import workloads as W
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+@pytest.fixture(scope="module")
+def nat():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1811_12498_amd import native
+    return native
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _sampled(nat, orc, w, rhs=0):
+    X = _t(w.src)
+    F, H, NU = _t(w.f[rhs]), _t(w.h[rhs]), _t(w.nu)
+    u64, plan = nat.evaluate(X, X, F, H, NU, w.p, w.theta, w.n0, "fp64", keep_plan=True)
+    umx = nat.evaluate(X, X, F, H, NU, w.p, w.theta, w.n0, "mixed")
+    counts = nat.plan_counts(plan)
+    S = w.sample
+    T = orc.build_tree(w.src, w.n0)
+    M, Mt = orc.moments(T, w.src, w.f[rhs], w.h[rhs], w.nu, w.p)
+    ref = orc.treecode(T, w.src, w.f[rhs], w.h[rhs], w.nu, M, Mt, w.p, w.theta, w.src[S])
+    for got, want in zip(counts, (ref.nfar, ref.nnear, ref.npairs)):
+        assert np.array_equal(got[S], want)
+    import torch
+    ud = nat.direct(X[torch.from_numpy(S).cuda()].contiguous(), X, F, H, NU).cpu().numpy()
+    return u64.cpu().numpy()[S], umx.cpu().numpy()[S], ref.u, ud
+
+
+@pytest.mark.parametrize("p", [4, 6, 8, 10])
+@pytest.mark.parametrize("theta", [0.5, 0.7])
+def test_cube100k_sweep(nat, orc, p, theta):
+    """N = 100,000 in [-1,1]^3, N0 = 500, 1000 sampled targets."""
+    w = W.c2_cube_100k(p, theta)
+    u64, umx, uref, ud = _sampled(nat, orc, w)
+    assert _rel(u64, uref) < 1e-12
+    assert _rel(umx, u64) < 1e-5
+    e64, emx = _rel(u64, ud), _rel(umx, ud)
+    # the mixed path adds at most a small fraction to the method's own error
+    assert emx <= e64 * 1.05 + 1e-6, (e64, emx)
+    print(f"p={p} theta={theta}: E_S fp64 {e64:.3e} mixed {emx:.3e}")
+
+
+def test_sphere1m(nat, orc):
+    """N = 1,000,000 on the unit sphere, p = 8, theta = 0.5, N0 = 1000, 2000 sampled targets."""
+    w = W.c3_sphere_1m()
+    u64, umx, uref, ud = _sampled(nat, orc, w)
+    assert _rel(u64, uref) < 1e-12
+    assert _rel(umx, u64) < 1e-5
+    print(f"sphere 1M: E_S fp64 {_rel(u64, ud):.3e} mixed {_rel(umx, ud):.3e}")
+
+
+def test_cube500k_k16_sampled_rhs(nat, orc):
+    """N = 500,000, K = 16 in one evaluation; right-hand sides 0, 7 and 15 against the oracle
+    at 1000 sampled targets (FP64 1e-12, mixed 1e-5)."""
+    w = W.c4_cube_multirhs()
+    X = _t(w.src)
+    F, H, NU = _t(w.f), _t(w.h), _t(w.nu)
+    u64 = nat.evaluate(X, X, F, H, NU, w.p, w.theta, w.n0, "fp64").cpu().numpy()
+    umx = nat.evaluate(X, X, F, H, NU, w.p, w.theta, w.n0, "mixed").cpu().numpy()
+    S = w.sample
+    T = orc.build_tree(w.src, w.n0)
+    for r in (0, 7, 15):
+        M, Mt = orc.moments(T, w.src, w.f[r], w.h[r], w.nu, w.p)
+        ref = orc.treecode(T, w.src, w.f[r], w.h[r], w.nu, M, Mt, w.p, w.theta, w.src[S])
+        assert _rel(u64[r][S], ref.u) < 1e-12, r
+        assert _rel(umx[r][S], ref.u) < 1e-5, r
