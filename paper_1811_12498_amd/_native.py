@@ -64,10 +64,12 @@ _lib.stk_plan_export_lists.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp]
 
 class Tiles(ctypes.Structure):
     """stk_tiles: kernel variants of the far and near fields."""
-    _fields_ = [("far_kb", ctypes.c_int32), ("near_kb", ctypes.c_int32), ("near_mfma", ctypes.c_int32)]
+    _fields_ = [("far_kb", ctypes.c_int32), ("near_kb", ctypes.c_int32), ("near_mfma", ctypes.c_int32),
+                ("far_mfma", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
-        return {"far_kb": self.far_kb, "near_kb": self.near_kb, "near_mfma": bool(self.near_mfma)}
+        return {"far_kb": self.far_kb, "near_kb": self.near_kb, "near_mfma": bool(self.near_mfma),
+                "far_mfma": bool(self.far_mfma)}
 
 
 _lib.stk_tiles_set.argtypes = [_i32, _i32, ctypes.c_int, ctypes.POINTER(Tiles)]
@@ -281,8 +283,8 @@ def plan_lists(plan: Plan, kind: str) -> dict:
 
 
 def tiles_set(p: int, k_rhs: int, precision: str, far_kb: int = 1, near_kb: int = 1, near_mfma: bool = False,
-              clear: bool = False) -> None:
-    t = Tiles(far_kb, near_kb, int(near_mfma))
+              far_mfma: bool = False, clear: bool = False) -> None:
+    t = Tiles(far_kb, near_kb, int(near_mfma), int(far_mfma))
     _check(_lib.stk_tiles_set(int(p), int(k_rhs), _prec(precision), None if clear else ctypes.byref(t)))
 
 

@@ -233,6 +233,23 @@ template <typename T, int KB> void dispatch_far(int p, const FarArgs &a, hipStre
     }
 }
 
+void dispatch_far_mfma(int p, const FarArgs &a, DBuf &bm, int32_t nn, hipStream_t s) {
+    switch (p) {
+        case 0: launch_far_mfma<0>(a, bm, nn, s); break;
+        case 1: launch_far_mfma<1>(a, bm, nn, s); break;
+        case 2: launch_far_mfma<2>(a, bm, nn, s); break;
+        case 3: launch_far_mfma<3>(a, bm, nn, s); break;
+        case 4: launch_far_mfma<4>(a, bm, nn, s); break;
+        case 5: launch_far_mfma<5>(a, bm, nn, s); break;
+        case 6: launch_far_mfma<6>(a, bm, nn, s); break;
+        case 7: launch_far_mfma<7>(a, bm, nn, s); break;
+        case 8: launch_far_mfma<8>(a, bm, nn, s); break;
+        case 9: launch_far_mfma<9>(a, bm, nn, s); break;
+        case 10: launch_far_mfma<10>(a, bm, nn, s); break;
+        default: throw Error(STK_EINVAL, "p out of range");
+    }
+}
+
 }  // namespace
 
 Plan::~Plan() {
@@ -316,6 +333,8 @@ void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, dou
                unear, tperm, u_out, ng, K};
     if (t.prec == STK_FP64)
         dispatch_far<double, 1>(t.p, fa, s);
+    else if (pl.tiles.far_mfma)
+        dispatch_far_mfma(t.p, fa, t.s_bm, t.nnodes, s);
     else if (kb == 4)
         dispatch_far<float, 4>(t.p, fa, s);
     else if (kb == 2)

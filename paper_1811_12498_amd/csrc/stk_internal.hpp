@@ -104,6 +104,7 @@ struct Tree {
     // reusable scratch for evaluation
     DBuf s_keys, s_vals, s_keys2, s_vals2, s_hist, s_tmp;
     DBuf s_scan;                   // tile sums of scan_exclusive_i32
+    DBuf s_bm;                     // operand blocks of the matrix-core far field
 };
 
 // lists re-sorted by node (cluster-major / leaf-major) and their work items
@@ -126,6 +127,7 @@ struct Tiles {
     int32_t far_kb = 1;      // right-hand sides per pass of the far-field kernel (1, 2, 4)
     int32_t near_kb = 1;     // right-hand sides per pass of the VALU near-field kernel
     bool near_mfma = false;  // near field on the matrix cores (FP32)
+    bool far_mfma = false;   // far field on the matrix cores (FP32)
 };
 
 struct Plan {

@@ -2,8 +2,8 @@
 //
 // For a given (device architecture, Taylor order p, number of right-hand sides K,
 // precision) the far and near fields can run as VALU kernels that take 1, 2 or 4
-// right-hand sides per pass, or (FP32, several right-hand sides) the near field on the
-// matrix cores.  stk_autotune times every candidate on a synthetic problem of the
+// right-hand sides per pass, or (FP32, several right-hand sides) run on the matrix
+// cores.  stk_autotune times every candidate on a synthetic problem of the
 // caller's shape (uniform points in the unit cube generated on the device) and records
 // the fastest; evaluations look the table up and fall back to a fixed rule otherwise.
 // The table can be written to and read from a text file.
@@ -83,7 +83,7 @@ Tiles default_tiles(int K, stk_precision prec) {
 bool tiles_valid(const Tiles &t, int K, stk_precision prec) {
     auto kb_ok = [&](int kb) { return (kb == 1 || kb == 2 || kb == 4) && K % kb == 0; };
     if (!kb_ok(t.far_kb) || !kb_ok(t.near_kb)) return false;
-    if (prec == STK_FP64 && (t.far_kb != 1 || t.near_kb != 1 || t.near_mfma)) return false;
+    if (prec == STK_FP64 && (t.far_kb != 1 || t.near_kb != 1 || t.near_mfma || t.far_mfma)) return false;
     return true;
 }
 
@@ -116,11 +116,11 @@ void tiles_save(const char *path) {
     std::lock_guard<std::mutex> lk(g_mu);
     FILE *fp = std::fopen(path, "w");
     if (!fp) throw Error(STK_EINVAL, std::string("cannot write ") + path);
-    std::fprintf(fp, "# arch p K precision far_kb near_kb near_mfma\n");
+    std::fprintf(fp, "# arch p K precision far_kb near_kb near_mfma far_mfma\n");
     for (const auto &e : g_table)
-        std::fprintf(fp, "%s %d %d %d %d %d %d\n", std::get<0>(e.first).c_str(), std::get<1>(e.first),
+        std::fprintf(fp, "%s %d %d %d %d %d %d %d\n", std::get<0>(e.first).c_str(), std::get<1>(e.first),
                      std::get<2>(e.first), std::get<3>(e.first), e.second.far_kb, e.second.near_kb,
-                     e.second.near_mfma ? 1 : 0);
+                     e.second.near_mfma ? 1 : 0, e.second.far_mfma ? 1 : 0);
     std::fclose(fp);
 }
 
@@ -134,8 +134,8 @@ int tiles_load(const char *path) {
         ++lineno;
         if (line[0] == '#' || line[0] == '\n') continue;
         char arch[128];
-        int p, K, prec, fkb, nkb, nm;
-        if (std::sscanf(line, "%127s %d %d %d %d %d %d", arch, &p, &K, &prec, &fkb, &nkb, &nm) != 7 ||
+        int p, K, prec, fkb, nkb, nm, fm;
+        if (std::sscanf(line, "%127s %d %d %d %d %d %d %d", arch, &p, &K, &prec, &fkb, &nkb, &nm, &fm) != 8 ||
             (prec != STK_FP64 && prec != STK_MIXED)) {
             std::fclose(fp);
             throw Error(STK_EINVAL, std::string(path) + ": malformed line " + std::to_string(lineno));
@@ -144,6 +144,7 @@ int tiles_load(const char *path) {
         t.far_kb = fkb;
         t.near_kb = nkb;
         t.near_mfma = nm != 0;
+        t.far_mfma = fm != 0;
         if (!tiles_valid(t, K, stk_precision(prec))) {
             std::fclose(fp);
             throw Error(STK_EINVAL, std::string(path) + ": invalid tiles on line " + std::to_string(lineno));
@@ -176,12 +177,16 @@ Tiles autotune(int p, int K, stk_precision prec, int64_t n, double theta, int32_
         if (tiles_valid(t, K, prec)) near_c.push_back(t);
         t = default_tiles(K, prec);
         t.far_kb = kb;
+        t.far_mfma = false;
         if (tiles_valid(t, K, prec)) far_c.push_back(t);
     }
     if (prec == STK_MIXED && K > 1) {
         Tiles t = default_tiles(K, prec);
         t.near_mfma = true;
         near_c.push_back(t);
+        t = default_tiles(K, prec);
+        t.far_mfma = true;
+        far_c.push_back(t);
     }
     hipEvent_t e0, e1;
     STK_HIP(hipEventCreate(&e0));

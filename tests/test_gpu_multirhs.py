@@ -105,3 +105,27 @@ def test_autotune_records_valid_tiles(nat):
     u64 = nat.evaluate(X, X, _t(w.f), _t(w.h), _t(w.nu), p, 0.6, 200, "fp64")
     assert float((u - u64).norm() / u64.norm()) < 1e-5
     nat.tiles_set(p, K, "mixed", clear=True)
+
+
+@pytest.mark.parametrize("K", [16, 20])
+@pytest.mark.parametrize("p", [3, 8])
+def test_far_mfma_matches_valu(nat, K, p):
+    """The matrix-core far field (16 right-hand sides per pass; K = 20 leaves a partial
+    pass) against the VALU far kernel, per right-hand side, and against FP64."""
+    w = W.cube(30_000, seed=80 + K + p, n0=300, k=K)
+    X = _t(w.src)
+    F, H, NU = _t(w.f), _t(w.h), _t(w.nu)
+    theta = 0.5
+    try:
+        nat.tiles_set(p, K, "mixed", far_kb=4, near_kb=4, near_mfma=False, far_mfma=False)
+        u_valu = nat.evaluate(X, X, F, H, NU, p, theta, 300, "mixed")
+        nat.tiles_set(p, K, "mixed", far_kb=4, near_kb=4, near_mfma=False, far_mfma=True)
+        u_mfma, plan = nat.evaluate(X, X, F, H, NU, p, theta, 300, "mixed", keep_plan=True)
+        assert nat.plan_tiles(plan)["far_mfma"]
+    finally:
+        nat.tiles_set(p, K, "mixed", clear=True)
+    u64 = nat.evaluate(X, X, F, H, NU, p, theta, 300, "fp64")
+    for r in range(K):
+        e_v = float((u_mfma[r] - u_valu[r]).norm() / u_valu[r].norm())
+        e_64 = float((u_mfma[r] - u64[r]).norm() / u64[r].norm())
+        assert e_v < 2e-6 and e_64 < 1e-5, (r, e_v, e_64)
