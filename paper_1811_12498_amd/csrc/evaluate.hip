@@ -233,6 +233,14 @@ template <typename T, int KB> void dispatch_far(int p, const FarArgs &a, hipStre
     }
 }
 
+}  // namespace
+
+// defined in far_mfma.hpp, instantiated in farm_p*.hip: FP32, K right-hand sides on the
+// matrix cores; bm is scratch for the clusters' operand blocks
+template <int P> void launch_far_mfma(const FarArgs &a, DBuf &bm, int32_t nn, hipStream_t s);
+
+namespace {
+
 void dispatch_far_mfma(int p, const FarArgs &a, DBuf &bm, int32_t nn, hipStream_t s) {
     switch (p) {
         case 0: launch_far_mfma<0>(a, bm, nn, s); break;

@@ -37,8 +37,5 @@ inline unsigned xcd_blocks(int32_t ngroups) { return unsigned(((ngroups + 7) >> 
 
 // defined in far_impl.hpp, instantiated per Taylor order in far_p*.hip / fark_p*.hip
 template <int P, typename T, int KB> void launch_far(const FarArgs &a, hipStream_t s);
-// defined in far_mfma.hpp, instantiated in farm_p*.hip: FP32, K right-hand sides on the
-// matrix cores; bm is scratch for the clusters' operand blocks
-template <int P> void launch_far_mfma(const FarArgs &a, DBuf &bm, int32_t nn, hipStream_t s);
 
 }  // namespace stk
