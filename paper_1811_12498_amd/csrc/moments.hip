@@ -67,12 +67,14 @@ __global__ __launch_bounds__(64) void k_moments(const double *__restrict__ pos, 
     for (int32_t b = first; b < last; b += STAGE) {
         const int cnt = min(STAGE, last - b);
         __syncthreads();
-        for (int idx = lane; idx < cnt * 3 * P1; idx += 64) {
-            const int pt = idx / (3 * P1), rem = idx % (3 * P1), ax = rem / P1, e = rem % P1;
+        if (lane < 3 * cnt) {  // one lane per (point, axis): d^0 .. d^p by repeated multiplication
+            const int pt = lane / 3, ax = lane - 3 * pt;
             const double d = pos[3 * int64_t(b + pt) + ax] - c3[ax];
             double v = 1.0;
-            for (int i = 0; i < e; ++i) v *= d;
-            pw[pt][ax][e] = v;
+            for (int e = 0; e < P1; ++e) {
+                pw[pt][ax][e] = v;
+                v *= d;
+            }
         }
         __syncthreads();
         for (int pt = 0; pt < cnt; ++pt) {
