@@ -13,7 +13,7 @@ namespace stk {
 namespace {
 
 constexpr int MT = 256;    // threads per block (reduction and block kernels)
-constexpr int STAGE = 16;  // points whose powers are tabulated in LDS per round
+constexpr int STAGE = 21;  // points whose powers are tabulated in LDS per round (3 STAGE <= 64 lanes)
 constexpr int AMAX = 5;    // multi-indices per lane: 64 * AMAX >= nidx(STK_P_MAX)
 
 __device__ inline int32_t node_of_chunk(const int32_t *__restrict__ off, int32_t nn, int32_t ch) {

@@ -227,3 +227,49 @@ def test_argument_errors(nat):
     with pytest.raises(nat.StkError) as e:
         nat.evaluate_tree(tr, x, 0.5)
     assert e.value.status == nat.STK_ESTATE
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_single_target_and_single_source(nat, orc, prec):
+    """Degenerate sizes: one target against many sources, many targets against one source
+    (a one-point tree: the root is a leaf of radius 0), and one against one."""
+    rng = np.random.default_rng(90)
+    src = rng.uniform(0, 1, (3000, 3))
+    f, h = rng.uniform(-1, 1, (2, 3000, 3))
+    nu = rng.normal(size=(3000, 3))
+    nu /= np.linalg.norm(nu, axis=1, keepdims=True)
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    for tg, s, ff, hh, nn in ((rng.uniform(0, 1, (1, 3)), src, f, h, nu),
+                              (rng.uniform(0, 1, (500, 3)), src[:1], f[:1], h[:1], nu[:1]),
+                              (src[:1] + 0.25, src[:1], f[:1], h[:1], nu[:1])):
+        T = orc.build_tree(s, 40)
+        M, Mt = orc.moments(T, s, ff, hh, nn, 4)
+        ref = orc.treecode(T, s, ff, hh, nn, M, Mt, 4, 0.5, tg)
+        u = nat.evaluate(_t(tg), _t(s), _t(ff), _t(hh), _t(nn), 4, 0.5, 40, prec)
+        assert orc.rel_l2(u.cpu().numpy(), ref.u) < tol
+
+
+def test_target_equal_to_only_source_gives_zero(nat):
+    """The only source coincides with the target: the pair is skipped (r = 0), u = 0."""
+    import torch
+    x = torch.tensor([[0.3, 0.4, 0.5]], dtype=torch.float64, device="cuda")
+    one = torch.ones_like(x)
+    for prec in ("fp64", "mixed"):
+        u = nat.evaluate(x, x, one, one, one / 3 ** 0.5, 6, 0.5, 10, prec)
+        assert torch.count_nonzero(u) == 0
+
+
+def test_maximum_rhs_count(nat):
+    """K = 64 right-hand sides (the largest accepted) against one-RHS runs, in both
+    precisions, with the default kernel variants."""
+    w = W.cube(6000, seed=91, n0=80, k=64)
+    X = _t(w.src)
+    F, H, NU = _t(w.f), _t(w.h), _t(w.nu)
+    for prec, tol in (("fp64", 1e-15), ("mixed", 2e-6)):
+        u = nat.evaluate(X, X, F, H, NU, 5, 0.5, 80, prec)
+        for r in (0, 17, 63):
+            u1 = nat.evaluate(X, X, F[r].contiguous(), H[r].contiguous(), NU, 5, 0.5, 80, prec)
+            assert float((u[r] - u1).norm() / u1.norm()) <= tol, (prec, r)
+    with pytest.raises(nat.StkError):
+        bad = _t(np.zeros((65, 10, 3)))
+        nat.evaluate(X[:10].contiguous(), X[:10].contiguous(), bad, bad, NU[:10].contiguous(), 5, 0.5, 80)
