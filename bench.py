@@ -115,7 +115,7 @@ def fwd_adjoint_times(reps=3):
         ms = (time.perf_counter() - t0) * 1e3 / reps
         native.profile_enable(False)
         prof = native.profile_read()
-        fwd_ms = sum(prof[k][0] for k in ("tree", "moments", "targets", "lists", "near", "far")) / reps
+        fwd_ms = sum(prof[k][0] for k in ("tree", "moments", "targets", "lists", "near", "far", "far_sparse")) / reps
         out["fp32" if prec == "mixed" else "fp64"] = {"fwd_adjoint_ms": round(ms, 3),
                                                       "forward_ms": round(fwd_ms, 3),
                                                       "adjoint_ms": round(prof["adjoint"][0] / reps, 3)}
@@ -234,6 +234,8 @@ def main():
     nfar, nnear, npairs = native.plan_counts(plan)
     pinfo = native.plan_info(plan)
     near_lists = native.plan_lists(plan, "near")
+    far_pc = np.bitwise_count(native.plan_lists(plan, "far")["mask"]).astype(np.int64)
+    sparse_max, sparse_inter = native.plan_far_split(plan)
     del plan
     leaf_count = native.tree_export(native.build_tree(X, w.n0))["count"].astype(np.int64)
     # leaf-major items: each leaf's (target, leaf) incidences in waves of 64 lanes
@@ -241,10 +243,13 @@ def main():
                       minlength=leaf_count.size).astype(np.int64)
     near_slots = int((64 * ((inc + 63) // 64) * leaf_count).sum())
     far_total = int(nfar.sum())
+    # the group-major far kernel runs the entries with more than sparse_max targets
+    far_dense = far_total - sparse_inter
+    dense_entries = int((far_pc > sparse_max).sum())
     pairs_total = int(npairs.sum())
     far_ms = prof["far"][0] / prof["far"][1]
     near_ms = prof["near"][0] / prof["near"][1]
-    far_flops = far_total * far_flops_per_interaction(w.p)
+    far_flops = far_dense * far_flops_per_interaction(w.p)
     near_flops = pairs_total * NEAR_FLOPS_PER_PAIR
     peak = PEAK_FP32_VALU if args.precision == "mixed" else PEAK_FP64_VALU
     far_tf = far_flops / (far_ms * 1e-3)
@@ -253,9 +258,13 @@ def main():
     traffic = profiled_traffic(kname) if (w.p == 8 and args.precision == "mixed") else None
     roofline = {"bound": "alu", "achieved": round(far_tf / 1e12, 3), "peak": peak / 1e12, "unit": "TFLOP/s",
                 "frac": round(far_tf / peak, 4), "traffic": traffic, "kernel": kname,
-                "far_interactions_per_launch": far_total, "flops_per_interaction": far_flops_per_interaction(w.p),
-                "avg_launch_ms": round(far_ms, 4), "far_entries": pinfo["far_entries"],
-                "lane_utilisation": round(far_total / (64.0 * pinfo["far_entries"]), 4)}
+                "far_interactions_per_launch": far_dense, "flops_per_interaction": far_flops_per_interaction(w.p),
+                "avg_launch_ms": round(far_ms, 4), "far_entries": dense_entries,
+                "lane_utilisation": round(far_dense / (64.0 * max(dense_entries, 1)), 4)}
+    sparse_ms = prof["far_sparse"][0] / max(prof["far_sparse"][1], 1)
+    far_split = {"sparse_max_targets": sparse_max, "sparse_interactions": sparse_inter,
+                 "sparse_entries": int(pinfo["far_entries"] - dense_entries), "sparse_ms": round(sparse_ms, 4),
+                 "all_far_interactions": far_total}
 
     # accuracy on the seeded sample against the FP64 GPU direct sum
     S = w.sample
@@ -288,7 +297,7 @@ def main():
                                  "frac_of_fp32_peak": round(near_tf / PEAK_FP32_VALU, 4),
                                  "pairs_per_launch": pairs_total, "avg_launch_ms": round(near_ms, 4),
                                  "lane_utilisation": round(pairs_total / near_slots, 4)},
-                  "phase_ms_per_step": phases}
+                  "phase_ms_per_step": phases, "far_split": far_split}
     log(f"accuracy: {acc}")
 
     if not args.no_extras:

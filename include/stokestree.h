@@ -211,7 +211,7 @@ stk_status stk_plan_tiles(const stk_plan *plan, stk_tiles *out);
  * per phase since the last read (host arrays of STK_NPHASES entries; either may be
  * NULL), and clears the record.  Timing is process-wide; calls on several streams
  * at once are not separated. */
-#define STK_NPHASES 8
+#define STK_NPHASES 9
 enum {
     STK_PHASE_TREE = 0,     /* root cube, Morton keys, sort, subdivision, boxes, radii */
     STK_PHASE_MOMENTS = 1,  /* moments, channel blocks, near-field records            */
@@ -220,7 +220,8 @@ enum {
     STK_PHASE_NEAR = 4,     /* near-field kernel                                        */
     STK_PHASE_FAR = 5,      /* far-field kernel                                         */
     STK_PHASE_DIRECT = 6,   /* FP64 direct sum                                          */
-    STK_PHASE_ADJOINT = 7   /* adjoint kernels                                          */
+    STK_PHASE_ADJOINT = 7,  /* adjoint kernels                                          */
+    STK_PHASE_FAR_SPARSE = 8 /* far entries applying to few targets, cluster major (K = 1) */
 };
 stk_status stk_profile_enable(int on);
 stk_status stk_profile_read(double *ms, int64_t *count);
@@ -228,6 +229,11 @@ stk_status stk_profile_read(double *ms, int64_t *count);
 /* Sizes of a plan's interaction lists: number of 64-target groups, far entries and near
  * entries (each entry is one cluster applied to a subset of one group's targets). */
 stk_status stk_plan_info(const stk_plan *plan, int64_t *ngroups, int64_t *n_far_entries, int64_t *n_near_entries);
+/* How the plan's far field was split (a scheduling choice, not part of Alg. 1): with one
+ * right-hand side, far entries whose lane mask has at most *max_pc bits ran cluster major
+ * (*sparse_interactions target-cluster pairs) and the group-major kernel took the rest;
+ * *max_pc = 0 means no split.  Either pointer may be NULL. */
+stk_status stk_plan_far_split(const stk_plan *plan, int32_t *max_pc, int64_t *sparse_interactions);
 
 void stk_tree_destroy(stk_tree *t);
 void stk_plan_destroy(stk_plan *plan);

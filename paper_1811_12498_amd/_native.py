@@ -26,11 +26,11 @@ _STATUS_NAMES = {STK_EINVAL: "STK_EINVAL", STK_ENOMEM: "STK_ENOMEM", STK_EDEVICE
 EXPORTS = ["stk_build_tree", "stk_compute_moments", "stk_evaluate_tree", "stk_evaluate", "stk_evaluate_adjoint",
            "stk_direct",
            "stk_tree_info", "stk_tree_export", "stk_tree_export_moments", "stk_plan_counts", "stk_plan_info",
-           "stk_plan_export_lists", "stk_tiles_set", "stk_tiles_get", "stk_autotune", "stk_tiles_save",
+           "stk_plan_export_lists", "stk_plan_far_split", "stk_tiles_set", "stk_tiles_get", "stk_autotune", "stk_tiles_save",
            "stk_tiles_load", "stk_plan_tiles",
            "stk_profile_enable", "stk_profile_read", "stk_tree_destroy", "stk_plan_destroy", "stk_last_error"]
 
-PHASES = ["tree", "moments", "targets", "lists", "near", "far", "direct", "adjoint"]
+PHASES = ["tree", "moments", "targets", "lists", "near", "far", "direct", "adjoint", "far_sparse"]
 
 
 class StkError(RuntimeError):
@@ -60,6 +60,7 @@ _lib.stk_tree_info.argtypes = [_vp, _i64p, _i32p, _dp]
 _lib.stk_tree_export.argtypes = [_vp] + [_vp] * 11
 _lib.stk_tree_export_moments.argtypes = [_vp, _i32, _vp, _vp]
 _lib.stk_plan_export_lists.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp]
+_lib.stk_plan_far_split.argtypes = [_vp, _i32p, _i64p]
 
 
 class Tiles(ctypes.Structure):
@@ -315,6 +316,13 @@ def plan_tiles(plan: Plan) -> dict:
     t = Tiles()
     _check(_lib.stk_plan_tiles(plan.handle, ctypes.byref(t)))
     return t.as_dict()
+
+
+def plan_far_split(plan: Plan) -> tuple[int, int]:
+    """(max_pc, sparse_interactions): far entries with at most max_pc targets ran cluster major."""
+    mp, ns = ctypes.c_int32(), ctypes.c_int64()
+    _check(_lib.stk_plan_far_split(plan.handle, ctypes.byref(mp), ctypes.byref(ns)))
+    return mp.value, ns.value
 
 
 def profile_enable(on: bool = True) -> None:

@@ -522,11 +522,11 @@ void adjoint(Plan &pl, const double *w, double *gf, double *gh, double *gt, doub
         gtn = reserve<double>(A.gt_near, size_t(m) * 3);
         gtf = reserve<double>(A.gt_far, size_t(m) * 3);
         na.gt = gtn;
-        NearTgradArgs nt{pl.tpos.as<double>(), ws, pl.item_leaf.as<int32_t>(), pl.item_i0.as<int32_t>(),
-                         pl.item_i1.as<int32_t>(), pl.inc_tgt.as<int32_t>(), pl.inc_slot.as<int32_t>(),
+        NearTgradArgs nt{pl.tpos.as<double>(), ws, pl.ncm.item_node.as<int32_t>(), pl.ncm.item_i0.as<int32_t>(),
+                         pl.ncm.item_i1.as<int32_t>(), pl.ncm.inc_tgt.as<int32_t>(), pl.ncm.inc_slot.as<int32_t>(),
                          t.nstart.as<int32_t>(), t.ncount.as<int32_t>(), t.geo.as<double>(), t.wts.p,
-                         pl.near_part.p, pl.n_near_items};
-        const int32_t *toff = pl.near_toff.as<int32_t>();
+                         pl.ncm.part.p, pl.ncm.n_items};
+        const int32_t *toff = pl.ncm.toff.as<int32_t>();
         if (fp64) {
             if (nt.nitems > 0) {
                 hipLaunchKernelGGL(k_near_tgrad<double>, dim3(xcd_blocks(nt.nitems)), dim3(64), 0, s, nt);

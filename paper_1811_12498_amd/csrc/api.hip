@@ -369,6 +369,14 @@ stk_status stk_plan_tiles(const stk_plan *plan, stk_tiles *out) {
     });
 }
 
+stk_status stk_plan_far_split(const stk_plan *plan, int32_t *max_pc, int64_t *sparse_interactions) {
+    return guarded([&] {
+        stk::require(plan != nullptr, "plan is NULL");
+        if (max_pc) *max_pc = plan->p.far_sparse_max;
+        if (sparse_interactions) *sparse_interactions = plan->p.far_sparse_max > 0 ? plan->p.fcm.n_inc : 0;
+    });
+}
+
 stk_status stk_profile_enable(int on) {
     return guarded([&] { stk::prof_enable(on != 0); });
 }

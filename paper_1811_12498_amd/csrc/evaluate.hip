@@ -241,6 +241,37 @@ template <int P> void launch_far_mfma(const FarArgs &a, DBuf &bm, int32_t nn, hi
 
 namespace {
 
+template <typename T> void dispatch_far_sparse(int p, const FarSparseArgs &a, hipStream_t s) {
+    switch (p) {
+        case 0: launch_far_sparse<0, T>(a, s); break;
+        case 1: launch_far_sparse<1, T>(a, s); break;
+        case 2: launch_far_sparse<2, T>(a, s); break;
+        case 3: launch_far_sparse<3, T>(a, s); break;
+        case 4: launch_far_sparse<4, T>(a, s); break;
+        case 5: launch_far_sparse<5, T>(a, s); break;
+        case 6: launch_far_sparse<6, T>(a, s); break;
+        case 7: launch_far_sparse<7, T>(a, s); break;
+        case 8: launch_far_sparse<8, T>(a, s); break;
+        case 9: launch_far_sparse<9, T>(a, s); break;
+        case 10: launch_far_sparse<10, T>(a, s); break;
+        default: throw Error(STK_EINVAL, "p out of range");
+    }
+}
+
+// per target: its sparse far velocities in list order, compensated, added to unear (m,3)
+template <typename T>
+__global__ void k_cm_add(const T *__restrict__ part, const int32_t *__restrict__ toff, int64_t m,
+                         double *__restrict__ unear) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= m) return;
+    const int32_t k0 = toff[t], k1 = toff[t + 1];
+    if (k0 == k1) return;
+    Comp<T> acc[3];
+    for (int32_t k = k0; k < k1; ++k)
+        for (int q = 0; q < 3; ++q) acc[q].add(part[3 * int64_t(k) + q]);
+    for (int q = 0; q < 3; ++q) unear[3 * t + q] += acc[q].value();
+}
+
 void dispatch_far_mfma(int p, const FarArgs &a, DBuf &bm, int32_t nn, hipStream_t s) {
     switch (p) {
         case 0: launch_far_mfma<0>(a, bm, nn, s); break;
@@ -259,6 +290,33 @@ void dispatch_far_mfma(int p, const FarArgs &a, DBuf &bm, int32_t nn, hipStream_
 }
 
 }  // namespace
+
+int far_sparse(Tree &t, Plan &pl, double *unear, hipStream_t s) {
+    const int64_t m = pl.m;
+    ClusterMajor &cm = pl.fcm;
+    cluster_major(t, cm, pl.far_off.as<int32_t>(), pl.far_node.as<int32_t>(), pl.far_mask.as<uint64_t>(),
+                  pl.n_far_entries, pl.ngroups, m, FAR_SPARSE_MAX, nullptr, s);
+    const size_t tsz = t.prec == STK_FP64 ? sizeof(double) : sizeof(float);
+    void *part = reserve<unsigned char>(cm.part, tsz * 3 * size_t(cm.n_inc) + tsz);
+    FarSparseArgs sa{pl.tpos.as<double>(), cm.item_node.as<int32_t>(), cm.item_i0.as<int32_t>(),
+                     cm.item_i1.as<int32_t>(), cm.inc_tgt.as<int32_t>(), cm.inc_slot.as<int32_t>(),
+                     t.ncenter.as<double>(), t.nrho.as<double>(), t.wblk.p, part, cm.n_items};
+    if (t.prec == STK_FP64)
+        dispatch_far_sparse<double>(t.p, sa, s);
+    else
+        dispatch_far_sparse<float>(t.p, sa, s);
+    if (m > 0 && cm.n_inc > 0) {
+        if (t.prec == STK_FP64)
+            hipLaunchKernelGGL(k_cm_add<double>, dim3(nblk(m, 256)), dim3(256), 0, s, static_cast<const double *>(part),
+                               cm.toff.as<int32_t>(), m, unear);
+        else
+            hipLaunchKernelGGL(k_cm_add<float>, dim3(nblk(m, 256)), dim3(256), 0, s, static_cast<const float *>(part),
+                               cm.toff.as<int32_t>(), m, unear);
+        STK_CHECK_LAUNCH();
+    }
+    prof_mark(STK_PHASE_FAR_SPARSE, s);
+    return FAR_SPARSE_MAX;
+}
 
 Plan::~Plan() {
     if (owns_tree) delete tree;
@@ -337,8 +395,12 @@ void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, dou
     // the near part and un-permutes)
     double *unear = reserve<double>(t.s_tmp, size_t(m) * K * 3);
     near_field(t, pl, unear, s);
+    // one right-hand side: far entries that apply to few targets of their group run cluster
+    // major (their velocities are added to unear); the group-major kernel skips them
+    const int sparse_max = K == 1 ? far_sparse(t, pl, unear, s) : 0;
+    pl.far_sparse_max = sparse_max;
     FarArgs fa{tpos, m, foff, ta.far_node, ta.far_mask, t.ncenter.as<double>(), t.nrho.as<double>(), t.wblk.p,
-               unear, tperm, u_out, ng, K};
+               unear, tperm, u_out, ng, K, sparse_max};
     if (t.prec == STK_FP64)
         dispatch_far<double, 1>(t.p, fa, s);
     else if (pl.tiles.far_mfma)

@@ -38,6 +38,7 @@ __global__ __launch_bounds__(64) void k_far(FarArgs a) {
         for (int32_t e = e0; e < e1; ++e) {
             const int32_t c = __builtin_amdgcn_readfirstlane(a.node[e]);
             const uint64_t mk = a.mask[e];
+            if (__popcll(mk) <= a.sparse_max) continue;  // done cluster major (k_far_sparse)
             if ((mk >> lane) & 1ull) {
                 const double d0 = x0 - a.center[3 * c], d1 = x1 - a.center[3 * c + 1], d2 = x2 - a.center[3 * c + 2];
                 const double R2 = d0 * d0 + d1 * d1 + d2 * d2;
@@ -71,6 +72,41 @@ __global__ __launch_bounds__(64) void k_far(FarArgs a) {
 template <int P, typename T, int KB> void launch_far(const FarArgs &a, hipStream_t s) {
     if (a.ngroups == 0) return;
     hipLaunchKernelGGL((k_far<P, T, KB>), dim3(xcd_blocks(a.ngroups), unsigned(a.K / KB)), dim3(64), 0, s, a);
+    STK_CHECK_LAUNCH();
+}
+
+// one wave per item: a cluster and up to 64 targets whose groups' entries for it were
+// sparse; each lane evaluates its (target, cluster) interaction and writes the velocity to
+// the interaction's slot in the target's list of sparse entries
+template <int P, typename T> __global__ __launch_bounds__(64) void k_far_sparse(FarSparseArgs a) {
+    constexpr int WS = 6 * nidx(P + 1);
+    const int32_t it = xcd_group(a.nitems);
+    if (it >= a.nitems) return;
+    const int lane = threadIdx.x;
+    const int32_t c = __builtin_amdgcn_readfirstlane(a.item_node[it]);
+    const int32_t i0 = a.item_i0[it];
+    if (lane < a.item_i1[it] - i0) {
+        const int64_t t = a.inc_tgt[i0 + lane];
+        const int32_t slot = a.inc_slot[i0 + lane];
+        const double d0 = a.tpos[3 * t] - a.center[3 * c], d1 = a.tpos[3 * t + 1] - a.center[3 * c + 1],
+                     d2 = a.tpos[3 * t + 2] - a.center[3 * c + 2];
+        const double rinv = 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        const T dh[3] = {T(d0 * rinv), T(d1 * rinv), T(d2 * rinv)};
+        const T tt = T(a.rho[c] * rinv);
+        T accG[3], accF[3];
+        FarEval<P, T>::run(dh, tt, static_cast<const T *>(a.wblk) + size_t(c) * WS, accG, accF);
+        T u[3];
+        far_velocity(accG, accF, T(rinv), u);
+        T *o = static_cast<T *>(a.part) + 3 * int64_t(slot);
+        o[0] = u[0];
+        o[1] = u[1];
+        o[2] = u[2];
+    }
+}
+
+template <int P, typename T> void launch_far_sparse(const FarSparseArgs &a, hipStream_t s) {
+    if (a.nitems == 0) return;
+    hipLaunchKernelGGL((k_far_sparse<P, T>), dim3(xcd_blocks(a.nitems)), dim3(64), 0, s, a);
     STK_CHECK_LAUNCH();
 }
 

@@ -26,6 +26,18 @@ struct FarArgs {
     double *u_out;           // (K,m,3) caller order
     int32_t ngroups;
     int32_t K;               // right-hand sides (a multiple of the kernel's block KB)
+    int32_t sparse_max;      // entries with at most this many targets are done elsewhere (0: none)
+};
+
+// cluster-major items of the sparse far entries (one right-hand side)
+struct FarSparseArgs {
+    const double *tpos;
+    const int32_t *item_node, *item_i0, *item_i1;
+    const int32_t *inc_tgt, *inc_slot;
+    const double *center, *rho;
+    const void *wblk;
+    void *part;              // (incidences, 3) T
+    int32_t nitems;
 };
 
 // block index -> group: XCD x = blockIdx % 8 gets groups [x * per, (x + 1) * per)
@@ -37,5 +49,6 @@ inline unsigned xcd_blocks(int32_t ngroups) { return unsigned(((ngroups + 7) >> 
 
 // defined in far_impl.hpp, instantiated per Taylor order in far_p*.hip / fark_p*.hip
 template <int P, typename T, int KB> void launch_far(const FarArgs &a, hipStream_t s);
+template <int P, typename T> void launch_far_sparse(const FarSparseArgs &a, hipStream_t s);
 
 }  // namespace stk

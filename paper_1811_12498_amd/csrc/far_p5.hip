@@ -1,7 +1,10 @@
-// Far-field kernels for Taylor order p = 5, one right-hand side per pass (both precisions).
+// Far-field kernels for Taylor order p = 5, one right-hand side per pass (both precisions), and its
+// cluster-major kernel for sparse far entries.
 #include "far_impl.hpp"
 
 namespace stk {
 template void launch_far<5, float, 1>(const FarArgs &, hipStream_t);
 template void launch_far<5, double, 1>(const FarArgs &, hipStream_t);
+template void launch_far_sparse<5, float>(const FarSparseArgs &, hipStream_t);
+template void launch_far_sparse<5, double>(const FarSparseArgs &, hipStream_t);
 }  // namespace stk

@@ -132,39 +132,110 @@ __device__ inline double box_dist2(double x0, double x1, double x2, const double
     return e0 * e0 + e1 * e1 + e2 * e2;
 }
 
-// ---- leaf-major plan -------------------------------------------------------------------
-// sorted entry k: popcount of its mask; pos[e] = sorted position of entry e
-__global__ void k_nl_pos(const int32_t *__restrict__ ent, const uint64_t *__restrict__ mask, int64_t ne,
+// ---- cluster-major view of group lists ---------------------------------------------------
+// an entry is kept iff its mask has at most max_pc bits
+__device__ inline bool kept(uint64_t mk, int max_pc) { return __popcll(mk) <= max_pc; }
+
+// sort keys: the node of a kept entry, nn (after every node) for the others
+__global__ void k_cm_keys(const int32_t *__restrict__ node, const uint64_t *__restrict__ mask, int64_t ne, int32_t nn,
+                          int max_pc, uint64_t *__restrict__ keys, int32_t *__restrict__ vals) {
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    keys[e] = kept(mask[e], max_pc) ? uint64_t(node[e]) : uint64_t(nn);
+    vals[e] = int32_t(e);
+}
+
+// compaction of the kept entries (when most are dropped): flags, then (node, entry) pairs
+__global__ void k_cm_flag(const uint64_t *__restrict__ mask, int64_t ne, int max_pc, int32_t *__restrict__ flag) {
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    flag[e] = kept(mask[e], max_pc) ? 1 : 0;
+}
+__global__ void k_cm_compact(const int32_t *__restrict__ node, const uint64_t *__restrict__ mask, int64_t ne,
+                             int max_pc, const int32_t *__restrict__ fpos, uint64_t *__restrict__ keys,
+                             int32_t *__restrict__ vals) {
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= ne || !kept(mask[e], max_pc)) return;
+    keys[fpos[e]] = uint64_t(node[e]);
+    vals[fpos[e]] = int32_t(e);
+}
+
+// sorted entry k: its incidences (0 if not kept); pos[e] = sorted position of entry e
+__global__ void k_cm_pos(const int32_t *__restrict__ ent, const uint64_t *__restrict__ mask, int64_t ne, int max_pc,
                          int32_t *__restrict__ pc, int32_t *__restrict__ pos) {
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= ne) return;
     const int32_t e = ent[k];
-    pc[k] = __popcll(mask[e]);
+    const uint64_t mk = mask[e];
+    pc[k] = kept(mk, max_pc) ? __popcll(mk) : 0;
     pos[e] = int32_t(k);
 }
 
-// loff[c] = first incidence of leaf c, c in [0, nn]
-__global__ void k_nl_loff(const int32_t *__restrict__ eoff, const int32_t *__restrict__ incoff, int32_t nn,
+// per target: number of kept entries of its group that apply to it
+__global__ __launch_bounds__(64) void k_cm_tcount(const int32_t *__restrict__ off, const uint64_t *__restrict__ mask,
+                                                  int64_t m, int max_pc, int32_t *__restrict__ tcnt) {
+    const int32_t g = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t t = int64_t(g) * 64 + lane;
+    int32_t c = 0;
+    const int32_t e0 = off[g], e1 = off[g + 1];
+    int32_t e = e0;
+    for (; e + 8 <= e1; e += 8) {  // eight masks per round: one wait on the scalar cache
+        uint64_t mk[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) mk[u] = mask[e + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (kept(mk[u], max_pc) && ((mk[u] >> lane) & 1ull)) ++c;
+    }
+    for (; e < e1; ++e) {
+        const uint64_t mk = mask[e];
+        if (kept(mk, max_pc) && ((mk >> lane) & 1ull)) ++c;
+    }
+    if (t < m) tcnt[t] = c;
+}
+
+// loff[c] = first incidence of node c, c in [0, nn]
+__global__ void k_cm_loff(const int32_t *__restrict__ eoff, const int32_t *__restrict__ incoff, int32_t nn,
                           int32_t *__restrict__ loff) {
     const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c > nn) return;
     loff[c] = incoff[eoff[c]];
 }
 
-// one wave per group: lane l walks the group's entries in list order and places each of
-// its incidences (target, slot) at the incidence's leaf-major position
-__global__ __launch_bounds__(64) void k_nl_fill(const int32_t *__restrict__ off, const uint64_t *__restrict__ mask,
-                                                const int32_t *__restrict__ pos, const int32_t *__restrict__ incoff,
-                                                const int32_t *__restrict__ toff, int64_t m,
-                                                int32_t *__restrict__ inc_tgt, int32_t *__restrict__ inc_slot) {
+// one wave per group: lane l walks the group's kept entries in list order and places each
+// of its incidences (target, slot) at the incidence's node-major position
+__global__ __launch_bounds__(64) void k_cm_fill(const int32_t *__restrict__ off, const uint64_t *__restrict__ mask,
+                                                int max_pc, const int32_t *__restrict__ pos,
+                                                const int32_t *__restrict__ incoff, const int32_t *__restrict__ toff,
+                                                int64_t m, int32_t *__restrict__ inc_tgt,
+                                                int32_t *__restrict__ inc_slot) {
     const int32_t g = blockIdx.x;
     const int lane = threadIdx.x;
     const int64_t t = int64_t(g) * 64 + lane;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     int32_t slot = t < m ? toff[t] : 0;
-    for (int32_t e = off[g]; e < off[g + 1]; ++e) {
+    const int32_t e0 = off[g], e1 = off[g + 1];
+    int32_t e = e0;
+    for (; e + 8 <= e1; e += 8) {  // eight entries per round: one wait on the scalar cache
+        uint64_t mk[8];
+        int32_t ps[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            mk[u] = mask[e + u];
+            ps[u] = pos[e + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (kept(mk[u], max_pc) && ((mk[u] >> lane) & 1ull)) {
+                const int32_t q = incoff[ps[u]] + __popcll(mk[u] & lt);
+                inc_tgt[q] = int32_t(t);
+                inc_slot[q] = slot++;
+            }
+    }
+    for (; e < e1; ++e) {
         const uint64_t mk = mask[e];
-        if ((mk >> lane) & 1ull) {
+        if (kept(mk, max_pc) && ((mk >> lane) & 1ull)) {
             const int32_t q = incoff[pos[e]] + __popcll(mk & lt);
             inc_tgt[q] = int32_t(t);
             inc_slot[q] = slot++;
@@ -396,75 +467,103 @@ template <typename T, int KB> void launch_near(const NearArgs &na, hipStream_t s
 
 }  // namespace
 
-void near_field(Tree &t, Plan &pl, double *unear, hipStream_t s) {
-    const int64_t m = pl.m;
-    const int64_t ne = pl.n_near_entries;
+void cluster_major(Tree &t, ClusterMajor &cm, const int32_t *off, const int32_t *node, const uint64_t *mask,
+                   int64_t ne, int32_t ng, int64_t m, int max_pc, const int32_t *tcount, hipStream_t s) {
     const int32_t nn = int32_t(t.nnodes);
-    const int32_t ng = pl.ngroups;
-    const int32_t *off = pl.near_off.as<int32_t>();
-    const int32_t *node = pl.near_node.as<int32_t>();
-    const uint64_t *mask = pl.near_mask.as<uint64_t>();
-
-    // entries sorted by leaf (stable: group order within a leaf)
-    uint64_t *keys = reserve<uint64_t>(pl.nl_keys, size_t(ne) + 1);
-    int32_t *ent = reserve<int32_t>(pl.nl_ent, size_t(ne) + 1);
-    if (ne > 0) {
-        hipLaunchKernelGGL(k_node_keys, dim3(nblk(ne, 256)), dim3(256), 0, s, node, ne, keys, ent);
+    // kept entries sorted by node (stable: group order within a node), the others last
+    uint64_t *keys = reserve<uint64_t>(cm.keys, size_t(ne) + 1);
+    int32_t *ent = reserve<int32_t>(cm.ent, size_t(ne) + 1);
+    int32_t *pc = reserve<int32_t>(cm.pc, size_t(ne) + 1);
+    int32_t *pos = reserve<int32_t>(cm.pos, size_t(ne) + 1);
+    int32_t *incoff = reserve<int32_t>(cm.incoff, size_t(ne) + 1);
+    int bits = 1;
+    while ((int64_t(1) << bits) <= int64_t(nn)) ++bits;
+    int64_t nk = ne;  // entries in the sorted array
+    if (ne > 0 && max_pc < 64) {
+        // few entries kept: compact them, then sort only those
+        int32_t *flag = reserve<int32_t>(cm.pc, size_t(ne) + 1);
+        int32_t *fpos = reserve<int32_t>(cm.incoff, size_t(ne) + 1);
+        hipLaunchKernelGGL(k_cm_flag, dim3(nblk(ne, 256)), dim3(256), 0, s, mask, ne, max_pc, flag);
         STK_CHECK_LAUNCH();
-        int bits = 1;
-        while ((int64_t(1) << bits) <= int64_t(nn)) ++bits;
+        scan_exclusive_i32(flag, fpos, ne, t.s_scan, s);
+        int32_t nkept = 0;
+        STK_HIP(hipMemcpyAsync(&nkept, fpos + ne, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        hipLaunchKernelGGL(k_cm_compact, dim3(nblk(ne, 256)), dim3(256), 0, s, node, mask, ne, max_pc, fpos, keys, ent);
+        STK_CHECK_LAUNCH();
+        STK_HIP(hipStreamSynchronize(s));
+        nk = nkept;
+        radix_sort_pairs(t, keys, ent, nk, bits, s);
+    } else if (ne > 0) {
+        hipLaunchKernelGGL(k_cm_keys, dim3(nblk(ne, 256)), dim3(256), 0, s, node, mask, ne, nn, max_pc, keys, ent);
+        STK_CHECK_LAUNCH();
         radix_sort_pairs(t, keys, ent, ne, bits, s);
     }
-    int32_t *pc = reserve<int32_t>(pl.nl_pc, size_t(ne) + 1);
-    int32_t *pos = reserve<int32_t>(pl.nl_pos, size_t(ne) + 1);
-    int32_t *incoff = reserve<int32_t>(pl.nl_incoff, size_t(ne) + 1);
-    if (ne > 0) {
-        hipLaunchKernelGGL(k_nl_pos, dim3(nblk(ne, 256)), dim3(256), 0, s, ent, mask, ne, pc, pos);
+    if (nk > 0) {
+        hipLaunchKernelGGL(k_cm_pos, dim3(nblk(nk, 256)), dim3(256), 0, s, ent, mask, nk, max_pc, pc, pos);
         STK_CHECK_LAUNCH();
     }
-    scan_exclusive_i32(pc, incoff, ne, t.s_scan, s);
-    // per target: first slot (exclusive scan of the near-leaf counts, sorted order)
-    int32_t *toff = reserve<int32_t>(pl.near_toff, size_t(m) + 1);
-    scan_exclusive_i32(pl.cnt_near.as<int32_t>(), toff, m, t.s_scan, s);
-    // per leaf: entry range, incidence range, items of up to 64 incidences
-    int32_t *eoff = reserve<int32_t>(pl.nl_eoff, size_t(nn) + 1);
-    int32_t *loff = reserve<int32_t>(pl.nl_loff, size_t(nn) + 1);
-    int32_t *icnt = reserve<int32_t>(pl.nl_icnt, size_t(nn) + 1);
-    int32_t *ioff = reserve<int32_t>(pl.nl_ioff, size_t(nn) + 1);
-    hipLaunchKernelGGL(k_node_off, dim3(nblk(int64_t(nn) + 1, 256)), dim3(256), 0, s, keys, ne, nn, eoff);
+    scan_exclusive_i32(pc, incoff, nk, t.s_scan, s);
+    // per target: first slot (exclusive scan of its kept-entry count, sorted order)
+    if (!tcount) {
+        int32_t *tc = reserve<int32_t>(cm.tcnt, size_t(m) + 1);
+        if (ng > 0) {
+            hipLaunchKernelGGL(k_cm_tcount, dim3(ng), dim3(64), 0, s, off, mask, m, max_pc, tc);
+            STK_CHECK_LAUNCH();
+        }
+        tcount = tc;
+    }
+    int32_t *toff = reserve<int32_t>(cm.toff, size_t(m) + 1);
+    scan_exclusive_i32(tcount, toff, m, t.s_scan, s);
+    // per node: entry range, incidence range, items of up to 64 incidences
+    int32_t *eoff = reserve<int32_t>(cm.eoff, size_t(nn) + 1);
+    int32_t *loff = reserve<int32_t>(cm.loff, size_t(nn) + 1);
+    int32_t *icnt = reserve<int32_t>(cm.icnt, size_t(nn) + 1);
+    int32_t *ioff = reserve<int32_t>(cm.ioff, size_t(nn) + 1);
+    hipLaunchKernelGGL(k_node_off, dim3(nblk(int64_t(nn) + 1, 256)), dim3(256), 0, s, keys, nk, nn, eoff);
     STK_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_nl_loff, dim3(nblk(int64_t(nn) + 1, 256)), dim3(256), 0, s, eoff, incoff, nn, loff);
+    hipLaunchKernelGGL(k_cm_loff, dim3(nblk(int64_t(nn) + 1, 256)), dim3(256), 0, s, eoff, incoff, nn, loff);
     STK_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_item_count, dim3(nblk(nn, 256)), dim3(256), 0, s, loff, nn, 64, icnt);
     STK_CHECK_LAUNCH();
     scan_exclusive_i32(icnt, ioff, nn, t.s_scan, s);
     int32_t tot[3];
-    STK_HIP(hipMemcpyAsync(&tot[0], incoff + ne, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    STK_HIP(hipMemcpyAsync(&tot[0], incoff + nk, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     STK_HIP(hipMemcpyAsync(&tot[1], ioff + nn, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     STK_HIP(hipMemcpyAsync(&tot[2], toff + m, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     STK_HIP(hipStreamSynchronize(s));
-    if (tot[0] != tot[2]) throw Error(STK_EDEVICE, "near lists: incidence count differs from the per-target counts");
-    pl.n_inc = tot[0];
-    pl.n_near_items = tot[1];
-    int32_t *inc_tgt = reserve<int32_t>(pl.inc_tgt, size_t(pl.n_inc) + 1);
-    int32_t *inc_slot = reserve<int32_t>(pl.inc_slot, size_t(pl.n_inc) + 1);
-    int32_t *ileaf = reserve<int32_t>(pl.item_leaf, size_t(pl.n_near_items) + 1);
-    int32_t *i0 = reserve<int32_t>(pl.item_i0, size_t(pl.n_near_items) + 1);
-    int32_t *i1 = reserve<int32_t>(pl.item_i1, size_t(pl.n_near_items) + 1);
-    hipLaunchKernelGGL(k_item_fill, dim3(nblk(nn, 256)), dim3(256), 0, s, loff, ioff, nn, 64, ileaf, i0, i1);
+    if (tot[0] != tot[2]) throw Error(STK_EDEVICE, "lists: incidence count differs from the per-target counts");
+    cm.n_inc = tot[0];
+    cm.n_items = tot[1];
+    int32_t *inc_tgt = reserve<int32_t>(cm.inc_tgt, size_t(cm.n_inc) + 1);
+    int32_t *inc_slot = reserve<int32_t>(cm.inc_slot, size_t(cm.n_inc) + 1);
+    int32_t *inode = reserve<int32_t>(cm.item_node, size_t(cm.n_items) + 1);
+    int32_t *i0 = reserve<int32_t>(cm.item_i0, size_t(cm.n_items) + 1);
+    int32_t *i1 = reserve<int32_t>(cm.item_i1, size_t(cm.n_items) + 1);
+    hipLaunchKernelGGL(k_item_fill, dim3(nblk(nn, 256)), dim3(256), 0, s, loff, ioff, nn, 64, inode, i0, i1);
     STK_CHECK_LAUNCH();
     if (ng > 0) {
-        hipLaunchKernelGGL(k_nl_fill, dim3(ng), dim3(64), 0, s, off, mask, pos, incoff, toff, m, inc_tgt, inc_slot);
+        hipLaunchKernelGGL(k_cm_fill, dim3(ng), dim3(64), 0, s, off, mask, max_pc, pos, incoff, toff, m, inc_tgt,
+                           inc_slot);
         STK_CHECK_LAUNCH();
     }
+}
+
+void near_field(Tree &t, Plan &pl, double *unear, hipStream_t s) {
+    const int64_t m = pl.m;
+    ClusterMajor &cm = pl.ncm;
+    cluster_major(t, cm, pl.near_off.as<int32_t>(), pl.near_node.as<int32_t>(), pl.near_mask.as<uint64_t>(),
+                  pl.n_near_entries, pl.ngroups, m, 64, pl.cnt_near.as<int32_t>(), s);
     prof_mark(STK_PHASE_LISTS, s);
+    const int32_t *ileaf = cm.item_node.as<int32_t>(), *i0 = cm.item_i0.as<int32_t>(), *i1 = cm.item_i1.as<int32_t>();
+    const int32_t *inc_tgt = cm.inc_tgt.as<int32_t>(), *inc_slot = cm.inc_slot.as<int32_t>();
+    const int32_t *toff = cm.toff.as<int32_t>();
 
     const int K = t.k_rhs;
     const size_t tsz = t.prec == STK_FP64 ? sizeof(double) : sizeof(float);
-    void *part = reserve<unsigned char>(pl.near_part, tsz * 3 * size_t(pl.n_inc) * K + tsz);
+    void *part = reserve<unsigned char>(cm.part, tsz * 3 * size_t(cm.n_inc) * K + tsz);
     NearArgs na{pl.tpos.as<double>(), ileaf, i0, i1, inc_tgt, inc_slot, t.nstart.as<int32_t>(),
                 t.ncount.as<int32_t>(), t.nbmin.as<double>(), t.nbmax.as<double>(), t.geo.as<double>(), t.wts.p,
-                part, pl.n_near_items, K};
+                part, cm.n_items, K};
     const int64_t mk = m * K;
     if (t.prec == STK_FP64) {
         launch_near<double, 1>(na, s);

@@ -122,6 +122,24 @@ struct AdjScratch {
 // ---------------------------------------------------------------------------------
 // plan handle: a tree plus one target set's interaction lists
 // ---------------------------------------------------------------------------------
+// Cluster-major view of (a filtered subset of) group-major lists: every (target, node)
+// incidence of the included entries placed in a node-sorted array, work items of up to 64
+// incidences of one node, and per target the slots of its incidences in the order of its
+// own list.
+struct ClusterMajor {
+    DBuf keys, ent;                // uint64 / int32 (entries): entries sorted by node
+    DBuf pc, pos;                  // int32: incidences of each sorted entry; sorted position of each entry
+    DBuf incoff;                   // int32 (entries + 1): first incidence of each sorted entry
+    DBuf eoff, loff;               // int32 (nn + 1): first sorted entry / first incidence of each node
+    DBuf icnt, ioff;               // int32: items per node (nn), their offsets (nn + 1)
+    DBuf tcnt, toff;               // int32: included entries per target (m), first slot (m + 1)
+    DBuf inc_tgt, inc_slot;        // int32 (incidences): sorted target and slot of each incidence
+    DBuf item_node, item_i0, item_i1;  // int32 (items)
+    DBuf part;                     // T (incidences, K, 3): per-incidence partial velocities
+    int64_t n_inc = 0;
+    int32_t n_items = 0;
+};
+
 // kernel variants of one evaluation (chosen per architecture, p, K and precision)
 struct Tiles {
     int32_t far_kb = 1;      // right-hand sides per pass of the far-field kernel (1, 2, 4)
@@ -143,20 +161,10 @@ struct Plan {
     DBuf far_mask, near_mask;      // uint64 entries (lane masks of the 64-target group)
     DBuf cnt_far, cnt_near, cnt_pairs;  // int32 per sorted target
     int64_t n_far_entries = 0, n_near_entries = 0;
-    // leaf-major near field, built from the group-major near lists: incidences (one per
-    // (target, near leaf)) sorted by leaf, work items of up to 64 incidences of one leaf,
-    // and per target the slots of its incidences in the order of its near list
-    DBuf nl_keys, nl_ent;          // uint64 / int32 (near entries): entries sorted by leaf
-    DBuf nl_pc, nl_pos;            // int32: popcount of each sorted entry; sorted position of each entry
-    DBuf nl_incoff;                // int32 (near entries + 1): first incidence of each sorted entry
-    DBuf nl_eoff, nl_loff;         // int32 (nn + 1): first sorted entry / first incidence of each leaf
-    DBuf nl_icnt, nl_ioff;         // int32: items per leaf (nn), their offsets (nn + 1)
-    DBuf near_toff;                // int32 (m + 1): first slot of each sorted target
-    DBuf inc_tgt, inc_slot;        // int32 (incidences): sorted target and slot of each incidence
-    DBuf item_leaf, item_i0, item_i1;  // int32 (items)
-    DBuf near_part;                // T (incidences, 3): per (target, leaf) partial velocities
-    int64_t n_inc = 0;
-    int32_t n_near_items = 0;
+    // cluster-major views of the group lists: the near field (every near entry) and, for
+    // one right-hand side, the far entries that apply to few targets of their group
+    ClusterMajor ncm, fcm;
+    int32_t far_sparse_max = 0;       // threshold of the last evaluation's sparse far split
     Tiles tiles;                      // kernel variants used by the last evaluation
     bool forced = false;              // use `force` instead of the table (autotuning)
     Tiles force;
@@ -198,9 +206,19 @@ void tiles_save(const char *path);
 int tiles_load(const char *path);
 Tiles autotune(int p, int K, stk_precision prec, int64_t n, double theta, int32_t n0, double *best_ms, hipStream_t s);
 
+// Build cm from group-major lists (off: ngroups + 1 offsets, node/mask: ne entries), keeping
+// the entries whose lane mask has at most max_pc bits (64: all).  tcount: per-target number
+// of kept entries if known (sorted order), else NULL (counted here).  Synchronises s once.
+void cluster_major(Tree &t, ClusterMajor &cm, const int32_t *off, const int32_t *node, const uint64_t *mask,
+                   int64_t ne, int32_t ng, int64_t m, int max_pc, const int32_t *tcount, hipStream_t s);
 // near field of a plan whose group-major near lists are filled: unear (m,K,3), sorted
 // target order, K = the tree's right-hand sides
 void near_field(Tree &t, Plan &plan, double *unear, hipStream_t s);
+// far entries with at most FAR_SPARSE_MAX targets (one right-hand side), cluster major:
+// adds their velocities to unear (m,3) and records the threshold the group-major far kernel
+// then skips; returns the threshold (0: nothing split off)
+constexpr int FAR_SPARSE_MAX = 32;
+int far_sparse(Tree &t, Plan &plan, double *unear, hipStream_t s);
 void direct_sum(const double *tgt, int64_t m, const double *src, int64_t n, const double *f, const double *h,
                 const double *nu, int32_t k, double *u_out, hipStream_t s);
 
