@@ -227,14 +227,18 @@ template <int P, typename T> struct TgradVisit {
         int pg = 0, pe = 0;
         stream_pos_c(kk, pg, pe);
         const T sig = dh[0] * W[pe] + dh[1] * W[pe + 1] + dh[2] * W[pe + 2];
-        // h_s = sum_i w_i (k_i+1)(k_s+1+delta_is) bt^{k+e_i+e_s}
-        const T w0 = wl[0] * T(K1 + 1), w1 = wl[1] * T(K2 + 1), w2 = wl[2] * T(K3 + 1);
-        const T hx = w0 * T(K1 + 2) * b[gidx(K1 + 2, K2, K3)] + w1 * T(K1 + 1) * b[gidx(K1 + 1, K2 + 1, K3)] +
-                     w2 * T(K1 + 1) * b[gidx(K1 + 1, K2, K3 + 1)];
-        const T hy = w0 * T(K2 + 1) * b[gidx(K1 + 1, K2 + 1, K3)] + w1 * T(K2 + 2) * b[gidx(K1, K2 + 2, K3)] +
-                     w2 * T(K2 + 1) * b[gidx(K1, K2 + 1, K3 + 1)];
-        const T hz = w0 * T(K3 + 1) * b[gidx(K1 + 1, K2, K3 + 1)] + w1 * T(K3 + 1) * b[gidx(K1, K2 + 1, K3 + 1)] +
-                     w2 * T(K3 + 2) * b[gidx(K1, K2, K3 + 2)];
+        // h_s = sum_i w_i (k_i+1)(k_s+1+delta_is) bt^{k+e_i+e_s}; every product takes a
+        // coefficient before the lane's weight, so no weight-times-constant product is
+        // invariant over the entry loop (hoisted, such products fill the register file)
+        const T hx = wl[0] * (T((K1 + 1) * (K1 + 2)) * b[gidx(K1 + 2, K2, K3)]) +
+                     wl[1] * (T((K2 + 1) * (K1 + 1)) * b[gidx(K1 + 1, K2 + 1, K3)]) +
+                     wl[2] * (T((K3 + 1) * (K1 + 1)) * b[gidx(K1 + 1, K2, K3 + 1)]);
+        const T hy = wl[0] * (T((K1 + 1) * (K2 + 1)) * b[gidx(K1 + 1, K2 + 1, K3)]) +
+                     wl[1] * (T((K2 + 1) * (K2 + 2)) * b[gidx(K1, K2 + 2, K3)]) +
+                     wl[2] * (T((K3 + 1) * (K2 + 1)) * b[gidx(K1, K2 + 1, K3 + 1)]);
+        const T hz = wl[0] * (T((K1 + 1) * (K3 + 1)) * b[gidx(K1 + 1, K2, K3 + 1)]) +
+                     wl[1] * (T((K2 + 1) * (K3 + 1)) * b[gidx(K1, K2 + 1, K3 + 1)]) +
+                     wl[2] * (T((K3 + 1) * (K3 + 2)) * b[gidx(K1, K2, K3 + 2)]);
         a2[0] += sig * hx;
         a2[1] += sig * hy;
         a2[2] += sig * hz;
@@ -248,7 +252,7 @@ template <int P, typename T> struct TgradVisit {
     }
 };
 
-template <int P, typename T> __global__ __launch_bounds__(64) void k_far_tgrad(TgradArgs a) {
+template <int P, typename T> __global__ __launch_bounds__(64, sizeof(T) == 4 ? 4 : 2) void k_far_tgrad(TgradArgs a) {
     constexpr int NG = nidx(P + 1);
     const int32_t g = xcd_group(a.ngroups);
     if (g >= a.ngroups) return;
