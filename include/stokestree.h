@@ -236,7 +236,13 @@ stk_status stk_plan_info(const stk_plan *plan, int64_t *ngroups, int64_t *n_far_
 stk_status stk_plan_far_split(const stk_plan *plan, int32_t *max_pc, int64_t *sparse_interactions);
 
 void stk_tree_destroy(stk_tree *t);
+/* Release a plan.  A plan made by stk_evaluate (it owns its tree) may instead be parked,
+ * after a device synchronisation, for reuse by the next stk_evaluate with keep_plan on the
+ * same device (at most 2 per device), so that repeated forward + adjoint calls do not
+ * allocate device memory; NULL is ignored. */
 void stk_plan_destroy(stk_plan *plan);
+/* Free the device memory of every parked plan. */
+void stk_plan_cache_clear(void);
 /* Message for the calling thread's last non-OK status ("" if none). */
 const char *stk_last_error(void);
 

@@ -28,7 +28,8 @@ EXPORTS = ["stk_build_tree", "stk_compute_moments", "stk_evaluate_tree", "stk_ev
            "stk_tree_info", "stk_tree_export", "stk_tree_export_moments", "stk_plan_counts", "stk_plan_info",
            "stk_plan_export_lists", "stk_plan_far_split", "stk_tiles_set", "stk_tiles_get", "stk_autotune", "stk_tiles_save",
            "stk_tiles_load", "stk_plan_tiles",
-           "stk_profile_enable", "stk_profile_read", "stk_tree_destroy", "stk_plan_destroy", "stk_last_error"]
+           "stk_profile_enable", "stk_profile_read", "stk_tree_destroy", "stk_plan_destroy",
+           "stk_plan_cache_clear", "stk_last_error"]
 
 PHASES = ["tree", "moments", "targets", "lists", "near", "far", "direct", "adjoint", "far_sparse"]
 
@@ -89,6 +90,7 @@ for _name in EXPORTS:
     _lib[_name].restype = ctypes.c_int if _name != "stk_last_error" else ctypes.c_char_p
 _lib.stk_tree_destroy.restype = None
 _lib.stk_plan_destroy.restype = None
+_lib.stk_plan_cache_clear.restype = None
 
 
 def _check(st: int) -> None:
@@ -323,6 +325,11 @@ def plan_far_split(plan: Plan) -> tuple[int, int]:
     mp, ns = ctypes.c_int32(), ctypes.c_int64()
     _check(_lib.stk_plan_far_split(plan.handle, ctypes.byref(mp), ctypes.byref(ns)))
     return mp.value, ns.value
+
+
+def plan_cache_clear() -> None:
+    """Free the device memory of the plans parked for reuse by evaluate(keep_plan=True)."""
+    _lib.stk_plan_cache_clear()
 
 
 def profile_enable(on: bool = True) -> None:

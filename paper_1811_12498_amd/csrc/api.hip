@@ -3,7 +3,9 @@
 // message for stk_last_error().
 #include <cmath>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "stk_internal.hpp"
 #include "stk_math.hpp"
@@ -51,6 +53,70 @@ void check_common(const double *pts, int64_t n, const char *what) {
     stk::require(pts != nullptr, std::string(what) + " is NULL");
     stk::require(n >= 1, std::string(what) + ": count must be >= 1");
     stk::require(n < (int64_t(1) << 31) / 8, std::string(what) + ": count too large (int32 indexing)");
+}
+
+// Plans that own their tree, parked by stk_plan_destroy for the next stk_evaluate with
+// keep_plan on the same device: their buffers keep their capacity, so a loop of
+// forward + adjoint calls allocates and frees no device memory after the first pass
+// (hipFree synchronises the device on every call).  The pool is never destroyed: parked
+// device memory returns to the system when the process exits or stk_plan_cache_clear
+// runs.
+constexpr size_t PLAN_POOL_PER_DEVICE = 2;
+
+struct PlanPool {
+    std::mutex mu;
+    std::vector<stk_plan *> parked;
+};
+
+PlanPool &plan_pool() {
+    static PlanPool *pool = new PlanPool();
+    return *pool;
+}
+
+stk_plan *take_plan(int dev) {
+    PlanPool &pp = plan_pool();
+    std::lock_guard<std::mutex> lk(pp.mu);
+    for (size_t i = 0; i < pp.parked.size(); ++i) {
+        stk_plan *pl = pp.parked[i];
+        if (pl->p.tree->device == dev) {
+            pp.parked.erase(pp.parked.begin() + i);
+            pl->p.forced = false;
+            return pl;
+        }
+    }
+    return nullptr;
+}
+
+// Park a plan with an owned tree when its device has room, after the device has finished
+// all work queued so far (the plan's kernels may still be in flight on any stream);
+// otherwise delete it.
+void park_or_delete(stk_plan *pl) {
+    if (!pl->p.owns_tree || pl->p.tree == nullptr) {
+        delete pl;
+        return;
+    }
+    const int dev = pl->p.tree->device;
+    PlanPool &pp = plan_pool();
+    {
+        std::lock_guard<std::mutex> lk(pp.mu);
+        size_t here = 0;
+        for (stk_plan *q : pp.parked) here += q->p.tree->device == dev;
+        if (here >= PLAN_POOL_PER_DEVICE) {
+            delete pl;
+            return;
+        }
+    }
+    int cur = -1;
+    bool ok = hipGetDevice(&cur) == hipSuccess;
+    if (ok && cur != dev) ok = hipSetDevice(dev) == hipSuccess;
+    if (ok) ok = hipDeviceSynchronize() == hipSuccess;
+    if (cur >= 0 && cur != dev) (void)hipSetDevice(cur);
+    if (!ok) {
+        delete pl;
+        return;
+    }
+    std::lock_guard<std::mutex> lk(pp.mu);
+    pp.parked.push_back(pl);
 }
 
 }  // namespace
@@ -150,14 +216,17 @@ stk_status stk_evaluate(const double *targets, int64_t m, const double *sources,
             STK_HIP(hipStreamSynchronize(s));
             return;
         }
-        std::unique_ptr<stk::Tree> tree(new stk::Tree());
-        tree->device = dev;
-        stk::build_tree(*tree, sources, n, n0, s);
-        stk::compute_moments(*tree, f, h, nu, k_rhs, p, prec, s);
-        std::unique_ptr<stk_plan> pl(new stk_plan());
-        stk::evaluate(*tree, pl->p, targets, m, theta, u_out, same, s);
-        pl->p.tree = tree.release();
-        pl->p.owns_tree = true;
+        std::unique_ptr<stk_plan> pl(take_plan(dev));
+        if (!pl) {
+            pl.reset(new stk_plan());
+            pl->p.tree = new stk::Tree();
+            pl->p.owns_tree = true;
+            pl->p.tree->device = dev;
+        }
+        stk::Tree &tree = *pl->p.tree;
+        stk::build_tree(tree, sources, n, n0, s);
+        stk::compute_moments(tree, f, h, nu, k_rhs, p, prec, s);
+        stk::evaluate(tree, pl->p, targets, m, theta, u_out, same, s);
         *keep_plan = pl.release();
     });
 }
@@ -386,6 +455,18 @@ stk_status stk_profile_read(double *ms, int64_t *count) {
 }
 
 void stk_tree_destroy(stk_tree *t) { delete t; }
-void stk_plan_destroy(stk_plan *plan) { delete plan; }
+void stk_plan_destroy(stk_plan *plan) {
+    if (plan) park_or_delete(plan);
+}
+
+void stk_plan_cache_clear(void) {
+    PlanPool &pp = plan_pool();
+    std::vector<stk_plan *> drop;
+    {
+        std::lock_guard<std::mutex> lk(pp.mu);
+        drop.swap(pp.parked);
+    }
+    for (stk_plan *pl : drop) delete pl;
+}
 
 }  // extern "C"
