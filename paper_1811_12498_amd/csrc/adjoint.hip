@@ -28,6 +28,10 @@ namespace {
 
 inline unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
 
+// incidences per cluster-adjoint work item (16 passes of 64 lanes): the item's LDS
+// accumulator is added to the cluster's stream adjoint once, with atomics, at its end
+constexpr int32_t LAMBDA_RUN = 16 * 64;
+
 // ---- near-field adjoint ------------------------------------------------------------------
 // dL/dx of one pair (w.u, u the contracted pair of Sec. 4.1) in FP64
 __device__ inline void pgrad_f64(const double d[3], const double f[3], const double h[3], const double nu[3],
@@ -545,47 +549,80 @@ void adjoint(Plan &pl, const double *w, double *gf, double *gh, double *gt, doub
         STK_CHECK_LAUNCH();
     }
 
-    // far field: stream adjoints (source side) and target gradients
+    // far field: stream adjoints (source side) and target gradients, both over the
+    // cluster-major view of every far entry (64 incidences of one cluster per pass)
     LambdaArgs la{};
     TgradArgs ta{};
     PhiT &ph = phit_for(t.device, p);
+    ClusterMajor &fc = A.far_cm;
+    if (src || gt)
+        cluster_major(t, fc, pl.far_off.as<int32_t>(), pl.far_node.as<int32_t>(), pl.far_mask.as<uint64_t>(),
+                      pl.n_far_entries, ng, m, 64, pl.cnt_far.as<int32_t>(), s);
     if (src) {
-        transpose(t, pl.far_off, pl.far_node, pl.n_far_entries, ng, A.far_t, true, 16, s);
+        // work items: runs of up to LAMBDA_RUN incidences of one cluster
+        const int32_t *loff = fc.loff.as<int32_t>();
+        int32_t *cnt = reserve<int32_t>(t.s_vals, size_t(nn) + 1);
+        int32_t *ioff = reserve<int32_t>(t.s_vals2, size_t(nn) + 1);
+        hipLaunchKernelGGL(k_item_count, dim3(nblk(nn, 256)), dim3(256), 0, s, loff, nn, LAMBDA_RUN, cnt);
+        STK_CHECK_LAUNCH();
+        scan_exclusive_i32(cnt, ioff, nn, t.s_scan, s);
+        int32_t nitems = 0;
+        STK_HIP(hipMemcpyAsync(&nitems, ioff + nn, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        STK_HIP(hipStreamSynchronize(s));
+        TransposedLists &tr = A.far_t;
+        tr.nitems = nitems;
+        int32_t *inode = reserve<int32_t>(tr.item_node, size_t(nitems) + 1);
+        int32_t *ia = reserve<int32_t>(tr.item_a, size_t(nitems) + 1);
+        int32_t *ib = reserve<int32_t>(tr.item_b, size_t(nitems) + 1);
+        hipLaunchKernelGGL(k_item_fill, dim3(nblk(nn, 256)), dim3(256), 0, s, loff, ioff, nn, LAMBDA_RUN, inode, ia,
+                           ib);
+        STK_CHECK_LAUNCH();
         double *lam = reserve<double>(A.lambda, size_t(nn) * 6 * ngc);
         STK_HIP(hipMemsetAsync(lam, 0, sizeof(double) * size_t(nn) * 6 * ngc, s));
         la.tpos = pl.tpos.as<double>();
         la.ws = ws;
         la.m = m;
-        la.item_node = A.far_t.item_node.as<int32_t>();
-        la.item_e0 = A.far_t.item_a.as<int32_t>();
-        la.item_e1 = A.far_t.item_b.as<int32_t>();
-        la.ent = A.far_t.ent.as<int32_t>();
-        la.ent_group = A.far_t.ent_group.as<int32_t>();
-        la.mask = pl.far_mask.as<uint64_t>();
+        la.item_node = inode;
+        la.item_i0 = ia;
+        la.item_i1 = ib;
+        la.inc_tgt = fc.inc_tgt.as<int32_t>();
         la.center = t.ncenter.as<double>();
         la.rho = t.nrho.as<double>();
         la.cpos = ph.cpos.as<int32_t>();
         la.ckind = ph.ckind.as<int32_t>();
         la.lambda = lam;
-        la.nitems = A.far_t.nitems;
+        la.nitems = nitems;
     }
     if (gt) {
+        const size_t tsz = fp64 ? sizeof(double) : sizeof(float);
         ta.tpos = pl.tpos.as<double>();
         ta.ws = ws;
-        ta.m = m;
-        ta.off = pl.far_off.as<int32_t>();
-        ta.node = pl.far_node.as<int32_t>();
-        ta.mask = pl.far_mask.as<uint64_t>();
+        ta.item_node = fc.item_node.as<int32_t>();
+        ta.item_i0 = fc.item_i0.as<int32_t>();
+        ta.item_i1 = fc.item_i1.as<int32_t>();
+        ta.inc_tgt = fc.inc_tgt.as<int32_t>();
+        ta.inc_slot = fc.inc_slot.as<int32_t>();
         ta.center = t.ncenter.as<double>();
         ta.rho = t.nrho.as<double>();
         ta.wblk = t.wblk.p;
-        ta.gt = gtf;
-        ta.ngroups = ng;
+        ta.part = reserve<unsigned char>(fc.part, tsz * 3 * size_t(fc.n_inc) + tsz);
+        ta.nitems = fc.n_items;
     }
     if (fp64)
         dispatch_adj<double>(p, la, ta, s);
     else
         dispatch_adj<float>(p, la, ta, s);
+    if (gt) {
+        // each target's far terms added in the order of its own list
+        const int32_t *toff = fc.toff.as<int32_t>();
+        if (fp64)
+            hipLaunchKernelGGL(k_slot_reduce<double>, dim3(nblk(m, 256)), dim3(256), 0, s,
+                               static_cast<const double *>(ta.part), toff, m, gtf);
+        else
+            hipLaunchKernelGGL(k_slot_reduce<float>, dim3(nblk(m, 256)), dim3(256), 0, s,
+                               static_cast<const float *>(ta.part), toff, m, gtf);
+        STK_CHECK_LAUNCH();
+    }
 
     if (src) {
         // stream adjoints -> moment adjoints -> per-level source gradients

@@ -7,9 +7,12 @@
 // which is linear in the cluster stream (Ghat, Ehat).  Two kernels use it:
 //   k_far_lambda  accumulates dL/dGhat_i^q = sum_m (w_i / R) bt^q and
 //                 dL/dEhat_l^k = sum_m dh_l zh^k over the targets that accept the cluster
-//                 (cluster-major work items; per order the wave writes its targets'
+//                 (work items: runs of a cluster's incidences, 64 per pass whatever
+//                 groups they come from; per order the wave writes its targets'
 //                 coefficients to LDS and each lane sums whole columns);
-//   k_far_tgrad   dL/dx for each target, from d/dx_s b^q = -(q_s + 1) b^{q + e_s}:
+//   k_far_tgrad   dL/dx for each target (one incidence per lane, the partial written to
+//                 the incidence's slot in the target's list and the slots added in list
+//                 order afterwards), from d/dx_s b^q = -(q_s + 1) b^{q + e_s}:
 //     dL/dx_s = -(1/(R rho)) sum_q (q_s+1) bt^{q+e_s} (w . Ghat^q)
 //               -(1/rho) sum_k (dh . Ehat^k) sum_i w_i (k_i+1)(k_s+1+delta_is) bt^{k+e_i+e_s}
 //               +(1/R) sum_k Ehat_s^k zh^k,
@@ -30,11 +33,9 @@ struct LambdaArgs {
     const double *ws;          // sorted adjoint seed w (m,3)
     int64_t m;
     const int32_t *item_node;  // work item -> cluster
-    const int32_t *item_e0;    // work item -> first position in the cluster-sorted entry list
-    const int32_t *item_e1;
-    const int32_t *ent;        // cluster-sorted far entries (indices into the group lists)
-    const int32_t *ent_group;  // far entry -> group
-    const uint64_t *mask;      // far entry -> lane mask
+    const int32_t *item_i0;    // work item -> its incidences [i0, i1) in the cluster-major view
+    const int32_t *item_i1;
+    const int32_t *inc_tgt;    // incidence -> sorted target
     const double *center, *rho;
     const int32_t *cpos;       // (batches, lam_tbl): stream position of each LDS column
     const int32_t *ckind;      // (batches, lam_tbl): 0 = G column (weights w / R), 1 = E column (weights dh)
@@ -103,13 +104,12 @@ template <int P, typename T> __host__ __device__ constexpr size_t lam_lds_bytes(
 // ---------------------------------------------------------------------------------
 struct TgradArgs {
     const double *tpos, *ws;
-    int64_t m;
-    const int32_t *off, *node;
-    const uint64_t *mask;
+    const int32_t *item_node, *item_i0, *item_i1;  // work items of up to 64 incidences of one cluster
+    const int32_t *inc_tgt, *inc_slot;             // incidence -> sorted target, slot in its list
     const double *center, *rho;
     const void *wblk;
-    double *gt;   // (m,3) sorted order, written
-    int32_t ngroups;
+    void *part;   // (incidences, 3) T: each incidence's term, at its slot
+    int32_t nitems;
 };
 
 // per source, from the moment adjoints of its node: dL/df, dL/dh, dL/dy (one partial

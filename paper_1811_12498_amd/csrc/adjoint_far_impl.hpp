@@ -148,12 +148,10 @@ template <int P, typename T> __global__ __launch_bounds__(64) void k_far_lambda(
     for (int q = lane; q < 6 * NG; q += 64) acc[q] = T(0);
     const double c0 = a.center[3 * c], c1 = a.center[3 * c + 1], c2 = a.center[3 * c + 2];
     const double rho = a.rho[c];
-    for (int32_t e = a.item_e0[it]; e < a.item_e1[it]; ++e) {
-        const int32_t ent = a.ent[e];
-        const int32_t g = a.ent_group[ent];
-        const uint64_t mk = a.mask[ent];
-        const int64_t t = int64_t(g) * 64 + lane;
-        const bool in = ((mk >> lane) & 1ull) && t < a.m;
+    const int32_t i1 = a.item_i1[it];
+    for (int32_t i0 = a.item_i0[it]; i0 < i1; i0 += 64) {
+        const bool in = i0 + lane < i1;
+        const int64_t t = in ? a.inc_tgt[i0 + lane] : 0;
         T dh[3] = {T(1), T(0), T(0)}, tt = T(0), wl[3] = {T(0), T(0), T(0)}, ri = T(0);
         if (in) {
             const double d0 = a.tpos[3 * t] - c0, d1 = a.tpos[3 * t + 1] - c1, d2 = a.tpos[3 * t + 2] - c2;
@@ -252,48 +250,33 @@ template <int P, typename T> struct TgradVisit {
     }
 };
 
+// one wave per work item: a cluster and up to 64 of its incidences; each lane forms its
+// target's term of this interaction and writes it to the incidence's slot
 template <int P, typename T> __global__ __launch_bounds__(64, sizeof(T) == 4 ? 4 : 2) void k_far_tgrad(TgradArgs a) {
     constexpr int NG = nidx(P + 1);
-    const int32_t g = xcd_group(a.ngroups);
-    if (g >= a.ngroups) return;
+    const int32_t it = xcd_group(a.nitems);
+    if (it >= a.nitems) return;
     const int lane = threadIdx.x;
-    const int64_t t = int64_t(g) * 64 + lane;
-    const bool valid = t < a.m;
-    double x0 = 0, x1 = 0, x2 = 0, w0 = 0, w1 = 0, w2 = 0;
-    if (valid) {
-        x0 = a.tpos[3 * t];
-        x1 = a.tpos[3 * t + 1];
-        x2 = a.tpos[3 * t + 2];
-        w0 = a.ws[3 * t];
-        w1 = a.ws[3 * t + 1];
-        w2 = a.ws[3 * t + 2];
-    }
-    const T *wb = static_cast<const T *>(a.wblk);
-    Comp<T> acc[3];
-    for (int32_t e = a.off[g]; e < a.off[g + 1]; ++e) {
-        const int32_t c = __builtin_amdgcn_readfirstlane(a.node[e]);
-        const uint64_t mk = a.mask[e];
-        if ((mk >> lane) & 1ull) {
-            const double d0 = x0 - a.center[3 * c], d1 = x1 - a.center[3 * c + 1], d2 = x2 - a.center[3 * c + 2];
-            const double rinv = 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-            const double rho = a.rho[c];
-            TgradVisit<P, T> v{wb + size_t(c) * 6 * NG,
-                               {T(d0 * rinv), T(d1 * rinv), T(d2 * rinv)},
-                               {T(w0), T(w1), T(w2)},
-                               {T(0), T(0), T(0)},
-                               {T(0), T(0), T(0)},
-                               {T(0), T(0), T(0)}};
-            T b[nidx(P + 3)];
-            Coefs<P + 3, T, TgradVisit<P, T>>::run(b, v.dh, T(rho * rinv), v);
-            const T f1 = T(-rinv / rho), f2 = T(-1.0 / rho), f3 = T(rinv);
-            for (int s = 0; s < 3; ++s) acc[s].add(f1 * v.a1[s] + f2 * v.a2[s] + f3 * v.a3[s]);
-        }
-    }
-    if (valid) {
-        a.gt[3 * t] = acc[0].value();
-        a.gt[3 * t + 1] = acc[1].value();
-        a.gt[3 * t + 2] = acc[2].value();
-    }
+    const int32_t c = __builtin_amdgcn_readfirstlane(a.item_node[it]);
+    const int32_t i0 = a.item_i0[it];
+    if (lane >= a.item_i1[it] - i0) return;
+    const int64_t t = a.inc_tgt[i0 + lane];
+    const int32_t slot = a.inc_slot[i0 + lane];
+    const double d0 = a.tpos[3 * t] - a.center[3 * c], d1 = a.tpos[3 * t + 1] - a.center[3 * c + 1],
+                 d2 = a.tpos[3 * t + 2] - a.center[3 * c + 2];
+    const double rinv = 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    const double rho = a.rho[c];
+    TgradVisit<P, T> v{static_cast<const T *>(a.wblk) + size_t(c) * 6 * NG,
+                       {T(d0 * rinv), T(d1 * rinv), T(d2 * rinv)},
+                       {T(a.ws[3 * t]), T(a.ws[3 * t + 1]), T(a.ws[3 * t + 2])},
+                       {T(0), T(0), T(0)},
+                       {T(0), T(0), T(0)},
+                       {T(0), T(0), T(0)}};
+    T b[nidx(P + 3)];
+    Coefs<P + 3, T, TgradVisit<P, T>>::run(b, v.dh, T(rho * rinv), v);
+    const T f1 = T(-rinv / rho), f2 = T(-1.0 / rho), f3 = T(rinv);
+    T *o = static_cast<T *>(a.part) + 3 * int64_t(slot);
+    for (int s = 0; s < 3; ++s) o[s] = f1 * v.a1[s] + f2 * v.a2[s] + f3 * v.a3[s];
 }
 
 template <int P, typename T> void launch_far_lambda(const LambdaArgs &a, hipStream_t s) {
@@ -303,8 +286,8 @@ template <int P, typename T> void launch_far_lambda(const LambdaArgs &a, hipStre
 }
 
 template <int P, typename T> void launch_far_tgrad(const TgradArgs &a, hipStream_t s) {
-    if (a.ngroups == 0) return;
-    hipLaunchKernelGGL((k_far_tgrad<P, T>), dim3(xcd_blocks(a.ngroups)), dim3(64), 0, s, a);
+    if (a.nitems == 0) return;
+    hipLaunchKernelGGL((k_far_tgrad<P, T>), dim3(xcd_blocks(a.nitems)), dim3(64), 0, s, a);
     STK_CHECK_LAUNCH();
 }
 

@@ -113,12 +113,6 @@ struct TransposedLists {
     int32_t nitems = 0;
 };
 
-// scratch of the adjoint, kept with the plan for repeated backward calls
-struct AdjScratch {
-    DBuf ws, gt_near, gt_far, lambda, lm, part, gs;
-    TransposedLists far_t, near_t;
-};
-
 // ---------------------------------------------------------------------------------
 // plan handle: a tree plus one target set's interaction lists
 // ---------------------------------------------------------------------------------
@@ -138,6 +132,13 @@ struct ClusterMajor {
     DBuf part;                     // T (incidences, K, 3): per-incidence partial velocities
     int64_t n_inc = 0;
     int32_t n_items = 0;
+};
+
+// scratch of the adjoint, kept with the plan for repeated backward calls
+struct AdjScratch {
+    DBuf ws, gt_near, gt_far, lambda, lm, part, gs;
+    TransposedLists far_t, near_t;  // far_t: the cluster-adjoint work items
+    ClusterMajor far_cm;            // every far entry, cluster major
 };
 
 // kernel variants of one evaluation (chosen per architecture, p, K and precision)
