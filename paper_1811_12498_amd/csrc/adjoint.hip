@@ -247,7 +247,7 @@ struct PhiT {
     int p = -1;
     DBuf col_off, rowpos, epow;  // int32
     DBuf coef;                   // double
-    DBuf cpos, ckind;            // int32 (batches, lam_tbl) for k_far_lambda
+    DBuf cpos, ckind;            // int32 (columns) for k_far_lambda
 };
 
 std::mutex g_phit_mu;
@@ -298,20 +298,26 @@ PhiT &phit_for(int dev, int p) {
             mom[size_t(a) * 12 + c] = 0.0;
         }
     }
-    // LDS column -> stream position and weight kind of k_far_lambda, per column batch
-    const int TBL = lam_tbl(p), NBT = lam_nbatch(p);
-    std::vector<int32_t> cpos(size_t(NBT) * TBL, 0), ckind(size_t(NBT) * TBL, 0);
-    for (int g = 0; g < lam_ngroup(p); ++g) {
-        const int n = g >> 1, kind = g & 1, ord = kind ? n - 1 : n;
-        const int cnt = lam_gsize(p, g);
-        if (cnt == 0) continue;
-        const int base = ord > 0 ? nidx(ord - 1) : 0, bt = lam_batch(p, g), off = lam_off(p, g);
-        for (int col = 0; col < cnt; ++col) {
+    // LDS column -> stream position and weight kind of k_far_lambda (columns in the order
+    // the kernel forms them, padded to whole batches)
+    const int ncol = lam_ncol(p);
+    std::vector<int32_t> cpos(size_t((ncol + LAM_TBL - 1) / LAM_TBL) * LAM_TBL, 0), ckind(cpos.size(), 0);
+    for (int n = 0; n <= p + 1; ++n)
+        for (int k3 = 0; k3 <= n; ++k3)
+            for (int k2 = 0; k2 <= n - k3; ++k2) {
+                const int q[3] = {n - k3 - k2, k2, k3};
+                int pg, pe;
+                stream_pos(p, q, pg, pe);
+                cpos[lam_gcol(p, q[0], q[1], q[2])] = pg;
+            }
+    for (int n = 1; n <= p + 2; ++n) {
+        const int ord = n - 1, base = ord > 0 ? nidx(ord - 1) : 0;
+        for (int a = 0; a < n * (n + 1) / 2; ++a) {
             int q[3], pg, pe;
-            kof(base + col, q);
+            kof(base + a, q);
             stream_pos(p, q, pg, pe);
-            cpos[size_t(bt) * TBL + off + col] = kind == 0 ? pg : pe;
-            ckind[size_t(bt) * TBL + off + col] = kind;
+            cpos[lam_ebase(p, n) + a] = pe;
+            ckind[lam_ebase(p, n) + a] = 1;
         }
     }
     auto *t = new PhiT();
@@ -445,11 +451,10 @@ __global__ void k_leaf_fill(const int32_t *__restrict__ eoff, const int32_t *__r
 }
 
 // Re-sort group-major list entries by node: ent = entry positions ordered by node,
-// ent_off = per-node offsets into ent, ent_group = entry -> group, plus work items:
-// by_entries: (node, [a, b) range of ent) with <= per entries; otherwise (leaf, first
-// point) blocks of per points for leaves that have entries.
+// ent_off = per-node offsets into ent, ent_group = entry -> group, plus work items
+// (leaf, first point): blocks of per points of the leaves that have entries.
 void transpose(Tree &t, const DBuf &goff, const DBuf &gnode, int64_t ne, int32_t ngroups, TransposedLists &tr,
-               bool by_entries, int32_t per, hipStream_t s) {
+               int32_t per, hipStream_t s) {
     const int32_t nn = t.nnodes;
     int32_t *eg = reserve<int32_t>(tr.ent_group, size_t(ne) + 1);
     hipLaunchKernelGGL(k_entry_group, dim3(nblk(ngroups, 256)), dim3(256), 0, s, goff.as<int32_t>(), ngroups, eg);
@@ -468,11 +473,7 @@ void transpose(Tree &t, const DBuf &goff, const DBuf &gnode, int64_t ne, int32_t
     STK_CHECK_LAUNCH();
     int32_t *cnt = reserve<int32_t>(t.s_vals, size_t(nn) + 1);
     int32_t *ioff = reserve<int32_t>(t.s_vals2, size_t(nn) + 1);
-    if (by_entries)
-        hipLaunchKernelGGL(k_item_count, dim3(nblk(nn, 256)), dim3(256), 0, s, eoff, nn, per, cnt);
-    else
-        hipLaunchKernelGGL(k_leaf_units, dim3(nblk(nn, 256)), dim3(256), 0, s, eoff, t.ncount.as<int32_t>(), nn, per,
-                           cnt);
+    hipLaunchKernelGGL(k_leaf_units, dim3(nblk(nn, 256)), dim3(256), 0, s, eoff, t.ncount.as<int32_t>(), nn, per, cnt);
     STK_CHECK_LAUNCH();
     scan_exclusive_i32(cnt, ioff, nn, t.s_scan, s);
     int32_t nitems = 0;
@@ -481,12 +482,8 @@ void transpose(Tree &t, const DBuf &goff, const DBuf &gnode, int64_t ne, int32_t
     tr.nitems = nitems;
     int32_t *inode = reserve<int32_t>(tr.item_node, size_t(nitems) + 1);
     int32_t *ia = reserve<int32_t>(tr.item_a, size_t(nitems) + 1);
-    int32_t *ib = reserve<int32_t>(tr.item_b, size_t(nitems) + 1);
-    if (by_entries)
-        hipLaunchKernelGGL(k_item_fill, dim3(nblk(nn, 256)), dim3(256), 0, s, eoff, ioff, nn, per, inode, ia, ib);
-    else
-        hipLaunchKernelGGL(k_leaf_fill, dim3(nblk(nn, 256)), dim3(256), 0, s, eoff, t.nstart.as<int32_t>(),
-                           t.ncount.as<int32_t>(), ioff, nn, per, inode, ia);
+    hipLaunchKernelGGL(k_leaf_fill, dim3(nblk(nn, 256)), dim3(256), 0, s, eoff, t.nstart.as<int32_t>(),
+                       t.ncount.as<int32_t>(), ioff, nn, per, inode, ia);
     STK_CHECK_LAUNCH();
 }
 
@@ -574,9 +571,11 @@ void adjoint(Plan &pl, const double *w, double *gf, double *gh, double *gt, doub
         int32_t *inode = reserve<int32_t>(tr.item_node, size_t(nitems) + 1);
         int32_t *ia = reserve<int32_t>(tr.item_a, size_t(nitems) + 1);
         int32_t *ib = reserve<int32_t>(tr.item_b, size_t(nitems) + 1);
-        hipLaunchKernelGGL(k_item_fill, dim3(nblk(nn, 256)), dim3(256), 0, s, loff, ioff, nn, LAMBDA_RUN, inode, ia,
-                           ib);
-        STK_CHECK_LAUNCH();
+        if (nitems > 0) {
+            hipLaunchKernelGGL(k_item_fill, dim3(nblk(nitems, 256)), dim3(256), 0, s, loff, ioff, nn, LAMBDA_RUN,
+                               nitems, inode, ia, ib);
+            STK_CHECK_LAUNCH();
+        }
         double *lam = reserve<double>(A.lambda, size_t(nn) * 6 * ngc);
         STK_HIP(hipMemsetAsync(lam, 0, sizeof(double) * size_t(nn) * 6 * ngc, s));
         la.tpos = pl.tpos.as<double>();
@@ -640,7 +639,7 @@ void adjoint(Plan &pl, const double *w, double *gf, double *gh, double *gt, doub
         dispatch_src_grad(p, sa, t.nchunks, s);
 
         // near field, source side
-        transpose(t, pl.near_off, pl.near_node, pl.n_near_entries, ng, A.near_t, false, 64, s);
+        transpose(t, pl.near_off, pl.near_node, pl.n_near_entries, ng, A.near_t, 64, s);
         double *gs = reserve<double>(A.gs, size_t(n) * 9);
         STK_HIP(hipMemsetAsync(gs, 0, sizeof(double) * size_t(n) * 9, s));
         na.item_node = A.near_t.item_node.as<int32_t>();

@@ -37,66 +37,46 @@ struct LambdaArgs {
     const int32_t *item_i1;
     const int32_t *inc_tgt;    // incidence -> sorted target
     const double *center, *rho;
-    const int32_t *cpos;       // (batches, lam_tbl): stream position of each LDS column
-    const int32_t *ckind;      // (batches, lam_tbl): 0 = G column (weights w / R), 1 = E column (weights dh)
+    const int32_t *cpos;       // (columns): stream position of each LDS column
+    const int32_t *ckind;      // (columns): 0 = G column (weights w / R), 1 = E column (weights dh)
     double *lambda;            // (nn, 6 nG) adjoint of the cluster streams, accumulated
     int32_t nitems;
 };
 
 constexpr int LPITCH = 65;   // LDS row pitch (targets), padded against bank conflicts
 
-// The LDS columns of k_far_lambda (one value per target lane), in the order they are
-// formed: group 2n = the G columns of order n (n <= p + 1), group 2n + 1 = the E columns
-// of order n - 1 (n = 1 .. p + 2).  Groups are packed greedily into batches of at most
-// lam_tbl(p) columns, and each batch is reduced over the 64 targets in one pass.
-__host__ __device__ constexpr int lam_gsize(int p, int g) {
-    const int n = g >> 1;
-    if (g & 1) return n >= 1 ? n * (n + 1) / 2 : 0;
-    return n <= p + 1 ? (n + 1) * (n + 2) / 2 : 0;
-}
-__host__ __device__ constexpr int lam_ngroup(int p) { return 2 * (p + 3); }
-__host__ __device__ constexpr int lam_tbl(int p) {
-    int m = 64;
-    for (int g = 0; g < lam_ngroup(p); ++g) m = lam_gsize(p, g) > m ? lam_gsize(p, g) : m;
-    return m;
-}
-__host__ __device__ constexpr int lam_batch(int p, int g) {
-    int pend = 0, b = 0;
-    for (int x = 0; x <= g; ++x) {
-        const int sz = lam_gsize(p, x);
-        if (pend + sz > lam_tbl(p)) {
-            ++b;
-            pend = 0;
-        }
-        pend += sz;
-    }
-    return b;
-}
-// first column of group g within its batch
-__host__ __device__ constexpr int lam_off(int p, int g) {
-    int pend = 0;
-    for (int x = 0; x <= g; ++x) {
-        const int sz = lam_gsize(p, x);
-        if (pend + sz > lam_tbl(p)) pend = 0;
-        if (x == g) return pend;
-        pend += sz;
-    }
-    return 0;
-}
-__host__ __device__ constexpr int lam_nbatch(int p) { return lam_batch(p, lam_ngroup(p) - 1) + 1; }
-__host__ __device__ constexpr int lam_bcount(int p, int b) {
-    int c = 0;
-    for (int g = 0; g < lam_ngroup(p); ++g)
-        if (lam_batch(p, g) == b) c += lam_gsize(p, g);
+// The LDS columns of k_far_lambda (one value per target lane) in the order they are
+// formed: the G column of order 0, then per order n = 1 .. p + 2 the G columns of order n
+// (n <= p + 1; layer k3 = 0 .. n, k2 = 0 .. n - k3 within a layer) followed by the E
+// columns of order n - 1 (graded-lex order).  Every LAM_TBL consecutive columns form a
+// batch, reduced over the 64 targets as soon as its last column is written, with
+// 64 / LAM_TBL lanes per column each summing LAM_TBL targets.
+constexpr int LAM_TBL = 32;
+constexpr int LAM_WP = 64 + 64 / LAM_TBL;  // weight table pitch: one pad value per target run
+__host__ __device__ constexpr int lam_wid(int t) { return t + t / LAM_TBL; }
+__host__ __device__ constexpr int lam_ncol(int p) { return 2 * nidx(p + 1); }
+// first column of the G columns of order n (n >= 0; past the last one for n > p + 1)
+__host__ __device__ constexpr int lam_gbase(int p, int n) {
+    if (n == 0) return 0;
+    int c = 1;
+    for (int m = 1; m < n; ++m) c += (m <= p + 1 ? (m + 1) * (m + 2) / 2 : 0) + m * (m + 1) / 2;
     return c;
 }
-__host__ __device__ constexpr bool lam_last_in_batch(int p, int g) {
-    return g == lam_ngroup(p) - 1 || lam_batch(p, g + 1) != lam_batch(p, g);
+// first column of the E columns of order n - 1 (n >= 1)
+__host__ __device__ constexpr int lam_ebase(int p, int n) {
+    return lam_gbase(p, n) + (n <= p + 1 ? (n + 1) * (n + 2) / 2 : 0);
 }
-// LDS of one work item: the stream accumulator (evaluation precision) first, then the
-// column table and the two weight tables
+// column of G^k, ||k|| = n <= p + 1
+__host__ __device__ constexpr int lam_gcol(int p, int k1, int k2, int k3) {
+    const int n = k1 + k2 + k3;
+    int c = lam_gbase(p, n) + k2;
+    for (int j = 0; j < k3; ++j) c += n - j + 1;
+    return c;
+}
+// LDS of one work item: the stream accumulator (evaluation precision), one batch of
+// columns and the two weight tables
 template <int P, typename T> __host__ __device__ constexpr size_t lam_lds_bytes() {
-    return sizeof(T) * (6 * size_t(nidx(P + 1)) + size_t(lam_tbl(P)) * LPITCH + 6 * 64);
+    return sizeof(T) * (6 * size_t(nidx(P + 1)) + size_t(LAM_TBL) * LPITCH + 6 * size_t(LAM_WP));
 }
 
 // ---------------------------------------------------------------------------------

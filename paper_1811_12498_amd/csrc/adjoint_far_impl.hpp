@@ -65,37 +65,43 @@ template <int PB, typename T, class Visit> struct Coefs {
 };
 
 template <int P, typename T> struct LambdaVisit {
-    static constexpr int TBL = lam_tbl(P);
-    T *cols;       // [col][LPITCH]
-    const T *cw;   // [3][64] w_i / R per target (0 for lanes outside the mask)
-    const T *dw;   // [3][64] dh_l per target (0 outside the mask)
+    static constexpr int NCOL = lam_ncol(P);
+    T *cols;       // [LAM_TBL][LPITCH]: the current batch
+    const T *cw;   // [3][LAM_WP] w_i / R per target (0 for idle lanes), at lam_wid(target)
+    const T *dw;   // [3][LAM_WP] dh_l per target (0 for idle lanes)
     T *acc;        // [6 nG] LDS accumulator in stream order
     const int32_t *cpos, *ckind;
     T wl[3];       // this lane's w
     int lane;
 
-    template <int Q, int N> STK_HD void coef(T bq) {
-        if constexpr (N <= P + 1) {
-            constexpr int COL = lam_off(P, 2 * N) + Q - (N > 0 ? nidx(N - 1) : 0);
-            cols[COL * LPITCH + lane] = bq;
-        }
-    }
-
-    // reduce the nc columns of batch bt over the 64 targets, each with its weights
+    // reduce the nc columns of batch bt over the 64 targets: lane = (column, run of
+    // LAM_TBL targets), the runs' sums combined across lanes
     STK_HD void reduce(int nc, int bt) {
         __syncthreads();
-        for (int col = lane; col < nc; col += 64) {
-            const T *wt = ckind[bt * TBL + col] ? dw : cw;
-            T a0 = T(0), a1 = T(0), a2 = T(0);
-            const T *row = cols + col * LPITCH;
-#pragma unroll 4
-            for (int mm = 0; mm < 64; ++mm) {
+        const int col = lane % LAM_TBL, run = lane / LAM_TBL, t0 = run * LAM_TBL;
+        const bool on = col < nc;
+        T a0 = T(0), a1 = T(0), a2 = T(0);
+        int p0 = 0;
+        if (on) {
+            const int c = bt * LAM_TBL + col;
+            p0 = cpos[c];
+            const T *wt = (ckind[c] ? dw : cw) + lam_wid(t0);
+            const T *row = cols + col * LPITCH + t0;
+#pragma unroll 8
+            for (int mm = 0; mm < LAM_TBL; ++mm) {
                 const T v = row[mm];
                 a0 += wt[mm] * v;
-                a1 += wt[64 + mm] * v;
-                a2 += wt[128 + mm] * v;
+                a1 += wt[LAM_WP + mm] * v;
+                a2 += wt[2 * LAM_WP + mm] * v;
             }
-            const int p0 = cpos[bt * TBL + col];
+        }
+#pragma unroll
+        for (int o = LAM_TBL; o < 64; o <<= 1) {
+            a0 += __shfl_xor(a0, o);
+            a1 += __shfl_xor(a1, o);
+            a2 += __shfl_xor(a2, o);
+        }
+        if (on && run == 0) {
             acc[p0] += a0;
             acc[p0 + 1] += a1;
             acc[p0 + 2] += a2;
@@ -103,20 +109,27 @@ template <int P, typename T> struct LambdaVisit {
         __syncthreads();
     }
 
-    // after group G is complete: reduce its batch if G closes it
-    template <int G> STK_HD void close_group() {
-        constexpr int BT = lam_batch(P, G);
-        constexpr int NC = lam_bcount(P, BT);
-        if constexpr (lam_last_in_batch(P, G) && NC > 0) reduce(NC, BT);
+    // write column COL; reduce its batch when COL completes it
+    template <int COL> STK_HD void put(T v) {
+        cols[(COL % LAM_TBL) * LPITCH + lane] = v;
+        if constexpr (COL % LAM_TBL == LAM_TBL - 1)
+            reduce(LAM_TBL, COL / LAM_TBL);
+        else if constexpr (COL == NCOL - 1)
+            reduce(NCOL % LAM_TBL, COL / LAM_TBL);
+    }
+
+    template <int Q, int N> STK_HD void coef(T bq) {
+        if constexpr (N <= P + 1) {
+            constexpr int K1 = kof1c(Q), K2 = kof2c(Q), K3 = N - K1 - K2;
+            put<lam_gcol(P, K1, K2, K3)>(bq);
+        }
     }
 
     template <int N, int J> STK_HD void layer_done(const T (&)[nidx(P + 2)]) {}
 
+    // after order N: the E columns zh^k of order N - 1
     template <int N> STK_HD void order_done(const T (&b)[nidx(P + 2)]) {
-        close_group<2 * N>();  // the G columns of order N (written by coef)
-        // E columns: zh^k for k of order N - 1
         if constexpr (N >= 1) ecol<N, N - 1, 0>(b);
-        close_group<2 * N + 1>();
     }
 
     // zh^k = sum_i w_i (k_i+1) bt^{k+e_i} for every k of order M, in graded-lex order
@@ -126,8 +139,7 @@ template <int P, typename T> struct LambdaVisit {
             constexpr int K1 = kof1c(Q), K2 = kof2c(Q), K3 = M - K1 - K2;
             const T z = wl[0] * (T(K1 + 1) * b[gidx(K1 + 1, K2, K3)]) + wl[1] * (T(K2 + 1) * b[gidx(K1, K2 + 1, K3)]) +
                         wl[2] * (T(K3 + 1) * b[gidx(K1, K2, K3 + 1)]);
-            constexpr int COL = lam_off(P, 2 * N + 1) + A;
-            cols[COL * LPITCH + lane] = z;
+            put<lam_ebase(P, N) + A>(z);
             ecol<N, M, A + 1>(b);
         }
     }
@@ -138,9 +150,8 @@ template <int P, typename T> __global__ __launch_bounds__(64) void k_far_lambda(
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T *acc = reinterpret_cast<T *>(lds_raw);
     T *cols = acc + 6 * NG;
-    constexpr int TBL = lam_tbl(P);
-    T *cw = cols + TBL * LPITCH;
-    T *dw = cw + 192;
+    T *cw = cols + LAM_TBL * LPITCH;
+    T *dw = cw + 3 * LAM_WP;
     const int lane = threadIdx.x;
     const int32_t it = blockIdx.x;
     if (it >= a.nitems) return;
@@ -167,8 +178,8 @@ template <int P, typename T> __global__ __launch_bounds__(64) void k_far_lambda(
         }
         __syncthreads();
         for (int i = 0; i < 3; ++i) {
-            cw[64 * i + lane] = wl[i] * ri;
-            dw[64 * i + lane] = in ? dh[i] : T(0);
+            cw[LAM_WP * i + lam_wid(lane)] = wl[i] * ri;
+            dw[LAM_WP * i + lam_wid(lane)] = in ? dh[i] : T(0);
         }
         LambdaVisit<P, T> v{cols, cw, dw, acc, a.cpos, a.ckind, {wl[0], wl[1], wl[2]}, lane};
         T b[nidx(P + 2)];

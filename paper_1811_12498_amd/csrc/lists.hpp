@@ -43,16 +43,25 @@ __global__ void k_item_count(const int32_t *__restrict__ off, int32_t nn, int32_
     cnt[c] = (off[c + 1] - off[c] + per - 1) / per;
 }
 
+// one thread per item: its node is the last c with ioff[c] <= item (nodes without items
+// have ioff[c] == ioff[c + 1]); a node's items cover its range in runs of `per`
 __global__ void k_item_fill(const int32_t *__restrict__ off, const int32_t *__restrict__ ioff, int32_t nn, int32_t per,
-                            int32_t *__restrict__ inode, int32_t *__restrict__ i0, int32_t *__restrict__ i1) {
-    const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nn) return;
-    int32_t it = ioff[c];
-    for (int32_t b = off[c]; b < off[c + 1]; b += per, ++it) {
-        inode[it] = c;
-        i0[it] = b;
-        i1[it] = min(b + per, off[c + 1]);
+                            int32_t nitems, int32_t *__restrict__ inode, int32_t *__restrict__ i0,
+                            int32_t *__restrict__ i1) {
+    const int32_t it = blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= nitems) return;
+    int32_t lo = 0, hi = nn;  // ioff[lo] <= it < ioff[hi]
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (ioff[mid] <= it)
+            lo = mid;
+        else
+            hi = mid;
     }
+    const int32_t b = off[lo] + (it - ioff[lo]) * per;
+    inode[it] = lo;
+    i0[it] = b;
+    i1[it] = min(b + per, off[lo + 1]);
 }
 
 }  // namespace

@@ -539,8 +539,11 @@ void cluster_major(Tree &t, ClusterMajor &cm, const int32_t *off, const int32_t 
     int32_t *inode = reserve<int32_t>(cm.item_node, size_t(cm.n_items) + 1);
     int32_t *i0 = reserve<int32_t>(cm.item_i0, size_t(cm.n_items) + 1);
     int32_t *i1 = reserve<int32_t>(cm.item_i1, size_t(cm.n_items) + 1);
-    hipLaunchKernelGGL(k_item_fill, dim3(nblk(nn, 256)), dim3(256), 0, s, loff, ioff, nn, 64, inode, i0, i1);
-    STK_CHECK_LAUNCH();
+    if (cm.n_items > 0) {
+        hipLaunchKernelGGL(k_item_fill, dim3(nblk(cm.n_items, 256)), dim3(256), 0, s, loff, ioff, nn, 64, cm.n_items,
+                           inode, i0, i1);
+        STK_CHECK_LAUNCH();
+    }
     if (ng > 0) {
         hipLaunchKernelGGL(k_cm_fill, dim3(ng), dim3(64), 0, s, off, mask, max_pc, pos, incoff, toff, m, inc_tgt,
                            inc_slot);
