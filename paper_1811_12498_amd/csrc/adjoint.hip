@@ -301,7 +301,7 @@ PhiT &phit_for(int dev, int p) {
     // LDS column -> stream position and weight kind of k_far_lambda (columns in the order
     // the kernel forms them, padded to whole batches)
     const int ncol = lam_ncol(p);
-    std::vector<int32_t> cpos(size_t((ncol + LAM_TBL - 1) / LAM_TBL) * LAM_TBL, 0), ckind(cpos.size(), 0);
+    std::vector<int32_t> cpos(size_t((ncol + LAM_TBL_MAX - 1) / LAM_TBL_MAX) * LAM_TBL_MAX, 0), ckind(cpos.size(), 0);
     for (int n = 0; n <= p + 1; ++n)
         for (int k3 = 0; k3 <= n; ++k3)
             for (int k2 = 0; k2 <= n - k3; ++k2) {

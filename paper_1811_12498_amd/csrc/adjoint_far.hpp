@@ -48,12 +48,15 @@ constexpr int LPITCH = 65;   // LDS row pitch (targets), padded against bank con
 // The LDS columns of k_far_lambda (one value per target lane) in the order they are
 // formed: the G column of order 0, then per order n = 1 .. p + 2 the G columns of order n
 // (n <= p + 1; layer k3 = 0 .. n, k2 = 0 .. n - k3 within a layer) followed by the E
-// columns of order n - 1 (graded-lex order).  Every LAM_TBL consecutive columns form a
-// batch, reduced over the 64 targets as soon as its last column is written, with
-// 64 / LAM_TBL lanes per column each summing LAM_TBL targets.
-constexpr int LAM_TBL = 32;
-constexpr int LAM_WP = 64 + 64 / LAM_TBL;  // weight table pitch: one pad value per target run
-__host__ __device__ constexpr int lam_wid(int t) { return t + t / LAM_TBL; }
+// columns of order n - 1 (graded-lex order).  Every lam_tbl<T> consecutive columns form
+// a batch, reduced over the 64 targets as soon as its last column is written, with
+// 64 / lam_tbl<T> lanes per column each summing lam_tbl<T> targets (narrower batches in
+// FP64 keep the LDS of a block small enough for more blocks per CU).
+template <typename T> __host__ __device__ constexpr int lam_tbl() { return sizeof(T) == 8 ? 16 : 32; }
+constexpr int LAM_TBL_MAX = 32;  // host column tables are padded to whole batches of this
+// weight table pitch and position: one pad value after each run of lam_tbl targets
+template <typename T> __host__ __device__ constexpr int lam_wp() { return 64 + 64 / lam_tbl<T>(); }
+template <typename T> __host__ __device__ constexpr int lam_wid(int t) { return t + t / lam_tbl<T>(); }
 __host__ __device__ constexpr int lam_ncol(int p) { return 2 * nidx(p + 1); }
 // first column of the G columns of order n (n >= 0; past the last one for n > p + 1)
 __host__ __device__ constexpr int lam_gbase(int p, int n) {
@@ -76,7 +79,7 @@ __host__ __device__ constexpr int lam_gcol(int p, int k1, int k2, int k3) {
 // LDS of one work item: the stream accumulator (evaluation precision), one batch of
 // columns and the two weight tables
 template <int P, typename T> __host__ __device__ constexpr size_t lam_lds_bytes() {
-    return sizeof(T) * (6 * size_t(nidx(P + 1)) + size_t(LAM_TBL) * LPITCH + 6 * size_t(LAM_WP));
+    return sizeof(T) * (6 * size_t(nidx(P + 1)) + size_t(lam_tbl<T>()) * LPITCH + 6 * size_t(lam_wp<T>()));
 }
 
 // ---------------------------------------------------------------------------------

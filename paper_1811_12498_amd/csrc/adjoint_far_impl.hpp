@@ -66,37 +66,38 @@ template <int PB, typename T, class Visit> struct Coefs {
 
 template <int P, typename T> struct LambdaVisit {
     static constexpr int NCOL = lam_ncol(P);
-    T *cols;       // [LAM_TBL][LPITCH]: the current batch
-    const T *cw;   // [3][LAM_WP] w_i / R per target (0 for idle lanes), at lam_wid(target)
-    const T *dw;   // [3][LAM_WP] dh_l per target (0 for idle lanes)
+    static constexpr int TBL = lam_tbl<T>(), WP = lam_wp<T>();
+    T *cols;       // [TBL][LPITCH]: the current batch
+    const T *cw;   // [3][WP] w_i / R per target (0 for idle lanes), at lam_wid(target)
+    const T *dw;   // [3][WP] dh_l per target (0 for idle lanes)
     T *acc;        // [6 nG] LDS accumulator in stream order
     const int32_t *cpos, *ckind;
     T wl[3];       // this lane's w
     int lane;
 
     // reduce the nc columns of batch bt over the 64 targets: lane = (column, run of
-    // LAM_TBL targets), the runs' sums combined across lanes
+    // TBL targets), the runs' sums combined across lanes
     STK_HD void reduce(int nc, int bt) {
         __syncthreads();
-        const int col = lane % LAM_TBL, run = lane / LAM_TBL, t0 = run * LAM_TBL;
+        const int col = lane % TBL, run = lane / TBL, t0 = run * TBL;
         const bool on = col < nc;
         T a0 = T(0), a1 = T(0), a2 = T(0);
         int p0 = 0;
         if (on) {
-            const int c = bt * LAM_TBL + col;
+            const int c = bt * TBL + col;
             p0 = cpos[c];
-            const T *wt = (ckind[c] ? dw : cw) + lam_wid(t0);
+            const T *wt = (ckind[c] ? dw : cw) + lam_wid<T>(t0);
             const T *row = cols + col * LPITCH + t0;
 #pragma unroll 8
-            for (int mm = 0; mm < LAM_TBL; ++mm) {
+            for (int mm = 0; mm < TBL; ++mm) {
                 const T v = row[mm];
                 a0 += wt[mm] * v;
-                a1 += wt[LAM_WP + mm] * v;
-                a2 += wt[2 * LAM_WP + mm] * v;
+                a1 += wt[WP + mm] * v;
+                a2 += wt[2 * WP + mm] * v;
             }
         }
 #pragma unroll
-        for (int o = LAM_TBL; o < 64; o <<= 1) {
+        for (int o = TBL; o < 64; o <<= 1) {
             a0 += __shfl_xor(a0, o);
             a1 += __shfl_xor(a1, o);
             a2 += __shfl_xor(a2, o);
@@ -111,11 +112,11 @@ template <int P, typename T> struct LambdaVisit {
 
     // write column COL; reduce its batch when COL completes it
     template <int COL> STK_HD void put(T v) {
-        cols[(COL % LAM_TBL) * LPITCH + lane] = v;
-        if constexpr (COL % LAM_TBL == LAM_TBL - 1)
-            reduce(LAM_TBL, COL / LAM_TBL);
+        cols[(COL % TBL) * LPITCH + lane] = v;
+        if constexpr (COL % TBL == TBL - 1)
+            reduce(TBL, COL / TBL);
         else if constexpr (COL == NCOL - 1)
-            reduce(NCOL % LAM_TBL, COL / LAM_TBL);
+            reduce(NCOL % TBL, COL / TBL);
     }
 
     template <int Q, int N> STK_HD void coef(T bq) {
@@ -150,8 +151,8 @@ template <int P, typename T> __global__ __launch_bounds__(64) void k_far_lambda(
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T *acc = reinterpret_cast<T *>(lds_raw);
     T *cols = acc + 6 * NG;
-    T *cw = cols + LAM_TBL * LPITCH;
-    T *dw = cw + 3 * LAM_WP;
+    T *cw = cols + lam_tbl<T>() * LPITCH;
+    T *dw = cw + 3 * lam_wp<T>();
     const int lane = threadIdx.x;
     const int32_t it = blockIdx.x;
     if (it >= a.nitems) return;
@@ -178,8 +179,8 @@ template <int P, typename T> __global__ __launch_bounds__(64) void k_far_lambda(
         }
         __syncthreads();
         for (int i = 0; i < 3; ++i) {
-            cw[LAM_WP * i + lam_wid(lane)] = wl[i] * ri;
-            dw[LAM_WP * i + lam_wid(lane)] = in ? dh[i] : T(0);
+            cw[lam_wp<T>() * i + lam_wid<T>(lane)] = wl[i] * ri;
+            dw[lam_wp<T>() * i + lam_wid<T>(lane)] = in ? dh[i] : T(0);
         }
         LambdaVisit<P, T> v{cols, cw, dw, acc, a.cpos, a.ckind, {wl[0], wl[1], wl[2]}, lane};
         T b[nidx(P + 2)];
