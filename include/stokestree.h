@@ -178,12 +178,20 @@ stk_status stk_plan_export_lists(const stk_plan *plan, int32_t kind, int32_t *of
  *   near_mfma  1: near field on the matrix cores (FP32 mixed precision only), 16
  *              right-hand sides per pass; near_kb is then unused.
  *   far_mfma   1: far field on the matrix cores (FP32 mixed precision only), 16
- *              right-hand sides per pass; far_kb is then unused. */
+ *              right-hand sides per pass; far_kb is then unused.
+ *   far_cm     0 (automatic): as 1 when the far group lists' lane masks are less than
+ *              75% full on average, else as 2;  1: every far entry cluster major (64 of a
+ *              cluster's targets per pass, whatever groups they belong to; each target's
+ *              terms added in the order of its own list; not with far_mfma; EINVAL from
+ *              the evaluation if the plan has 2^31 - 64 or more far pairs);  2: only
+ *              entries with at most 32 of their group's 64 targets, and only with one
+ *              right-hand side.  With far_mfma, 0 means 2. */
 typedef struct stk_tiles {
     int32_t far_kb;
     int32_t near_kb;
     int32_t near_mfma;
     int32_t far_mfma;
+    int32_t far_cm;
 } stk_tiles;
 /* Record tiles for (current device's architecture, p, k_rhs, prec); NULL removes the
  * entry.  EINVAL if the tiles do not fit k_rhs and prec. */
@@ -198,7 +206,7 @@ stk_status stk_tiles_get(int32_t p, int32_t k_rhs, stk_precision prec, stk_tiles
 stk_status stk_autotune(int32_t p, int32_t k_rhs, stk_precision prec, int64_t n, double theta, int32_t n0,
                         stk_tiles *best, double *best_ms, void *stream);
 /* Write the table to / merge it from a text file (one "arch p K precision far_kb
- * near_kb near_mfma far_mfma" line per entry).  Load is all-or-nothing: EINVAL on a malformed
+ * near_kb near_mfma far_mfma far_cm" line per entry).  Load is all-or-nothing: EINVAL on a malformed
  * or invalid line, and nothing is merged. */
 stk_status stk_tiles_save(const char *path);
 stk_status stk_tiles_load(const char *path, int32_t *n_entries);

@@ -551,8 +551,12 @@ void adjoint(Plan &pl, const double *w, double *gf, double *gh, double *gt, doub
     LambdaArgs la{};
     TgradArgs ta{};
     PhiT &ph = phit_for(t.device, p);
-    ClusterMajor &fc = A.far_cm;
-    if (src || gt)
+    // (the forward's own view when it took every far entry cluster major)
+    const bool reuse = pl.far_sparse_max >= 64;
+    if ((src || gt) && pl.n_far_inc >= CM_MAX_INC)
+        throw Error(STK_EINVAL, "adjoint: too many far interactions for the cluster-major lists");
+    ClusterMajor &fc = reuse ? pl.fcm : A.far_cm;
+    if ((src || gt) && !reuse)
         cluster_major(t, fc, pl.far_off.as<int32_t>(), pl.far_node.as<int32_t>(), pl.far_mask.as<uint64_t>(),
                       pl.n_far_entries, ng, m, 64, pl.cnt_far.as<int32_t>(), s);
     if (src) {

@@ -34,6 +34,7 @@ struct TravArgs {
     // count pass outputs
     int32_t *gfar, *gnear;              // per group entry counts
     int32_t *cnt_far, *cnt_near, *cnt_pairs;  // per sorted target
+    unsigned long long *far_inc;        // total far (target, cluster) pairs, accumulated
     // fill pass
     const int32_t *far_off, *near_off;
     int32_t *far_node, *near_node;
@@ -114,9 +115,13 @@ template <bool FILL> __global__ __launch_bounds__(64) void k_traverse(TravArgs a
         __syncthreads();
     }
     if (!FILL) {
+        int32_t gf = nf;  // the group's far pairs
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) gf += __shfl_xor(gf, o);
         if (lane == 0) {
             a.gfar[g] = fo;
             a.gnear[g] = no;
+            atomicAdd(a.far_inc, (unsigned long long)gf);
         }
         if (valid) {
             a.cnt_far[t] = nf;
@@ -258,18 +263,21 @@ template <typename T> void dispatch_far_sparse(int p, const FarSparseArgs &a, hi
     }
 }
 
-// per target: its sparse far velocities in list order, compensated, added to unear (m,3)
+// per (target, right-hand side): its cluster-major far velocities in list order,
+// compensated, added to unear (m,K,3)
 template <typename T>
-__global__ void k_cm_add(const T *__restrict__ part, const int32_t *__restrict__ toff, int64_t m,
+__global__ void k_cm_add(const T *__restrict__ part, const int32_t *__restrict__ toff, int64_t m, int32_t K,
                          double *__restrict__ unear) {
-    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= m) return;
+    const int64_t tr = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (tr >= m * K) return;
+    const int64_t t = tr / K;
     const int32_t k0 = toff[t], k1 = toff[t + 1];
     if (k0 == k1) return;
+    const int64_t r = tr - t * K;
     Comp<T> acc[3];
     for (int32_t k = k0; k < k1; ++k)
-        for (int q = 0; q < 3; ++q) acc[q].add(part[3 * int64_t(k) + q]);
-    for (int q = 0; q < 3; ++q) unear[3 * t + q] += acc[q].value();
+        for (int q = 0; q < 3; ++q) acc[q].add(part[3 * (int64_t(k) * K + r) + q]);
+    for (int q = 0; q < 3; ++q) unear[3 * tr + q] += acc[q].value();
 }
 
 void dispatch_far_mfma(int p, const FarArgs &a, DBuf &bm, int32_t nn, hipStream_t s) {
@@ -291,31 +299,31 @@ void dispatch_far_mfma(int p, const FarArgs &a, DBuf &bm, int32_t nn, hipStream_
 
 }  // namespace
 
-int far_sparse(Tree &t, Plan &pl, double *unear, hipStream_t s) {
+void far_sparse(Tree &t, Plan &pl, double *unear, int max_pc, hipStream_t s) {
     const int64_t m = pl.m;
+    const int K = t.k_rhs;
     ClusterMajor &cm = pl.fcm;
     cluster_major(t, cm, pl.far_off.as<int32_t>(), pl.far_node.as<int32_t>(), pl.far_mask.as<uint64_t>(),
-                  pl.n_far_entries, pl.ngroups, m, FAR_SPARSE_MAX, nullptr, s);
+                  pl.n_far_entries, pl.ngroups, m, max_pc, max_pc >= 64 ? pl.cnt_far.as<int32_t>() : nullptr, s);
     const size_t tsz = t.prec == STK_FP64 ? sizeof(double) : sizeof(float);
-    void *part = reserve<unsigned char>(cm.part, tsz * 3 * size_t(cm.n_inc) + tsz);
+    void *part = reserve<unsigned char>(cm.part, tsz * 3 * size_t(K) * size_t(cm.n_inc) + tsz);
     FarSparseArgs sa{pl.tpos.as<double>(), cm.item_node.as<int32_t>(), cm.item_i0.as<int32_t>(),
                      cm.item_i1.as<int32_t>(), cm.inc_tgt.as<int32_t>(), cm.inc_slot.as<int32_t>(),
-                     t.ncenter.as<double>(), t.nrho.as<double>(), t.wblk.p, part, cm.n_items};
+                     t.ncenter.as<double>(), t.nrho.as<double>(), t.wblk.p, part, cm.n_items, K};
     if (t.prec == STK_FP64)
         dispatch_far_sparse<double>(t.p, sa, s);
     else
         dispatch_far_sparse<float>(t.p, sa, s);
     if (m > 0 && cm.n_inc > 0) {
         if (t.prec == STK_FP64)
-            hipLaunchKernelGGL(k_cm_add<double>, dim3(nblk(m, 256)), dim3(256), 0, s, static_cast<const double *>(part),
-                               cm.toff.as<int32_t>(), m, unear);
+            hipLaunchKernelGGL(k_cm_add<double>, dim3(nblk(m * K, 256)), dim3(256), 0, s,
+                               static_cast<const double *>(part), cm.toff.as<int32_t>(), m, K, unear);
         else
-            hipLaunchKernelGGL(k_cm_add<float>, dim3(nblk(m, 256)), dim3(256), 0, s, static_cast<const float *>(part),
-                               cm.toff.as<int32_t>(), m, unear);
+            hipLaunchKernelGGL(k_cm_add<float>, dim3(nblk(m * K, 256)), dim3(256), 0, s,
+                               static_cast<const float *>(part), cm.toff.as<int32_t>(), m, K, unear);
         STK_CHECK_LAUNCH();
     }
     prof_mark(STK_PHASE_FAR_SPARSE, s);
-    return FAR_SPARSE_MAX;
 }
 
 Plan::~Plan() {
@@ -364,6 +372,8 @@ void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, dou
     ta.cnt_far = reserve<int32_t>(pl.cnt_far, size_t(m));
     ta.cnt_near = reserve<int32_t>(pl.cnt_near, size_t(m));
     ta.cnt_pairs = reserve<int32_t>(pl.cnt_pairs, size_t(m));
+    ta.far_inc = reserve<unsigned long long>(pl.far_inc, 1);
+    STK_HIP(hipMemsetAsync(ta.far_inc, 0, sizeof(unsigned long long), s));
     hipLaunchKernelGGL(k_traverse<false>, dim3(ng), dim3(64), 0, s, ta);
     STK_CHECK_LAUNCH();
     int32_t *foff = reserve<int32_t>(pl.far_off, size_t(ng) + 1);
@@ -371,11 +381,14 @@ void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, dou
     scan_exclusive_i32(ta.gfar, foff, ng, t.s_scan, s);
     scan_exclusive_i32(ta.gnear, noff, ng, t.s_scan, s);
     int32_t tot[2];
+    unsigned long long far_inc = 0;
     STK_HIP(hipMemcpyAsync(&tot[0], foff + ng, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     STK_HIP(hipMemcpyAsync(&tot[1], noff + ng, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    STK_HIP(hipMemcpyAsync(&far_inc, ta.far_inc, sizeof(far_inc), hipMemcpyDeviceToHost, s));
     STK_HIP(hipStreamSynchronize(s));
     pl.n_far_entries = tot[0];
     pl.n_near_entries = tot[1];
+    pl.n_far_inc = int64_t(far_inc);
     ta.far_off = foff;
     ta.near_off = noff;
     ta.far_node = reserve<int32_t>(pl.far_node, size_t(tot[0]) + 1);
@@ -395,9 +408,18 @@ void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, dou
     // the near part and un-permutes)
     double *unear = reserve<double>(t.s_tmp, size_t(m) * K * 3);
     near_field(t, pl, unear, s);
-    // one right-hand side: far entries that apply to few targets of their group run cluster
-    // major (their velocities are added to unear); the group-major kernel skips them
-    const int sparse_max = K == 1 ? far_sparse(t, pl, unear, s) : 0;
+    // far entries that apply to few targets of their group (one right-hand side), or every
+    // far entry (tile far_cm, or automatically when the group lists' lanes are mostly
+    // idle), run cluster major (their velocities are added to unear); the group-major
+    // kernel skips them
+    const double util = pl.n_far_entries > 0 ? double(pl.n_far_inc) / (64.0 * double(pl.n_far_entries)) : 1.0;
+    const bool cm_fits = pl.n_far_inc < CM_MAX_INC;
+    const bool all_cm = !pl.tiles.far_mfma && cm_fits &&
+                        (pl.tiles.far_cm == FAR_CM_ON || (pl.tiles.far_cm == FAR_CM_AUTO && util < FAR_CM_UTIL));
+    if (pl.tiles.far_cm == FAR_CM_ON && !cm_fits)
+        throw Error(STK_EINVAL, "far_cm: too many far interactions for the cluster-major lists");
+    const int sparse_max = all_cm ? 64 : (K == 1 ? FAR_SPARSE_MAX : 0);
+    if (sparse_max > 0) far_sparse(t, pl, unear, sparse_max, s);
     pl.far_sparse_max = sparse_max;
     FarArgs fa{tpos, m, foff, ta.far_node, ta.far_mask, t.ncenter.as<double>(), t.nrho.as<double>(), t.wblk.p,
                unear, tperm, u_out, ng, K, sparse_max};

@@ -75,9 +75,10 @@ template <int P, typename T, int KB> void launch_far(const FarArgs &a, hipStream
     STK_CHECK_LAUNCH();
 }
 
-// one wave per item: a cluster and up to 64 targets whose groups' entries for it were
-// sparse; each lane evaluates its (target, cluster) interaction and writes the velocity to
-// the interaction's slot in the target's list of sparse entries
+// one wave per item: a cluster and up to 64 targets whose groups' entries for it run
+// cluster major; each lane evaluates its (target, cluster) interaction for every
+// right-hand side and writes the velocities to the interaction's slot in the target's list
+// of cluster-major entries
 template <int P, typename T> __global__ __launch_bounds__(64) void k_far_sparse(FarSparseArgs a) {
     constexpr int WS = 6 * nidx(P + 1);
     const int32_t it = xcd_group(a.nitems);
@@ -93,14 +94,27 @@ template <int P, typename T> __global__ __launch_bounds__(64) void k_far_sparse(
         const double rinv = 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
         const T dh[3] = {T(d0 * rinv), T(d1 * rinv), T(d2 * rinv)};
         const T tt = T(a.rho[c] * rinv);
-        T accG[3], accF[3];
-        FarEval<P, T>::run(dh, tt, static_cast<const T *>(a.wblk) + size_t(c) * WS, accG, accF);
-        T u[3];
-        far_velocity(accG, accF, T(rinv), u);
-        T *o = static_cast<T *>(a.part) + 3 * int64_t(slot);
-        o[0] = u[0];
-        o[1] = u[1];
-        o[2] = u[2];
+        // the streams are read through the constant address space: the partial stores below
+        // cannot alias them, so their uniform loads stay scalar across the loop
+        using Eval = FarEval<P, T, 1, true>;
+        const T *wb = static_cast<const T *>(a.wblk) + size_t(c) * a.K * WS;
+        T *o = static_cast<T *>(a.part) + 3 * int64_t(slot) * a.K;
+        for (int r = 0; r < a.K; ++r) {
+            // the recurrence is redone per right-hand side: opaque copies of its inputs keep
+            // the compiler from hoisting all coefficients out of the loop (they would not
+            // fit the register file)
+            T dr[3] = {dh[0], dh[1], dh[2]}, tr = tt;
+#if defined(__HIP_DEVICE_COMPILE__)
+            asm("" : "+v"(dr[0]), "+v"(dr[1]), "+v"(dr[2]), "+v"(tr));
+#endif
+            T accG[3], accF[3];
+            Eval::run(dr, tr, (typename Eval::Ptr)(wb + size_t(r) * WS), accG, accF);
+            T u[3];
+            far_velocity(accG, accF, T(rinv), u);
+            o[3 * r] = u[0];
+            o[3 * r + 1] = u[1];
+            o[3 * r + 2] = u[2];
+        }
     }
 }
 

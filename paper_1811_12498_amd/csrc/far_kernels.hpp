@@ -36,8 +36,9 @@ struct FarSparseArgs {
     const int32_t *inc_tgt, *inc_slot;
     const double *center, *rho;
     const void *wblk;
-    void *part;              // (incidences, 3) T
+    void *part;              // (incidences, K, 3) T
     int32_t nitems;
+    int32_t K;               // right-hand sides
 };
 
 // block index -> group: XCD x = blockIdx % 8 gets groups [x * per, (x + 1) * per)

@@ -147,7 +147,16 @@ struct Tiles {
     int32_t near_kb = 1;     // right-hand sides per pass of the VALU near-field kernel
     bool near_mfma = false;  // near field on the matrix cores (FP32)
     bool far_mfma = false;   // far field on the matrix cores (FP32)
+    int32_t far_cm = 0;      // FAR_CM_AUTO / FAR_CM_ON / FAR_CM_OFF
 };
+
+// far_cm modes: every far entry cluster major when the group lists' lanes are less than
+// FAR_CM_UTIL full (auto), always (on), or never (off: only the split of sparse entries
+// with one right-hand side)
+constexpr int32_t FAR_CM_AUTO = 0, FAR_CM_ON = 1, FAR_CM_OFF = 2;
+constexpr double FAR_CM_UTIL = 0.75;
+// cluster-major lists index incidences with int32
+constexpr int64_t CM_MAX_INC = (int64_t(1) << 31) - 64;
 
 struct Plan {
     Tree *tree = nullptr;
@@ -161,7 +170,8 @@ struct Plan {
     DBuf far_node, near_node;      // int32 entries
     DBuf far_mask, near_mask;      // uint64 entries (lane masks of the 64-target group)
     DBuf cnt_far, cnt_near, cnt_pairs;  // int32 per sorted target
-    int64_t n_far_entries = 0, n_near_entries = 0;
+    DBuf far_inc;                       // uint64: far (target, cluster) pairs, counted by the traversal
+    int64_t n_far_entries = 0, n_near_entries = 0, n_far_inc = 0;
     // cluster-major views of the group lists: the near field (every near entry) and, for
     // one right-hand side, the far entries that apply to few targets of their group
     ClusterMajor ncm, fcm;
@@ -215,11 +225,12 @@ void cluster_major(Tree &t, ClusterMajor &cm, const int32_t *off, const int32_t 
 // near field of a plan whose group-major near lists are filled: unear (m,K,3), sorted
 // target order, K = the tree's right-hand sides
 void near_field(Tree &t, Plan &plan, double *unear, hipStream_t s);
-// far entries with at most FAR_SPARSE_MAX targets (one right-hand side), cluster major:
-// adds their velocities to unear (m,3) and records the threshold the group-major far kernel
-// then skips; returns the threshold (0: nothing split off)
+// far entries with at most max_pc targets, cluster major: adds their velocities (every
+// right-hand side) to unear (m,K,3); the group-major far kernel then skips entries of at
+// most max_pc targets.  FAR_SPARSE_MAX is the split used by default with one right-hand
+// side; max_pc = 64 takes every far entry.
 constexpr int FAR_SPARSE_MAX = 32;
-int far_sparse(Tree &t, Plan &plan, double *unear, hipStream_t s);
+void far_sparse(Tree &t, Plan &plan, double *unear, int max_pc, hipStream_t s);
 void direct_sum(const double *tgt, int64_t m, const double *src, int64_t n, const double *f, const double *h,
                 const double *nu, int32_t k, double *u_out, hipStream_t s);
 

@@ -84,6 +84,8 @@ bool tiles_valid(const Tiles &t, int K, stk_precision prec) {
     auto kb_ok = [&](int kb) { return (kb == 1 || kb == 2 || kb == 4) && K % kb == 0; };
     if (!kb_ok(t.far_kb) || !kb_ok(t.near_kb)) return false;
     if (prec == STK_FP64 && (t.far_kb != 1 || t.near_kb != 1 || t.near_mfma || t.far_mfma)) return false;
+    if (t.far_cm != FAR_CM_AUTO && t.far_cm != FAR_CM_ON && t.far_cm != FAR_CM_OFF) return false;
+    if (t.far_cm == FAR_CM_ON && t.far_mfma) return false;  // the matrix-core far kernel has no cluster-major split
     return true;
 }
 
@@ -116,11 +118,11 @@ void tiles_save(const char *path) {
     std::lock_guard<std::mutex> lk(g_mu);
     FILE *fp = std::fopen(path, "w");
     if (!fp) throw Error(STK_EINVAL, std::string("cannot write ") + path);
-    std::fprintf(fp, "# arch p K precision far_kb near_kb near_mfma far_mfma\n");
+    std::fprintf(fp, "# arch p K precision far_kb near_kb near_mfma far_mfma far_cm\n");
     for (const auto &e : g_table)
-        std::fprintf(fp, "%s %d %d %d %d %d %d %d\n", std::get<0>(e.first).c_str(), std::get<1>(e.first),
+        std::fprintf(fp, "%s %d %d %d %d %d %d %d %d\n", std::get<0>(e.first).c_str(), std::get<1>(e.first),
                      std::get<2>(e.first), std::get<3>(e.first), e.second.far_kb, e.second.near_kb,
-                     e.second.near_mfma ? 1 : 0, e.second.far_mfma ? 1 : 0);
+                     e.second.near_mfma ? 1 : 0, e.second.far_mfma ? 1 : 0, e.second.far_cm);
     std::fclose(fp);
 }
 
@@ -134,8 +136,8 @@ int tiles_load(const char *path) {
         ++lineno;
         if (line[0] == '#' || line[0] == '\n') continue;
         char arch[128];
-        int p, K, prec, fkb, nkb, nm, fm;
-        if (std::sscanf(line, "%127s %d %d %d %d %d %d %d", arch, &p, &K, &prec, &fkb, &nkb, &nm, &fm) != 8 ||
+        int p, K, prec, fkb, nkb, nm, fm, fc;
+        if (std::sscanf(line, "%127s %d %d %d %d %d %d %d %d", arch, &p, &K, &prec, &fkb, &nkb, &nm, &fm, &fc) != 9 ||
             (prec != STK_FP64 && prec != STK_MIXED)) {
             std::fclose(fp);
             throw Error(STK_EINVAL, std::string(path) + ": malformed line " + std::to_string(lineno));
@@ -145,6 +147,7 @@ int tiles_load(const char *path) {
         t.near_kb = nkb;
         t.near_mfma = nm != 0;
         t.far_mfma = fm != 0;
+        t.far_cm = fc;
         if (!tiles_valid(t, K, stk_precision(prec))) {
             std::fclose(fp);
             throw Error(STK_EINVAL, std::string(path) + ": invalid tiles on line " + std::to_string(lineno));
@@ -186,6 +189,15 @@ Tiles autotune(int p, int K, stk_precision prec, int64_t n, double theta, int32_
         near_c.push_back(t);
         t = default_tiles(K, prec);
         t.far_mfma = true;
+        far_c.push_back(t);
+    }
+    for (int32_t mode : {FAR_CM_ON, FAR_CM_OFF}) {
+        // every far entry cluster major (the group-major kernel then only writes the sums),
+        // or never
+        Tiles t = default_tiles(K, prec);
+        t.far_kb = mode == FAR_CM_ON ? 1 : t.far_kb;
+        t.far_mfma = false;
+        t.far_cm = mode;
         far_c.push_back(t);
     }
     hipEvent_t e0, e1;

@@ -162,3 +162,25 @@ def test_finite_differences_full_size(nat):
         print(kind, j, ax, fd, ad, tol, flush=True)
         assert abs(fd - ad) <= tol, (kind, j, ax, fd, ad, tol)
         checked[kind] += 1
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("mixed", 1e-4)])
+def test_adjoint_after_cluster_major_forward(nat, orc, prec, tol):
+    """With tile far_cm the forward builds the cluster-major view of every far entry and the
+    adjoint reuses it; gradients against the oracle's adjoint."""
+    n, seed, n0, p, theta = 1400, 36, 40, 5, 0.5
+    w = W.cube(n, seed=seed, n0=n0, with_w=True)
+    T = orc.build_tree(w.src, n0)
+    L = orc.lists(T, theta, w.src)
+    ref = orc.frozen_adjoint(T, L, w.src, w.f[0], w.h[0], w.nu, p, w.src, w.w)
+    X = _t(w.src)
+    try:
+        nat.tiles_set(p, 1, prec, far_cm=1)
+        u, plan = nat.evaluate(X, X, _t(w.f[0]), _t(w.h[0]), _t(w.nu), p, theta, n0, prec, keep_plan=True)
+        assert nat.plan_far_split(plan)[0] == 64
+        g = nat.evaluate_adjoint(plan, _t(w.w), n)
+    finally:
+        nat.tiles_set(p, 1, prec, clear=True)
+    for key, r in zip(("f", "h", "sources", "targets"), ref):
+        err = orc.rel_l2(g[key].cpu().numpy(), r)
+        assert err < tol, (key, err)

@@ -129,3 +129,49 @@ def test_far_mfma_matches_valu(nat, K, p):
         e_v = float((u_mfma[r] - u_valu[r]).norm() / u_valu[r].norm())
         e_64 = float((u_mfma[r] - u64[r]).norm() / u64[r].norm())
         assert e_v < 2e-6 and e_64 < 1e-5, (r, e_v, e_64)
+
+
+@pytest.mark.parametrize("K,prec", [(1, "fp64"), (1, "mixed"), (5, "fp64"), (16, "mixed")])
+def test_far_cluster_major_matches_split(nat, K, prec):
+    """Tile far_cm = 1 (every far entry cluster major: per-incidence terms added per target
+    in list order) against far_cm = 2 (group major, sparse split with one right-hand side),
+    per right-hand side; the plan reports the split it used."""
+    p, theta, n0 = 6, 0.5, 200
+    w = W.cube(25_000, seed=90 + K, n0=n0, k=K)
+    X = _t(w.src)
+    F, H, NU = _t(w.f), _t(w.h), _t(w.nu)
+    try:
+        nat.tiles_set(p, K, prec, far_kb=1, near_kb=1, far_cm=2)
+        u_ref, pl_ref = nat.evaluate(X, X, F, H, NU, p, theta, n0, prec, keep_plan=True)
+        nat.tiles_set(p, K, prec, far_kb=1, near_kb=1, far_cm=1)
+        u_cm, pl_cm = nat.evaluate(X, X, F, H, NU, p, theta, n0, prec, keep_plan=True)
+        assert nat.plan_tiles(pl_cm)["far_cm"] == 1
+        assert nat.plan_far_split(pl_ref)[0] == (32 if K == 1 else 0)
+    finally:
+        nat.tiles_set(p, K, prec, clear=True)
+    max_pc, n_cm = nat.plan_far_split(pl_cm)
+    nfar = int(nat.plan_counts(pl_cm)[0].sum())
+    assert max_pc == 64 and n_cm == nfar
+    if K == 1:
+        u_ref, u_cm = u_ref[None], u_cm[None]
+    for r in range(K):
+        e = float((u_cm[r] - u_ref[r]).norm() / u_ref[r].norm())
+        assert e < (1e-14 if prec == "fp64" else 1e-6), (r, e)
+
+
+def test_far_cluster_major_fp64_matches_oracle(nat, orc):
+    """The cluster-major far schedule in FP64 against the oracle treecode (disjoint
+    targets, two right-hand sides)."""
+    K, n0, p, theta = 2, 64, 5, 0.6
+    w = W.cube(4000, seed=97, n0=n0, k=K)
+    tg = np.random.default_rng(98).uniform(-0.1, 1.1, (1700, 3))
+    try:
+        nat.tiles_set(p, K, "fp64", far_cm=1)
+        u = nat.evaluate(_t(tg), _t(w.src), _t(w.f), _t(w.h), _t(w.nu), p, theta, n0, "fp64")
+    finally:
+        nat.tiles_set(p, K, "fp64", clear=True)
+    T = orc.build_tree(w.src, n0)
+    for r in range(K):
+        M, Mt = orc.moments(T, w.src, w.f[r], w.h[r], w.nu, p)
+        ref = orc.treecode(T, w.src, w.f[r], w.h[r], w.nu, M, Mt, p, theta, tg)
+        assert orc.rel_l2(u[r].cpu().numpy(), ref.u) < 1e-12, r
