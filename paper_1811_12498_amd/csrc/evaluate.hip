@@ -246,19 +246,19 @@ template <int P> void launch_far_mfma(const FarArgs &a, DBuf &bm, int32_t nn, hi
 
 namespace {
 
-template <typename T> void dispatch_far_sparse(int p, const FarSparseArgs &a, hipStream_t s) {
+template <typename T, int KB> void dispatch_far_sparse(int p, const FarSparseArgs &a, hipStream_t s) {
     switch (p) {
-        case 0: launch_far_sparse<0, T>(a, s); break;
-        case 1: launch_far_sparse<1, T>(a, s); break;
-        case 2: launch_far_sparse<2, T>(a, s); break;
-        case 3: launch_far_sparse<3, T>(a, s); break;
-        case 4: launch_far_sparse<4, T>(a, s); break;
-        case 5: launch_far_sparse<5, T>(a, s); break;
-        case 6: launch_far_sparse<6, T>(a, s); break;
-        case 7: launch_far_sparse<7, T>(a, s); break;
-        case 8: launch_far_sparse<8, T>(a, s); break;
-        case 9: launch_far_sparse<9, T>(a, s); break;
-        case 10: launch_far_sparse<10, T>(a, s); break;
+        case 0: launch_far_sparse<0, T, KB>(a, s); break;
+        case 1: launch_far_sparse<1, T, KB>(a, s); break;
+        case 2: launch_far_sparse<2, T, KB>(a, s); break;
+        case 3: launch_far_sparse<3, T, KB>(a, s); break;
+        case 4: launch_far_sparse<4, T, KB>(a, s); break;
+        case 5: launch_far_sparse<5, T, KB>(a, s); break;
+        case 6: launch_far_sparse<6, T, KB>(a, s); break;
+        case 7: launch_far_sparse<7, T, KB>(a, s); break;
+        case 8: launch_far_sparse<8, T, KB>(a, s); break;
+        case 9: launch_far_sparse<9, T, KB>(a, s); break;
+        case 10: launch_far_sparse<10, T, KB>(a, s); break;
         default: throw Error(STK_EINVAL, "p out of range");
     }
 }
@@ -310,10 +310,15 @@ void far_sparse(Tree &t, Plan &pl, double *unear, int max_pc, hipStream_t s) {
     FarSparseArgs sa{pl.tpos.as<double>(), cm.item_node.as<int32_t>(), cm.item_i0.as<int32_t>(),
                      cm.item_i1.as<int32_t>(), cm.inc_tgt.as<int32_t>(), cm.inc_slot.as<int32_t>(),
                      t.ncenter.as<double>(), t.nrho.as<double>(), t.wblk.p, part, cm.n_items, K};
+    const int kb = pl.tiles.far_kb;
     if (t.prec == STK_FP64)
-        dispatch_far_sparse<double>(t.p, sa, s);
+        dispatch_far_sparse<double, 1>(t.p, sa, s);
+    else if (kb == 4)
+        dispatch_far_sparse<float, 4>(t.p, sa, s);
+    else if (kb == 2)
+        dispatch_far_sparse<float, 2>(t.p, sa, s);
     else
-        dispatch_far_sparse<float>(t.p, sa, s);
+        dispatch_far_sparse<float, 1>(t.p, sa, s);
     if (m > 0 && cm.n_inc > 0) {
         if (t.prec == STK_FP64)
             hipLaunchKernelGGL(k_cm_add<double>, dim3(nblk(m * K, 256)), dim3(256), 0, s,

@@ -77,10 +77,13 @@ template <int P, typename T, int KB> void launch_far(const FarArgs &a, hipStream
 
 // one wave per item: a cluster and up to 64 targets whose groups' entries for it run
 // cluster major; each lane evaluates its (target, cluster) interaction for every
-// right-hand side and writes the velocities to the interaction's slot in the target's list
-// of cluster-major entries
-template <int P, typename T> __global__ __launch_bounds__(64) void k_far_sparse(FarSparseArgs a) {
+// right-hand side (KB of them per Taylor-coefficient recurrence) and writes the velocities
+// to the interaction's slot in the target's list of cluster-major entries
+template <int P, typename T, int KB> __global__ __launch_bounds__(64) void k_far_sparse(FarSparseArgs a) {
     constexpr int WS = 6 * nidx(P + 1);
+    // the streams are read through the constant address space: the partial stores below
+    // cannot alias them, so their uniform loads stay scalar across the loop
+    using Eval = FarEval<P, T, KB, true>;
     const int32_t it = xcd_group(a.nitems);
     if (it >= a.nitems) return;
     const int lane = threadIdx.x;
@@ -94,33 +97,33 @@ template <int P, typename T> __global__ __launch_bounds__(64) void k_far_sparse(
         const double rinv = 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
         const T dh[3] = {T(d0 * rinv), T(d1 * rinv), T(d2 * rinv)};
         const T tt = T(a.rho[c] * rinv);
-        // the streams are read through the constant address space: the partial stores below
-        // cannot alias them, so their uniform loads stay scalar across the loop
-        using Eval = FarEval<P, T, 1, true>;
         const T *wb = static_cast<const T *>(a.wblk) + size_t(c) * a.K * WS;
         T *o = static_cast<T *>(a.part) + 3 * int64_t(slot) * a.K;
-        for (int r = 0; r < a.K; ++r) {
-            // the recurrence is redone per right-hand side: opaque copies of its inputs keep
-            // the compiler from hoisting all coefficients out of the loop (they would not
-            // fit the register file)
+        for (int r0 = 0; r0 < a.K; r0 += KB) {
+            // the recurrence is redone per block of right-hand sides: opaque copies of its
+            // inputs keep the compiler from hoisting all coefficients out of the loop (they
+            // would not fit the register file)
             T dr[3] = {dh[0], dh[1], dh[2]}, tr = tt;
 #if defined(__HIP_DEVICE_COMPILE__)
             asm("" : "+v"(dr[0]), "+v"(dr[1]), "+v"(dr[2]), "+v"(tr));
 #endif
-            T accG[3], accF[3];
-            Eval::run(dr, tr, (typename Eval::Ptr)(wb + size_t(r) * WS), accG, accF);
-            T u[3];
-            far_velocity(accG, accF, T(rinv), u);
-            o[3 * r] = u[0];
-            o[3 * r + 1] = u[1];
-            o[3 * r + 2] = u[2];
+            T accG[KB][3], accF[KB][3];
+            Eval::run(dr, tr, (typename Eval::Ptr)(wb + size_t(r0) * WS), accG, accF);
+#pragma unroll
+            for (int r = 0; r < KB; ++r) {
+                T u[3];
+                far_velocity(accG[r], accF[r], T(rinv), u);
+                o[3 * (r0 + r)] = u[0];
+                o[3 * (r0 + r) + 1] = u[1];
+                o[3 * (r0 + r) + 2] = u[2];
+            }
         }
     }
 }
 
-template <int P, typename T> void launch_far_sparse(const FarSparseArgs &a, hipStream_t s) {
+template <int P, typename T, int KB> void launch_far_sparse(const FarSparseArgs &a, hipStream_t s) {
     if (a.nitems == 0) return;
-    hipLaunchKernelGGL((k_far_sparse<P, T>), dim3(xcd_blocks(a.nitems)), dim3(64), 0, s, a);
+    hipLaunchKernelGGL((k_far_sparse<P, T, KB>), dim3(xcd_blocks(a.nitems)), dim3(64), 0, s, a);
     STK_CHECK_LAUNCH();
 }
 

@@ -50,6 +50,6 @@ inline unsigned xcd_blocks(int32_t ngroups) { return unsigned(((ngroups + 7) >> 
 
 // defined in far_impl.hpp, instantiated per Taylor order in far_p*.hip / fark_p*.hip
 template <int P, typename T, int KB> void launch_far(const FarArgs &a, hipStream_t s);
-template <int P, typename T> void launch_far_sparse(const FarSparseArgs &a, hipStream_t s);
+template <int P, typename T, int KB> void launch_far_sparse(const FarSparseArgs &a, hipStream_t s);
 
 }  // namespace stk

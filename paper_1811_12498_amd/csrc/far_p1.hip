@@ -5,6 +5,6 @@
 namespace stk {
 template void launch_far<1, float, 1>(const FarArgs &, hipStream_t);
 template void launch_far<1, double, 1>(const FarArgs &, hipStream_t);
-template void launch_far_sparse<1, float>(const FarSparseArgs &, hipStream_t);
-template void launch_far_sparse<1, double>(const FarSparseArgs &, hipStream_t);
+template void launch_far_sparse<1, float, 1>(const FarSparseArgs &, hipStream_t);
+template void launch_far_sparse<1, double, 1>(const FarSparseArgs &, hipStream_t);
 }  // namespace stk

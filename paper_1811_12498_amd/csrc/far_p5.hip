@@ -5,6 +5,6 @@
 namespace stk {
 template void launch_far<5, float, 1>(const FarArgs &, hipStream_t);
 template void launch_far<5, double, 1>(const FarArgs &, hipStream_t);
-template void launch_far_sparse<5, float>(const FarSparseArgs &, hipStream_t);
-template void launch_far_sparse<5, double>(const FarSparseArgs &, hipStream_t);
+template void launch_far_sparse<5, float, 1>(const FarSparseArgs &, hipStream_t);
+template void launch_far_sparse<5, double, 1>(const FarSparseArgs &, hipStream_t);
 }  // namespace stk

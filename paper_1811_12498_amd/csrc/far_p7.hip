@@ -5,6 +5,6 @@
 namespace stk {
 template void launch_far<7, float, 1>(const FarArgs &, hipStream_t);
 template void launch_far<7, double, 1>(const FarArgs &, hipStream_t);
-template void launch_far_sparse<7, float>(const FarSparseArgs &, hipStream_t);
-template void launch_far_sparse<7, double>(const FarSparseArgs &, hipStream_t);
+template void launch_far_sparse<7, float, 1>(const FarSparseArgs &, hipStream_t);
+template void launch_far_sparse<7, double, 1>(const FarSparseArgs &, hipStream_t);
 }  // namespace stk

@@ -191,15 +191,16 @@ Tiles autotune(int p, int K, stk_precision prec, int64_t n, double theta, int32_
         t.far_mfma = true;
         far_c.push_back(t);
     }
-    for (int32_t mode : {FAR_CM_ON, FAR_CM_OFF}) {
-        // every far entry cluster major (the group-major kernel then only writes the sums),
-        // or never
-        Tiles t = default_tiles(K, prec);
-        t.far_kb = mode == FAR_CM_ON ? 1 : t.far_kb;
-        t.far_mfma = false;
-        t.far_cm = mode;
-        far_c.push_back(t);
-    }
+    for (int32_t mode : {FAR_CM_ON, FAR_CM_OFF})
+        for (int kb : {1, 2, 4}) {
+            // every far entry cluster major (the group-major kernel then only writes the
+            // sums), or never, with kb right-hand sides per recurrence
+            Tiles t = default_tiles(K, prec);
+            t.far_kb = kb;
+            t.far_mfma = false;
+            t.far_cm = mode;
+            if (tiles_valid(t, K, prec)) far_c.push_back(t);
+        }
     hipEvent_t e0, e1;
     STK_HIP(hipEventCreate(&e0));
     STK_HIP(hipEventCreate(&e1));
