@@ -2,10 +2,13 @@
 //
 //   M_j^k(C) = sum_{y in C} (y - y_c)^k f_j,   Mt_jl^k(C) = sum_{y in C} (y - y_c)^k h_j nu_l
 //
-// computed directly from each node's points (every point contributes to each of its
-// ancestors), in FP64.  Work items are (node, chunk of <= CHUNK points); each item
-// writes a partial sum and a second kernel adds a node's partials in chunk order, so
-// the result does not depend on scheduling.
+// in FP64.  A leaf's moments are summed directly from its points: work items are (leaf,
+// chunk of <= CHUNK points), each writes a partial sum and a second kernel adds a leaf's
+// partials in chunk order.  An inner node's moments are its children's, moved to its
+// centre by the binomial expansion
+//   (y - c)^k = sum_{j <= k} C(k, j) (c' - c)^(k - j) (y - c')^j    (c' a child's centre),
+// exact in exact arithmetic, level by level from the leaves up; children and terms are
+// added in a fixed order, so the result does not depend on scheduling.
 #include "stk_internal.hpp"
 #include "stk_math.hpp"
 
@@ -125,6 +128,102 @@ __global__ __launch_bounds__(MT) void k_moments_reduce(const double *__restrict_
     mom[(size_t(node) * nm + a) * 12 * K + 12 * r + c] = s;
 }
 
+// grid (nodes of one level, K), MT threads, 3 nm * 12 doubles of dynamic LDS: an inner
+// node's moments from its children's (already final), each moved to the node's centre one
+// axis at a time,
+//   M'(k) = sum_{j <= k_i} C(k_i, j) d_i^(k_i - j) M(k with k_i -> j)   (i = x, y, z),
+// which composes to the binomial expansion and keeps every index within ||k|| <= p.  A
+// thread takes whole lines along the axis (the other two components and the channel
+// fixed): at most p + 1 values in registers and a triangular update.  Children are added in
+// order into an LDS accumulator.
+constexpr int NM_MAX = (STK_P_MAX + 1) * (STK_P_MAX + 2) * (STK_P_MAX + 3) / 6;
+
+__device__ inline int m2m_index(int ax, int kl, int u, int v) {
+    // multi-index with component ax = kl and the other two (in axis order) = u, v
+    return ax == 0 ? gidx(kl, u, v) : (ax == 1 ? gidx(u, kl, v) : gidx(u, v, kl));
+}
+
+__global__ __launch_bounds__(MT) void k_m2m(const double *__restrict__ center, const int32_t *__restrict__ child0,
+                                            const int32_t *__restrict__ nchild, int32_t lev_begin, int p, int nm,
+                                            double *__restrict__ mom) {
+    extern __shared__ double m2m_lds[];
+    __shared__ double fac[3][STK_P_MAX + 1][STK_P_MAX + 1];  // C(k, j) d^(k - j) per axis
+    const int32_t node = lev_begin + blockIdx.x;
+    const int r = blockIdx.y, K = gridDim.y;
+    const int nc = nchild[node];
+    if (nc == 0) return;  // a leaf keeps its direct moments
+    const int tid = threadIdx.x;
+    const int nq = nm * 12;
+    double *buf0 = m2m_lds, *buf1 = m2m_lds + nq, *acc = m2m_lds + 2 * nq;
+    for (int q = tid; q < nq; q += MT) acc[q] = 0.0;
+    const int npair = (p + 1) * (p + 2) / 2;  // (u, v) with u + v <= p
+    const int nline = npair * 12;
+    // the next child's moments are loaded into registers while the current one is moved
+    constexpr int QMAX = (NM_MAX * 12 + MT - 1) / MT;
+    double pre[QMAX];
+    auto fetch = [&](int32_t ch) {
+#pragma unroll
+        for (int i = 0; i < QMAX; ++i) {
+            const int q = tid + MT * i;
+            pre[i] = q < nq ? mom[(size_t(ch) * nm + q / 12) * 12 * K + 12 * r + q % 12] : 0.0;
+        }
+    };
+    fetch(child0[node]);
+    for (int ci = 0; ci < nc; ++ci) {
+        const int32_t ch = child0[node] + ci;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < QMAX; ++i)
+            if (tid + MT * i < nq) buf0[tid + MT * i] = pre[i];
+        if (ci + 1 < nc) fetch(ch + 1);
+        if (tid < 3) {
+            // row k: C(k, j) d^(k - j), with C(k, j) = C(k - 1, j - 1) + C(k - 1, j)
+            const double d = center[3 * ch + tid] - center[3 * node + tid];
+            double dp[STK_P_MAX + 1];
+            dp[0] = 1.0;
+            for (int e = 1; e <= p; ++e) dp[e] = dp[e - 1] * d;
+            double bin[STK_P_MAX + 1];
+            for (int k = 0; k <= p; ++k) {
+                bin[k] = 1.0;
+                for (int j = k - 1; j > 0; --j) bin[j] += bin[j - 1];
+                for (int j = 0; j <= k; ++j) fac[tid][k][j] = bin[j] * dp[k - j];
+            }
+        }
+        for (int ax = 0; ax < 3; ++ax) {
+            __syncthreads();
+            const double *in = ax == 1 ? buf1 : buf0;
+            double *out = ax == 2 ? acc : (ax == 0 ? buf1 : buf0);
+            for (int ln = tid; ln < nline; ln += MT) {
+                const int c = ln % 12, pr = ln / 12;
+                // pair pr -> (u, v): u + v = s, v = pr - s (s + 1) / 2
+                int sv = 0;
+                while ((sv + 1) * (sv + 2) / 2 <= pr) ++sv;
+                const int v = pr - sv * (sv + 1) / 2, u = sv - v;
+                const int len = p - sv + 1;  // kl = 0 .. p - u - v
+                double x[STK_P_MAX + 1];
+#pragma unroll
+                for (int kl = 0; kl <= STK_P_MAX; ++kl)
+                    x[kl] = kl < len ? in[m2m_index(ax, kl, u, v) * 12 + c] : 0.0;
+#pragma unroll
+                for (int kl = 0; kl <= STK_P_MAX; ++kl) {
+                    if (kl < len) {
+                        double y = 0.0;
+#pragma unroll
+                        for (int jj = 0; jj <= kl; ++jj) y += fac[ax][kl][jj] * x[jj];
+                        const int o = m2m_index(ax, kl, u, v) * 12 + c;
+                        if (ax == 2)
+                            out[o] += y;
+                        else
+                            out[o] = y;
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int q = tid; q < nq; q += MT) mom[(size_t(node) * nm + q / 12) * 12 * K + 12 * r + q % 12] = acc[q];
+}
+
 // grid (nnodes, K): each cluster's far-field stream (stk_math.hpp) in the evaluation
 // precision, wblk[(node * K + r) * 6 nG + pos], nG = nidx(p + 1)
 template <typename T>
@@ -184,11 +283,13 @@ inline unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
 
 }  // namespace
 
+// direct moments of the leaves (their chunks only)
 template <int A>
 static void launch_moments(Tree &t, int K, int p, int nm, const double *w12, double *part, hipStream_t s) {
-    hipLaunchKernelGGL(k_moments<A>, dim3(t.nchunks, K), dim3(64), 0, s, t.pos.as<double>(), t.nstart.as<int32_t>(),
-                       t.ncount.as<int32_t>(), t.chunk_off.as<int32_t>(), t.nnodes, t.ncenter.as<double>(), w12, p, nm,
-                       part);
+    if (t.nleafchunks == 0) return;
+    hipLaunchKernelGGL(k_moments<A>, dim3(t.nleafchunks, K), dim3(64), 0, s, t.pos.as<double>(),
+                       t.nstart.as<int32_t>(), t.ncount.as<int32_t>(), t.leaf_coff.as<int32_t>(), t.nnodes,
+                       t.ncenter.as<double>(), w12, p, nm, part);
     STK_CHECK_LAUNCH();
 }
 
@@ -210,7 +311,7 @@ void compute_moments(Tree &t, const double *f, const double *h, const double *nu
                            t.perm.as<int32_t>(), t.n, K, f, h, nu, t.geo.as<double>(), t.wts.as<float>(), w12);
     STK_CHECK_LAUNCH();
 
-    double *part = reserve<double>(t.s_tmp, size_t(t.nchunks) * K * nm * 12);
+    double *part = reserve<double>(t.s_tmp, size_t(t.nleafchunks) * K * nm * 12 + 1);
     const int A = (nm + 63) / 64;
     switch (A) {
         case 1: launch_moments<1>(t, K, p, nm, w12, part, s); break;
@@ -222,8 +323,17 @@ void compute_moments(Tree &t, const double *f, const double *h, const double *nu
     }
     double *mom = reserve<double>(t.mom, size_t(nn) * nm * 12 * K);
     hipLaunchKernelGGL(k_moments_reduce, dim3(nn, K, (nm * 12 + MT - 1) / MT), dim3(MT), 0, s, part,
-                       t.chunk_off.as<int32_t>(), nm, mom);
+                       t.leaf_coff.as<int32_t>(), nm, mom);
     STK_CHECK_LAUNCH();
+    // inner nodes, from the deepest level that has any up to the root
+    for (int l = t.nlevels - 2; l >= 0; --l) {
+        const int32_t b = t.level_begin[l], e = t.level_begin[l + 1];
+        if (e > b) {
+            hipLaunchKernelGGL(k_m2m, dim3(e - b, K), dim3(MT), sizeof(double) * 3 * nm * 12, s,
+                               t.ncenter.as<double>(), t.nchild0.as<int32_t>(), t.nnchild.as<int32_t>(), b, p, nm, mom);
+            STK_CHECK_LAUNCH();
+        }
+    }
     if (prec == STK_FP64)
         hipLaunchKernelGGL(k_channels<double>, dim3(nn, K), dim3(MT), 0, s, mom, t.nrho.as<double>(), p, nm, ng,
                            t.wblk.as<double>());

@@ -90,6 +90,8 @@ struct Tree {
     // work chunks over (node, particle range) for per-node reductions
     DBuf chunk_off;              // int32 (nn + 1): first chunk of each node
     int32_t nchunks = 0;
+    DBuf leaf_coff;              // int32 (nn + 1): the same over leaves only (0 chunks for inner nodes)
+    int32_t nleafchunks = 0;
 
     // moments state
     bool have_moments = false;

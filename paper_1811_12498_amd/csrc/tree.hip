@@ -234,6 +234,12 @@ __global__ void k_chunk_count(const int32_t *__restrict__ count, int32_t nn, int
     if (i < nn) out[i] = (count[i] + CHUNK - 1) / CHUNK;
 }
 
+__global__ void k_leaf_chunk_count(const int32_t *__restrict__ count, const int32_t *__restrict__ nchild, int32_t nn,
+                                   int32_t *__restrict__ out) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nn) out[i] = nchild[i] == 0 ? (count[i] + CHUNK - 1) / CHUNK : 0;
+}
+
 __device__ inline int32_t node_of_chunk(const int32_t *__restrict__ off, int32_t nn, int32_t ch) {
     int32_t lo = 0, hi = nn;  // last node with off[node] <= ch
     while (hi - lo > 1) {
@@ -405,6 +411,13 @@ void build_tree(Tree &t, const double *src, int64_t n, int32_t n0, hipStream_t s
     STK_CHECK_LAUNCH();
     scan_exclusive_i32(cnt, coff, nnodes, t.s_scan, s);
     STK_HIP(hipMemcpyAsync(&t.nchunks, coff + nnodes, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    int32_t *lcnt = reserve<int32_t>(t.s_vals2, size_t(nnodes));
+    int32_t *lcoff = reserve<int32_t>(t.leaf_coff, size_t(nnodes) + 1);
+    hipLaunchKernelGGL(k_leaf_chunk_count, dim3(nblk(nnodes, BT)), dim3(BT), 0, s, t.ncount.as<int32_t>(),
+                       t.nnchild.as<int32_t>(), nnodes, lcnt);
+    STK_CHECK_LAUNCH();
+    scan_exclusive_i32(lcnt, lcoff, nnodes, t.s_scan, s);
+    STK_HIP(hipMemcpyAsync(&t.nleafchunks, lcoff + nnodes, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     double *rad = reserve<double>(t.nradius, size_t(nnodes));
     double *rho = reserve<double>(t.nrho, size_t(nnodes));
     STK_HIP(hipMemsetAsync(rad, 0, sizeof(double) * nnodes, s));
