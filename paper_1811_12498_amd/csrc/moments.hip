@@ -128,100 +128,89 @@ __global__ __launch_bounds__(MT) void k_moments_reduce(const double *__restrict_
     mom[(size_t(node) * nm + a) * 12 * K + 12 * r + c] = s;
 }
 
-// grid (nodes of one level, K), MT threads, 3 nm * 12 doubles of dynamic LDS: an inner
-// node's moments from its children's (already final), each moved to the node's centre one
+// grid (nodes of one level, K), MT threads, 2 nm * 12 doubles of dynamic LDS; one launch
+// per level from the deepest up.  A block first completes its node's moments (an inner
+// node: the sum of its children's moments moved to its centre, children in order; a leaf:
+// its direct moments), then moves them to its parent's centre for the level above, one
 // axis at a time,
 //   M'(k) = sum_{j <= k_i} C(k_i, j) d_i^(k_i - j) M(k with k_i -> j)   (i = x, y, z),
 // which composes to the binomial expansion and keeps every index within ||k|| <= p.  A
 // thread takes whole lines along the axis (the other two components and the channel
-// fixed): at most p + 1 values in registers and a triangular update.  Children are added in
-// order into an LDS accumulator.
-constexpr int NM_MAX = (STK_P_MAX + 1) * (STK_P_MAX + 2) * (STK_P_MAX + 3) / 6;
-
+// fixed): at most p + 1 values in registers and a triangular update.
 __device__ inline int m2m_index(int ax, int kl, int u, int v) {
     // multi-index with component ax = kl and the other two (in axis order) = u, v
     return ax == 0 ? gidx(kl, u, v) : (ax == 1 ? gidx(u, kl, v) : gidx(u, v, kl));
 }
 
 __global__ __launch_bounds__(MT) void k_m2m(const double *__restrict__ center, const int32_t *__restrict__ child0,
-                                            const int32_t *__restrict__ nchild, int32_t lev_begin, int p, int nm,
-                                            double *__restrict__ mom) {
+                                            const int32_t *__restrict__ nchild, const int32_t *__restrict__ parent,
+                                            int32_t lev_begin, int p, int nm, double *__restrict__ mom,
+                                            double *__restrict__ up) {
     extern __shared__ double m2m_lds[];
     __shared__ double fac[3][STK_P_MAX + 1][STK_P_MAX + 1];  // C(k, j) d^(k - j) per axis
     const int32_t node = lev_begin + blockIdx.x;
     const int r = blockIdx.y, K = gridDim.y;
-    const int nc = nchild[node];
-    if (nc == 0) return;  // a leaf keeps its direct moments
     const int tid = threadIdx.x;
     const int nq = nm * 12;
-    double *buf0 = m2m_lds, *buf1 = m2m_lds + nq, *acc = m2m_lds + 2 * nq;
-    for (int q = tid; q < nq; q += MT) acc[q] = 0.0;
-    const int npair = (p + 1) * (p + 2) / 2;  // (u, v) with u + v <= p
-    const int nline = npair * 12;
-    // the next child's moments are loaded into registers while the current one is moved
-    constexpr int QMAX = (NM_MAX * 12 + MT - 1) / MT;
-    double pre[QMAX];
-    auto fetch = [&](int32_t ch) {
-#pragma unroll
-        for (int i = 0; i < QMAX; ++i) {
-            const int q = tid + MT * i;
-            pre[i] = q < nq ? mom[(size_t(ch) * nm + q / 12) * 12 * K + 12 * r + q % 12] : 0.0;
+    double *buf0 = m2m_lds, *buf1 = m2m_lds + nq;
+    auto at = [&](int32_t nd, int q) { return (size_t(nd) * nm + q / 12) * 12 * K + 12 * r + q % 12; };
+    const int nc = nchild[node];
+    if (nc > 0) {
+        const int32_t c0 = child0[node];
+        for (int q = tid; q < nq; q += MT) {
+            double s = 0.0;
+            for (int ci = 0; ci < nc; ++ci) s += up[at(c0 + ci, q)];
+            mom[at(node, q)] = s;
+            buf0[q] = s;
         }
-    };
-    fetch(child0[node]);
-    for (int ci = 0; ci < nc; ++ci) {
-        const int32_t ch = child0[node] + ci;
+    } else {
+        for (int q = tid; q < nq; q += MT) buf0[q] = mom[at(node, q)];
+    }
+    const int32_t par = parent[node];
+    if (par < 0) return;  // the root
+    if (tid < 3) {
+        // row k: C(k, j) d^(k - j), with C(k, j) = C(k - 1, j - 1) + C(k - 1, j)
+        const double d = center[3 * node + tid] - center[3 * par + tid];
+        double dp[STK_P_MAX + 1];
+        dp[0] = 1.0;
+        for (int e = 1; e <= p; ++e) dp[e] = dp[e - 1] * d;
+        double bin[STK_P_MAX + 1];
+        for (int k = 0; k <= p; ++k) {
+            bin[k] = 1.0;
+            for (int j = k - 1; j > 0; --j) bin[j] += bin[j - 1];
+            for (int j = 0; j <= k; ++j) fac[tid][k][j] = bin[j] * dp[k - j];
+        }
+    }
+    const int nline = (p + 1) * (p + 2) / 2 * 12;  // (u, v) with u + v <= p, channel
+    for (int ax = 0; ax < 3; ++ax) {
         __syncthreads();
+        const double *in = ax == 1 ? buf1 : buf0;
+        double *out = ax == 0 ? buf1 : buf0;
+        for (int ln = tid; ln < nline; ln += MT) {
+            const int c = ln % 12, pr = ln / 12;
+            // pair pr -> (u, v): u + v = s, v = pr - s (s + 1) / 2
+            int sv = 0;
+            while ((sv + 1) * (sv + 2) / 2 <= pr) ++sv;
+            const int v = pr - sv * (sv + 1) / 2, u = sv - v;
+            const int len = p - sv + 1;  // kl = 0 .. p - u - v
+            double x[STK_P_MAX + 1];
 #pragma unroll
-        for (int i = 0; i < QMAX; ++i)
-            if (tid + MT * i < nq) buf0[tid + MT * i] = pre[i];
-        if (ci + 1 < nc) fetch(ch + 1);
-        if (tid < 3) {
-            // row k: C(k, j) d^(k - j), with C(k, j) = C(k - 1, j - 1) + C(k - 1, j)
-            const double d = center[3 * ch + tid] - center[3 * node + tid];
-            double dp[STK_P_MAX + 1];
-            dp[0] = 1.0;
-            for (int e = 1; e <= p; ++e) dp[e] = dp[e - 1] * d;
-            double bin[STK_P_MAX + 1];
-            for (int k = 0; k <= p; ++k) {
-                bin[k] = 1.0;
-                for (int j = k - 1; j > 0; --j) bin[j] += bin[j - 1];
-                for (int j = 0; j <= k; ++j) fac[tid][k][j] = bin[j] * dp[k - j];
-            }
-        }
-        for (int ax = 0; ax < 3; ++ax) {
-            __syncthreads();
-            const double *in = ax == 1 ? buf1 : buf0;
-            double *out = ax == 2 ? acc : (ax == 0 ? buf1 : buf0);
-            for (int ln = tid; ln < nline; ln += MT) {
-                const int c = ln % 12, pr = ln / 12;
-                // pair pr -> (u, v): u + v = s, v = pr - s (s + 1) / 2
-                int sv = 0;
-                while ((sv + 1) * (sv + 2) / 2 <= pr) ++sv;
-                const int v = pr - sv * (sv + 1) / 2, u = sv - v;
-                const int len = p - sv + 1;  // kl = 0 .. p - u - v
-                double x[STK_P_MAX + 1];
+            for (int kl = 0; kl <= STK_P_MAX; ++kl) x[kl] = kl < len ? in[m2m_index(ax, kl, u, v) * 12 + c] : 0.0;
 #pragma unroll
-                for (int kl = 0; kl <= STK_P_MAX; ++kl)
-                    x[kl] = kl < len ? in[m2m_index(ax, kl, u, v) * 12 + c] : 0.0;
+            for (int kl = 0; kl <= STK_P_MAX; ++kl) {
+                if (kl < len) {
+                    double y = 0.0;
 #pragma unroll
-                for (int kl = 0; kl <= STK_P_MAX; ++kl) {
-                    if (kl < len) {
-                        double y = 0.0;
-#pragma unroll
-                        for (int jj = 0; jj <= kl; ++jj) y += fac[ax][kl][jj] * x[jj];
-                        const int o = m2m_index(ax, kl, u, v) * 12 + c;
-                        if (ax == 2)
-                            out[o] += y;
-                        else
-                            out[o] = y;
-                    }
+                    for (int jj = 0; jj <= kl; ++jj) y += fac[ax][kl][jj] * x[jj];
+                    const int o = m2m_index(ax, kl, u, v) * 12 + c;
+                    if (ax == 2)
+                        up[at(node, o)] = y;
+                    else
+                        out[o] = y;
                 }
             }
         }
     }
-    __syncthreads();
-    for (int q = tid; q < nq; q += MT) mom[(size_t(node) * nm + q / 12) * 12 * K + 12 * r + q % 12] = acc[q];
 }
 
 // grid (nnodes, K): each cluster's far-field stream (stk_math.hpp) in the evaluation
@@ -325,12 +314,15 @@ void compute_moments(Tree &t, const double *f, const double *h, const double *nu
     hipLaunchKernelGGL(k_moments_reduce, dim3(nn, K, (nm * 12 + MT - 1) / MT), dim3(MT), 0, s, part,
                        t.leaf_coff.as<int32_t>(), nm, mom);
     STK_CHECK_LAUNCH();
-    // inner nodes, from the deepest level that has any up to the root
-    for (int l = t.nlevels - 2; l >= 0; --l) {
+    // every level from the deepest up: complete inner nodes from their children, move each
+    // node's moments to its parent's centre
+    double *up = reserve<double>(t.mom_up, size_t(nn) * nm * 12 * K);
+    for (int l = t.nlevels - 1; l >= 0; --l) {
         const int32_t b = t.level_begin[l], e = t.level_begin[l + 1];
         if (e > b) {
-            hipLaunchKernelGGL(k_m2m, dim3(e - b, K), dim3(MT), sizeof(double) * 3 * nm * 12, s,
-                               t.ncenter.as<double>(), t.nchild0.as<int32_t>(), t.nnchild.as<int32_t>(), b, p, nm, mom);
+            hipLaunchKernelGGL(k_m2m, dim3(e - b, K), dim3(MT), sizeof(double) * 2 * nm * 12, s,
+                               t.ncenter.as<double>(), t.nchild0.as<int32_t>(), t.nnchild.as<int32_t>(),
+                               t.nparent.as<int32_t>(), b, p, nm, mom, up);
             STK_CHECK_LAUNCH();
         }
     }

@@ -98,6 +98,7 @@ struct Tree {
     int32_t p = -1, k_rhs = 0;
     stk_precision prec = STK_FP64;
     DBuf mom;     // double (nn, nm, 12*K): channels 0..2 = M_j, 3..11 = Mt_jl (3 + 3j + l)
+    DBuf mom_up;  // double, as mom: each node's moments moved to its parent's centre
     DBuf wblk;    // T (nn, nb, 12*K): scaled far-field channel blocks
     DBuf geo;     // double (n, 6): sorted (y, nu) per source
     DBuf wts;     // T (n, K, 6): sorted (f, h) per source and right-hand side
