@@ -163,6 +163,49 @@ def multi_rhs_times(reps=3):
             "E_S_rhs0_vs_fp64_direct": err, "sample_targets": int(w.sample.size)}
 
 
+def table1_icosphere(levels=(6, 7, 8), thetas=(0.2, 0.5, 0.8), ps=(0, 2, 4, 6, 8, 10), reps=2):
+    """Test case 1 of Sec. 6 in the regime of the paper's Table 1: Stokeslets and stresslets
+    at the centroids of the level-L refined icosahedron (N = 20 * 4^L) on the unit sphere,
+    nu = outward normal, f, h ~ U[-1, 1]^3 (seed 11), N0 = 2000.  Per (N, theta, p) and
+    precision: the treecode time (one stk_evaluate: tree, moments, lists, near and far
+    field), its error E over all N targets against the FP64 direct sum on the GPU, and the
+    speedup d/t over that direct sum's time."""
+    import torch
+
+    from paper_1811_12498_amd import native, workloads
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    rows, direct_ms = [], {}
+    for L in levels:
+        w = workloads.ico_sphere(L, seed=11, n0=2000)
+        X, F, H, NU = t(w.src), t(w.f[0]), t(w.h[0]), t(w.nu)
+        native.direct(X[:64].contiguous(), X, F, H, NU)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ud = native.direct(X, X, F, H, NU)
+        torch.cuda.synchronize()
+        d_ms = (time.perf_counter() - t0) * 1e3
+        direct_ms[w.n] = round(d_ms, 3)
+        nd = torch.linalg.norm(ud)
+        log(f"table1: N={w.n} direct FP64 {d_ms:.1f} ms")
+        for theta in thetas:
+            for p in ps:
+                for prec in ("fp64", "mixed"):
+                    u = native.evaluate(X, X, F, H, NU, p, theta, w.n0, prec)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for _ in range(reps):
+                        u = native.evaluate(X, X, F, H, NU, p, theta, w.n0, prec)
+                    torch.cuda.synchronize()
+                    ms = (time.perf_counter() - t0) * 1e3 / reps
+                    e = float(torch.linalg.norm(u - ud) / nd)
+                    rows.append({"N": w.n, "theta": theta, "p": p, "precision": prec, "ms": round(ms, 3),
+                                 "d_over_t": round(d_ms / ms, 2), "E": e})
+            log(f"table1: N={w.n} theta={theta} done")
+    return {"workload": "icosahedral sphere (Sec. 6 test case 1), S+T, nu = normal, N0 = 2000, E over all N "
+                        "targets vs the FP64 GPU direct sum", "direct_ms": direct_ms, "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,7 +216,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 comparison runs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 256 MiB device copy (a reference for HBM counters)")
-    ap.add_argument("--only", choices=["fwd_adjoint", "multi_rhs"],
+    ap.add_argument("--only", choices=["fwd_adjoint", "multi_rhs", "table1"],
                     help="run only this secondary measurement and print its JSON object (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -187,7 +230,8 @@ def main():
     from paper_1811_12498_amd import native, workloads
 
     if args.only:
-        res = fwd_adjoint_times() if args.only == "fwd_adjoint" else multi_rhs_times()
+        res = {"fwd_adjoint": fwd_adjoint_times, "multi_rhs": multi_rhs_times,
+               "table1": table1_icosphere}[args.only]()
         print(json.dumps(res), flush=True)
         return
 

@@ -107,35 +107,33 @@ def icosahedral_points(level: int) -> np.ndarray:
     """Centroids of the level-L refined icosahedron projected onto the unit sphere,
     N = 20 * 4**L (Sec. 6, test case 1).  Each refinement splits every triangle into
     four by its edge midpoints, which are pushed out to the sphere (the paper does not
-    say whether midpoints are projected at every level; this generator does)."""
+    say whether midpoints are projected at every level; this generator does).  The four
+    children of a face follow it in the order (a, ab, ca), (b, bc, ab), (c, ca, bc),
+    (ab, bc, ca)."""
     t = (1.0 + 5.0 ** 0.5) / 2.0
-    v = np.array([[-1, t, 0], [1, t, 0], [-1, -t, 0], [1, -t, 0], [0, -1, t], [0, 1, t],
+    V = np.array([[-1, t, 0], [1, t, 0], [-1, -t, 0], [1, -t, 0], [0, -1, t], [0, 1, t],
                   [0, -1, -t], [0, 1, -t], [t, 0, -1], [t, 0, 1], [-t, 0, -1], [-t, 0, 1]], float)
-    v /= np.linalg.norm(v, axis=1, keepdims=True)
-    faces = np.array([[0, 11, 5], [0, 5, 1], [0, 1, 7], [0, 7, 10], [0, 10, 11], [1, 5, 9],
-                      [5, 11, 4], [11, 10, 2], [10, 7, 6], [7, 1, 8], [3, 9, 4], [3, 4, 2],
-                      [3, 2, 6], [3, 6, 8], [3, 8, 9], [4, 9, 5], [2, 4, 11], [6, 2, 10],
-                      [8, 6, 7], [9, 8, 1]])
-    verts = [tuple(x) for x in v]
+    V /= np.linalg.norm(V, axis=1, keepdims=True)
+    F = np.array([[0, 11, 5], [0, 5, 1], [0, 1, 7], [0, 7, 10], [0, 10, 11], [1, 5, 9],
+                  [5, 11, 4], [11, 10, 2], [10, 7, 6], [7, 1, 8], [3, 9, 4], [3, 4, 2],
+                  [3, 2, 6], [3, 6, 8], [3, 8, 9], [4, 9, 5], [2, 4, 11], [6, 2, 10],
+                  [8, 6, 7], [9, 8, 1]])
     for _ in range(level):
-        cache: dict = {}
-        new_faces = []
-
-        def mid(a, b):
-            key = (min(a, b), max(a, b))
-            if key not in cache:
-                m = (np.asarray(verts[a]) + np.asarray(verts[b])) / 2.0
-                m /= np.linalg.norm(m)
-                cache[key] = len(verts)
-                verts.append(tuple(m))
-            return cache[key]
-
-        for a, b, c in faces:
-            ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
-            new_faces += [[a, ab, ca], [b, bc, ab], [c, ca, bc], [ab, bc, ca]]
-        faces = np.array(new_faces)
-    V = np.asarray(verts)
-    cen = V[faces].mean(axis=1)
+        # one midpoint per undirected edge (ab, bc, ca of every face)
+        E = np.concatenate([F[:, [0, 1]], F[:, [1, 2]], F[:, [2, 0]]])
+        key = np.sort(E, axis=1)
+        uniq, inv = np.unique(key, axis=0, return_inverse=True)
+        inv = inv.reshape(-1)
+        M = (V[uniq[:, 0]] + V[uniq[:, 1]]) / 2.0
+        M /= np.linalg.norm(M, axis=1, keepdims=True)
+        base = V.shape[0]
+        nf = F.shape[0]
+        ab, bc, ca = base + inv[:nf], base + inv[nf:2 * nf], base + inv[2 * nf:]
+        a, b, c = F[:, 0], F[:, 1], F[:, 2]
+        F = np.stack([np.stack([a, ab, ca], 1), np.stack([b, bc, ab], 1), np.stack([c, ca, bc], 1),
+                      np.stack([ab, bc, ca], 1)], axis=1).reshape(-1, 3)
+        V = np.concatenate([V, M])
+    cen = V[F].mean(axis=1)
     return cen / np.linalg.norm(cen, axis=1, keepdims=True)
 
 
