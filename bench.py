@@ -44,8 +44,9 @@ def far_flops_per_interaction(p, k=1):
 NEAR_FLOPS_PER_PAIR = 48  # Stokeslet + stresslet contracted pair (Sec. 4.1)
 
 
-# fastest (p, theta, N0) with E <= 1e-5 on the 1M sphere in the tuning sweep (bench.py --only tune)
-AT_ERROR_BAR = (8, 0.3, 500)
+# a fast (p, theta, N0) with E <= 1e-5 on the 1M sphere in the tuning sweep (bench.py --only
+# tune), with a margin under the bar (the fastest, p 7 / theta 0.3, sits 7% under it)
+AT_ERROR_BAR = (8, 0.325, 500)
 
 
 def log(msg):
@@ -221,8 +222,9 @@ def tune_c3(targets=(1e-3, 1e-4, 1e-5)):
     dev = torch.device("cuda:0")
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     X, F, H, NU = t(w.src), t(w.f[0]), t(w.h[0]), t(w.nu)
-    table = tuning.sweep(X, X, F, H, NU, "mixed", ps=(4, 6, 8, 10), thetas=(0.3, 0.4, 0.5, 0.6, 0.7),
-                         n0s=(250, 500, 1000, 2000), n_sample=2000)
+    table = tuning.sweep(X, X, F, H, NU, "mixed", ps=(4, 6, 7, 8, 9, 10),
+                         thetas=(0.3, 0.325, 0.35, 0.375, 0.4, 0.5, 0.6, 0.7), n0s=(250, 500, 1000, 2000),
+                         n_sample=2000)
     ref = [c for c in table if (c.p, c.theta, c.n0) == (w.p, w.theta, w.n0)]
     best = {}
     for e in targets:
