@@ -168,12 +168,17 @@ __global__ void k_slot_reduce(const T *__restrict__ part, const int32_t *__restr
     for (int q = 0; q < 3; ++q) out[3 * t + q] = acc[q].value();
 }
 
-// one source per lane; loops over every near entry of its leaf and the targets of each
-template <typename T> __global__ __launch_bounds__(64) void k_near_sgrad(NearAdjArgs a) {
+// one source per lane, SG_WAVES waves per block on the same 64 sources: wave w loops over
+// the w-th quarter of the leaf's near entries (in order) and the targets of each; the
+// waves' partial sums are added in wave order
+constexpr int SG_WAVES = 4;
+template <typename T> __global__ __launch_bounds__(64 * SG_WAVES) void k_near_sgrad(NearAdjArgs a) {
+    __shared__ double red[SG_WAVES - 1][9][64];
     const int32_t it = blockIdx.x;
     if (it >= a.nitems) return;
+    const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int32_t c = a.item_node[it];
-    const int32_t j = a.item_j0[it] + threadIdx.x;
+    const int32_t j = a.item_j0[it] + lane;
     const bool valid = j < a.start[c] + a.count[c];
     const int32_t jj = valid ? j : a.start[c];
     double y[3], nu[3];
@@ -184,7 +189,9 @@ template <typename T> __global__ __launch_bounds__(64) void k_near_sgrad(NearAdj
     const T *wj = static_cast<const T *>(a.wts) + 6 * int64_t(jj);
     const T f[3] = {wj[0], wj[1], wj[2]}, h[3] = {wj[3], wj[4], wj[5]};
     Comp<T> af[3], ah[3], ay[3];
-    for (int32_t e = a.ent_off[c]; e < a.ent_off[c + 1]; ++e) {
+    const int64_t ne = a.ent_off[c + 1] - a.ent_off[c];
+    const int32_t eb = a.ent_off[c] + int32_t(ne * wv / SG_WAVES), ee = a.ent_off[c] + int32_t(ne * (wv + 1) / SG_WAVES);
+    for (int32_t e = eb; e < ee; ++e) {
         const int32_t ent = a.ent[e];
         const int32_t g = a.ent_group[ent];
         uint64_t mk = a.mask[ent];
@@ -232,12 +239,21 @@ template <typename T> __global__ __launch_bounds__(64) void k_near_sgrad(NearAdj
             ay[q].add(sy[q]);
         }
     }
-    if (valid) {
+    double v[9];
+    for (int q = 0; q < 3; ++q) {
+        v[q] = af[q].value();
+        v[3 + q] = ah[q].value();
+        v[6 + q] = ay[q].value();
+    }
+    if (wv > 0)
+        for (int q = 0; q < 9; ++q) red[wv - 1][q][lane] = v[q];
+    __syncthreads();
+    if (wv == 0 && valid) {
         double *o = a.gs + 9 * int64_t(j);
-        for (int q = 0; q < 3; ++q) {
-            o[q] = af[q].value();
-            o[3 + q] = ah[q].value();
-            o[6 + q] = ay[q].value();
+        for (int q = 0; q < 9; ++q) {
+            double s = v[q];
+            for (int w = 0; w < SG_WAVES - 1; ++w) s += red[w][q][lane];
+            o[q] = s;
         }
     }
 }
@@ -655,9 +671,9 @@ void adjoint(Plan &pl, const double *w, double *gf, double *gh, double *gt, doub
         na.nitems = A.near_t.nitems;
         if (na.nitems > 0) {
             if (fp64)
-                hipLaunchKernelGGL(k_near_sgrad<double>, dim3(na.nitems), dim3(64), 0, s, na);
+                hipLaunchKernelGGL(k_near_sgrad<double>, dim3(na.nitems), dim3(64 * SG_WAVES), 0, s, na);
             else
-                hipLaunchKernelGGL(k_near_sgrad<float>, dim3(na.nitems), dim3(64), 0, s, na);
+                hipLaunchKernelGGL(k_near_sgrad<float>, dim3(na.nitems), dim3(64 * SG_WAVES), 0, s, na);
             STK_CHECK_LAUNCH();
         }
         hipLaunchKernelGGL(k_src_total, dim3(nblk(n, 256)), dim3(256), 0, s, part, nlev, n, gs,
