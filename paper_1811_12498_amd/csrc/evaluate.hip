@@ -34,7 +34,8 @@ struct TravArgs {
     // count pass outputs
     int32_t *gfar, *gnear;              // per group entry counts
     int32_t *cnt_far, *cnt_near, *cnt_pairs;  // per sorted target
-    unsigned long long *far_inc;        // total far (target, cluster) pairs, accumulated
+    unsigned long long *far_inc;        // total far (target, cluster) and near (target, leaf)
+                                        // pairs, accumulated (2 counters)
     // fill pass
     const int32_t *far_off, *near_off;
     int32_t *far_node, *near_node;
@@ -115,13 +116,17 @@ template <bool FILL> __global__ __launch_bounds__(64) void k_traverse(TravArgs a
         __syncthreads();
     }
     if (!FILL) {
-        int32_t gf = nf;  // the group's far pairs
+        int32_t gf = nf, gn = nnr;  // the group's far and near pairs
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) gf += __shfl_xor(gf, o);
+        for (int o = 32; o > 0; o >>= 1) {
+            gf += __shfl_xor(gf, o);
+            gn += __shfl_xor(gn, o);
+        }
         if (lane == 0) {
             a.gfar[g] = fo;
             a.gnear[g] = no;
             atomicAdd(a.far_inc, (unsigned long long)gf);
+            atomicAdd(a.far_inc + 1, (unsigned long long)gn);
         }
         if (valid) {
             a.cnt_far[t] = nf;
@@ -377,8 +382,8 @@ void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, dou
     ta.cnt_far = reserve<int32_t>(pl.cnt_far, size_t(m));
     ta.cnt_near = reserve<int32_t>(pl.cnt_near, size_t(m));
     ta.cnt_pairs = reserve<int32_t>(pl.cnt_pairs, size_t(m));
-    ta.far_inc = reserve<unsigned long long>(pl.far_inc, 1);
-    STK_HIP(hipMemsetAsync(ta.far_inc, 0, sizeof(unsigned long long), s));
+    ta.far_inc = reserve<unsigned long long>(pl.far_inc, 2);
+    STK_HIP(hipMemsetAsync(ta.far_inc, 0, 2 * sizeof(unsigned long long), s));
     hipLaunchKernelGGL(k_traverse<false>, dim3(ng), dim3(64), 0, s, ta);
     STK_CHECK_LAUNCH();
     int32_t *foff = reserve<int32_t>(pl.far_off, size_t(ng) + 1);
@@ -386,14 +391,17 @@ void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, dou
     scan_exclusive_i32(ta.gfar, foff, ng, t.s_scan, s);
     scan_exclusive_i32(ta.gnear, noff, ng, t.s_scan, s);
     int32_t tot[2];
-    unsigned long long far_inc = 0;
+    unsigned long long inc[2] = {0, 0};
     STK_HIP(hipMemcpyAsync(&tot[0], foff + ng, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     STK_HIP(hipMemcpyAsync(&tot[1], noff + ng, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    STK_HIP(hipMemcpyAsync(&far_inc, ta.far_inc, sizeof(far_inc), hipMemcpyDeviceToHost, s));
+    STK_HIP(hipMemcpyAsync(inc, ta.far_inc, sizeof(inc), hipMemcpyDeviceToHost, s));
     STK_HIP(hipStreamSynchronize(s));
     pl.n_far_entries = tot[0];
     pl.n_near_entries = tot[1];
-    pl.n_far_inc = int64_t(far_inc);
+    pl.n_far_inc = int64_t(inc[0]);
+    // the near field always runs on its cluster-major (leaf-major) view
+    if (int64_t(inc[1]) >= CM_MAX_INC)
+        throw Error(STK_EINVAL, "too many near-field (target, leaf) pairs for the leaf-major lists");
     ta.far_off = foff;
     ta.near_off = noff;
     ta.far_node = reserve<int32_t>(pl.far_node, size_t(tot[0]) + 1);
@@ -423,7 +431,7 @@ void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, dou
                         (pl.tiles.far_cm == FAR_CM_ON || (pl.tiles.far_cm == FAR_CM_AUTO && util < FAR_CM_UTIL));
     if (pl.tiles.far_cm == FAR_CM_ON && !cm_fits)
         throw Error(STK_EINVAL, "far_cm: too many far interactions for the cluster-major lists");
-    const int sparse_max = all_cm ? 64 : (K == 1 ? FAR_SPARSE_MAX : 0);
+    const int sparse_max = all_cm ? 64 : (K == 1 && cm_fits ? FAR_SPARSE_MAX : 0);
     if (sparse_max > 0) far_sparse(t, pl, unear, sparse_max, s);
     pl.far_sparse_max = sparse_max;
     FarArgs fa{tpos, m, foff, ta.far_node, ta.far_mask, t.ncenter.as<double>(), t.nrho.as<double>(), t.wblk.p,

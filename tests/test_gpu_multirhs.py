@@ -175,3 +175,16 @@ def test_far_cluster_major_fp64_matches_oracle(nat, orc):
         M, Mt = orc.moments(T, w.src, w.f[r], w.h[r], w.nu, p)
         ref = orc.treecode(T, w.src, w.f[r], w.h[r], w.nu, M, Mt, p, theta, tg)
         assert orc.rel_l2(u[r].cpu().numpy(), ref.u) < 1e-12, r
+
+
+@pytest.mark.parametrize("kind", ["cube", "sphere"])
+def test_far_schedule_automatic_rule(nat, kind):
+    """Tile far_cm = 0: every far entry runs cluster major exactly when the far group lists'
+    lane masks are less than 75% full on average; otherwise (one right-hand side) only the
+    entries with at most 32 targets."""
+    w = W.cube(60_000, seed=93, n0=2000) if kind == "cube" else W.sphere(60_000, seed=94, n0=1000)
+    X = _t(w.src)
+    u, plan = nat.evaluate(X, X, _t(w.f[0]), _t(w.h[0]), _t(w.nu), 6, 0.5, w.n0, "mixed", keep_plan=True)
+    assert nat.plan_tiles(plan)["far_cm"] == 0
+    util = nat.plan_counts(plan)[0].sum() / (64.0 * nat.plan_info(plan)["far_entries"])
+    assert nat.plan_far_split(plan)[0] == (64 if util < 0.75 else 32), util
