@@ -43,7 +43,6 @@ struct LambdaArgs {
     int32_t nitems;
 };
 
-constexpr int LPITCH = 65;   // LDS row pitch (targets), padded against bank conflicts
 
 // The LDS columns of k_far_lambda (one value per target lane) in the order they are
 // formed: the G column of order 0, then per order n = 1 .. p + 2 the G columns of order n
@@ -54,9 +53,15 @@ constexpr int LPITCH = 65;   // LDS row pitch (targets), padded against bank con
 // FP64 keep the LDS of a block small enough for more blocks per CU).
 template <typename T> __host__ __device__ constexpr int lam_tbl() { return sizeof(T) == 8 ? 16 : 32; }
 constexpr int LAM_TBL_MAX = 32;  // host column tables are padded to whole batches of this
-// weight table pitch and position: one pad value after each run of lam_tbl targets
-template <typename T> __host__ __device__ constexpr int lam_wp() { return 64 + 64 / lam_tbl<T>(); }
-template <typename T> __host__ __device__ constexpr int lam_wid(int t) { return t + t / lam_tbl<T>(); }
+// values per 16-byte LDS read
+template <typename T> __host__ __device__ constexpr int lam_nv() { return 16 / int(sizeof(T)); }
+// column row pitch (targets): 16-byte aligned rows whose 16-byte reads by consecutive
+// columns fall in distinct banks
+template <typename T> __host__ __device__ constexpr int lam_pitch() { return 64 + lam_nv<T>(); }
+// weight table pitch and position: 16 pad bytes after each run of lam_tbl targets, so that
+// every run starts 16-byte aligned and the runs read at once fall in distinct banks
+template <typename T> __host__ __device__ constexpr int lam_wp() { return 64 + (64 / lam_tbl<T>()) * lam_nv<T>(); }
+template <typename T> __host__ __device__ constexpr int lam_wid(int t) { return t + (t / lam_tbl<T>()) * lam_nv<T>(); }
 __host__ __device__ constexpr int lam_ncol(int p) { return 2 * nidx(p + 1); }
 // first column of the G columns of order n (n >= 0; past the last one for n > p + 1)
 __host__ __device__ constexpr int lam_gbase(int p, int n) {
@@ -79,7 +84,7 @@ __host__ __device__ constexpr int lam_gcol(int p, int k1, int k2, int k3) {
 // LDS of one work item: the stream accumulator (evaluation precision), one batch of
 // columns and the two weight tables
 template <int P, typename T> __host__ __device__ constexpr size_t lam_lds_bytes() {
-    return sizeof(T) * (6 * size_t(nidx(P + 1)) + size_t(lam_tbl<T>()) * LPITCH + 6 * size_t(lam_wp<T>()));
+    return sizeof(T) * (6 * size_t(nidx(P + 1)) + size_t(lam_tbl<T>()) * lam_pitch<T>() + 6 * size_t(lam_wp<T>()));
 }
 
 // ---------------------------------------------------------------------------------

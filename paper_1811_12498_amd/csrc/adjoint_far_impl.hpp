@@ -67,7 +67,9 @@ template <int PB, typename T, class Visit> struct Coefs {
 template <int P, typename T> struct LambdaVisit {
     static constexpr int NCOL = lam_ncol(P);
     static constexpr int TBL = lam_tbl<T>(), WP = lam_wp<T>();
-    T *cols;       // [TBL][LPITCH]: the current batch
+    static constexpr int PITCH = lam_pitch<T>(), NV = lam_nv<T>();
+    using V = std::conditional_t<sizeof(T) == 4, float4, double2>;  // one 16-byte LDS read
+    T *cols;       // [TBL][PITCH]: the current batch
     const T *cw;   // [3][WP] w_i / R per target (0 for idle lanes), at lam_wid(target)
     const T *dw;   // [3][WP] dh_l per target (0 for idle lanes)
     T *acc;        // [6 nG] LDS accumulator in stream order
@@ -86,14 +88,29 @@ template <int P, typename T> struct LambdaVisit {
         if (on) {
             const int c = bt * TBL + col;
             p0 = cpos[c];
+            // rows and weight runs are 16-byte aligned: NV values per LDS read
             const T *wt = (ckind[c] ? dw : cw) + lam_wid<T>(t0);
-            const T *row = cols + col * LPITCH + t0;
-#pragma unroll 8
-            for (int mm = 0; mm < TBL; ++mm) {
-                const T v = row[mm];
-                a0 += wt[mm] * v;
-                a1 += wt[WP + mm] * v;
-                a2 += wt[2 * WP + mm] * v;
+            const T *row = cols + col * PITCH + t0;
+#pragma unroll 2
+            for (int mm = 0; mm < TBL; mm += NV) {
+                const V rv = *reinterpret_cast<const V *>(row + mm);
+                const V w0 = *reinterpret_cast<const V *>(wt + mm);
+                const V w1 = *reinterpret_cast<const V *>(wt + WP + mm);
+                const V w2 = *reinterpret_cast<const V *>(wt + 2 * WP + mm);
+                a0 += w0.x * rv.x;
+                a1 += w1.x * rv.x;
+                a2 += w2.x * rv.x;
+                a0 += w0.y * rv.y;
+                a1 += w1.y * rv.y;
+                a2 += w2.y * rv.y;
+                if constexpr (NV == 4) {
+                    a0 += w0.z * rv.z;
+                    a1 += w1.z * rv.z;
+                    a2 += w2.z * rv.z;
+                    a0 += w0.w * rv.w;
+                    a1 += w1.w * rv.w;
+                    a2 += w2.w * rv.w;
+                }
             }
         }
 #pragma unroll
@@ -112,7 +129,7 @@ template <int P, typename T> struct LambdaVisit {
 
     // write column COL; reduce its batch when COL completes it
     template <int COL> STK_HD void put(T v) {
-        cols[(COL % TBL) * LPITCH + lane] = v;
+        cols[(COL % TBL) * PITCH + lane] = v;
         if constexpr (COL % TBL == TBL - 1)
             reduce(TBL, COL / TBL);
         else if constexpr (COL == NCOL - 1)
@@ -151,7 +168,7 @@ template <int P, typename T> __global__ __launch_bounds__(64) void k_far_lambda(
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T *acc = reinterpret_cast<T *>(lds_raw);
     T *cols = acc + 6 * NG;
-    T *cw = cols + lam_tbl<T>() * LPITCH;
+    T *cw = cols + lam_tbl<T>() * lam_pitch<T>();
     T *dw = cw + 3 * lam_wp<T>();
     const int lane = threadIdx.x;
     const int32_t it = blockIdx.x;
