@@ -64,6 +64,35 @@ template <int PB, typename T, class Visit> struct Coefs {
     }
 };
 
+// x + (x of lane ^ o) in every lane, o = 16 or 32, through the VALU's lane-half swaps (the
+// two outputs of a swap of x with itself hold x and its partner in opposite halves, so their
+// sum is the pair sum whatever the orientation)
+STK_HD inline float pair_sum(float x, int o) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const unsigned u = __float_as_uint(x);
+    const auto r = o == 32 ? __builtin_amdgcn_permlane32_swap(u, u, false, false)
+                           : __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+#else
+    return x + __shfl_xor(x, o);
+#endif
+}
+STK_HD inline double pair_sum(double x, int o) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const unsigned long long b = __double_as_longlong(x);
+    const unsigned lo = unsigned(b), hi = unsigned(b >> 32);
+    const auto l = o == 32 ? __builtin_amdgcn_permlane32_swap(lo, lo, false, false)
+                           : __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h = o == 32 ? __builtin_amdgcn_permlane32_swap(hi, hi, false, false)
+                           : __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    const double x0 = __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(h[0]) << 32) | l[0]));
+    const double x1 = __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(h[1]) << 32) | l[1]));
+    return x0 + x1;
+#else
+    return x + __shfl_xor(x, o);
+#endif
+}
+
 template <int P, typename T> struct LambdaVisit {
     static constexpr int NCOL = lam_ncol(P);
     static constexpr int TBL = lam_tbl<T>(), WP = lam_wp<T>();
@@ -113,11 +142,12 @@ template <int P, typename T> struct LambdaVisit {
                 }
             }
         }
+        static_assert(TBL >= 16, "runs are combined by 16- and 32-lane swaps");
 #pragma unroll
         for (int o = TBL; o < 64; o <<= 1) {
-            a0 += __shfl_xor(a0, o);
-            a1 += __shfl_xor(a1, o);
-            a2 += __shfl_xor(a2, o);
+            a0 = pair_sum(a0, o);
+            a1 = pair_sum(a1, o);
+            a2 = pair_sum(a2, o);
         }
         if (on && run == 0) {
             acc[p0] += a0;
