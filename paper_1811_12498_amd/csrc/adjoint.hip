@@ -176,7 +176,9 @@ template <typename T> __global__ __launch_bounds__(64 * SG_WAVES) void k_near_sg
     __shared__ double red[SG_WAVES - 1][9][64];
     const int32_t it = blockIdx.x;
     if (it >= a.nitems) return;
-    const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
+    // the wave index made visibly wave-uniform: the entry range, masks and target loads of
+    // the loop below then stay scalar
+    const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x / 64)), lane = threadIdx.x % 64;
     const int32_t c = a.item_node[it];
     const int32_t j = a.item_j0[it] + lane;
     const bool valid = j < a.start[c] + a.count[c];
