@@ -34,8 +34,7 @@ struct TravArgs {
     // count pass outputs
     int32_t *gfar, *gnear;              // per group entry counts
     int32_t *cnt_far, *cnt_near, *cnt_pairs;  // per sorted target
-    unsigned long long *far_inc;        // total far (target, cluster) and near (target, leaf)
-                                        // pairs, accumulated (2 counters)
+    int32_t *gpf, *gpn;                 // per group far (target, cluster) / near (target, leaf) pairs
     // fill pass
     const int32_t *far_off, *near_off;
     int32_t *far_node, *near_node;
@@ -125,14 +124,39 @@ template <bool FILL> __global__ __launch_bounds__(64) void k_traverse(TravArgs a
         if (lane == 0) {
             a.gfar[g] = fo;
             a.gnear[g] = no;
-            atomicAdd(a.far_inc, (unsigned long long)gf);
-            atomicAdd(a.far_inc + 1, (unsigned long long)gn);
+            a.gpf[g] = gf;
+            a.gpn[g] = gn;
         }
         if (valid) {
             a.cnt_far[t] = nf;
             a.cnt_near[t] = nnr;
             a.cnt_pairs[t] = npr;
         }
+    }
+}
+
+// one block: out[0] = sum of a[0..n), out[1] = sum of b[0..n), in int64
+__global__ __launch_bounds__(1024) void k_sum2_i64(const int32_t *__restrict__ a, const int32_t *__restrict__ b,
+                                                   int32_t n, long long *__restrict__ out) {
+    __shared__ long long red[2][1024];
+    long long sa = 0, sb = 0;
+    for (int32_t i = threadIdx.x; i < n; i += 1024) {
+        sa += a[i];
+        sb += b[i];
+    }
+    red[0][threadIdx.x] = sa;
+    red[1][threadIdx.x] = sb;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if (int(threadIdx.x) < o) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + o];
+            red[1][threadIdx.x] += red[1][threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = red[0][0];
+        out[1] = red[1][0];
     }
 }
 
@@ -376,25 +400,28 @@ void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, dou
     ta.nchild = t.nnchild.as<int32_t>();
     ta.count = t.ncount.as<int32_t>();
     ta.theta = theta;
-    int32_t *gcnt = reserve<int32_t>(t.s_vals, size_t(ng) * 2);
+    int32_t *gcnt = reserve<int32_t>(t.s_vals, size_t(ng) * 4);
     ta.gfar = gcnt;
     ta.gnear = gcnt + ng;
+    ta.gpf = gcnt + 2 * size_t(ng);
+    ta.gpn = gcnt + 3 * size_t(ng);
     ta.cnt_far = reserve<int32_t>(pl.cnt_far, size_t(m));
     ta.cnt_near = reserve<int32_t>(pl.cnt_near, size_t(m));
     ta.cnt_pairs = reserve<int32_t>(pl.cnt_pairs, size_t(m));
-    ta.far_inc = reserve<unsigned long long>(pl.far_inc, 2);
-    STK_HIP(hipMemsetAsync(ta.far_inc, 0, 2 * sizeof(unsigned long long), s));
     hipLaunchKernelGGL(k_traverse<false>, dim3(ng), dim3(64), 0, s, ta);
+    STK_CHECK_LAUNCH();
+    long long *inc_d = reserve<long long>(pl.far_inc, 2);
+    hipLaunchKernelGGL(k_sum2_i64, dim3(1), dim3(1024), 0, s, ta.gpf, ta.gpn, ng, inc_d);
     STK_CHECK_LAUNCH();
     int32_t *foff = reserve<int32_t>(pl.far_off, size_t(ng) + 1);
     int32_t *noff = reserve<int32_t>(pl.near_off, size_t(ng) + 1);
     scan_exclusive_i32(ta.gfar, foff, ng, t.s_scan, s);
     scan_exclusive_i32(ta.gnear, noff, ng, t.s_scan, s);
     int32_t tot[2];
-    unsigned long long inc[2] = {0, 0};
+    long long inc[2] = {0, 0};
     STK_HIP(hipMemcpyAsync(&tot[0], foff + ng, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     STK_HIP(hipMemcpyAsync(&tot[1], noff + ng, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    STK_HIP(hipMemcpyAsync(inc, ta.far_inc, sizeof(inc), hipMemcpyDeviceToHost, s));
+    STK_HIP(hipMemcpyAsync(inc, inc_d, sizeof(inc), hipMemcpyDeviceToHost, s));
     STK_HIP(hipStreamSynchronize(s));
     pl.n_far_entries = tot[0];
     pl.n_near_entries = tot[1];

@@ -173,7 +173,7 @@ struct Plan {
     DBuf far_node, near_node;      // int32 entries
     DBuf far_mask, near_mask;      // uint64 entries (lane masks of the 64-target group)
     DBuf cnt_far, cnt_near, cnt_pairs;  // int32 per sorted target
-    DBuf far_inc;                       // uint64 (2): far (target, cluster) and near (target, leaf) pairs
+    DBuf far_inc;                       // int64 (2): far (target, cluster) and near (target, leaf) pairs
     int64_t n_far_entries = 0, n_near_entries = 0, n_far_inc = 0;
     // cluster-major views of the group lists: the near field (every near entry) and, for
     // one right-hand side, the far entries that apply to few targets of their group
