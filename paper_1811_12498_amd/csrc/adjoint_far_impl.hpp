@@ -242,6 +242,7 @@ template <int P, typename T> struct TgradVisit {
     const T *W;   // cluster stream
     T dh[3], wl[3];
     T a1[3], a2[3], a3[3];
+    T lag;        // the sums as they stood one layer back
 
     template <int Q, int N> STK_HD void coef(T) {}
     template <int N> STK_HD void order_done(const T (&)[nidx(P + 3)]) {}
@@ -254,8 +255,10 @@ template <int P, typename T> struct TgradVisit {
     // so each layer of order N is last read two layers later and the coefficients alive
     // at a time are three layers of the current order plus those the recurrence keeps
     template <int N, int J> STK_HD void layer_done(const T (&b)[nidx(P + 3)]) {
-        // the fence pins this layer's scalar loads after the previous layer's sums
-        const T *__restrict__ Wf = W + FarEval<P, T>::fence(a1[0] + a2[0] + a3[0]);
+        // the fence pins this layer's scalar loads after the sums of two layers back, so they
+        // can be in flight while the previous layer is consumed
+        const T *__restrict__ Wf = W + FarEval<P, T>::fence(lag);
+        lag = a1[0] + a2[0] + a3[0];
         if constexpr (J >= 1 && N - 1 <= P + 1) walk13<N - 1, J - 1, N - J>(b, Wf);
         if constexpr (J >= 2 && N - 2 <= P + 1) walk2<N - 2, J - 2, N - J>(b, Wf);
     }
@@ -330,7 +333,8 @@ template <int P, typename T> __global__ __launch_bounds__(64, sizeof(T) == 4 ? 4
                        {T(a.ws[3 * t]), T(a.ws[3 * t + 1]), T(a.ws[3 * t + 2])},
                        {T(0), T(0), T(0)},
                        {T(0), T(0), T(0)},
-                       {T(0), T(0), T(0)}};
+                       {T(0), T(0), T(0)},
+                       T(0)};
     T b[nidx(P + 3)];
     Coefs<P + 3, T, TgradVisit<P, T>>::run(b, v.dh, T(rho * rinv), v);
     const T f1 = T(-rinv / rho), f2 = T(-1.0 / rho), f3 = T(rinv);
