@@ -55,6 +55,49 @@ void check_common(const double *pts, int64_t n, const char *what) {
     stk::require(n < (int64_t(1) << 31) / 8, std::string(what) + ": count too large (int32 indexing)");
 }
 
+// A second stream per device, on which stk_evaluate computes the moments while the caller's
+// stream sorts the targets and builds the interaction lists (default priority; created on
+// first use, kept until the process exits).
+hipStream_t side_stream(int dev) {
+    static std::mutex mu;
+    static std::vector<hipStream_t> *streams = new std::vector<hipStream_t>();
+    std::lock_guard<std::mutex> lk(mu);
+    if (size_t(dev) >= streams->size()) streams->resize(size_t(dev) + 1, nullptr);
+    hipStream_t &sd = (*streams)[size_t(dev)];
+    if (!sd) STK_HIP(hipStreamCreateWithFlags(&sd, hipStreamNonBlocking));
+    return sd;
+}
+
+// Tree on the caller's stream, then the moments on the side stream (after the tree and
+// everything queued before it) while the evaluation proceeds; the evaluation waits for
+// them before its near field.
+void tree_moments_evaluate(stk::Tree &tree, stk::Plan &pl, const double *targets, int64_t m, const double *sources,
+                           int64_t n, const double *f, const double *h, const double *nu, int32_t k_rhs, int32_t p,
+                           double theta, int32_t n0, stk_precision prec, double *u_out, bool same, hipStream_t s) {
+    stk::build_tree(tree, sources, n, n0, s);
+    hipStream_t s2 = side_stream(tree.device);
+    hipEvent_t built = nullptr, ready = nullptr;
+    STK_HIP(hipEventCreateWithFlags(&built, hipEventDisableTiming));
+    STK_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    try {
+        STK_HIP(hipEventRecord(built, s));
+        STK_HIP(hipStreamWaitEvent(s2, built, 0));
+        stk::compute_moments(tree, f, h, nu, k_rhs, p, prec, s2);
+        STK_HIP(hipEventRecord(ready, s2));
+        pl.moments_ready = ready;
+        stk::evaluate(tree, pl, targets, m, theta, u_out, same, s);
+    } catch (...) {
+        pl.moments_ready = nullptr;
+        (void)hipStreamSynchronize(s2);
+        (void)hipEventDestroy(built);
+        (void)hipEventDestroy(ready);
+        throw;
+    }
+    pl.moments_ready = nullptr;
+    (void)hipEventDestroy(built);
+    (void)hipEventDestroy(ready);
+}
+
 // Plans that own their tree, parked by stk_plan_destroy for the next stk_evaluate with
 // keep_plan on the same device: their buffers keep their capacity, so a loop of
 // forward + adjoint calls allocates and frees no device memory after the first pass
@@ -210,9 +253,8 @@ stk_status stk_evaluate(const double *targets, int64_t m, const double *sources,
                 ws_plan = new stk_plan();
                 ws_tree->device = dev;
             }
-            stk::build_tree(*ws_tree, sources, n, n0, s);
-            stk::compute_moments(*ws_tree, f, h, nu, k_rhs, p, prec, s);
-            stk::evaluate(*ws_tree, ws_plan->p, targets, m, theta, u_out, same, s);
+            tree_moments_evaluate(*ws_tree, ws_plan->p, targets, m, sources, n, f, h, nu, k_rhs, p, theta, n0, prec,
+                                  u_out, same, s);
             STK_HIP(hipStreamSynchronize(s));
             return;
         }
@@ -223,10 +265,8 @@ stk_status stk_evaluate(const double *targets, int64_t m, const double *sources,
             pl->p.owns_tree = true;
             pl->p.tree->device = dev;
         }
-        stk::Tree &tree = *pl->p.tree;
-        stk::build_tree(tree, sources, n, n0, s);
-        stk::compute_moments(tree, f, h, nu, k_rhs, p, prec, s);
-        stk::evaluate(tree, pl->p, targets, m, theta, u_out, same, s);
+        tree_moments_evaluate(*pl->p.tree, pl->p, targets, m, sources, n, f, h, nu, k_rhs, p, theta, n0, prec, u_out,
+                              same, s);
         *keep_plan = pl.release();
     });
 }

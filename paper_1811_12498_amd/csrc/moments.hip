@@ -300,7 +300,7 @@ void compute_moments(Tree &t, const double *f, const double *h, const double *nu
                            t.perm.as<int32_t>(), t.n, K, f, h, nu, t.geo.as<double>(), t.wts.as<float>(), w12);
     STK_CHECK_LAUNCH();
 
-    double *part = reserve<double>(t.s_tmp, size_t(t.nleafchunks) * K * nm * 12 + 1);
+    double *part = reserve<double>(t.mom_part, size_t(t.nleafchunks) * K * nm * 12 + 1);
     const int A = (nm + 63) / 64;
     switch (A) {
         case 1: launch_moments<1>(t, K, p, nm, w12, part, s); break;

@@ -557,6 +557,12 @@ void near_field(Tree &t, Plan &pl, double *unear, hipStream_t s) {
     cluster_major(t, cm, pl.near_off.as<int32_t>(), pl.near_node.as<int32_t>(), pl.near_mask.as<uint64_t>(),
                   pl.n_near_entries, pl.ngroups, m, 64, pl.cnt_near.as<int32_t>(), s);
     prof_mark(STK_PHASE_LISTS, s);
+    // moments computed beside the lists (on another stream) must be complete from here on:
+    // the near field reads their source records, the far field their streams
+    if (pl.moments_ready) {
+        STK_HIP(hipStreamWaitEvent(s, pl.moments_ready, 0));
+        pl.moments_ready = nullptr;
+    }
     const int32_t *ileaf = cm.item_node.as<int32_t>(), *i0 = cm.item_i0.as<int32_t>(), *i1 = cm.item_i1.as<int32_t>();
     const int32_t *inc_tgt = cm.inc_tgt.as<int32_t>(), *inc_slot = cm.inc_slot.as<int32_t>();
     const int32_t *toff = cm.toff.as<int32_t>();

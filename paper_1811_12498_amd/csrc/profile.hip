@@ -1,6 +1,6 @@
-// Phase timing: while enabled, the library records a HIP event on the caller's stream
-// at the start of each entry point and after each phase, so the elapsed time of a
-// phase is measured on the stream its kernels ran on.
+// Phase timing: while enabled, the library records a HIP event on a stream at the start
+// of each entry point (or of work it moves to another stream) and after each phase; a
+// phase's time is measured from the previous mark on the same stream.
 #include <mutex>
 
 #include "stk_internal.hpp"
@@ -11,6 +11,7 @@ namespace {
 struct Mark {
     int phase;  // -1 = start of an entry point
     hipEvent_t ev;
+    hipStream_t s;
 };
 
 std::mutex g_mu;
@@ -25,7 +26,7 @@ void prof_mark(int phase, hipStream_t s) {
     hipEvent_t e;
     STK_HIP(hipEventCreate(&e));
     STK_HIP(hipEventRecord(e, s));
-    g_marks.push_back({phase, e});
+    g_marks.push_back({phase, e, s});
 }
 
 void prof_enable(bool on) {
@@ -41,9 +42,12 @@ void prof_read(double *ms, int64_t *count) {
     }
     for (size_t i = 0; i < g_marks.size(); ++i) {
         STK_HIP(hipEventSynchronize(g_marks[i].ev));
-        if (g_marks[i].phase < 0 || i == 0) continue;
+        if (g_marks[i].phase < 0) continue;
+        size_t j = i;  // the previous mark on the same stream
+        while (j > 0 && g_marks[j - 1].s != g_marks[i].s) --j;
+        if (j == 0) continue;
         float t = 0.f;
-        STK_HIP(hipEventElapsedTime(&t, g_marks[i - 1].ev, g_marks[i].ev));
+        STK_HIP(hipEventElapsedTime(&t, g_marks[j - 1].ev, g_marks[i].ev));
         const int p = g_marks[i].phase;
         if (p < STK_NPHASES) {
             if (ms) ms[p] += t;

@@ -99,6 +99,7 @@ struct Tree {
     stk_precision prec = STK_FP64;
     DBuf mom;     // double (nn, nm, 12*K): channels 0..2 = M_j, 3..11 = Mt_jl (3 + 3j + l)
     DBuf mom_up;  // double, as mom: each node's moments moved to its parent's centre
+    DBuf mom_part;  // double: the leaves' chunk partials (moments may run beside an evaluation)
     DBuf wblk;    // T (nn, nb, 12*K): scaled far-field channel blocks
     DBuf geo;     // double (n, 6): sorted (y, nu) per source
     DBuf wts;     // T (n, K, 6): sorted (f, h) per source and right-hand side
@@ -181,6 +182,7 @@ struct Plan {
     int32_t far_sparse_max = 0;       // threshold of the last evaluation's sparse far split
     Tiles tiles;                      // kernel variants used by the last evaluation
     bool forced = false;              // use `force` instead of the table (autotuning)
+    hipEvent_t moments_ready = nullptr;  // if set, the evaluation's stream waits on it before the near field
     Tiles force;
     AdjScratch adj;
     ~Plan();
