@@ -65,3 +65,24 @@ def test_reused_plans_match_fresh(nat):
             d = np.linalg.norm(got[key] - ref[key]) / np.linalg.norm(ref[key])
             assert d < 1e-12, (case, key, d)
     nat.plan_cache_clear()
+
+
+def test_caller_stream_ordering(nat):
+    """stk_evaluate computes the moments on a second stream: inputs written by the caller's
+    stream just before the call are seen (the second stream waits for the caller's queued
+    work), and the result is complete on the caller's stream when it returns."""
+    import torch
+    w = W.cube(40_000, seed=66, n0=300)
+    X = _t(w.src)
+    F0, H0, NU = _t(w.f[0]), _t(w.h[0]), _t(w.nu)
+    ref = nat.evaluate(X, X, 2.0 * F0, H0 - 1.0, NU, 6, 0.5, 300, "mixed")
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for _ in range(3):
+            F = 2.0 * F0          # produced on s, immediately consumed by the library
+            H = H0 - 1.0
+            u = nat.evaluate(X, X, F, H, NU, 6, 0.5, 300, "mixed")
+            v = u * 1.0           # consumed on s right after the call
+    s.synchronize()
+    assert torch.equal(v, ref)
