@@ -60,6 +60,13 @@ template <bool FILL> __global__ __launch_bounds__(64) void k_traverse(TravArgs a
         fo = a.far_off[g];
         no = a.near_off[g];
     }
+    // the node table is read only: through the constant address space its loads at the
+    // wave-uniform node index stay scalar even in the fill pass, which stores lists
+    const STK_CONST_AS double *cen = (const STK_CONST_AS double *)(a.center);
+    const STK_CONST_AS double *rad = (const STK_CONST_AS double *)(a.radius);
+    const STK_CONST_AS int32_t *nch = (const STK_CONST_AS int32_t *)(a.nchild);
+    const STK_CONST_AS int32_t *ch0 = (const STK_CONST_AS int32_t *)(a.child0);
+    const STK_CONST_AS int32_t *cnt = (const STK_CONST_AS int32_t *)(a.count);
     const uint64_t vmask = __ballot(valid);
     if (lane == 0) {
         st_node[0] = 0;
@@ -72,13 +79,16 @@ template <bool FILL> __global__ __launch_bounds__(64) void k_traverse(TravArgs a
         const int32_t c = __builtin_amdgcn_readfirstlane(st_node[sp]);
         const uint64_t mk = rfl64(st_mask[sp]);
         __syncthreads();
+        // every field of the node is requested at once: one round trip per visit
+        const double y0 = cen[3 * c], y1 = cen[3 * c + 1], y2 = cen[3 * c + 2], rc = rad[c];
+        const int32_t k = nch[c], c0 = ch0[c], nc = cnt[c];
         const bool in = (mk >> lane) & 1ull;
         bool accept = false;
         {
 #pragma clang fp contract(off)
-            const double d0 = x0 - a.center[3 * c], d1 = x1 - a.center[3 * c + 1], d2 = x2 - a.center[3 * c + 2];
+            const double d0 = x0 - y0, d1 = x1 - y1, d2 = x2 - y2;
             const double R = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-            accept = in && R > 0.0 && a.radius[c] <= a.theta * R;
+            accept = in && R > 0.0 && rc <= a.theta * R;
         }
         const uint64_t am = __ballot(accept);
         const uint64_t rm = mk & ~am;
@@ -91,7 +101,6 @@ template <bool FILL> __global__ __launch_bounds__(64) void k_traverse(TravArgs a
             nf += accept;
         }
         if (rm) {
-            const int32_t k = a.nchild[c];
             if (k == 0) {
                 if (FILL && lane == 0) {
                     a.near_node[no] = c;
@@ -100,10 +109,9 @@ template <bool FILL> __global__ __launch_bounds__(64) void k_traverse(TravArgs a
                 ++no;
                 if ((rm >> lane) & 1ull) {
                     ++nnr;
-                    npr += a.count[c];
+                    npr += nc;
                 }
             } else {
-                const int32_t c0 = a.child0[c];
                 if (lane == 0)
                     for (int32_t j = k - 1; j >= 0; --j) {
                         st_node[sp + (k - 1 - j)] = c0 + j;
