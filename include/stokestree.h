@@ -115,7 +115,13 @@ stk_status stk_evaluate_tree(stk_tree *t, const double *targets, int64_t m, doub
 
 /* One call: build the tree, compute moments and evaluate (eq. StoStre by
  * Algorithm 1).  Arguments as above; if keep_plan is non-NULL the plan owns the
- * tree it was built on. */
+ * tree it was built on.  The moments are computed on a second stream of the
+ * library's (one per device, default priority, kept until the process ends) that
+ * waits for `stream`'s work up to the tree and that `stream` waits for before the
+ * near field, so f, h and nu follow the same rule as the other inputs and all work
+ * of the call is ordered before what the caller enqueues on `stream` after it.
+ * Concurrent calls from several host threads on one device share that stream:
+ * their moments run one after another. */
 stk_status stk_evaluate(const double *targets, int64_t m, const double *sources, int64_t n, const double *f,
                         const double *h, const double *nu, int32_t k_rhs, int32_t p, double theta, int32_t n0,
                         stk_precision prec, double *u_out, stk_plan **keep_plan, void *stream);
