@@ -3,9 +3,9 @@
 This module only draws random numbers; it holds none of the method's arithmetic.
 It is the one piece shared by the HIP path's tests/benchmark and the oracle checks.
 
-Shapes follow Sec. 6 of Wang, Tlupova & Krasny: points on the unit sphere with the
-outward normal as nu (test case 1, here random points instead of the icosahedral
-centroids) and random points in a cube (test case 2).  All draws use
+Shapes follow Sec. 6 of Wang, Tlupova & Krasny: points on the unit sphere (test case 1:
+the icosahedral centroids, nu random unit vectors; the benchmark's random sphere points
+take the outward normal as nu) and random points in a cube (test case 2).  All draws use
 ``numpy.random.default_rng(seed)`` (PCG64) in FP64, in this order: positions, f, h,
 nu, w (when asked), then the sampled target indices.
 """
@@ -138,13 +138,19 @@ def icosahedral_points(level: int) -> np.ndarray:
 
 
 def ico_sphere(level: int, seed: int, n_sample: int = 0, p: int = 8, theta: float = 0.5,
-               n0: int = 2000, stresslet: bool = True, name: str = "icosphere") -> Workload:
-    """Test case 1 of Sec. 6: icosahedral centroids, nu = outward normal, f, h ~ U[-1, 1]^3."""
+               n0: int = 2000, stresslet: bool = True, nu: str = "random",
+               name: str = "icosphere") -> Workload:
+    """Test case 1 of Sec. 6: icosahedral centroids, f, h ~ U[-1, 1]^3.  The test case
+    gives f and h but not nu; nu = "random" draws unit vectors (normalised Gaussians, after
+    h), the reading under which the paper's Table 1 error levels are reproduced;
+    nu = "normal" uses the outward normal (the point itself) and draws nothing for it."""
+    if nu not in ("random", "normal"):
+        raise ValueError(f"nu must be 'random' or 'normal', not {nu!r}")
     rng = np.random.default_rng(seed)
     src = icosahedral_points(level)
     n = src.shape[0]
     f = rng.uniform(-1.0, 1.0, size=(1, n, 3))
     h = rng.uniform(-1.0, 1.0, size=(1, n, 3)) if stresslet else np.zeros((1, n, 3))
-    nu = src.copy()
+    nrm = _unit_gauss(rng, n) if nu == "random" else src.copy()
     sample = np.sort(rng.choice(n, n_sample, replace=False)) if n_sample else None
-    return Workload(name, src, f, h, nu, p, theta, n0, None, sample)
+    return Workload(name, src, f, h, nrm, p, theta, n0, None, sample, meta={"nu": nu})
