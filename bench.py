@@ -171,7 +171,8 @@ def multi_rhs_times(reps=3):
 def table1_icosphere(levels=(6, 7, 8), thetas=(0.2, 0.5, 0.8), ps=(0, 2, 4, 6, 8, 10), reps=2):
     """Test case 1 of Sec. 6 in the regime of the paper's Table 1: Stokeslets and stresslets
     at the centroids of the level-L refined icosahedron (N = 20 * 4^L) on the unit sphere,
-    nu = outward normal, f, h ~ U[-1, 1]^3 (seed 11), N0 = 2000.  Per (N, theta, p) and
+    f, h ~ U[-1, 1]^3 and nu random unit vectors (seed 11; the reading under which the
+    oracle reproduces Table 1), N0 = 2000.  Per (N, theta, p) and
     precision: the treecode time (one stk_evaluate: tree, moments, lists, near and far
     field), its error E over all N targets against the FP64 direct sum on the GPU, and the
     speedup d/t over that direct sum's time."""
@@ -207,7 +208,7 @@ def table1_icosphere(levels=(6, 7, 8), thetas=(0.2, 0.5, 0.8), ps=(0, 2, 4, 6, 8
                     rows.append({"N": w.n, "theta": theta, "p": p, "precision": prec, "ms": round(ms, 3),
                                  "d_over_t": round(d_ms / ms, 2), "E": e})
             log(f"table1: N={w.n} theta={theta} done")
-    return {"workload": "icosahedral sphere (Sec. 6 test case 1), S+T, nu = normal, N0 = 2000, E over all N "
+    return {"workload": "icosahedral sphere (Sec. 6 test case 1), S+T, nu = random unit, N0 = 2000, E over all N "
                         "targets vs the FP64 GPU direct sum", "direct_ms": direct_ms, "rows": rows}
 
 

@@ -1,5 +1,5 @@
 """Test case 1 of Sec. 6 on the GPU (icosahedral sphere, Stokeslets and stresslets,
-nu = outward normal): the full-N error E of the treecode against the FP64 direct sum,
+nu random unit vectors): the full-N error E of the treecode against the FP64 direct sum,
 both computed on the GPU, equals the oracle's E (its treecode against its direct sum over
 all targets), and the GPU treecode and direct sum match the oracle's element by element."""
 import numpy as np
