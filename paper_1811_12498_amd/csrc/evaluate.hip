@@ -209,13 +209,14 @@ __global__ void k_gather3(const double *__restrict__ src, const int32_t *__restr
 }
 
 // ---- FP64 direct sum -----------------------------------------------------------------
-// grid (target groups, source chunks); each wave sums one source chunk for 64 targets
-constexpr int DCH = 8192;
-
+// grid (target groups, source chunks); each wave sums one chunk of `chunk` consecutive
+// sources for 64 targets and writes its partial velocities, which k_direct_reduce adds
+// in chunk order
 __global__ __launch_bounds__(64) void k_direct(const double *__restrict__ tgt, int64_t m,
                                                const double *__restrict__ src, int64_t n,
                                                const double *__restrict__ f, const double *__restrict__ h,
-                                               const double *__restrict__ nu, double *__restrict__ part) {
+                                               const double *__restrict__ nu, int32_t chunk,
+                                               double *__restrict__ part) {
     const int64_t t = int64_t(blockIdx.x) * 64 + threadIdx.x;
     const bool valid = t < m;
     double x0 = 0, x1 = 0, x2 = 0;
@@ -224,8 +225,8 @@ __global__ __launch_bounds__(64) void k_direct(const double *__restrict__ tgt, i
         x1 = tgt[3 * t + 1];
         x2 = tgt[3 * t + 2];
     }
-    const int64_t j0 = int64_t(blockIdx.y) * DCH;
-    const int64_t j1 = j0 + DCH < n ? j0 + DCH : n;
+    const int64_t j0 = int64_t(blockIdx.y) * chunk;
+    const int64_t j1 = j0 + chunk < n ? j0 + chunk : n;
     double u0 = 0, u1 = 0, u2 = 0;
     for (int64_t j = j0; j < j1; ++j) {
         const double d0 = x0 - src[3 * j], d1 = x1 - src[3 * j + 1], d2 = x2 - src[3 * j + 2];
@@ -484,21 +485,40 @@ void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, dou
     prof_mark(STK_PHASE_FAR, s);
 }
 
+DirectShape direct_shape(int64_t m, int64_t n) {
+    // about DIRECT_WAVES (target group, chunk) waves when the targets are few, so a
+    // sampled-target reference still fills the chip; at most DIRECT_CHUNK_MAX sources per
+    // wave (the partial buffer stays 3 m ceil(n / 8192) doubles for large m)
+    constexpr int64_t DIRECT_WAVES = 32768, DIRECT_CHUNK_MIN = 512, DIRECT_CHUNK_MAX = 8192;
+    const int64_t ng = (m + 63) / 64;
+    const int64_t want = (DIRECT_WAVES + ng - 1) / ng;
+    int64_t c = (n + want - 1) / want;
+    c = (c + 255) / 256 * 256;
+    c = c < DIRECT_CHUNK_MIN ? DIRECT_CHUNK_MIN : (c > DIRECT_CHUNK_MAX ? DIRECT_CHUNK_MAX : c);
+    DirectShape d;
+    d.chunk = int32_t(c);
+    d.nch = int32_t((n + c - 1) / c);
+    return d;
+}
+
+void direct_launch(const double *tgt, int64_t m, const double *src, int64_t n, const double *f, const double *h,
+                   const double *nu, const DirectShape &d, double *part, double *u, hipStream_t s) {
+    hipLaunchKernelGGL(k_direct, dim3(nblk(m, 64), unsigned(d.nch)), dim3(64), 0, s, tgt, m, src, n, f, h, nu,
+                       d.chunk, part);
+    STK_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_direct_reduce, dim3(nblk(3 * m, 256)), dim3(256), 0, s, part, m, d.nch, u);
+    STK_CHECK_LAUNCH();
+}
+
 void direct_sum(const double *tgt, int64_t m, const double *src, int64_t n, const double *f, const double *h,
                 const double *nu, int32_t K, double *u_out, hipStream_t s) {
-    const int nch = int((n + DCH - 1) / DCH);
-    const unsigned ng = nblk(m, 64);
+    const DirectShape d = direct_shape(m, n);
     double *part = nullptr;
     prof_mark(-1, s);
-    STK_HIP(hipMallocAsync((void **)&part, sizeof(double) * 3 * size_t(m) * nch, s));
-    for (int r = 0; r < K; ++r) {
-        hipLaunchKernelGGL(k_direct, dim3(ng, nch), dim3(64), 0, s, tgt, m, src, n, f + size_t(r) * n * 3,
-                           h + size_t(r) * n * 3, nu, part);
-        STK_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_direct_reduce, dim3(nblk(3 * m, 256)), dim3(256), 0, s, part, m, nch,
-                           u_out + size_t(r) * m * 3);
-        STK_CHECK_LAUNCH();
-    }
+    STK_HIP(hipMallocAsync((void **)&part, sizeof(double) * 3 * size_t(m) * d.nch, s));
+    for (int r = 0; r < K; ++r)
+        direct_launch(tgt, m, src, n, f + size_t(r) * n * 3, h + size_t(r) * n * 3, nu, d, part,
+                      u_out + size_t(r) * m * 3, s);
     prof_mark(STK_PHASE_DIRECT, s);
     STK_HIP(hipFreeAsync(part, s));
 }

@@ -236,6 +236,15 @@ void near_field(Tree &t, Plan &plan, double *unear, hipStream_t s);
 // side; max_pc = 64 takes every far entry.
 constexpr int FAR_SPARSE_MAX = 32;
 void far_sparse(Tree &t, Plan &plan, double *unear, int max_pc, hipStream_t s);
+// FP64 direct sum: k_direct sums `chunk` consecutive sources per wave for 64 targets into
+// partial velocities (3 m nch doubles), k_direct_reduce adds them in chunk order; the shape
+// depends only on (m, n)
+struct DirectShape {
+    int32_t chunk, nch;
+};
+DirectShape direct_shape(int64_t m, int64_t n);
+void direct_launch(const double *tgt, int64_t m, const double *src, int64_t n, const double *f, const double *h,
+                   const double *nu, const DirectShape &d, double *part, double *u, hipStream_t s);
 void direct_sum(const double *tgt, int64_t m, const double *src, int64_t n, const double *f, const double *h,
                 const double *nu, int32_t k, double *u_out, hipStream_t s);
 
