@@ -147,6 +147,22 @@ stk_status stk_evaluate_adjoint(stk_plan *plan, const double *w, double *grad_f,
 stk_status stk_direct(const double *targets, int64_t m, const double *sources, int64_t n, const double *f,
                       const double *h, const double *nu, int32_t k_rhs, double *u_out, void *stream);
 
+/* For callers that cannot allocate device memory (work under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): stk_direct with the partial sums in
+ * a fixed device array of STK_DIRECT_NOALLOC_SCRATCH_BYTES that each device holds until
+ * the process ends, so the call allocates nothing (stk_direct allocates 24 m ceil(n/c)
+ * bytes per call, c the source chunk of 512..8192).  Same arguments, conventions and
+ * kernels, and results bit-identical to stk_direct's.  Targets are processed in slices
+ * whose partial sums fit the array; fails with STK_EINVAL when 64 targets do not fit
+ * (n above about 1.7e8 sources).  Every call on a device shares that device's array:
+ * calls that overlap on one device (on different streams, or from several threads
+ * without ordering) race and give wrong results.  The first call on a device looks up
+ * the array's device address (hipGetSymbolAddress). */
+#define STK_DIRECT_NOALLOC_SCRATCH_BYTES (32u << 20)
+stk_status stk_direct_noalloc(const double *targets, int64_t m, const double *sources, int64_t n,
+                              const double *f, const double *h, const double *nu, int32_t k_rhs, double *u_out,
+                              void *stream);
+
 /* Introspection, for verification and reporting. */
 /* nnodes, number of levels, and root = (lo_x, lo_y, lo_z, L). Host outputs. */
 stk_status stk_tree_info(const stk_tree *t, int64_t *nnodes, int32_t *nlevels, double root[4]);

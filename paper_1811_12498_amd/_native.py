@@ -24,7 +24,7 @@ _STATUS_NAMES = {STK_EINVAL: "STK_EINVAL", STK_ENOMEM: "STK_ENOMEM", STK_EDEVICE
 
 # every symbol include/stokestree.h declares
 EXPORTS = ["stk_build_tree", "stk_compute_moments", "stk_evaluate_tree", "stk_evaluate", "stk_evaluate_adjoint",
-           "stk_direct",
+           "stk_direct", "stk_direct_noalloc",
            "stk_tree_info", "stk_tree_export", "stk_tree_export_moments", "stk_plan_counts", "stk_plan_info",
            "stk_plan_export_lists", "stk_plan_far_split", "stk_tiles_set", "stk_tiles_get", "stk_autotune", "stk_tiles_save",
            "stk_tiles_load", "stk_plan_tiles",
@@ -56,6 +56,7 @@ _lib.stk_evaluate_tree.argtypes = [_vp, _vp, _i64, _d, _vp, ctypes.POINTER(_vp),
 _lib.stk_evaluate.argtypes = [_vp, _i64, _vp, _i64, _vp, _vp, _vp, _i32, _i32, _d, _i32, ctypes.c_int, _vp,
                               ctypes.POINTER(_vp), _vp]
 _lib.stk_direct.argtypes = [_vp, _i64, _vp, _i64, _vp, _vp, _vp, _i32, _vp, _vp]
+_lib.stk_direct_noalloc.argtypes = [_vp, _i64, _vp, _i64, _vp, _vp, _vp, _i32, _vp, _vp]
 _lib.stk_evaluate_adjoint.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.stk_tree_info.argtypes = [_vp, _i64p, _i32p, _dp]
 _lib.stk_tree_export.argtypes = [_vp] + [_vp] * 11
@@ -226,6 +227,23 @@ def direct(targets, sources, f, h, nu) -> torch.Tensor:
     _check(_lib.stk_direct(_ptr(targets), m, _ptr(sources), n, _ptr(f), _ptr(h), _ptr(nu), k, _ptr(u),
                            _stream()))
     return u
+
+
+def direct_noalloc(targets, sources, f, h, nu, out=None) -> torch.Tensor:
+    """stk_direct_noalloc: the direct sum with the library's fixed scratch array (the
+    library allocates nothing; `out`, if given, receives the result)."""
+    for t, nm in ((targets, "targets"), (sources, "sources"), (f, "f"), (h, "h"), (nu, "nu")):
+        _dev(t, nm)
+    m, n = targets.shape[0], sources.shape[0]
+    k = f.shape[0] if f.dim() == 3 else 1
+    shape = (m, 3) if k == 1 else (k, m, 3)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float64, device=targets.device)
+    elif tuple(out.shape) != shape or out.dtype != torch.float64 or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous float64 tensor of shape {shape}")
+    _check(_lib.stk_direct_noalloc(_ptr(targets), m, _ptr(sources), n, _ptr(f), _ptr(h), _ptr(nu), k, _ptr(out),
+                                   _stream()))
+    return out
 
 
 def tree_info(tree: Tree):

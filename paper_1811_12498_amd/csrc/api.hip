@@ -292,6 +292,17 @@ stk_status stk_direct(const double *targets, int64_t m, const double *sources, i
     });
 }
 
+stk_status stk_direct_noalloc(const double *targets, int64_t m, const double *sources, int64_t n, const double *f,
+                              const double *h, const double *nu, int32_t k_rhs, double *u_out, void *stream) {
+    return guarded([&] {
+        check_common(targets, m, "targets");
+        check_common(sources, n, "sources");
+        stk::require(f && h && nu && u_out, "f, h, nu and u_out must be non-NULL");
+        stk::require(k_rhs >= 1 && k_rhs <= 64, "k_rhs must be in [1, 64]");
+        stk::direct_sum_noalloc(targets, m, sources, n, f, h, nu, k_rhs, u_out, as_stream(stream));
+    });
+}
+
 stk_status stk_tree_info(const stk_tree *t, int64_t *nnodes, int32_t *nlevels, double root[4]) {
     return guarded([&] {
         stk::require(t != nullptr, "tree is NULL");

@@ -247,6 +247,11 @@ void direct_launch(const double *tgt, int64_t m, const double *src, int64_t n, c
                    const double *nu, const DirectShape &d, double *part, double *u, hipStream_t s);
 void direct_sum(const double *tgt, int64_t m, const double *src, int64_t n, const double *f, const double *h,
                 const double *nu, int32_t k, double *u_out, hipStream_t s);
+// the same sum with the partials in a fixed per-device array (noalloc.hip): targets in
+// slices of direct_noalloc_slice(m, n) (0 when 64 targets do not fit)
+int64_t direct_noalloc_slice(int64_t m, int64_t n);
+void direct_sum_noalloc(const double *tgt, int64_t m, const double *src, int64_t n, const double *f,
+                        const double *h, const double *nu, int32_t k, double *u_out, hipStream_t s);
 
 // phase timing (profile.hip); phases are the STK_PHASE_* values of the public header
 void prof_mark(int phase, hipStream_t s);
