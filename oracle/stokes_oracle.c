@@ -853,6 +853,62 @@ void orc_frozen_adjoint(const orc_tree *t, const double *src, const double *f, c
     memset(gsrc, 0, sizeof(double) * 3 * n);
     memset(gtgt, 0, sizeof(double) * 3 * m);
 
+    /* far-field target-position derivative: it writes only target i's gradient, so the
+     * targets run in parallel; the weight adjoints and the near field follow serially */
+#pragma omp parallel
+    {
+        double *bp = malloc(sizeof(double) * S * S * S);
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t i = 0; i < m; i++) {
+            const double *x = tgt + 3 * i, *wi = w + 3 * i;
+            for (int64_t e = far_ptr[i]; e < far_ptr[i + 1]; e++) {
+                const int64_t c = far_nodes[e];
+                double d[3];
+                for (int q = 0; q < 3; q++) d[q] = x[q] - t->center[3 * c + q];
+                orc_coulomb_taylor(d, P, bp);
+                const double *b = bp;
+                const double *Mc = M + (size_t)c * nm * 3, *Tc = Mt + (size_t)c * nm * 9;
+                for (int q = 0; q < nm; q++) {
+                    const int k[3] = {kk[3 * q], kk[3 * q + 1], kk[3 * q + 2]};
+                    /* target-position derivative of the coefficients */
+                    for (int s = 0; s < 3; s++) {
+                        double g = 0.0;
+                        for (int ii = 0; ii < 3; ii++) {
+                            int ei[3];
+                            ev(ii, ei);
+                            for (int j = 0; j < 3; j++) {
+                                int ej[3];
+                                ev(j, ej);
+                                const double da = delta(ii, j) * dbx(b, P, k[0], k[1], k[2], s) +
+                                                  delta(j, s) * (k[ii] + 1) * bsh(b, P, k, ei[0], ei[1], ei[2]) +
+                                                  d[j] * (k[ii] + 1) * dbx(b, P, k[0] + ei[0], k[1] + ei[1], k[2] + ei[2], s) -
+                                                  (k[ii] + 1 - delta(ii, j)) *
+                                                      dbx(b, P, k[0] + ei[0] - ej[0], k[1] + ei[1] - ej[1], k[2] + ei[2] - ej[2], s);
+                                g += wi[ii] * da * Mc[3 * q + j];
+                                for (int l = 0; l < 3; l++) {
+                                    int el[3];
+                                    ev(l, el);
+                                    const double cij = (k[ii] + 1) * (k[j] + 1 + delta(ii, j));
+                                    const double dat =
+                                        (delta(l, s) * cij * bsh(b, P, k, ei[0] + ej[0], ei[1] + ej[1], ei[2] + ej[2]) +
+                                         d[l] * cij * dbx(b, P, k[0] + ei[0] + ej[0], k[1] + ei[1] + ej[1], k[2] + ei[2] + ej[2], s) -
+                                         (k[ii] + 1 - delta(ii, l)) * (k[j] + 1 + delta(ii, j) - delta(j, l)) *
+                                             dbx(b, P, k[0] + ei[0] + ej[0] - el[0], k[1] + ei[1] + ej[1] - el[1],
+                                                 k[2] + ei[2] + ej[2] - el[2], s) +
+                                         delta(ii, j) * (k[l] + 1) * dbx(b, P, k[0] + el[0], k[1] + el[1], k[2] + el[2], s)) /
+                                        3.0;
+                                    g += wi[ii] * dat * Tc[9 * q + 3 * j + l];
+                                }
+                            }
+                        }
+                        gtgt[3 * i + s] += g;
+                    }
+                }
+            }
+        }
+        free(bp);
+    }
+
     for (int64_t i = 0; i < m; i++) {
         const double *x = tgt + 3 * i, *wi = w + 3 * i;
         for (int64_t e = far_ptr[i]; e < far_ptr[i + 1]; e++) {
@@ -862,7 +918,6 @@ void orc_frozen_adjoint(const orc_tree *t, const double *src, const double *f, c
             orc_coulomb_taylor(d, P, b);
             stokeslet_coeffs_from_b(d, p, b, P, a);
             stresslet_coeffs_from_b(d, p, b, P, at);
-            const double *Mc = M + (size_t)c * nm * 3, *Tc = Mt + (size_t)c * nm * 9;
             double *LMc = LM + (size_t)c * nm * 3, *LTc = LT + (size_t)c * nm * 9;
             for (int q = 0; q < nm; q++) {
                 const int k[3] = {kk[3 * q], kk[3 * q + 1], kk[3 * q + 2]};
@@ -871,39 +926,6 @@ void orc_frozen_adjoint(const orc_tree *t, const double *src, const double *f, c
                         LMc[3 * q + j] += wi[ii] * a[(q * 3 + ii) * 3 + j];
                         for (int l = 0; l < 3; l++) LTc[9 * q + 3 * j + l] += wi[ii] * at[((q * 3 + ii) * 3 + j) * 3 + l];
                     }
-                }
-                /* target-position derivative of the coefficients */
-                for (int s = 0; s < 3; s++) {
-                    double g = 0.0;
-                    for (int ii = 0; ii < 3; ii++) {
-                        int ei[3];
-                        ev(ii, ei);
-                        for (int j = 0; j < 3; j++) {
-                            int ej[3];
-                            ev(j, ej);
-                            const double da = delta(ii, j) * dbx(b, P, k[0], k[1], k[2], s) +
-                                              delta(j, s) * (k[ii] + 1) * bsh(b, P, k, ei[0], ei[1], ei[2]) +
-                                              d[j] * (k[ii] + 1) * dbx(b, P, k[0] + ei[0], k[1] + ei[1], k[2] + ei[2], s) -
-                                              (k[ii] + 1 - delta(ii, j)) *
-                                                  dbx(b, P, k[0] + ei[0] - ej[0], k[1] + ei[1] - ej[1], k[2] + ei[2] - ej[2], s);
-                            g += wi[ii] * da * Mc[3 * q + j];
-                            for (int l = 0; l < 3; l++) {
-                                int el[3];
-                                ev(l, el);
-                                const double cij = (k[ii] + 1) * (k[j] + 1 + delta(ii, j));
-                                const double dat =
-                                    (delta(l, s) * cij * bsh(b, P, k, ei[0] + ej[0], ei[1] + ej[1], ei[2] + ej[2]) +
-                                     d[l] * cij * dbx(b, P, k[0] + ei[0] + ej[0], k[1] + ei[1] + ej[1], k[2] + ei[2] + ej[2], s) -
-                                     (k[ii] + 1 - delta(ii, l)) * (k[j] + 1 + delta(ii, j) - delta(j, l)) *
-                                         dbx(b, P, k[0] + ei[0] + ej[0] - el[0], k[1] + ei[1] + ej[1] - el[1],
-                                             k[2] + ei[2] + ej[2] - el[2], s) +
-                                     delta(ii, j) * (k[l] + 1) * dbx(b, P, k[0] + el[0], k[1] + el[1], k[2] + el[2], s)) /
-                                    3.0;
-                                g += wi[ii] * dat * Tc[9 * q + 3 * j + l];
-                            }
-                        }
-                    }
-                    gtgt[3 * i + s] += g;
                 }
             }
         }
@@ -920,34 +942,42 @@ void orc_frozen_adjoint(const orc_tree *t, const double *src, const double *f, c
             }
         }
     }
-    /* moment adjoints back to every source of every node */
-    for (int64_t c = 0; c < nnodes; c++) {
-        const double *LMc = LM + (size_t)c * nm * 3, *LTc = LT + (size_t)c * nm * 9;
-        for (int64_t s = t->start[c]; s < t->start[c] + t->count[c]; s++) {
-            const int64_t nn = t->perm[s];
-            double dy[3];
-            for (int q = 0; q < 3; q++) dy[q] = src[3 * nn + q] - t->center[3 * c + q];
-            for (int q = 0; q < nm; q++) {
-                const int k[3] = {kk[3 * q], kk[3 * q + 1], kk[3 * q + 2]};
-                const double mono = monomial(dy, k[0], k[1], k[2]);
-                double pf = 0.0;
-                for (int j = 0; j < 3; j++) {
-                    gf[3 * nn + j] += mono * LMc[3 * q + j];
-                    pf += f[3 * nn + j] * LMc[3 * q + j];
-                    for (int l = 0; l < 3; l++) {
-                        gh[3 * nn + j] += mono * nu[3 * nn + l] * LTc[9 * q + 3 * j + l];
-                        pf += h[3 * nn + j] * nu[3 * nn + l] * LTc[9 * q + 3 * j + l];
+    /* moment adjoints back to every source of every node.  Nodes are numbered level by
+     * level and the nodes of one level hold disjoint sources, so the nodes of a level run
+     * in parallel while every source still receives its terms root first, in node order. */
+    for (int64_t c0 = 0; c0 < nnodes;) {
+        int64_t c1 = c0;
+        while (c1 < nnodes && t->level[c1] == t->level[c0]) c1++;
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t c = c0; c < c1; c++) {
+            const double *LMc = LM + (size_t)c * nm * 3, *LTc = LT + (size_t)c * nm * 9;
+            for (int64_t s = t->start[c]; s < t->start[c] + t->count[c]; s++) {
+                const int64_t nn = t->perm[s];
+                double dy[3];
+                for (int q = 0; q < 3; q++) dy[q] = src[3 * nn + q] - t->center[3 * c + q];
+                for (int q = 0; q < nm; q++) {
+                    const int k[3] = {kk[3 * q], kk[3 * q + 1], kk[3 * q + 2]};
+                    const double mono = monomial(dy, k[0], k[1], k[2]);
+                    double pf = 0.0;
+                    for (int j = 0; j < 3; j++) {
+                        gf[3 * nn + j] += mono * LMc[3 * q + j];
+                        pf += f[3 * nn + j] * LMc[3 * q + j];
+                        for (int l = 0; l < 3; l++) {
+                            gh[3 * nn + j] += mono * nu[3 * nn + l] * LTc[9 * q + 3 * j + l];
+                            pf += h[3 * nn + j] * nu[3 * nn + l] * LTc[9 * q + 3 * j + l];
+                        }
                     }
-                }
-                for (int sx = 0; sx < 3; sx++) {
-                    if (k[sx] == 0) continue;
-                    int e[3];
-                    ev(sx, e);
-                    const double dm = k[sx] * monomial(dy, k[0] - e[0], k[1] - e[1], k[2] - e[2]);
-                    gsrc[3 * nn + sx] += dm * pf;
+                    for (int sx = 0; sx < 3; sx++) {
+                        if (k[sx] == 0) continue;
+                        int e[3];
+                        ev(sx, e);
+                        const double dm = k[sx] * monomial(dy, k[0] - e[0], k[1] - e[1], k[2] - e[2]);
+                        gsrc[3 * nn + sx] += dm * pf;
+                    }
                 }
             }
         }
+        c0 = c1;
     }
     free(at);
     free(a);

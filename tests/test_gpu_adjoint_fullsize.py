@@ -1,0 +1,144 @@
+"""Adjoint at full size on the GPU: the N = 200,000 cube (p 8, theta 0.5, N0 2000) whose
+forward + adjoint the benchmark times, and the N = 1,000,000 sphere (nu the outward normal,
+h = f; p 8, theta 0.5, N0 1000).
+
+* Sampled weights: w is non-zero on 1000 seeded targets only.  Then L = sum w.u involves
+  only those targets, and the oracle's frozen-plan adjoint evaluated at them alone gives
+  the whole gradient: dL/df, dL/dh and dL/dy for every source, dL/dx for the sampled
+  targets (every other target's gradient is zero).  All of it is compared element by
+  element with the HIP adjoint (FP64 within 1e-11, mixed within 1e-4).
+* Mixed against FP64 with w on every target, per key, within 1e-5 (measured at most 4.3e-7;
+  the FP64 adjoint at the cube is also checked by central differences in
+  test_gpu_adjoint.py).
+* The dot-product identity at N = 1,000,000 in both precisions.
+* The treecode gradient against the gradient of the exact direct sum (both from the
+  oracle's side for the truth): within a multiple of the forward error E."""
+import numpy as np
+import pytest
+
+from paper_1811_12498_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+N_W = 1000
+TOL = {"fp64": 1e-11, "mixed": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def nat():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1811_12498_amd import native
+    return native
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _workload(name):
+    return W.c5_cube_adjoint() if name == "cube200k" else W.c3_sphere_1m()
+
+
+@pytest.fixture(scope="module")
+def sampled(orc):
+    """Per workload: the sampled targets, their weights and the oracle's gradient."""
+    out = {}
+
+    def get(name):
+        if name not in out:
+            w = _workload(name)
+            rng = np.random.default_rng(61)
+            S = np.sort(rng.choice(w.n, N_W, replace=False))
+            ws = rng.uniform(-1.0, 1.0, (N_W, 3))
+            T = orc.build_tree(w.src, w.n0)
+            L = orc.lists(T, w.theta, w.src[S])
+            ref = orc.frozen_adjoint(T, L, w.src, w.f[0], w.h[0], w.nu, w.p, w.src[S], ws)
+            out[name] = (w, S, ws, ref)
+        return out[name]
+    return get
+
+
+@pytest.mark.parametrize("name", ["cube200k", "sphere1m"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_sampled_weights_match_oracle(nat, orc, sampled, name, prec):
+    import torch
+    w, S, ws, ref = sampled(name)
+    X = _t(w.src)
+    wfull = np.zeros((w.n, 3))
+    wfull[S] = ws
+    u, plan = nat.evaluate(X, X, _t(w.f[0]), _t(w.h[0]), _t(w.nu), w.p, w.theta, w.n0, prec, keep_plan=True)
+    g = nat.evaluate_adjoint(plan, _t(wfull), w.n)
+    gt = g["targets"].cpu().numpy()
+    errs = {}
+    for key, r in zip(("f", "h", "sources"), ref[:3]):
+        errs[key] = orc.rel_l2(g[key].cpu().numpy(), r)
+    errs["targets"] = orc.rel_l2(gt[S], ref[3])
+    print(name, prec, errs, flush=True)
+    rest = np.ones(w.n, bool)
+    rest[S] = False
+    assert not np.any(gt[rest]), "targets with zero weight got a gradient"
+    for key, e in errs.items():
+        assert e < TOL[prec], (key, e)
+    del torch
+
+
+@pytest.mark.parametrize("name,tol", [("cube200k", 1e-5), ("sphere1m", 1e-5)])
+def test_mixed_adjoint_matches_fp64(nat, name, tol):
+    import torch
+    w = _workload(name)
+    rng = np.random.default_rng(62)
+    Wt = _t(rng.uniform(-1.0, 1.0, (w.n, 3)))
+    X, F, H, NU = _t(w.src), _t(w.f[0]), _t(w.h[0]), _t(w.nu)
+    g = {}
+    for prec in ("fp64", "mixed"):
+        _, plan = nat.evaluate(X, X, F, H, NU, w.p, w.theta, w.n0, prec, keep_plan=True)
+        g[prec] = nat.evaluate_adjoint(plan, Wt, w.n)
+        del plan
+    errs = {k: float((g["mixed"][k] - g["fp64"][k]).norm() / g["fp64"][k].norm()) for k in g["fp64"]}
+    print(name, errs, flush=True)
+    for k, e in errs.items():
+        assert e < tol, (k, e)
+    del torch
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
+def test_dot_product_identity_sphere1m(nat, prec, tol):
+    """L is linear in (f, h): sum(w * u) = sum(grad_f * f) + sum(grad_h * h) at N = 1M."""
+    import torch
+    w = W.c3_sphere_1m()
+    Wt = _t(np.random.default_rng(63).uniform(-1.0, 1.0, (w.n, 3)))
+    X, F, H = _t(w.src), _t(w.f[0]), _t(w.h[0])
+    u, plan = nat.evaluate(X, X, F, H, _t(w.nu), w.p, w.theta, w.n0, prec, keep_plan=True)
+    g = nat.evaluate_adjoint(plan, Wt, w.n, ("f", "h"))
+    lhs = float(torch.sum(Wt * u))
+    rhs = float(torch.sum(g["f"] * F) + torch.sum(g["h"] * H))
+    scale = float(torch.sum(torch.abs(Wt * u)))
+    print(prec, lhs, rhs, abs(lhs - rhs) / scale, flush=True)
+    assert abs(lhs - rhs) <= tol * scale
+
+
+@pytest.mark.parametrize("prec,extra", [("fp64", 0.0), ("mixed", 1e-5)])
+def test_gradient_close_to_direct_sum_gradient(nat, orc, prec, extra):
+    """N = 5000 in the unit cube, p 8, theta 0.5: every gradient of L = sum w.u from the
+    GPU adjoint against the analytic gradient of the exact direct sum (oracle).  The f and
+    h gradients carry the far-field truncation error, so they are held to 3 E, with E the
+    forward error of the treecode against the direct sum; the position gradients, which
+    the exact near field dominates, to E / 2 (CPU calibration: at most 1.4 E and 0.2 E at
+    p = 6..10)."""
+    w = W.cube(5000, seed=41, n0=200, with_w=True)
+    X = _t(w.src)
+    u, plan = nat.evaluate(X, X, _t(w.f[0]), _t(w.h[0]), _t(w.nu), 8, 0.5, 200, prec, keep_plan=True)
+    g = nat.evaluate_adjoint(plan, _t(w.w), w.n)
+    ud = orc.direct(w.src, w.src, w.f[0], w.h[0], w.nu)
+    E = orc.rel_l2(u.cpu().numpy(), ud)
+    gd = orc.direct_grad(w.src, w.src, w.f[0], w.h[0], w.nu, w.w)
+    errs = {k: orc.rel_l2(g[k].cpu().numpy(), r) for k, r in zip(("f", "h", "sources", "targets"), gd)}
+    print(prec, "E", E, errs, flush=True)
+    assert E < 1e-3
+    for k in ("f", "h"):
+        assert errs[k] <= 3 * E + extra, (k, errs[k], E)
+    for k in ("sources", "targets"):
+        assert errs[k] <= 0.5 * E + extra, (k, errs[k], E)

@@ -109,9 +109,11 @@ def test_autotune_records_valid_tiles(nat):
 
 @pytest.mark.parametrize("K", [16, 20])
 @pytest.mark.parametrize("p", [3, 8])
-def test_far_mfma_matches_valu(nat, K, p):
+def test_far_mfma_matches_valu(nat, orc, K, p):
     """The matrix-core far field (16 right-hand sides per pass; K = 20 leaves a partial
-    pass) against the VALU far kernel, per right-hand side, and against FP64."""
+    pass) against the VALU far kernel, per right-hand side, and against FP64; at K = 16
+    also every right-hand side against the oracle's treecode on 1000 seeded targets
+    (mixed-precision bar 1e-5)."""
     w = W.cube(30_000, seed=80 + K + p, n0=300, k=K)
     X = _t(w.src)
     F, H, NU = _t(w.f), _t(w.h), _t(w.nu)
@@ -129,6 +131,15 @@ def test_far_mfma_matches_valu(nat, K, p):
         e_v = float((u_mfma[r] - u_valu[r]).norm() / u_valu[r].norm())
         e_64 = float((u_mfma[r] - u64[r]).norm() / u64[r].norm())
         assert e_v < 2e-6 and e_64 < 1e-5, (r, e_v, e_64)
+    if K == 16:
+        S = np.sort(np.random.default_rng(K + p).choice(w.n, 1000, replace=False))
+        T = orc.build_tree(w.src, 300)
+        um = u_mfma.cpu().numpy()
+        for r in range(K):
+            M, Mt = orc.moments(T, w.src, w.f[r], w.h[r], w.nu, p)
+            ref = orc.treecode(T, w.src, w.f[r], w.h[r], w.nu, M, Mt, p, theta, w.src[S]).u
+            e_o = orc.rel_l2(um[r][S], ref)
+            assert e_o < 1e-5, (r, e_o)
 
 
 @pytest.mark.parametrize("K,prec", [(1, "fp64"), (1, "mixed"), (5, "fp64"), (16, "mixed")])
