@@ -44,6 +44,8 @@ def far_flops_per_interaction(p, k=1):
 NEAR_FLOPS_PER_PAIR = 48  # Stokeslet + stresslet contracted pair (Sec. 4.1)
 
 
+# the metric's accuracy bar: relative L2 error against the FP64 direct sum on the sample
+ERROR_BAR = 1e-5
 # a fast (p, theta, N0) with E <= 1e-5 on the 1M sphere in the tuning sweep (bench.py --only
 # tune), with a margin under the bar (the fastest, p 7 / theta 0.3, sits 7% under it)
 AT_ERROR_BAR = (8, 0.325, 500)
@@ -53,23 +55,159 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, f, h, n_sample=100_000, seed=99):
-    """The FP64 oracle on the host: tree + moments for all N, then Algorithm 1 at a
-    seeded sample of targets; extrapolated to whole-job targets/s."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, f, h, sample, n_tree_all=50_000, n_tree_one=5_000, n_direct_one=200, seed=99):
+    """The FP64 oracle on the host, on all its threads and on one: (i) the direct sum at the
+    sampled targets over all N sources, (ii) tree + moments for all N sources, (iii)
+    Algorithm 1 at a seeded subset of the targets.  `value` is whole-job targets/s on all
+    threads, (ii) plus (iii) extrapolated to N targets."""
     import oracle
     oracle.build(force=False)
+    threads = oracle.num_threads()
     rng = np.random.default_rng(seed)
-    idx = np.sort(rng.choice(w.n, n_sample, replace=False))
+    order = rng.permutation(w.n)
+
+    def leg(k, n_tree, n_direct):
+        oracle.set_num_threads(k)
+        idx = np.sort(order[:n_tree])
+        t0 = time.perf_counter()
+        T = oracle.build_tree(w.src, w.n0)
+        M, Mt = oracle.moments(T, w.src, f, h, w.nu, w.p)
+        t1 = time.perf_counter()
+        oracle.treecode(T, w.src, f, h, w.nu, M, Mt, w.p, w.theta, w.src[idx])
+        t2 = time.perf_counter()
+        oracle.direct(w.src[sample[:n_direct]], w.src, f, h, w.nu)
+        t3 = time.perf_counter()
+        t_job = (t1 - t0) + (t2 - t1) * w.n / n_tree
+        return {"threads": k, "targets_per_s": w.n / t_job, "tree_moments_s": round(t1 - t0, 3),
+                "treecode_targets": n_tree, "treecode_s": round(t2 - t1, 3),
+                "direct_targets": int(n_direct), "direct_s": round(t3 - t2, 3),
+                "direct_pairs_per_s": n_direct * w.n / (t3 - t2)}
+
+    try:
+        full = leg(threads, n_tree_all, sample.size)
+        one = leg(1, n_tree_one, n_direct_one)
+    finally:
+        oracle.set_num_threads(threads)
+    return {"value": full["targets_per_s"], "unit": "targets/s", "cores": threads, "kind": "oracle",
+            "sample": f"tree+moments for all {w.n} sources ({full['tree_moments_s']:.2f} s) + Algorithm 1 at "
+                      f"{n_tree_all} seeded targets ({full['treecode_s']:.2f} s), extrapolated to {w.n} targets; "
+                      f"{threads} threads",
+            "cpu_model": _cpu_model(), "omp_num_threads": os.environ.get("OMP_NUM_THREADS"),
+            "hardware_concurrency": os.cpu_count(), "all_threads": full, "one_thread": one}
+
+
+def run_config(X, F, H, NU, p, theta, n0, prec, steps, warmup):
+    """Time `steps` whole-path evaluations (after `warmup`) at (p, theta, N0) with the
+    library's per-phase HIP-event timing on its own streams, then derive the far and near
+    kernels' algorithmic rates from the plan's exact interaction counts."""
+    import torch
+
+    from paper_1811_12498_amd import native
+    n = X.shape[0]
+
+    def step():
+        return native.evaluate(X, X, F, H, NU, p, theta, n0, prec)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    native.profile_read()  # discard warm-up timings
+    native.profile_enable(True)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    T = oracle.build_tree(w.src, w.n0)
-    M, Mt = oracle.moments(T, w.src, f, h, w.nu, w.p)
+    for _ in range(steps):
+        u = step()
+    torch.cuda.synchronize()
     t1 = time.perf_counter()
-    oracle.treecode(T, w.src, f, h, w.nu, M, Mt, w.p, w.theta, w.src[idx])
-    t2 = time.perf_counter()
-    t_job = (t1 - t0) + (t2 - t1) * w.n / n_sample
-    return {"value": w.n / t_job, "unit": "targets/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"tree+moments for all {w.n} sources ({t1 - t0:.2f} s) + Algorithm 1 at {n_sample} "
-                      f"seeded targets ({t2 - t1:.2f} s), extrapolated to {w.n} targets"}
+    native.profile_enable(False)
+    prof = native.profile_read()
+    phases = {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items() if v[1]}
+
+    # algorithmic work of one step (exact interaction counts from the lists)
+    _, plan = native.evaluate(X, X, F, H, NU, p, theta, n0, prec, keep_plan=True)
+    nfar, nnear, npairs = native.plan_counts(plan)
+    pinfo = native.plan_info(plan)
+    near_lists = native.plan_lists(plan, "near")
+    far_pc = np.bitwise_count(native.plan_lists(plan, "far")["mask"]).astype(np.int64)
+    sparse_max, sparse_inter = native.plan_far_split(plan)
+    del plan
+    leaf_count = native.tree_export(native.build_tree(X, n0))["count"].astype(np.int64)
+    # leaf-major items: each leaf's (target, leaf) incidences in waves of 64 lanes
+    inc = np.bincount(near_lists["node"], weights=np.bitwise_count(near_lists["mask"]),
+                      minlength=leaf_count.size).astype(np.int64)
+    near_slots = int((64 * ((inc + 63) // 64) * leaf_count).sum())
+    far_total = int(nfar.sum())
+    # the group-major far kernel runs the entries with more than sparse_max targets
+    far_dense = far_total - sparse_inter
+    dense_entries = int((far_pc > sparse_max).sum())
+    pairs_total = int(npairs.sum())
+    far_ms = prof["far"][0] / prof["far"][1]
+    near_ms = prof["near"][0] / prof["near"][1]
+    far_flops = far_dense * far_flops_per_interaction(p)
+    near_flops = pairs_total * NEAR_FLOPS_PER_PAIR
+    peak = PEAK_FP32_VALU if prec == "mixed" else PEAK_FP64_VALU
+    far_tf = far_flops / (far_ms * 1e-3)
+    near_tf = near_flops / (near_ms * 1e-3)
+    kname = f"k_far<{p},{'float' if prec == 'mixed' else 'double'},1>"
+    traffic = profiled_traffic(kname) if (p == 8 and theta == 0.5 and n0 == 1000 and prec == "mixed") else None
+    roofline = {"bound": "alu", "achieved": round(far_tf / 1e12, 3), "peak": peak / 1e12, "unit": "TFLOP/s",
+                "frac": round(far_tf / peak, 4), "traffic": traffic, "kernel": kname,
+                "far_interactions_per_launch": far_dense, "flops_per_interaction": far_flops_per_interaction(p),
+                "avg_launch_ms": round(far_ms, 4), "far_entries": dense_entries,
+                "lane_utilisation": round(far_dense / (64.0 * max(dense_entries, 1)), 4)}
+    sparse_ms = prof["far_sparse"][0] / max(prof["far_sparse"][1], 1)
+    far_split = {"sparse_max_targets": sparse_max, "sparse_interactions": sparse_inter,
+                 "sparse_entries": int(pinfo["far_entries"] - dense_entries), "sparse_ms": round(sparse_ms, 4),
+                 "all_far_interactions": far_total}
+    near_field = {"kernel": f"k_near<{'float' if prec == 'mixed' else 'double'},1>",
+                  "achieved_tflops": round(near_tf / 1e12, 3),
+                  "frac_of_fp32_peak" if prec == "mixed" else "frac_of_fp64_peak": round(near_tf / peak, 4),
+                  "pairs_per_launch": pairs_total, "avg_launch_ms": round(near_ms, 4),
+                  "lane_utilisation": round(pairs_total / max(near_slots, 1), 4)}
+    return {"ms_per_step": (t1 - t0) * 1e3 / steps, "u": u, "phase_ms_per_step": phases, "roofline": roofline,
+            "near_field": near_field, "far_split": far_split}
+
+
+def c2_grid(reps=3):
+    """The plain method at N = 100,000 uniform in [-1, 1]^3 (seed 2, N0 = 500): p in
+    {4, 6, 8, 10} x theta in {0.5, 0.7}, FP64 and mixed; per point one whole-path
+    evaluation's time and E on the 1000 seeded targets against the FP64 direct sum."""
+    import torch
+
+    from paper_1811_12498_amd import native, workloads
+    w = workloads.c2_cube_100k()
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    X, F, H, NU = t(w.src), t(w.f[0]), t(w.h[0]), t(w.nu)
+    St = torch.from_numpy(w.sample).to(dev)
+    ud = native.direct(X[St].contiguous(), X, F, H, NU)
+    rows = []
+    for p in (4, 6, 8, 10):
+        for theta in (0.5, 0.7):
+            for prec in ("fp64", "mixed"):
+                u = native.evaluate(X, X, F, H, NU, p, theta, w.n0, prec)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    u = native.evaluate(X, X, F, H, NU, p, theta, w.n0, prec)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) * 1e3 / reps
+                e = float(torch.linalg.norm(u[St] - ud) / torch.linalg.norm(ud))
+                rows.append({"p": p, "theta": theta, "precision": prec, "ms": round(ms, 3),
+                             "targets_per_s": w.n / (ms * 1e-3), "E_S": e})
+    return {"workload": f"cube N={w.n} in [-1,1]^3, N0={w.n0}, E on {w.sample.size} targets vs FP64 direct",
+            "rows": rows}
 
 
 def profiled_traffic(kernel: str):
@@ -156,6 +294,29 @@ def multi_rhs_times(reps=3):
         return u, ms, {k: round(v[0] / max(v[1], 1), 3) for k, v in prof.items() if v[1]}
 
     u, ms, phases = timed(F, H)
+    # algorithmic rates of the two fields from the plan's exact counts: the near field's
+    # contraction is 2 x 18 x K flops per pair (the 3 x 6 pair block against K weight
+    # columns; on the matrix cores when near_mfma), the far field 11 nb + 24 nb K + 21 per
+    # interaction; the cluster-major far kernel's time is the far_sparse phase
+    _, plan = native.evaluate(X, X, F, H, NU, w.p, w.theta, w.n0, "mixed", keep_plan=True)
+    nfar, _, npairs = native.plan_counts(plan)
+    far_split = native.plan_far_split(plan)
+    del plan
+    pairs, far_i = int(npairs.sum()), int(nfar.sum())
+    near_flops = pairs * 36 * K
+    far_cm = far_split[0] == 64
+    far_ms = phases["far_sparse"] if far_cm else phases["far"]
+    rates = {"near": {"kernel": "k_near_mfma" if tiles["near_mfma"] else f"k_near<float,{tiles['near_kb']}>",
+                      "unit": "MFMA FP32" if tiles["near_mfma"] else "VALU FP32", "pairs": pairs,
+                      "ms": phases["near"], "tflops": round(near_flops / (phases["near"] * 1e-3) / 1e12, 3),
+                      "frac_of_fp32_peak": round(near_flops / (phases["near"] * 1e-3) / PEAK_FP32_VALU, 4)},
+             "far": {"kernel": ("k_far_mfma" if tiles["far_mfma"] else
+                                ("k_far_cm" if far_cm else "k_far") + f"<{w.p},float,{tiles['far_kb']}>"),
+                     "unit": "MFMA FP32" if tiles["far_mfma"] else "VALU FP32", "interactions": far_i,
+                     "ms": far_ms,
+                     "tflops": round(far_i * far_flops_per_interaction(w.p, K) / (far_ms * 1e-3) / 1e12, 3),
+                     "frac_of_fp32_peak": round(far_i * far_flops_per_interaction(w.p, K) / (far_ms * 1e-3)
+                                                / PEAK_FP32_VALU, 4)}}
     f0, h0 = F[0].contiguous(), H[0].contiguous()
     _, ms1, _ = timed(f0, h0)
     S = torch.from_numpy(w.sample).to(dev)
@@ -164,7 +325,7 @@ def multi_rhs_times(reps=3):
     return {"workload": f"cube N={w.n}, K={K}, p={w.p}, theta={w.theta}, N0={w.n0}, mixed",
             "ms": round(ms, 3), "rhs_targets_per_s": K * w.n / (ms * 1e-3), "tiles": tiles,
             "autotune_best_ms": round(tune_ms, 3), "one_rhs_ms": round(ms1, 3),
-            "batch_speedup_vs_K_calls": round(K * ms1 / ms, 3), "phase_ms": phases,
+            "batch_speedup_vs_K_calls": round(K * ms1 / ms, 3), "phase_ms": phases, "kernel_rates": rates,
             "E_S_rhs0_vs_fp64_direct": err, "sample_targets": int(w.sample.size)}
 
 
@@ -247,7 +408,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 comparison runs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 256 MiB device copy (a reference for HBM counters)")
-    ap.add_argument("--only", choices=["fwd_adjoint", "multi_rhs", "table1", "tune"],
+    ap.add_argument("--only", choices=["fwd_adjoint", "multi_rhs", "table1", "tune", "c2"],
                     help="run only this secondary measurement and print its JSON object (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -262,7 +423,7 @@ def main():
 
     if args.only:
         res = {"fwd_adjoint": fwd_adjoint_times, "multi_rhs": multi_rhs_times,
-               "table1": table1_icosphere, "tune": tune_c3}[args.only]()
+               "table1": table1_icosphere, "tune": tune_c3, "c2": c2_grid}[args.only]()
         print(json.dumps(res), flush=True)
         return
 
@@ -274,9 +435,6 @@ def main():
     torch.cuda.synchronize()
     log(f"workload {w.name}: N={w.n} p={w.p} theta={w.theta} N0={w.n0} precision={args.precision}")
 
-    def step(prec=args.precision):
-        return native.evaluate(X, X, F, H, NU, w.p, w.theta, w.n0, prec)
-
     if args.copy_probe:
         a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device=dev).fill_(1.0)
         b = torch.empty_like(a)
@@ -284,83 +442,44 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    for i in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    native.profile_read()  # discard warm-up timings
-
-    native.profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        u = step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    native.profile_enable(False)
-    prof = native.profile_read()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    head = run_config(X, F, H, NU, w.p, w.theta, w.n0, args.precision, args.steps, args.warmup)
+    ms_per_step = head["ms_per_step"]
     value = w.n / (ms_per_step / 1e3)
+    u = head.pop("u")
     log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, {value:.4g} targets/s")
-    phases = {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items() if v[1]}
-    log(f"phase ms/launch: {phases}")
-
-    # algorithmic work of one step (exact interaction counts from the lists)
-    _, plan = native.evaluate(X, X, F, H, NU, w.p, w.theta, w.n0, args.precision, keep_plan=True)
-    nfar, nnear, npairs = native.plan_counts(plan)
-    pinfo = native.plan_info(plan)
-    near_lists = native.plan_lists(plan, "near")
-    far_pc = np.bitwise_count(native.plan_lists(plan, "far")["mask"]).astype(np.int64)
-    sparse_max, sparse_inter = native.plan_far_split(plan)
-    del plan
-    leaf_count = native.tree_export(native.build_tree(X, w.n0))["count"].astype(np.int64)
-    # leaf-major items: each leaf's (target, leaf) incidences in waves of 64 lanes
-    inc = np.bincount(near_lists["node"], weights=np.bitwise_count(near_lists["mask"]),
-                      minlength=leaf_count.size).astype(np.int64)
-    near_slots = int((64 * ((inc + 63) // 64) * leaf_count).sum())
-    far_total = int(nfar.sum())
-    # the group-major far kernel runs the entries with more than sparse_max targets
-    far_dense = far_total - sparse_inter
-    dense_entries = int((far_pc > sparse_max).sum())
-    pairs_total = int(npairs.sum())
-    far_ms = prof["far"][0] / prof["far"][1]
-    near_ms = prof["near"][0] / prof["near"][1]
-    far_flops = far_dense * far_flops_per_interaction(w.p)
-    near_flops = pairs_total * NEAR_FLOPS_PER_PAIR
-    peak = PEAK_FP32_VALU if args.precision == "mixed" else PEAK_FP64_VALU
-    far_tf = far_flops / (far_ms * 1e-3)
-    near_tf = near_flops / (near_ms * 1e-3)
-    kname = f"k_far<{w.p},{'float' if args.precision == 'mixed' else 'double'},1>"
-    traffic = profiled_traffic(kname) if (w.p == 8 and args.precision == "mixed") else None
-    roofline = {"bound": "alu", "achieved": round(far_tf / 1e12, 3), "peak": peak / 1e12, "unit": "TFLOP/s",
-                "frac": round(far_tf / peak, 4), "traffic": traffic, "kernel": kname,
-                "far_interactions_per_launch": far_dense, "flops_per_interaction": far_flops_per_interaction(w.p),
-                "avg_launch_ms": round(far_ms, 4), "far_entries": dense_entries,
-                "lane_utilisation": round(far_dense / (64.0 * max(dense_entries, 1)), 4)}
-    sparse_ms = prof["far_sparse"][0] / max(prof["far_sparse"][1], 1)
-    far_split = {"sparse_max_targets": sparse_max, "sparse_interactions": sparse_inter,
-                 "sparse_entries": int(pinfo["far_entries"] - dense_entries), "sparse_ms": round(sparse_ms, 4),
-                 "all_far_interactions": far_total}
+    log(f"phase ms/launch: {head['phase_ms_per_step']}")
+    roofline = head["roofline"]
 
     # accuracy on the seeded sample against the FP64 GPU direct sum
     S = w.sample
-    XS = X[torch.from_numpy(S).to(dev)].contiguous()
+    St = torch.from_numpy(S).to(dev)
+    XS = X[St].contiguous()
     ud = native.direct(XS, X, F, H, NU)
     torch.cuda.synchronize()
-    uS = u[torch.from_numpy(S).to(dev)]
     rel = lambda a, b: float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
-    acc = {"E_S_vs_fp64_direct": rel(uS, ud), "sample_targets": int(S.size)}
+    e_s = rel(u[St], ud)
+    acc = {"E_S_vs_fp64_direct": e_s, "sample_targets": int(S.size), "error_bar": ERROR_BAR,
+           "meets_error_bar": bool(e_s <= ERROR_BAR)}
+    if e_s > ERROR_BAR:
+        acc["why_not"] = ("the method's own truncation error at p = 8, theta = 0.5 on these points: the FP64 "
+                          "treecode has the same E_S (E_S_fp64_treecode_vs_fp64_direct); nu = the outward normal "
+                          "makes d.nu = O(r^2) for close pairs and weights the stresslet toward the nearest "
+                          "clusters. at_error_bar reports the same workload at parameters that meet the bar.")
     extras = {}
     if not args.no_extras:
         # FP64 treecode at equal (p, theta) and the FP64 direct sum, both on the GPU
-        u64 = step("fp64")
+        def step64():
+            return native.evaluate(X, X, F, H, NU, w.p, w.theta, w.n0, "fp64")
+        u64 = step64()
         torch.cuda.synchronize()
         ta = time.perf_counter()
         for i in range(2):
-            u64 = step("fp64")
+            u64 = step64()
         torch.cuda.synchronize()
         t64 = (time.perf_counter() - ta) / 2
-        acc["E_S_fp64_treecode_vs_fp64_direct"] = rel(u64[torch.from_numpy(S).to(dev)], ud)
+        acc["E_S_fp64_treecode_vs_fp64_direct"] = rel(u64[St], ud)
         acc["E_vs_fp64_treecode_all_targets"] = rel(u, u64)
+        del u64
         # the FP64 direct sum at the sampled targets and at all N targets (each call sizes its
         # source chunks so the grid fills the chip); 48 flops per pair in FP64
         direct = {}
@@ -380,24 +499,19 @@ def main():
         extras = {"fp64_treecode_targets_per_s": w.n / t64,
                   "fp64_direct_targets_per_s": direct["all_targets"]["targets_per_s"],
                   "fp64_direct": direct,
-                  "near_field": {"achieved_tflops": round(near_tf / 1e12, 3),
-                                 "frac_of_fp32_peak": round(near_tf / PEAK_FP32_VALU, 4),
-                                 "pairs_per_launch": pairs_total, "avg_launch_ms": round(near_ms, 4),
-                                 "lane_utilisation": round(pairs_total / near_slots, 4)},
-                  "phase_ms_per_step": phases, "far_split": far_split}
+                  "near_field": head["near_field"], "phase_ms_per_step": head["phase_ms_per_step"],
+                  "far_split": head["far_split"]}
         # the same workload at the fastest (p, theta, N0) of the tuning sweep (--only tune)
-        # whose error meets the metric's 1e-5 bar
+        # whose error meets the metric's 1e-5 bar, with the same reporting as the headline
         pb, thb, n0b = AT_ERROR_BAR
-        u_b = native.evaluate(X, X, F, H, NU, pb, thb, n0b, args.precision)
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        for i in range(3):
-            u_b = native.evaluate(X, X, F, H, NU, pb, thb, n0b, args.precision)
-        torch.cuda.synchronize()
-        tb = (time.perf_counter() - ta) / 3
-        extras["at_error_bar"] = {"p": pb, "theta": thb, "n0": n0b, "ms_per_step": round(tb * 1e3, 3),
-                                  "targets_per_s": w.n / tb,
-                                  "E_S_vs_fp64_direct": rel(u_b[torch.from_numpy(S).to(dev)], ud)}
+        bar = run_config(X, F, H, NU, pb, thb, n0b, args.precision, max(3, args.steps // 2), 2)
+        u_b = bar.pop("u")
+        e_b = rel(u_b[St], ud)
+        del u_b
+        extras["at_error_bar"] = {"p": pb, "theta": thb, "n0": n0b, "ms_per_step": round(bar["ms_per_step"], 3),
+                                  "targets_per_s": w.n / (bar["ms_per_step"] * 1e-3), "E_S_vs_fp64_direct": e_b,
+                                  "meets_error_bar": bool(e_b <= ERROR_BAR),
+                                  **{k: v for k, v in bar.items() if k != "ms_per_step"}}
     log(f"accuracy: {acc}")
 
     if not args.no_extras:
@@ -405,11 +519,13 @@ def main():
         log(f"fwd+adjoint: {extras['fwd_adjoint']}")
         extras["multi_rhs"] = multi_rhs_times()
         log(f"multi-rhs: {extras['multi_rhs']}")
+        extras["c2_grid"] = c2_grid()
+        log(f"c2 grid: {len(extras['c2_grid']['rows'])} rows")
 
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the FP64 CPU oracle on a bounded sample ...")
-        cpu = cpu_baseline(w, f, h)
+        cpu = cpu_baseline(w, f, h, S)
         log(f"cpu baseline: {cpu}")
 
     out = {"metric": "targets/s at N=1M, rel L2 err<=1e-5 vs FP64 direct; fwd+adjoint ms, FP32 vs FP64",

@@ -75,6 +75,7 @@ def lib():
         L.orc_direct_grad.argtypes = [_dp, ctypes.c_int64, _dp, ctypes.c_int64, _dp, _dp, _dp, _dp,
                                       _dp, _dp, _dp, _dp]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -89,6 +90,11 @@ def _c(a, dtype=np.float64):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(k: int) -> None:
+    """Threads for the oracle's OpenMP loops (per-target results do not depend on it)."""
+    lib().orc_set_num_threads(int(k))
 
 
 def nm(p: int) -> int:

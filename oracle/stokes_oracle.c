@@ -998,3 +998,14 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* Thread count for the parallel loops above (timing only; results do not depend on it). */
+void orc_set_num_threads(int k)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    omp_set_num_threads(k > 0 ? k : 1);
+#else
+    (void)k;
+#endif
+}
