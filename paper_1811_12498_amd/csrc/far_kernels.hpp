@@ -48,6 +48,22 @@ __device__ inline int32_t xcd_group(int32_t ngroups) {
 }
 inline unsigned xcd_blocks(int32_t ngroups) { return unsigned(((ngroups + 7) >> 3) << 3); }
 
+// block index -> work item for item lists whose cost varies along the list (one leaf or
+// cluster per run of items, runs of very different lengths and leaf sizes): runs of
+// XCD_CHUNK consecutive items are dealt to the eight XCDs in turn, so every XCD gets an
+// even share of the work (contiguous eighths of the 1M-sphere near items differ by up to
+// 1.5x in cost) while neighbouring items, which read the same source records, still share
+// an L2.  Indices run over [0, xcd_item_blocks(n)); those >= n have no item.
+constexpr int32_t XCD_CHUNK = 16;
+__device__ inline int32_t xcd_item() {
+    const int32_t j = int32_t(blockIdx.x >> 3);
+    return ((j / XCD_CHUNK) * 8 + int32_t(blockIdx.x & 7)) * XCD_CHUNK + j % XCD_CHUNK;
+}
+inline unsigned xcd_item_blocks(int32_t nitems) {
+    const int32_t chunks = (nitems + XCD_CHUNK - 1) / XCD_CHUNK;
+    return unsigned(((chunks + 7) / 8) * 8 * XCD_CHUNK);
+}
+
 // defined in far_impl.hpp, instantiated per Taylor order in far_p*.hip / fark_p*.hip
 template <int P, typename T, int KB> void launch_far(const FarArgs &a, hipStream_t s);
 template <int P, typename T, int KB> void launch_far_sparse(const FarSparseArgs &a, hipStream_t s);

@@ -261,7 +261,7 @@ struct NearArgs {
 // sides in blocks of KB.  Items of one leaf are consecutive and go to one XCD, so the
 // leaf's records are shared in its L2.
 template <typename T, int KB> __global__ __launch_bounds__(64) void k_near(NearArgs a) {
-    const int32_t it = xcd_group(a.nitems);
+    const int32_t it = xcd_item();
     if (it >= a.nitems) return;
     const int lane = threadIdx.x;
     const int32_t c = a.item_leaf[it];
@@ -381,7 +381,7 @@ __device__ inline void near_mfma_leaf(const double *__restrict__ geo, const floa
 }
 
 __global__ __launch_bounds__(64) void k_near_mfma(NearArgs a) {
-    const int32_t it = xcd_group(a.nitems);
+    const int32_t it = xcd_item();
     if (it >= a.nitems) return;
     const int lane = threadIdx.x;
     const int tl = lane & 15, q4 = lane >> 4;
@@ -460,7 +460,7 @@ __global__ void k_near_reduce(const T *__restrict__ part, const int32_t *__restr
 
 template <typename T, int KB> void launch_near(const NearArgs &na, hipStream_t s) {
     if (na.nitems > 0) {
-        hipLaunchKernelGGL((k_near<T, KB>), dim3(xcd_blocks(na.nitems)), dim3(64), 0, s, na);
+        hipLaunchKernelGGL((k_near<T, KB>), dim3(xcd_item_blocks(na.nitems)), dim3(64), 0, s, na);
         STK_CHECK_LAUNCH();
     }
 }
@@ -584,7 +584,7 @@ void near_field(Tree &t, Plan &pl, double *unear, hipStream_t s) {
     } else {
         if (pl.tiles.near_mfma) {
             if (na.nitems > 0) {
-                hipLaunchKernelGGL(k_near_mfma, dim3(xcd_blocks(na.nitems)), dim3(64), 0, s, na);
+                hipLaunchKernelGGL(k_near_mfma, dim3(xcd_item_blocks(na.nitems)), dim3(64), 0, s, na);
                 STK_CHECK_LAUNCH();
             }
         } else if (pl.tiles.near_kb == 4)
