@@ -73,28 +73,53 @@ __device__ inline void pair_mixed(double x0, double x1, double x2, const double 
 }
 
 // sum over sources [s, s + n) of one leaf for KB right-hand sides; wr points at source
-// 0's weights of the first of them and ws is the per-source stride (both wave-uniform);
-// records are read NBATCH at a time (one wait on the scalar cache per batch)
-template <typename T, bool CHECK, int KB>
+// 0's weights of the first of them and ws is the per-source stride (both wave-uniform).
+// The records are walked with uniform pointers advanced once per batch of NBATCH
+// sources, read at constant offsets (WS = ws known at compile time when the call has
+// exactly KB right-hand sides; 0 = the runtime stride), so the scalar loads of a batch
+// merge into a few wide ones and no address is rebuilt per source.
+template <typename T, bool CHECK, int KB, int WS>
 __device__ inline void near_leaf(const double *__restrict__ geo_g, const T *__restrict__ wr_g, int ws, int32_t s,
                                  int32_t n, double x0, double x1, double x2, T (*u)[3]) {
     constexpr int NBATCH = KB == 1 ? 4 : (KB == 2 ? 2 : 1);
+    const int wstride = WS ? WS : ws;
     // the records are not written while the kernel runs: read them as constant memory, so
     // the partial stores between right-hand-side blocks do not turn them into vector loads
-    const STK_CONST_AS double *geo = (const STK_CONST_AS double *)(geo_g);
-    const STK_CONST_AS T *wr = (const STK_CONST_AS T *)(wr_g);
-    int32_t j = s;
-    for (; j + NBATCH <= s + n; j += NBATCH) {
+    const STK_CONST_AS double *g = (const STK_CONST_AS double *)(geo_g) + 6 * int64_t(s);
+    const STK_CONST_AS T *w = (const STK_CONST_AS T *)(wr_g) + int64_t(s) * wstride;
+    int32_t left = n;
+    // a batch's records as single aggregates (one base address, merged wide loads)
+    struct GeoBatch {
+        double v[NBATCH][6];
+    };
+    struct WtsBatch {
+        T v[NBATCH][KB][6];
+    };
+    for (; left >= NBATCH; left -= NBATCH, g += 6 * NBATCH, w += NBATCH * wstride) {
         double gb[NBATCH][6];
         T wb[NBATCH][KB][6];
+        {
+            const GeoBatch gg = *(const STK_CONST_AS GeoBatch *)g;
 #pragma unroll
-        for (int b = 0; b < NBATCH; ++b) {
+            for (int b = 0; b < NBATCH; ++b)
 #pragma unroll
-            for (int q = 0; q < 6; ++q) gb[b][q] = geo[6 * int64_t(j + b) + q];
+                for (int q = 0; q < 6; ++q) gb[b][q] = gg.v[b][q];
+        }
+        if constexpr (WS == 6 * KB) {
+            const WtsBatch ww = *(const STK_CONST_AS WtsBatch *)w;
 #pragma unroll
-            for (int r = 0; r < KB; ++r)
+            for (int b = 0; b < NBATCH; ++b)
 #pragma unroll
-                for (int q = 0; q < 6; ++q) wb[b][r][q] = wr[int64_t(j + b) * ws + 6 * r + q];
+                for (int r = 0; r < KB; ++r)
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) wb[b][r][q] = ww.v[b][r][q];
+        } else {
+#pragma unroll
+            for (int b = 0; b < NBATCH; ++b)
+#pragma unroll
+                for (int r = 0; r < KB; ++r)
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) wb[b][r][q] = w[b * wstride + 6 * r + q];
         }
 #pragma unroll
         for (int b = 0; b < NBATCH; ++b) {
@@ -106,15 +131,15 @@ __device__ inline void near_leaf(const double *__restrict__ geo_g, const T *__re
                                       reinterpret_cast<float(*)[3]>(u));
         }
     }
-    for (; j < s + n; ++j) {
+    for (; left > 0; --left, g += 6, w += wstride) {
         double gc[6];
         T wc[KB][6];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) gc[q] = geo[6 * int64_t(j) + q];
+        for (int q = 0; q < 6; ++q) gc[q] = g[q];
 #pragma unroll
         for (int r = 0; r < KB; ++r)
 #pragma unroll
-            for (int q = 0; q < 6; ++q) wc[r][q] = wr[int64_t(j) * ws + 6 * r + q];
+            for (int q = 0; q < 6; ++q) wc[r][q] = w[6 * r + q];
         if constexpr (sizeof(T) == 8)
             pair_f64<CHECK, KB>(x0, x1, x2, gc, reinterpret_cast<const double(*)[6]>(wc),
                                 reinterpret_cast<double(*)[3]>(u));
@@ -291,10 +316,17 @@ template <typename T, int KB> __global__ __launch_bounds__(64) void k_near(NearA
 #pragma unroll
         for (int r = 0; r < KB; ++r) u[r][0] = u[r][1] = u[r][2] = T(0);
         const T *__restrict__ wr = wts + 6 * r0;
-        if (any_close)
-            near_leaf<T, true, KB>(a.geo, wr, ws, s, n, x0, x1, x2, u);
-        else
-            near_leaf<T, false, KB>(a.geo, wr, ws, s, n, x0, x1, x2, u);
+        if (K == KB) {
+            if (any_close)
+                near_leaf<T, true, KB, 6 * KB>(a.geo, wr, ws, s, n, x0, x1, x2, u);
+            else
+                near_leaf<T, false, KB, 6 * KB>(a.geo, wr, ws, s, n, x0, x1, x2, u);
+        } else {
+            if (any_close)
+                near_leaf<T, true, KB, 0>(a.geo, wr, ws, s, n, x0, x1, x2, u);
+            else
+                near_leaf<T, false, KB, 0>(a.geo, wr, ws, s, n, x0, x1, x2, u);
+        }
         if (on) {
             T *o = static_cast<T *>(a.part) + (int64_t(slot) * K + r0) * 3;
 #pragma unroll
