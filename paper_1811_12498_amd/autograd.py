@@ -16,11 +16,15 @@ from . import _native as native
 class StokesTreecode(torch.autograd.Function):
     @staticmethod
     def forward(ctx, targets, sources, f, h, nu, p: int, theta: float, n0: int, precision: str = "mixed"):
+        # the adjoint applies the transpose of a one-right-hand-side operator: a batch of K
+        # (f, h) sets can be evaluated, but not differentiated, through this function
+        if f.dim() == 3 and f.shape[0] > 1 and any(ctx.needs_input_grad[:4]):
+            raise ValueError("stokes_treecode: gradients need one right-hand side (f, h of shape (N, 3)); "
+                             f"got K = {f.shape[0]}")
         args = [t.detach().contiguous() for t in (targets, sources, f, h, nu)]
         u, plan = native.evaluate(*args, p, theta, n0, precision, keep_plan=True)
         ctx.plan = plan
         ctx.n_sources = sources.shape[0]
-        ctx.same = targets.data_ptr() == sources.data_ptr()
         return u
 
     @staticmethod

@@ -184,3 +184,18 @@ def test_adjoint_after_cluster_major_forward(nat, orc, prec, tol):
     for key, r in zip(("f", "h", "sources", "targets"), ref):
         err = orc.rel_l2(g[key].cpu().numpy(), r)
         assert err < tol, (key, err)
+
+
+def test_autograd_rejects_multi_rhs_gradients(nat):
+    """K > 1 right-hand sides evaluate through the Function, but asking for gradients fails
+    in forward (the adjoint is that of a one-right-hand-side operator)."""
+    import torch
+    from paper_1811_12498_amd.autograd import stokes_treecode
+    w = W.cube(2000, seed=37, n0=64, k=3)
+    X, NU = _t(w.src), _t(w.nu)
+    F, H = _t(w.f), _t(w.h)
+    u = stokes_treecode(X, X, F, H, NU, p=4, theta=0.5, n0=64, precision="fp64")
+    assert u.shape == (3, w.n, 3)
+    with pytest.raises(ValueError, match="one right-hand side"):
+        stokes_treecode(X, X, F.clone().requires_grad_(True), H, NU, p=4, theta=0.5, n0=64, precision="fp64")
+    del torch
