@@ -161,11 +161,26 @@ def run_config(X, F, H, NU, p, theta, n0, prec, steps, warmup):
     near_tf = near_flops / (near_ms * 1e-3)
     kname = f"k_far<{p},{'float' if prec == 'mixed' else 'double'},1>"
     traffic = profiled_traffic(kname) if (p == 8 and theta == 0.5 and n0 == 1000 and prec == "mixed") else None
+    # model work: the algorithmic count per interaction of the 12-channel form
     roofline = {"bound": "alu", "achieved": round(far_tf / 1e12, 3), "peak": peak / 1e12, "unit": "TFLOP/s",
                 "frac": round(far_tf / peak, 4), "traffic": traffic, "kernel": kname,
                 "far_interactions_per_launch": far_dense, "flops_per_interaction": far_flops_per_interaction(p),
                 "avg_launch_ms": round(far_ms, 4), "far_entries": dense_entries,
                 "lane_utilisation": round(far_dense / (64.0 * max(dense_entries, 1)), 4)}
+    metric_point = p == 8 and theta == 0.5 and n0 == 1000 and prec == "mixed"
+    vr = profiled_valu(kname) if metric_point else None
+    if vr:
+        # executed work (counter record): FP32 flops the kernel's instructions perform per
+        # entry, over the live launch time, against the same peak
+        ex = dense_entries * vr["exec_fp32_flops_per_entry"] / (far_ms * 1e-3)
+        roofline["executed"] = {"fp32_flops_per_entry": vr["exec_fp32_flops_per_entry"],
+                                "fp32_flops_per_interaction": round(vr["exec_fp32_flops_per_entry"] / 64, 1),
+                                "achieved_tflops": round(ex / 1e12, 3), "frac": round(ex / peak, 4),
+                                "valu_insts_per_entry": vr["valu_insts_per_entry"],
+                                "valu_issue_per_cu_cycle": vr["valu_issue_per_cu_cycle"],
+                                "issue_frac_of_dual_issue_peak": round(vr["valu_issue_per_cu_cycle"] / 2, 3),
+                                "clock_ghz_under_load": vr["clock_ghz"],
+                                "source": "rocprofv3 counters, profiles/valu_counters_sphere1m_p8_mixed.md"}
     sparse_ms = prof["far_sparse"][0] / max(prof["far_sparse"][1], 1)
     far_split = {"sparse_max_targets": sparse_max, "sparse_interactions": sparse_inter,
                  "sparse_entries": int(pinfo["far_entries"] - dense_entries), "sparse_ms": round(sparse_ms, 4),
@@ -175,6 +190,14 @@ def run_config(X, F, H, NU, p, theta, n0, prec, steps, warmup):
                   "frac_of_fp32_peak" if prec == "mixed" else "frac_of_fp64_peak": round(near_tf / peak, 4),
                   "pairs_per_launch": pairs_total, "avg_launch_ms": round(near_ms, 4),
                   "lane_utilisation": round(pairs_total / max(near_slots, 1), 4)}
+    nr = profiled_valu(near_field["kernel"]) if metric_point else None
+    if nr:
+        fl = pairs_total * (nr["exec_fp32_flops_per_pair"] + nr["exec_fp64_flops_per_pair"]) / (near_ms * 1e-3)
+        near_field["executed"] = {"flops_per_pair": round(nr["exec_fp32_flops_per_pair"] + nr["exec_fp64_flops_per_pair"], 2),
+                                  "achieved_tflops": round(fl / 1e12, 3), "frac_of_fp32_peak": round(fl / PEAK_FP32_VALU, 4),
+                                  "valu_insts_per_64_pairs": nr["valu_insts_per_64_pairs"],
+                                  "valu_issue_per_cu_cycle": nr["valu_issue_per_cu_cycle"],
+                                  "source": "rocprofv3 counters, profiles/valu_counters_sphere1m_p8_mixed.md"}
     return {"ms_per_step": (t1 - t0) * 1e3 / steps, "u": u, "phase_ms_per_step": phases, "roofline": roofline,
             "near_field": near_field, "far_split": far_split}
 
@@ -208,6 +231,23 @@ def c2_grid(reps=3):
                              "targets_per_s": w.n / (ms * 1e-3), "E_S": e})
     return {"workload": f"cube N={w.n} in [-1,1]^3, N0={w.n0}, E on {w.sample.size} targets vs FP64 direct",
             "rows": rows}
+
+
+def profiled_valu(kernel: str):
+    """Per-unit executed work of `kernel` from the committed rocprofv3 VALU counter record
+    (profiles/valu_counters_sphere1m_p8_mixed.md), or None when its sources have changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "valu_counters_sphere1m_p8_mixed.md")
+    try:
+        text = open(path).read()
+        rec = json.loads(text.split("<!-- valu-record ", 1)[1].split(" -->", 1)[0])[kernel]
+    except (OSError, IndexError, ValueError, KeyError):
+        return None
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as fh:
+            h.update(fh.read())
+    return rec if h.hexdigest() == rec["source_sha256"] else None
 
 
 def profiled_traffic(kernel: str):
@@ -415,7 +455,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the treecode would shard over targets with replicated sources; see DESIGN.md)",
+              "(the treecode would shard over targets with replicated sources)",
               file=sys.stderr)
         sys.exit(2)
 
