@@ -75,6 +75,13 @@ def lib():
         L.orc_direct_grad.argtypes = [_dp, ctypes.c_int64, _dp, ctypes.c_int64, _dp, _dp, _dp, _dp,
                                       _dp, _dp, _dp, _dp]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_reg_taylor.argtypes = [_dp, ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp]
+        L.orc_reg_coeffs.argtypes = [_dp, ctypes.c_double, ctypes.c_int, _dp, _dp]
+        L.orc_reg_far.argtypes = [_dp, ctypes.c_double, ctypes.c_int, _dp, _dp, _dp]
+        L.orc_reg_direct.argtypes = [_dp, ctypes.c_int64, _dp, ctypes.c_int64, _dp, _dp, _dp, ctypes.c_double, _dp]
+        L.orc_reg_direct_tensor.argtypes = L.orc_reg_direct.argtypes
+        L.orc_reg_treecode.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int, ctypes.c_double,
+                                       ctypes.c_double, _dp, ctypes.c_int64, _dp, _i64p, _i64p, _i64p]
         L.orc_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
@@ -290,6 +297,53 @@ def frozen_adjoint(tree: Tree, L: Lists, src, f, h, nu, p: int, tgt, w):
                              L.near_ptr.ctypes.data_as(_i64p), L.near_nodes.ctypes.data_as(_i32p), _d(w),
                              _d(gf), _d(gh), _d(gs), _d(gt))
     return gf, gh, gs, gt
+
+
+# ---- regularized Stokeslets and stresslets (the extension named in Sec. 7) ----
+
+def reg_taylor(d, eps: float, nu2: int, P: int) -> np.ndarray:
+    """Coefficients (1/k!) D_y^k of (|d|^2 + eps^2)^(-nu2/2), dense (P+1)^3 like coulomb_taylor."""
+    d = _c(d)
+    a = np.zeros((P + 1) ** 3)
+    lib().orc_reg_taylor(_d(d), float(eps), int(nu2), int(P), _d(a))
+    return a.reshape(P + 1, P + 1, P + 1)
+
+
+def reg_coeffs(d, eps: float, p: int):
+    """a^k_ij (nm,3,3) and at^k_ijl (nm,3,3,3) of the regularized kernels at d."""
+    d = _c(d)
+    a = np.zeros((nm(p), 3, 3))
+    at = np.zeros((nm(p), 3, 3, 3))
+    lib().orc_reg_coeffs(_d(d), float(eps), int(p), _d(a), _d(at))
+    return a, at
+
+
+def reg_far(d, eps: float, p: int, M, Mt) -> np.ndarray:
+    d, M, Mt = _c(d), _c(M), _c(Mt)
+    u = np.zeros(3)
+    lib().orc_reg_far(_d(d), float(eps), int(p), _d(M), _d(Mt), _d(u))
+    return u
+
+
+def reg_direct(tgt, src, f, h, nu, eps: float, tensor: bool = False) -> np.ndarray:
+    """Regularized direct sum (contracted, or with S^eps and T^eps formed as tensors)."""
+    tgt, src, f, h, nu = (_c(a) for a in (tgt, src, f, h, nu))
+    u = np.zeros_like(tgt)
+    fn = lib().orc_reg_direct_tensor if tensor else lib().orc_reg_direct
+    fn(_d(tgt), tgt.shape[0], _d(src), src.shape[0], _d(f), _d(h), _d(nu), float(eps), _d(u))
+    return u
+
+
+def reg_treecode(tree: Tree, src, f, h, nu, M, Mt, p: int, theta: float, eps: float, tgt) -> TreecodeResult:
+    """Algorithm 1 with the regularized kernels (same tree, moments and MAC)."""
+    src, f, h, nu, M, Mt, tgt = (_c(a) for a in (src, f, h, nu, M, Mt, tgt))
+    m = tgt.shape[0]
+    u = np.zeros((m, 3))
+    nfar, nnear, npairs = (np.zeros(m, np.int64) for _ in range(3))
+    lib().orc_reg_treecode(ctypes.c_void_p(tree.handle), _d(src), _d(f), _d(h), _d(nu), _d(M), _d(Mt), p,
+                           float(theta), float(eps), _d(tgt), m, _d(u), nfar.ctypes.data_as(_i64p),
+                           nnear.ctypes.data_as(_i64p), npairs.ctypes.data_as(_i64p))
+    return TreecodeResult(u, nfar, nnear, npairs)
 
 
 def rel_l2(a, b) -> float:

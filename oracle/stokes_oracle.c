@@ -920,7 +920,6 @@ void orc_frozen_adjoint(const orc_tree *t, const double *src, const double *f, c
             stresslet_coeffs_from_b(d, p, b, P, at);
             double *LMc = LM + (size_t)c * nm * 3, *LTc = LT + (size_t)c * nm * 9;
             for (int q = 0; q < nm; q++) {
-                const int k[3] = {kk[3 * q], kk[3 * q + 1], kk[3 * q + 2]};
                 for (int ii = 0; ii < 3; ii++) {
                     for (int j = 0; j < 3; j++) {
                         LMc[3 * q + j] += wi[ii] * a[(q * 3 + ii) * 3 + j];
@@ -1008,4 +1007,248 @@ void orc_set_num_threads(int k)
 #else
     (void)k;
 #endif
+}
+
+/* ------------------------------------------------------------------------- */
+/* Regularized Stokeslets and stresslets (the extension Sec. 7 names as      */
+/* future work; Cortez 2001, Cortez-Fauci-Medovikov 2005).                    */
+/* ------------------------------------------------------------------------- */
+/*
+ * Kernels, with the paper's normalisation (no 1/(8 pi); at eps = 0 they are
+ * eqs. Stokeslet and stresslet exactly), R^2 = |d|^2 + eps^2:
+ *   S^eps_ij  = delta_ij (|d|^2 + 2 eps^2) / R^3 + d_i d_j / R^3
+ *               (the regularized Stokeslet of the 3D method of regularized
+ *               Stokeslets, blob 15 eps^4 / (8 pi R^7));
+ *   T^eps_ijl = [d_i d_j d_l + (eps^2/2)(delta_ij d_l + delta_jl d_i + delta_il d_j)] / R^5
+ *               (-1/6 of the stress tensor -delta_il p_j + d_l S_ij + d_i S_lj of
+ *               that flow, p_j = d_j (2|d|^2 + 5 eps^2) / R^5; at eps = 0 this is
+ *               -1/6 of the classical -6 d_i d_j d_l / r^5).
+ * With eps > 0 both are finite at d = 0, so every pair is summed (the self
+ * pair adds 2 f / eps); with eps = 0 the pair d = 0 is skipped as above.
+ *
+ * Far field: the order-p Taylor expansion in y about the cluster centre,
+ *   u_i = sum_k a^k_ij M_j^k + at^k_ijl Mt_jl^k,
+ * the particle-cluster form of Sec. 3 with the regularized kernels.  With
+ * phi_nu = R^(-2 nu) and g^k_nu its coefficients (1/k!) D_y^k phi_nu at y_c,
+ * the product rule on the linear factors d = x - y (D_y d_i = -e_i) gives
+ *   a^k_ij  = delta_ij (g^k_1/2 + eps^2 g^k_3/2)
+ *             + d_i d_j g^k - d_i g^(k-e_j) - d_j g^(k-e_i) + g^(k-e_i-e_j)   (g = g_3/2)
+ *   at^k_ijl = d_i d_j d_l e^k - d_j d_l e^(k-e_i) - d_i d_l e^(k-e_j) - d_i d_j e^(k-e_l)
+ *             + d_l e^(k-e_i-e_j) + d_j e^(k-e_i-e_l) + d_i e^(k-e_j-e_l) - e^(k-e_i-e_j-e_l)
+ *             + (eps^2/2) [delta_ij L_l + delta_jl L_i + delta_il L_j],  L_m = d_m e^k - e^(k-e_m)
+ * (e = g_5/2; terms with a negative index vanish).  The coefficients of phi_nu
+ * follow recurrence_1 generalised to R^2 = |d|^2 + eps^2 and exponent nu:
+ *   n R^2 g^k = (2n + 2nu - 2) sum_i d_i g^(k-e_i) - (n + 2nu - 2) sum_i g^(k-2e_i),  n = ||k||,
+ * which for nu = 1/2, eps = 0 is recurrence_1.
+ */
+
+/* coefficients of (|d|^2 + eps^2)^(-nu2/2) for ||k|| <= P, dense (P+1)^3 as b */
+void orc_reg_taylor(const double d[3], double eps, int nu2, int P, double *a)
+{
+    const int S = P + 1;
+    const double R2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + eps * eps;
+    for (int i = 0; i < S * S * S; i++) a[i] = 0.0;
+    a[0] = pow(R2, -0.5 * nu2);
+    for (int n = 1; n <= P; n++)
+        for (int k1 = n; k1 >= 0; k1--)
+            for (int k2 = n - k1; k2 >= 0; k2--) {
+                const int k3 = n - k1 - k2;
+                double s1 = 0.0, s2 = 0.0;
+                for (int i = 0; i < 3; i++) {
+                    int q[3] = {k1, k2, k3};
+                    q[i] -= 1;
+                    if (q[i] >= 0) s1 += d[i] * bget(a, P, q[0], q[1], q[2]);
+                    q[i] -= 1;
+                    if (q[i] >= 0) s2 += bget(a, P, q[0], q[1], q[2]);
+                }
+                a[(k1 * S + k2) * S + k3] = ((2.0 * n + nu2 - 2.0) * s1 - (n + nu2 - 2.0) * s2) / (n * R2);
+            }
+}
+
+/* g^(k - sum of shifts), 0 when an index goes negative */
+static double rget(const double *a, int P, const int k[3], int i0, int i1, int i2)
+{
+    int q[3] = {k[0], k[1], k[2]};
+    if (i0 >= 0) q[i0]--;
+    if (i1 >= 0) q[i1]--;
+    if (i2 >= 0) q[i2]--;
+    if (q[0] < 0 || q[1] < 0 || q[2] < 0) return 0.0;
+    return bget(a, P, q[0], q[1], q[2]);
+}
+
+/* a^k_ij (nm,3,3) and at^k_ijl (nm,3,3,3) of the regularized kernels at d, ||k|| <= p */
+void orc_reg_coeffs(const double d[3], double eps, int p, double *a, double *at)
+{
+    const int nm = orc_nm(p), S = p + 1;
+    double *g1 = malloc(sizeof(double) * S * S * S);
+    double *g3 = malloc(sizeof(double) * S * S * S);
+    double *g5 = malloc(sizeof(double) * S * S * S);
+    orc_reg_taylor(d, eps, 1, p, g1);
+    orc_reg_taylor(d, eps, 3, p, g3);
+    orc_reg_taylor(d, eps, 5, p, g5);
+    int32_t *kk = malloc(sizeof(int32_t) * 3 * nm);
+    orc_kindex(p, kk);
+    const double e2 = eps * eps;
+    for (int q = 0; q < nm; q++) {
+        const int k[3] = {kk[3 * q], kk[3 * q + 1], kk[3 * q + 2]};
+        const double G1 = bget(g1, p, k[0], k[1], k[2]), G3 = bget(g3, p, k[0], k[1], k[2]);
+        const double E = bget(g5, p, k[0], k[1], k[2]);
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++) {
+                double v = d[i] * d[j] * G3 - d[i] * rget(g3, p, k, j, -1, -1) - d[j] * rget(g3, p, k, i, -1, -1) +
+                           rget(g3, p, k, i, j, -1);
+                if (i == j) v += G1 + e2 * G3;
+                a[(q * 3 + i) * 3 + j] = v;
+                for (int l = 0; l < 3; l++) {
+                    double w = d[i] * d[j] * d[l] * E - d[j] * d[l] * rget(g5, p, k, i, -1, -1) -
+                               d[i] * d[l] * rget(g5, p, k, j, -1, -1) - d[i] * d[j] * rget(g5, p, k, l, -1, -1) +
+                               d[l] * rget(g5, p, k, i, j, -1) + d[j] * rget(g5, p, k, i, l, -1) +
+                               d[i] * rget(g5, p, k, j, l, -1) - rget(g5, p, k, i, j, l);
+                    double lin = 0.0;
+                    if (i == j) lin += d[l] * E - rget(g5, p, k, l, -1, -1);
+                    if (j == l) lin += d[i] * E - rget(g5, p, k, i, -1, -1);
+                    if (i == l) lin += d[j] * E - rget(g5, p, k, j, -1, -1);
+                    at[((q * 3 + i) * 3 + j) * 3 + l] = w + 0.5 * e2 * lin;
+                }
+            }
+    }
+    free(kk);
+    free(g5);
+    free(g3);
+    free(g1);
+}
+
+/* far-field velocity of one cluster: sum_k a^k_ij M_j^k + at^k_ijl Mt_jl^k */
+void orc_reg_far(const double d[3], double eps, int p, const double *M, const double *Mt, double u[3])
+{
+    const int nm = orc_nm(p);
+    double *a = malloc(sizeof(double) * nm * 9);
+    double *at = malloc(sizeof(double) * nm * 27);
+    orc_reg_coeffs(d, eps, p, a, at);
+    u[0] = u[1] = u[2] = 0.0;
+    for (int q = 0; q < nm; q++)
+        for (int i = 0; i < 3; i++) {
+            for (int j = 0; j < 3; j++) {
+                u[i] += a[(q * 3 + i) * 3 + j] * M[3 * q + j];
+                for (int l = 0; l < 3; l++) u[i] += at[((q * 3 + i) * 3 + j) * 3 + l] * Mt[9 * q + 3 * j + l];
+            }
+        }
+    free(at);
+    free(a);
+}
+
+/* one source's regularized contribution, contracted:
+ *   u_i += f_i (|d|^2 + 2 eps^2)/R^3 + d_i (d.f)/R^3
+ *        + [d_i (d.h)(d.nu) + (eps^2/2)(h_i (d.nu) + d_i (h.nu) + nu_i (d.h))] / R^5 */
+static void reg_pair(const double x[3], const double y[3], const double f[3], const double h[3],
+                     const double nu[3], double eps, double u[3])
+{
+    const double d0 = x[0] - y[0], d1 = x[1] - y[1], d2 = x[2] - y[2];
+    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    if (r2 == 0.0 && eps == 0.0) return;
+    const double e2 = eps * eps;
+    const double R2 = r2 + e2;
+    const double R = sqrt(R2);
+    const double R3 = R2 * R, R5 = R3 * R2;
+    const double df = d0 * f[0] + d1 * f[1] + d2 * f[2];
+    const double dh = d0 * h[0] + d1 * h[1] + d2 * h[2];
+    const double dn = d0 * nu[0] + d1 * nu[1] + d2 * nu[2];
+    const double hn = h[0] * nu[0] + h[1] * nu[1] + h[2] * nu[2];
+    const double cs = (r2 + 2.0 * e2) / R3;
+    const double dd[3] = {d0, d1, d2};
+    for (int i = 0; i < 3; i++)
+        u[i] += f[i] * cs + dd[i] * df / R3 +
+                (dd[i] * dh * dn + 0.5 * e2 * (h[i] * dn + dd[i] * hn + nu[i] * dh)) / R5;
+}
+
+/* regularized direct sum over all sources, for each target */
+void orc_reg_direct(const double *tgt, int64_t m, const double *src, int64_t n, const double *f,
+                    const double *h, const double *nu, double eps, double *u)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < m; t++) {
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int64_t s = 0; s < n; s++)
+            reg_pair(tgt + 3 * t, src + 3 * s, f + 3 * s, h + 3 * s, nu + 3 * s, eps, acc);
+        u[3 * t + 0] = acc[0];
+        u[3 * t + 1] = acc[1];
+        u[3 * t + 2] = acc[2];
+    }
+}
+
+/* the same sum with S^eps and T^eps formed as tensors */
+void orc_reg_direct_tensor(const double *tgt, int64_t m, const double *src, int64_t n, const double *f,
+                           const double *h, const double *nu, double eps, double *u)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < m; t++) {
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int64_t s = 0; s < n; s++) {
+            double d[3];
+            for (int a = 0; a < 3; a++) d[a] = tgt[3 * t + a] - src[3 * s + a];
+            const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            if (r2 == 0.0 && eps == 0.0) continue;
+            const double R2 = r2 + eps * eps, R = sqrt(R2);
+            for (int i = 0; i < 3; i++)
+                for (int j = 0; j < 3; j++) {
+                    const double Sij = (i == j ? (r2 + 2.0 * eps * eps) / (R2 * R) : 0.0) + d[i] * d[j] / (R2 * R);
+                    acc[i] += Sij * f[3 * s + j];
+                    for (int l = 0; l < 3; l++) {
+                        const double Tijl = (d[i] * d[j] * d[l] + 0.5 * eps * eps *
+                                                                      ((i == j ? d[l] : 0.0) + (j == l ? d[i] : 0.0) +
+                                                                       (i == l ? d[j] : 0.0))) /
+                                            (R2 * R2 * R);
+                        acc[i] += Tijl * h[3 * s + j] * nu[3 * s + l];
+                    }
+                }
+        }
+        for (int a = 0; a < 3; a++) u[3 * t + a] = acc[a];
+    }
+}
+
+typedef struct {
+    const orc_tree *t;
+    const double *pos, *f, *h, *nu, *M, *Mt;
+    int p;
+    double theta, eps;
+} reg_ctx;
+
+/* compute-velocity(x, C) of Algorithm 1 with the regularized kernels */
+static void reg_velocity(const reg_ctx *cx, const double x[3], int64_t c, tc_acc *acc)
+{
+    const orc_tree *t = cx->t;
+    if (mac_accept(t, c, x, cx->theta)) {
+        const int nm = orc_nm(cx->p);
+        double d[3], v[3];
+        for (int a = 0; a < 3; a++) d[a] = x[a] - t->center[3 * c + a];
+        orc_reg_far(d, cx->eps, cx->p, cx->M + (size_t)c * nm * 3, cx->Mt + (size_t)c * nm * 9, v);
+        for (int a = 0; a < 3; a++) acc->u[a] += v[a];
+        acc->nfar++;
+    } else if (t->nchild[c] == 0) {
+        for (int64_t s = t->start[c]; s < t->start[c] + t->count[c]; s++) {
+            const int64_t n = t->perm[s];
+            reg_pair(x, cx->pos + 3 * n, cx->f + 3 * n, cx->h + 3 * n, cx->nu + 3 * n, cx->eps, acc->u);
+        }
+        acc->nnear++;
+        acc->npairs += t->count[c];
+    } else {
+        for (int32_t ch = 0; ch < t->nchild[c]; ch++) reg_velocity(cx, x, t->child0[c] + ch, acc);
+    }
+}
+
+/* regularized treecode velocity at arbitrary targets (same tree, moments and MAC) */
+void orc_reg_treecode(const orc_tree *t, const double *src, const double *f, const double *h, const double *nu,
+                      const double *M, const double *Mt, int p, double theta, double eps, const double *tgt,
+                      int64_t m, double *u, int64_t *nfar, int64_t *nnear, int64_t *npairs)
+{
+    reg_ctx cx = {t, src, f, h, nu, M, Mt, p, theta, eps};
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t i = 0; i < m; i++) {
+        tc_acc acc = {{0.0, 0.0, 0.0}, 0, 0, 0, NULL};
+        reg_velocity(&cx, tgt + 3 * i, 0, &acc);
+        for (int a = 0; a < 3; a++) u[3 * i + a] = acc.u[a];
+        if (nfar) nfar[i] = acc.nfar;
+        if (nnear) nnear[i] = acc.nnear;
+        if (npairs) npairs[i] = acc.npairs;
+    }
 }
