@@ -202,6 +202,86 @@ def run_config(X, F, H, NU, p, theta, n0, prec, steps, warmup):
             "near_field": near_field, "far_split": far_split}
 
 
+def reg_far_flops_per_interaction(p):
+    # regularized far field, explicit form: three coefficient recurrences (11 flops per
+    # multi-index each) and the contraction sum_k a^k_ij M_j^k + at^k_ijl Mt_jl^k (36 terms,
+    # 72 flops per multi-index), + 21 per interaction
+    nm = (p + 1) * (p + 2) * (p + 3) // 6
+    return 33 * nm + 72 * nm + 21
+
+
+REG_NEAR_FLOPS_PER_PAIR = 70  # regularized Stokeslet + stresslet pair, contracted
+
+
+def regularized_times(eps=0.01, ps=(6, 8), theta=0.5, reps=3, n_oracle=400):
+    """Regularized Stokeslets and stresslets (stk_evaluate_regularized, FP64) on the
+    100,000-point [-1, 1]^3 cube (seed 2, N0 = 500), eps = 0.01 (about a third of the mean
+    spacing): time per evaluation, far and near phases with their model rates, E against the
+    same call at theta = 0 (the exact regularized sum) on 1000 seeded targets, and the FP64
+    oracle's regularized treecode timed on the host at a sample of targets."""
+    import torch
+
+    import oracle
+    from paper_1811_12498_amd import native, workloads
+    w = workloads.c2_cube_100k()
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    X, F, H, NU = t(w.src), t(w.f[0]), t(w.h[0]), t(w.nu)
+    St = torch.from_numpy(w.sample).to(dev)
+    native.profile_enable(True)
+    ud = native.evaluate_regularized(X, X, F, H, NU, eps, 0, 0.0, w.n0)
+    torch.cuda.synchronize()
+    native.profile_enable(False)
+    d_prof = native.profile_read()
+    direct_ms = sum(v[0] for v in d_prof.values())
+    rows = []
+    for p in ps:
+        native.evaluate_regularized(X, X, F, H, NU, eps, p, theta, w.n0)
+        torch.cuda.synchronize()
+        native.profile_read()
+        native.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            u = native.evaluate_regularized(X, X, F, H, NU, eps, p, theta, w.n0)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        native.profile_enable(False)
+        prof = native.profile_read()
+        phases = {k: round(v[0] / max(v[1], 1), 3) for k, v in prof.items() if v[1]}
+        # the same interaction counts as the plain evaluation (same tree, MAC and lists)
+        _, plan = native.evaluate(X, X, F, H, NU, p, theta, w.n0, "fp64", keep_plan=True)
+        nfar, _, npairs = native.plan_counts(plan)
+        del plan
+        far_i, pairs = int(nfar.sum()), int(npairs.sum())
+        far_tf = far_i * reg_far_flops_per_interaction(p) / (phases["far"] * 1e-3)
+        near_tf = pairs * REG_NEAR_FLOPS_PER_PAIR / (phases["near"] * 1e-3)
+        e = float(torch.linalg.norm(u[St] - ud[St]) / torch.linalg.norm(ud[St]))
+        rows.append({"p": p, "theta": theta, "ms": round(ms, 3), "targets_per_s": w.n / (ms * 1e-3),
+                     "E_S_vs_exact": e, "phase_ms": phases,
+                     "far": {"kernel": f"k_reg_far<{p}>", "interactions": far_i,
+                             "flops_per_interaction": reg_far_flops_per_interaction(p),
+                             "fp64_tflops": round(far_tf / 1e12, 3), "frac_of_fp64_peak": round(far_tf / PEAK_FP64_VALU, 4)},
+                     "near": {"kernel": "k_near_reg", "pairs": pairs, "flops_per_pair": REG_NEAR_FLOPS_PER_PAIR,
+                              "fp64_tflops": round(near_tf / 1e12, 3),
+                              "frac_of_fp64_peak": round(near_tf / PEAK_FP64_VALU, 4)}})
+    # the oracle beside it: tree + moments for all N, Algorithm 1 at a seeded sample
+    oracle.build(force=False)
+    idx = np.sort(np.random.default_rng(98).choice(w.n, n_oracle, replace=False))
+    p = ps[-1]
+    t0 = time.perf_counter()
+    T = oracle.build_tree(w.src, w.n0)
+    M, Mt = oracle.moments(T, w.src, w.f[0], w.h[0], w.nu, p)
+    t1 = time.perf_counter()
+    oracle.reg_treecode(T, w.src, w.f[0], w.h[0], w.nu, M, Mt, p, theta, eps, w.src[idx])
+    t2 = time.perf_counter()
+    t_job = (t1 - t0) + (t2 - t1) * w.n / n_oracle
+    cpu = {"value": w.n / t_job, "unit": "targets/s", "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": f"p={p}: tree+moments for all {w.n} sources ({t1 - t0:.2f} s) + regularized Algorithm 1 at "
+                     f"{n_oracle} seeded targets ({t2 - t1:.2f} s), extrapolated to {w.n} targets"}
+    return {"workload": f"cube N={w.n} in [-1,1]^3, N0={w.n0}, eps={eps}, FP64 regularized Stokeslets+stresslets",
+            "exact_ms": round(direct_ms, 3), "rows": rows, "cpu_baseline": cpu}
+
+
 def c2_grid(reps=3):
     """The plain method at N = 100,000 uniform in [-1, 1]^3 (seed 2, N0 = 500): p in
     {4, 6, 8, 10} x theta in {0.5, 0.7}, FP64 and mixed; per point one whole-path
@@ -450,7 +530,7 @@ def main():
                     help="also run one plain 256 MiB device copy (a reference for HBM counters)")
     ap.add_argument("--params", nargs=3, metavar=("P", "THETA", "N0"),
                     help="evaluate the metric's points at these treecode parameters instead (for profiling)")
-    ap.add_argument("--only", choices=["fwd_adjoint", "multi_rhs", "table1", "tune", "c2"],
+    ap.add_argument("--only", choices=["fwd_adjoint", "multi_rhs", "table1", "tune", "c2", "regularized"],
                     help="run only this secondary measurement and print its JSON object (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -465,7 +545,8 @@ def main():
 
     if args.only:
         res = {"fwd_adjoint": fwd_adjoint_times, "multi_rhs": multi_rhs_times,
-               "table1": table1_icosphere, "tune": tune_c3, "c2": c2_grid}[args.only]()
+               "table1": table1_icosphere, "tune": tune_c3, "c2": c2_grid,
+               "regularized": regularized_times}[args.only]()
         print(json.dumps(res), flush=True)
         return
 

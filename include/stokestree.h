@@ -142,6 +142,26 @@ stk_status stk_evaluate(const double *targets, int64_t m, const double *sources,
 stk_status stk_evaluate_adjoint(stk_plan *plan, const double *w, double *grad_f, double *grad_h,
                                 double *grad_targets, double *grad_sources, void *stream);
 
+/* The treecode with regularized Stokeslets and stresslets, the extension Sec. 7 names as
+ * future work (kernels of the method of regularized Stokeslets, Cortez 2001 and
+ * Cortez-Fauci-Medovikov 2005, normalised like eqs. Stokeslet and stresslet), FP64, one
+ * right-hand side.  With R^2 = |x - y|^2 + epsilon^2 and d = x - y:
+ *   u_i(x) = sum_n S^eps_ij f_j + T^eps_ijl h_j nu_l,
+ *   S^eps_ij  = delta_ij (|d|^2 + 2 epsilon^2)/R^3 + d_i d_j/R^3,
+ *   T^eps_ijl = [d_i d_j d_l + (epsilon^2/2)(delta_ij d_l + delta_jl d_i + delta_il d_j)]/R^5
+ * (T^eps is -1/6 of the stress of the regularized Stokeslet's flow).  With epsilon > 0
+ * every pair is finite and summed, the coincident one included (it adds 2 f/epsilon);
+ * epsilon = 0 is eq. StoStre and skips it.  Same tree, moments, MAC (eq. MAC) and lists as
+ * stk_evaluate (Algorithm 1); the far field is the order-p Taylor expansion of the
+ * regularized kernels about each accepted cluster's centre (particle-cluster form of
+ * Sec. 3 with coefficients from recurrence_1 generalised to R and to the exponents
+ * -1, -3, -5).  Arguments and layouts as stk_evaluate with k_rhs = 1 (u_out (m,3) FP64,
+ * caller's target order); epsilon finite and >= 0, else STK_EINVAL.  Synchronises
+ * `stream` before returning. */
+stk_status stk_evaluate_regularized(const double *targets, int64_t m, const double *sources, int64_t n,
+                                    const double *f, const double *h, const double *nu, double epsilon, int32_t p,
+                                    double theta, int32_t n0, double *u_out, void *stream);
+
 /* Exact O(m n) direct sum of eq. StoStre in FP64 (contracted form of Sec. 4.1),
  * the reference the treecode is measured against.  Same array conventions. */
 stk_status stk_direct(const double *targets, int64_t m, const double *sources, int64_t n, const double *f,

@@ -24,7 +24,7 @@ _STATUS_NAMES = {STK_EINVAL: "STK_EINVAL", STK_ENOMEM: "STK_ENOMEM", STK_EDEVICE
 
 # every symbol include/stokestree.h declares
 EXPORTS = ["stk_build_tree", "stk_compute_moments", "stk_evaluate_tree", "stk_evaluate", "stk_evaluate_adjoint",
-           "stk_direct", "stk_direct_noalloc",
+           "stk_direct", "stk_direct_noalloc", "stk_evaluate_regularized",
            "stk_tree_info", "stk_tree_export", "stk_tree_export_moments", "stk_plan_counts", "stk_plan_info",
            "stk_plan_export_lists", "stk_plan_far_split", "stk_tiles_set", "stk_tiles_get", "stk_autotune", "stk_tiles_save",
            "stk_tiles_load", "stk_plan_tiles",
@@ -57,6 +57,8 @@ _lib.stk_evaluate.argtypes = [_vp, _i64, _vp, _i64, _vp, _vp, _vp, _i32, _i32, _
                               ctypes.POINTER(_vp), _vp]
 _lib.stk_direct.argtypes = [_vp, _i64, _vp, _i64, _vp, _vp, _vp, _i32, _vp, _vp]
 _lib.stk_direct_noalloc.argtypes = [_vp, _i64, _vp, _i64, _vp, _vp, _vp, _i32, _vp, _vp]
+_lib.stk_evaluate_regularized.argtypes = [_vp, _i64, _vp, _i64, _vp, _vp, _vp, ctypes.c_double, _i32,
+                                          ctypes.c_double, _i32, _vp, _vp]
 _lib.stk_evaluate_adjoint.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.stk_tree_info.argtypes = [_vp, _i64p, _i32p, _dp]
 _lib.stk_tree_export.argtypes = [_vp] + [_vp] * 11
@@ -226,6 +228,18 @@ def direct(targets, sources, f, h, nu) -> torch.Tensor:
     u = torch.empty((m, 3) if k == 1 else (k, m, 3), dtype=torch.float64, device=targets.device)
     _check(_lib.stk_direct(_ptr(targets), m, _ptr(sources), n, _ptr(f), _ptr(h), _ptr(nu), k, _ptr(u),
                            _stream()))
+    return u
+
+
+def evaluate_regularized(targets, sources, f, h, nu, eps: float, p: int, theta: float, n0: int) -> torch.Tensor:
+    """stk_evaluate_regularized: the treecode with regularized Stokeslets and stresslets
+    (FP64, one right-hand side); u of shape (m, 3)."""
+    for t, nm in ((targets, "targets"), (sources, "sources"), (f, "f"), (h, "h"), (nu, "nu")):
+        _dev(t, nm)
+    m, n = targets.shape[0], sources.shape[0]
+    u = torch.empty((m, 3), dtype=torch.float64, device=targets.device)
+    _check(_lib.stk_evaluate_regularized(_ptr(targets), m, _ptr(sources), n, _ptr(f), _ptr(h), _ptr(nu), float(eps),
+                                         int(p), float(theta), int(n0), _ptr(u), _stream()))
     return u
 
 

@@ -271,6 +271,37 @@ stk_status stk_evaluate(const double *targets, int64_t m, const double *sources,
     });
 }
 
+stk_status stk_evaluate_regularized(const double *targets, int64_t m, const double *sources, int64_t n,
+                                    const double *f, const double *h, const double *nu, double epsilon, int32_t p,
+                                    double theta, int32_t n0, double *u_out, void *stream) {
+    return guarded([&] {
+        check_common(sources, n, "sources");
+        check_common(targets, m, "targets");
+        stk::require(f && h && nu && u_out, "f, h, nu and u_out must be non-NULL");
+        stk::require(n0 >= 1, "n0 must be >= 1");
+        stk::require(p >= 0 && p <= STK_P_MAX, "p must be in [0, STK_P_MAX]");
+        stk::require(theta >= 0.0 && theta < 1.0, "theta must be in [0, 1)");
+        stk::require(std::isfinite(epsilon) && epsilon >= 0.0, "epsilon must be finite and >= 0");
+        hipStream_t s = as_stream(stream);
+        int dev = 0;
+        STK_HIP(hipGetDevice(&dev));
+        // this thread's workspace (as the one-shot stk_evaluate): steady-state calls do not
+        // allocate; its device memory is returned when the process exits
+        thread_local stk::Tree *ws_tree = nullptr;
+        thread_local stk_plan *ws_plan = nullptr;
+        if (!ws_tree || ws_tree->device != dev) {
+            ws_tree = new stk::Tree();
+            ws_plan = new stk_plan();
+            ws_tree->device = dev;
+        }
+        stk::build_tree(*ws_tree, sources, n, n0, s);
+        stk::compute_moments(*ws_tree, f, h, nu, 1, p, STK_FP64, s);
+        stk::evaluate_regularized(*ws_tree, ws_plan->p, targets, m, theta, epsilon, u_out,
+                                  targets == sources && m == n, s);
+        STK_HIP(hipStreamSynchronize(s));
+    });
+}
+
 stk_status stk_evaluate_adjoint(stk_plan *plan, const double *w, double *grad_f, double *grad_h,
                                 double *grad_targets, double *grad_sources, void *stream) {
     return guarded([&] {

@@ -373,8 +373,8 @@ Plan::~Plan() {
     if (owns_tree) delete tree;
 }
 
-void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, double *u_out, bool same_as_sources,
-              hipStream_t s) {
+void build_lists(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, bool same_as_sources,
+                 hipStream_t s) {
     pl.tree = &t;
     pl.m = m;
     pl.theta = theta;
@@ -446,6 +446,16 @@ void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, dou
     ta.near_mask = reserve<uint64_t>(pl.near_mask, size_t(tot[1]) + 1);
     hipLaunchKernelGGL(k_traverse<true>, dim3(ng), dim3(64), 0, s, ta);
     STK_CHECK_LAUNCH();
+}
+
+void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, double *u_out, bool same_as_sources,
+              hipStream_t s) {
+    pl.reg_eps = -1.0;
+    build_lists(t, pl, tgt, m, theta, same_as_sources, s);
+    const int32_t ng = pl.ngroups;
+    const double *tpos = pl.tpos.as<double>();
+    const int32_t *tperm = pl.tperm.as<int32_t>();
+    const int32_t *foff = pl.far_off.as<int32_t>();
 
     // kernel variants: right-hand sides per pass, matrix cores
     const int K = t.k_rhs;
@@ -470,8 +480,8 @@ void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, dou
     const int sparse_max = all_cm ? 64 : (K == 1 && cm_fits ? FAR_SPARSE_MAX : 0);
     if (sparse_max > 0) far_sparse(t, pl, unear, sparse_max, s);
     pl.far_sparse_max = sparse_max;
-    FarArgs fa{tpos, m, foff, ta.far_node, ta.far_mask, t.ncenter.as<double>(), t.nrho.as<double>(), t.wblk.p,
-               unear, tperm, u_out, ng, K, sparse_max};
+    FarArgs fa{tpos, m, foff, pl.far_node.as<int32_t>(), pl.far_mask.as<uint64_t>(), t.ncenter.as<double>(),
+               t.nrho.as<double>(), t.wblk.p, unear, tperm, u_out, ng, K, sparse_max};
     if (t.prec == STK_FP64)
         dispatch_far<double, 1>(t.p, fa, s);
     else if (pl.tiles.far_mfma)

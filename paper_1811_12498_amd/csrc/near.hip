@@ -280,6 +280,7 @@ struct NearArgs {
     void *part;                            // (incidences, K, 3) T
     int32_t nitems;
     int32_t K;                             // right-hand sides (a multiple of KB)
+    double eps2 = 0.0;                     // regularized kernels: eps^2
 };
 
 // one wave per item: the item's leaf against up to 64 of its targets, for all right-hand
@@ -336,6 +337,86 @@ template <typename T, int KB> __global__ __launch_bounds__(64) void k_near(NearA
                 o[3 * r + 2] = u[r][2];
             }
         }
+    }
+}
+
+// Regularized Stokeslet + stresslet pair (FP64, one right-hand side), R^2 = |d|^2 + eps^2:
+//   u_i += f_i (|d|^2 + 2 eps^2)/R^3 + d_i [(d.f)/R^3 + (d.h)(d.nu)/R^5 + (eps^2/2)(h.nu)/R^5]
+//          + h_i (eps^2/2)(d.nu)/R^5 + nu_i (eps^2/2)(d.h)/R^5
+// (the kernels S^eps_ij f_j + T^eps_ijl h_j nu_l).  With eps > 0 every pair is finite and
+// summed, the coincident one included; with eps = 0 R = 0 only there, and it is skipped.
+__device__ inline void pair_reg(double x0, double x1, double x2, const double g[6], const double w[6], double e2,
+                                double u[3]) {
+    const double d0 = x0 - g[0], d1 = x1 - g[1], d2 = x2 - g[2];
+    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    const double R2 = r2 + e2;
+    double ri = rsqrt(R2);
+    ri = R2 > 0.0 ? ri : 0.0;
+    const double ri3 = ri * ri * ri;
+    const double ri5 = ri3 * ri * ri;
+    const double dn = d0 * g[3] + d1 * g[4] + d2 * g[5];
+    const double df = d0 * w[0] + d1 * w[1] + d2 * w[2];
+    const double dh = d0 * w[3] + d1 * w[4] + d2 * w[5];
+    const double hn = w[3] * g[3] + w[4] * g[4] + w[5] * g[5];
+    const double he = 0.5 * e2 * ri5;
+    const double cs = (r2 + 2.0 * e2) * ri3;
+    const double sd = df * ri3 + (dh * dn) * ri5 + he * hn;
+    const double sh = he * dn, sn = he * dh;
+    u[0] += w[0] * cs + d0 * sd + w[3] * sh + g[3] * sn;
+    u[1] += w[1] * cs + d1 * sd + w[4] * sh + g[4] * sn;
+    u[2] += w[2] * cs + d2 * sd + w[5] * sh + g[5] * sn;
+}
+
+// one wave per item as k_near, with the regularized pair: the leaf's records are walked
+// with a uniform pointer, four sources per batch
+__global__ __launch_bounds__(64) void k_near_reg(NearArgs a) {
+    const int32_t it = xcd_item();
+    if (it >= a.nitems) return;
+    const int lane = threadIdx.x;
+    const int32_t c = a.item_leaf[it];
+    const int32_t i0 = a.item_i0[it];
+    const bool on = lane < a.item_i1[it] - i0;
+    int32_t slot = 0;
+    double x0 = 0, x1 = 0, x2 = 0;
+    if (on) {
+        const int64_t t = a.inc_tgt[i0 + lane];
+        slot = a.inc_slot[i0 + lane];
+        x0 = a.tpos[3 * t];
+        x1 = a.tpos[3 * t + 1];
+        x2 = a.tpos[3 * t + 2];
+    }
+    const int32_t s = a.start[c], n = a.count[c];
+    const STK_CONST_AS double *g = (const STK_CONST_AS double *)(a.geo) + 6 * int64_t(s);
+    const STK_CONST_AS double *w = (const STK_CONST_AS double *)(a.wts) + 6 * int64_t(s);
+    const double e2 = a.eps2;
+    double u[3] = {0.0, 0.0, 0.0};
+    int32_t left = n;
+    for (; left >= 4; left -= 4, g += 24, w += 24) {
+        double gb[4][6], wb[4][6];
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                gb[b][q] = g[6 * b + q];
+                wb[b][q] = w[6 * b + q];
+            }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) pair_reg(x0, x1, x2, gb[b], wb[b], e2, u);
+    }
+    for (; left > 0; --left, g += 6, w += 6) {
+        double gc[6], wc[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            gc[q] = g[q];
+            wc[q] = w[q];
+        }
+        pair_reg(x0, x1, x2, gc, wc, e2, u);
+    }
+    if (on) {
+        double *o = static_cast<double *>(a.part) + int64_t(slot) * 3;
+        o[0] = u[0];
+        o[1] = u[1];
+        o[2] = u[2];
     }
 }
 
@@ -606,7 +687,19 @@ void near_field(Tree &t, Plan &pl, double *unear, hipStream_t s) {
                 t.ncount.as<int32_t>(), t.nbmin.as<double>(), t.nbmax.as<double>(), t.geo.as<double>(), t.wts.p,
                 part, cm.n_items, K};
     const int64_t mk = m * K;
-    if (t.prec == STK_FP64) {
+    if (pl.reg_eps >= 0.0) {
+        if (t.prec != STK_FP64 || K != 1) throw Error(STK_EINVAL, "regularized kernels: FP64, one right-hand side");
+        na.eps2 = pl.reg_eps * pl.reg_eps;
+        if (na.nitems > 0) {
+            hipLaunchKernelGGL(k_near_reg, dim3(xcd_item_blocks(na.nitems)), dim3(64), 0, s, na);
+            STK_CHECK_LAUNCH();
+        }
+        if (mk > 0) {
+            hipLaunchKernelGGL(k_near_reduce<double>, dim3(nblk(mk, 256)), dim3(256), 0, s,
+                               static_cast<const double *>(part), toff, m, K, unear);
+            STK_CHECK_LAUNCH();
+        }
+    } else if (t.prec == STK_FP64) {
         launch_near<double, 1>(na, s);
         if (mk > 0) {
             hipLaunchKernelGGL(k_near_reduce<double>, dim3(nblk(mk, 256)), dim3(256), 0, s,

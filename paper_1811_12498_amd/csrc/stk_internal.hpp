@@ -183,6 +183,7 @@ struct Plan {
     Tiles tiles;                      // kernel variants used by the last evaluation
     bool forced = false;              // use `force` instead of the table (autotuning)
     hipEvent_t moments_ready = nullptr;  // if set, the evaluation's stream waits on it before the near field
+    double reg_eps = -1.0;            // >= 0: the last evaluation used the regularized kernels with this eps
     Tiles force;
     AdjScratch adj;
     ~Plan();
@@ -208,6 +209,13 @@ void compute_moments(Tree &t, const double *f, const double *h, const double *nu
 // Morton order is the tree's and they are not sorted again
 void evaluate(Tree &t, Plan &plan, const double *tgt, int64_t m, double theta, double *u_out, bool same_as_sources,
               hipStream_t s);
+// the first part of evaluate: targets in Morton order and Algorithm 1's interaction lists
+void build_lists(Tree &t, Plan &plan, const double *tgt, int64_t m, double theta, bool same_as_sources,
+                 hipStream_t s);
+// the same evaluation with the regularized Stokeslet and stresslet of parameter eps (FP64
+// tree and moments, one right-hand side; regularized.hip)
+void evaluate_regularized(Tree &t, Plan &plan, const double *tgt, int64_t m, double theta, double eps,
+                          double *u_out, bool same_as_sources, hipStream_t s);
 // gradients of L = sum_m w^m . u^m for the plan's frozen operator (any output may be
 // NULL); w and the outputs in the caller's orders
 void adjoint(Plan &plan, const double *w, double *grad_f, double *grad_h, double *grad_targets,
