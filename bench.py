@@ -385,10 +385,11 @@ def fwd_adjoint_times(reps=3):
     return out
 
 
-def multi_rhs_times(reps=3):
+def multi_rhs_times(reps=3, force_tiles=None):
     """Batched workload: N = 500,000 uniform in the unit cube (seed 4), K = 16 (f, h)
     pairs sharing positions and nu, p = 8, theta = 0.6, N0 = 2000, mixed precision, with
-    the kernel variants chosen by the library's autotuner; compared with K one-RHS calls."""
+    the kernel variants chosen by the library's autotuner (or the given ones, for
+    profiling a variant); compared with K one-RHS calls."""
     import torch
 
     from paper_1811_12498_amd import native, workloads
@@ -397,7 +398,11 @@ def multi_rhs_times(reps=3):
     dev = torch.device("cuda:0")
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     X, F, H, NU = t(w.src), t(w.f), t(w.h), t(w.nu)
-    tiles, tune_ms = native.autotune(w.p, K, "mixed", w.n, w.theta, w.n0)
+    if force_tiles:
+        native.tiles_set(w.p, K, "mixed", **force_tiles)
+        tiles, tune_ms = native.tiles_get(w.p, K, "mixed")[0], float("nan")
+    else:
+        tiles, tune_ms = native.autotune(w.p, K, "mixed", w.n, w.theta, w.n0)
 
     def timed(f_, h_):
         u = native.evaluate(X, X, f_, h_, NU, w.p, w.theta, w.n0, "mixed")
@@ -444,7 +449,7 @@ def multi_rhs_times(reps=3):
     err = float(torch.linalg.norm(u[0][S] - ud) / torch.linalg.norm(ud))
     return {"workload": f"cube N={w.n}, K={K}, p={w.p}, theta={w.theta}, N0={w.n0}, mixed",
             "ms": round(ms, 3), "rhs_targets_per_s": K * w.n / (ms * 1e-3), "tiles": tiles,
-            "autotune_best_ms": round(tune_ms, 3), "one_rhs_ms": round(ms1, 3),
+            "autotune_best_ms": round(tune_ms, 3) if tune_ms == tune_ms else None, "one_rhs_ms": round(ms1, 3),
             "batch_speedup_vs_K_calls": round(K * ms1 / ms, 3), "phase_ms": phases, "kernel_rates": rates,
             "E_S_rhs0_vs_fp64_direct": err, "sample_targets": int(w.sample.size)}
 
@@ -528,6 +533,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 comparison runs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 256 MiB device copy (a reference for HBM counters)")
+    ap.add_argument("--tiles", help="with --only multi_rhs: kernel variants instead of the autotuner's, "
+                                    "e.g. far_mfma=1,near_mfma=1,far_kb=4,near_kb=4 (for profiling)")
     ap.add_argument("--params", nargs=3, metavar=("P", "THETA", "N0"),
                     help="evaluate the metric's points at these treecode parameters instead (for profiling)")
     ap.add_argument("--only", choices=["fwd_adjoint", "multi_rhs", "table1", "tune", "c2", "regularized"],
@@ -543,6 +550,10 @@ def main():
 
     from paper_1811_12498_amd import native, workloads
 
+    if args.only == "multi_rhs" and args.tiles:
+        kv = dict(item.split("=") for item in args.tiles.split(","))
+        print(json.dumps(multi_rhs_times(force_tiles={k: int(v) for k, v in kv.items()})), flush=True)
+        return
     if args.only:
         res = {"fwd_adjoint": fwd_adjoint_times, "multi_rhs": multi_rhs_times,
                "table1": table1_icosphere, "tune": tune_c3, "c2": c2_grid,

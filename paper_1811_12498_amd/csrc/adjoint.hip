@@ -102,7 +102,7 @@ struct NearTgradArgs {
 };
 
 template <typename T> __global__ __launch_bounds__(64) void k_near_tgrad(NearTgradArgs a) {
-    const int32_t it = xcd_item();
+    const int32_t it = xcd_item<XCD_CHUNK_NEAR>();
     if (it >= a.nitems) return;
     const int lane = threadIdx.x;
     const int32_t c = a.item_leaf[it];
@@ -548,14 +548,14 @@ void adjoint(Plan &pl, const double *w, double *gf, double *gh, double *gt, doub
         const int32_t *toff = pl.ncm.toff.as<int32_t>();
         if (fp64) {
             if (nt.nitems > 0) {
-                hipLaunchKernelGGL(k_near_tgrad<double>, dim3(xcd_item_blocks(nt.nitems)), dim3(64), 0, s, nt);
+                hipLaunchKernelGGL(k_near_tgrad<double>, dim3(xcd_item_blocks<XCD_CHUNK_NEAR>(nt.nitems)), dim3(64), 0, s, nt);
                 STK_CHECK_LAUNCH();
             }
             hipLaunchKernelGGL(k_slot_reduce<double>, dim3(nblk(m, 256)), dim3(256), 0, s,
                                static_cast<const double *>(nt.part), toff, m, gtn);
         } else {
             if (nt.nitems > 0) {
-                hipLaunchKernelGGL(k_near_tgrad<float>, dim3(xcd_item_blocks(nt.nitems)), dim3(64), 0, s, nt);
+                hipLaunchKernelGGL(k_near_tgrad<float>, dim3(xcd_item_blocks<XCD_CHUNK_NEAR>(nt.nitems)), dim3(64), 0, s, nt);
                 STK_CHECK_LAUNCH();
             }
             hipLaunchKernelGGL(k_slot_reduce<float>, dim3(nblk(m, 256)), dim3(256), 0, s,

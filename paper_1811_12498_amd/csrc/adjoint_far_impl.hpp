@@ -316,7 +316,7 @@ template <int P, typename T> struct TgradVisit {
 // target's term of this interaction and writes it to the incidence's slot
 template <int P, typename T> __global__ __launch_bounds__(64, sizeof(T) == 4 ? 4 : 2) void k_far_tgrad(TgradArgs a) {
     constexpr int NG = nidx(P + 1);
-    const int32_t it = xcd_item();
+    const int32_t it = xcd_group(a.nitems);
     if (it >= a.nitems) return;
     const int lane = threadIdx.x;
     const int32_t c = __builtin_amdgcn_readfirstlane(a.item_node[it]);
@@ -350,7 +350,7 @@ template <int P, typename T> void launch_far_lambda(const LambdaArgs &a, hipStre
 
 template <int P, typename T> void launch_far_tgrad(const TgradArgs &a, hipStream_t s) {
     if (a.nitems == 0) return;
-    hipLaunchKernelGGL((k_far_tgrad<P, T>), dim3(xcd_item_blocks(a.nitems)), dim3(64), 0, s, a);
+    hipLaunchKernelGGL((k_far_tgrad<P, T>), dim3(xcd_blocks(a.nitems)), dim3(64), 0, s, a);
     STK_CHECK_LAUNCH();
 }
 

@@ -84,7 +84,7 @@ template <int P, typename T, int KB> __global__ __launch_bounds__(64) void k_far
     // the streams are read through the constant address space: the partial stores below
     // cannot alias them, so their uniform loads stay scalar across the loop
     using Eval = FarEval<P, T, KB, true>;
-    const int32_t it = xcd_item();
+    const int32_t it = xcd_item<XCD_CHUNK_FAR>();
     if (it >= a.nitems) return;
     const int lane = threadIdx.x;
     const int32_t c = __builtin_amdgcn_readfirstlane(a.item_node[it]);
@@ -123,7 +123,7 @@ template <int P, typename T, int KB> __global__ __launch_bounds__(64) void k_far
 
 template <int P, typename T, int KB> void launch_far_sparse(const FarSparseArgs &a, hipStream_t s) {
     if (a.nitems == 0) return;
-    hipLaunchKernelGGL((k_far_sparse<P, T, KB>), dim3(xcd_item_blocks(a.nitems)), dim3(64), 0, s, a);
+    hipLaunchKernelGGL((k_far_sparse<P, T, KB>), dim3(xcd_item_blocks<XCD_CHUNK_FAR>(a.nitems)), dim3(64), 0, s, a);
     STK_CHECK_LAUNCH();
 }
 

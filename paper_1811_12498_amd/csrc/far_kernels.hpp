@@ -50,18 +50,20 @@ inline unsigned xcd_blocks(int32_t ngroups) { return unsigned(((ngroups + 7) >> 
 
 // block index -> work item for item lists whose cost varies along the list (one leaf or
 // cluster per run of items, runs of very different lengths and leaf sizes): runs of
-// XCD_CHUNK consecutive items are dealt to the eight XCDs in turn, so every XCD gets an
-// even share of the work (contiguous eighths of the 1M-sphere near items differ by up to
-// 1.5x in cost) while neighbouring items, which read the same source records, still share
-// an L2.  Indices run over [0, xcd_item_blocks(n)); those >= n have no item.
-constexpr int32_t XCD_CHUNK = 16;
-__device__ inline int32_t xcd_item() {
+// CHUNK consecutive items are dealt to the eight XCDs in turn, so every XCD gets an even
+// share of the work (contiguous eighths of the 1M-sphere near items differ by up to 1.5x
+// in cost) while neighbouring items, which read the same source records or cluster
+// streams, still share an L2.  The near-field items use runs of 16; the far field's
+// cluster-major items, whose per-cluster streams are larger (FP64 in particular), runs of
+// 256.  Indices run over [0, xcd_item_blocks(n)); those >= n have no item.
+constexpr int32_t XCD_CHUNK_NEAR = 16, XCD_CHUNK_FAR = 256;
+template <int32_t CHUNK> __device__ inline int32_t xcd_item() {
     const int32_t j = int32_t(blockIdx.x >> 3);
-    return ((j / XCD_CHUNK) * 8 + int32_t(blockIdx.x & 7)) * XCD_CHUNK + j % XCD_CHUNK;
+    return ((j / CHUNK) * 8 + int32_t(blockIdx.x & 7)) * CHUNK + j % CHUNK;
 }
-inline unsigned xcd_item_blocks(int32_t nitems) {
-    const int32_t chunks = (nitems + XCD_CHUNK - 1) / XCD_CHUNK;
-    return unsigned(((chunks + 7) / 8) * 8 * XCD_CHUNK);
+template <int32_t CHUNK> inline unsigned xcd_item_blocks(int32_t nitems) {
+    const int32_t chunks = (nitems + CHUNK - 1) / CHUNK;
+    return unsigned(((chunks + 7) / 8) * 8 * CHUNK);
 }
 
 // defined in far_impl.hpp, instantiated per Taylor order in far_p*.hip / fark_p*.hip

@@ -287,7 +287,7 @@ struct NearArgs {
 // sides in blocks of KB.  Items of one leaf are consecutive and go to one XCD, so the
 // leaf's records are shared in its L2.
 template <typename T, int KB> __global__ __launch_bounds__(64) void k_near(NearArgs a) {
-    const int32_t it = xcd_item();
+    const int32_t it = xcd_item<XCD_CHUNK_NEAR>();
     if (it >= a.nitems) return;
     const int lane = threadIdx.x;
     const int32_t c = a.item_leaf[it];
@@ -370,7 +370,7 @@ __device__ inline void pair_reg(double x0, double x1, double x2, const double g[
 // one wave per item as k_near, with the regularized pair: the leaf's records are walked
 // with a uniform pointer, four sources per batch
 __global__ __launch_bounds__(64) void k_near_reg(NearArgs a) {
-    const int32_t it = xcd_item();
+    const int32_t it = xcd_item<XCD_CHUNK_NEAR>();
     if (it >= a.nitems) return;
     const int lane = threadIdx.x;
     const int32_t c = a.item_leaf[it];
@@ -494,7 +494,7 @@ __device__ inline void near_mfma_leaf(const double *__restrict__ geo, const floa
 }
 
 __global__ __launch_bounds__(64) void k_near_mfma(NearArgs a) {
-    const int32_t it = xcd_item();
+    const int32_t it = xcd_item<XCD_CHUNK_NEAR>();
     if (it >= a.nitems) return;
     const int lane = threadIdx.x;
     const int tl = lane & 15, q4 = lane >> 4;
@@ -573,7 +573,7 @@ __global__ void k_near_reduce(const T *__restrict__ part, const int32_t *__restr
 
 template <typename T, int KB> void launch_near(const NearArgs &na, hipStream_t s) {
     if (na.nitems > 0) {
-        hipLaunchKernelGGL((k_near<T, KB>), dim3(xcd_item_blocks(na.nitems)), dim3(64), 0, s, na);
+        hipLaunchKernelGGL((k_near<T, KB>), dim3(xcd_item_blocks<XCD_CHUNK_NEAR>(na.nitems)), dim3(64), 0, s, na);
         STK_CHECK_LAUNCH();
     }
 }
@@ -691,7 +691,7 @@ void near_field(Tree &t, Plan &pl, double *unear, hipStream_t s) {
         if (t.prec != STK_FP64 || K != 1) throw Error(STK_EINVAL, "regularized kernels: FP64, one right-hand side");
         na.eps2 = pl.reg_eps * pl.reg_eps;
         if (na.nitems > 0) {
-            hipLaunchKernelGGL(k_near_reg, dim3(xcd_item_blocks(na.nitems)), dim3(64), 0, s, na);
+            hipLaunchKernelGGL(k_near_reg, dim3(xcd_item_blocks<XCD_CHUNK_NEAR>(na.nitems)), dim3(64), 0, s, na);
             STK_CHECK_LAUNCH();
         }
         if (mk > 0) {
@@ -709,7 +709,7 @@ void near_field(Tree &t, Plan &pl, double *unear, hipStream_t s) {
     } else {
         if (pl.tiles.near_mfma) {
             if (na.nitems > 0) {
-                hipLaunchKernelGGL(k_near_mfma, dim3(xcd_item_blocks(na.nitems)), dim3(64), 0, s, na);
+                hipLaunchKernelGGL(k_near_mfma, dim3(xcd_item_blocks<XCD_CHUNK_NEAR>(na.nitems)), dim3(64), 0, s, na);
                 STK_CHECK_LAUNCH();
             }
         } else if (pl.tiles.near_kb == 4)

@@ -75,7 +75,7 @@ template <int P> __global__ __launch_bounds__(64) void k_reg_far_cm(RegCmArgs a)
     constexpr int NM = nidx(P);
     __shared__ double gl[3][NM];
     __shared__ int16_t tab[NM][TSLOTS];
-    const int32_t it = xcd_item();
+    const int32_t it = xcd_item<XCD_CHUNK_FAR>();
     if (it >= a.nitems) return;
     const int lane = threadIdx.x;
     for (int q = lane; q < NM; q += 64) {
@@ -224,7 +224,7 @@ template <int P> __global__ __launch_bounds__(64) void k_reg_far_cm(RegCmArgs a)
 
 template <int P> void launch_reg_far(const RegCmArgs &a, hipStream_t s) {
     if (a.nitems == 0) return;
-    hipLaunchKernelGGL(k_reg_far_cm<P>, dim3(xcd_item_blocks(a.nitems)), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_reg_far_cm<P>, dim3(xcd_item_blocks<XCD_CHUNK_FAR>(a.nitems)), dim3(64), 0, s, a);
     STK_CHECK_LAUNCH();
 }
 
