@@ -203,9 +203,37 @@ def run_config(X, F, H, NU, p, theta, n0, prec, steps, warmup):
 
 
 def reg_far_flops_per_interaction(p):
-    # regularized far field, explicit form: three coefficient recurrences (11 flops per
-    # multi-index each) and the contraction sum_k a^k_ij M_j^k + at^k_ijl Mt_jl^k (36 terms,
-    # 72 flops per multi-index), + 21 per interaction
+    """Flops of one regularized far interaction in the form the kernel evaluates: the
+    recurrence of the Taylor coefficients of R = sqrt(|d|^2 + eps^2) to order p + 3 (per
+    coefficient: the sum over its parents weighted by d scaled with the order's first factor,
+    the sum of its grandparents and one multiply-add with the second factor; no grandparent
+    term at order 3, where its factor is zero, nor at the top order, whose grandparent term
+    is contracted at order p + 1 against the stream's V values), three multiply-adds per
+    coefficient of order >= 2 against the cluster's stream (six at order p + 1), plus d,
+    R^2, 1/R^2, sqrt R^2, the scaled d and the two factors of each order and the final
+    combination."""
+    pb = p + 3
+    f = 12 + 5 * pb + (6 if p >= 1 else 0)
+    for n in range(1, pb + 1):
+        for k1 in range(n, -1, -1):
+            for k2 in range(n - k1, -1, -1):
+                k = (k1, k2, n - k1 - k2)
+                t1 = sum(v > 0 for v in k)
+                t2 = sum(v > 1 for v in k)
+                f += 2 * t1 - 1
+                if t2 > 0 and n not in (1, 3, pb):
+                    f += (t2 - 1) + 2
+                if n >= 2:
+                    f += 6
+                if p >= 1 and n == p + 1:
+                    f += 6
+    return f
+
+
+def reg_far_explicit_flops_per_interaction(p):
+    # the same interaction in the explicit form (three coefficient families of R^-1, R^-3,
+    # R^-5 to order p, 11 flops per multi-index each, and the contraction
+    # sum_k a^k_ij M_j^k + at^k_ijl Mt_jl^k, 72 flops per multi-index, + 21): for comparison
     nm = (p + 1) * (p + 2) * (p + 3) // 6
     return 33 * nm + 72 * nm + 21
 
@@ -247,7 +275,9 @@ def regularized_times(eps=0.01, ps=(6, 8), theta=0.5, reps=3, n_oracle=400):
         ms = (time.perf_counter() - t0) * 1e3 / reps
         native.profile_enable(False)
         prof = native.profile_read()
-        phases = {k: round(v[0] / max(v[1], 1), 3) for k, v in prof.items() if v[1]}
+        # per evaluation: lists include the transposition to cluster-major items, moments the
+        # clusters' streams, far the far kernel and the per-target sums
+        phases = {k: round(v[0] / reps, 3) for k, v in prof.items() if v[1]}
         # the same interaction counts as the plain evaluation (same tree, MAC and lists)
         _, plan = native.evaluate(X, X, F, H, NU, p, theta, w.n0, "fp64", keep_plan=True)
         nfar, _, npairs = native.plan_counts(plan)
@@ -260,6 +290,7 @@ def regularized_times(eps=0.01, ps=(6, 8), theta=0.5, reps=3, n_oracle=400):
                      "E_S_vs_exact": e, "phase_ms": phases,
                      "far": {"kernel": f"k_reg_far<{p}>", "interactions": far_i,
                              "flops_per_interaction": reg_far_flops_per_interaction(p),
+                             "explicit_form_flops_per_interaction": reg_far_explicit_flops_per_interaction(p),
                              "fp64_tflops": round(far_tf / 1e12, 3), "frac_of_fp64_peak": round(far_tf / PEAK_FP64_VALU, 4)},
                      "near": {"kernel": "k_near_reg", "pairs": pairs, "flops_per_pair": REG_NEAR_FLOPS_PER_PAIR,
                               "fp64_tflops": round(near_tf / 1e12, 3),

@@ -101,6 +101,7 @@ struct Tree {
     DBuf mom_up;  // double, as mom: each node's moments moved to its parent's centre
     DBuf mom_part;  // double: the leaves' chunk partials (moments may run beside an evaluation)
     DBuf wblk;    // T (nn, nb, 12*K): scaled far-field channel blocks
+    DBuf wreg;    // double (nn, reg_stream_len(p)): regularized far-field streams
     DBuf geo;     // double (n, 6): sorted (y, nu) per source
     DBuf wts;     // T (n, K, 6): sorted (f, h) per source and right-hand side
     DBuf w12;     // double (n, K, 12): sorted (f_j, h_j nu_l) for the moments
