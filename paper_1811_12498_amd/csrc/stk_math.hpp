@@ -242,22 +242,37 @@ template <int P, typename T, int KB = 1, bool CAS = false> struct FarEval {
     }
 
     // all coefficients of order N in layer K3 (k1 = N - K3 .. 0), with their G terms;
-    // G points at the chunk (N, K3)
+    // G points at the chunk (N, K3).  e = c1 dh (the order's first factor folded into the
+    // direction, once per order); the recurrence's sums start from their first term (a
+    // literal 0 + x is not folded in IEEE arithmetic).
     template <int N, int K3, int K1>
-    STK_HD static void layer(T (&b)[NB], const T dh[3], T c1, T c2, Ptr __restrict__ G, T (*accG)[3]) {
+    STK_HD static void layer(T (&b)[NB], const T e[3], T c2, Ptr __restrict__ G, T (*accG)[3]) {
         constexpr int K2 = N - K3 - K1;
         constexpr int Q = gidx(K1, K2, K3);
         if constexpr (K3 <= 1) {  // recurrence_1, scaled
-            T s1 = T(0), s2 = T(0);
-            if constexpr (K1 > 0) s1 += dh[0] * b[gidx(K1 - 1, K2, K3)];
-            if constexpr (K2 > 0) s1 += dh[1] * b[gidx(K1, K2 - 1, K3)];
-            if constexpr (K3 > 0) s1 += dh[2] * b[gidx(K1, K2, K3 - 1)];
-            if constexpr (K1 > 1) s2 += b[gidx(K1 - 2, K2, K3)];
-            if constexpr (K2 > 1) s2 += b[gidx(K1, K2 - 2, K3)];
-            if constexpr (N > 1)
-                b[Q] = c1 * s1 - c2 * s2;
-            else
-                b[Q] = c1 * s1;
+            T s1;
+            if constexpr (K1 > 0) {
+                s1 = e[0] * b[gidx(K1 - 1, K2, K3)];
+                if constexpr (K2 > 0) s1 += e[1] * b[gidx(K1, K2 - 1, K3)];
+                if constexpr (K3 > 0) s1 += e[2] * b[gidx(K1, K2, K3 - 1)];
+            } else if constexpr (K2 > 0) {
+                s1 = e[1] * b[gidx(K1, K2 - 1, K3)];
+                if constexpr (K3 > 0) s1 += e[2] * b[gidx(K1, K2, K3 - 1)];
+            } else {
+                s1 = e[2] * b[gidx(K1, K2, K3 - 1)];
+            }
+            if constexpr (N > 1 && (K1 > 1 || K2 > 1)) {
+                T s2;
+                if constexpr (K1 > 1) {
+                    s2 = b[gidx(K1 - 2, K2, K3)];
+                    if constexpr (K2 > 1) s2 += b[gidx(K1, K2 - 2, K3)];
+                } else {
+                    s2 = b[gidx(K1, K2 - 2, K3)];
+                }
+                b[Q] = s1 - c2 * s2;
+            } else {
+                b[Q] = s1;
+            }
         } else {  // harmonic fill
             constexpr double den = double(K3 * (K3 - 1));
             constexpr double ca = -double((K1 + 1) * (K1 + 2)) / den;
@@ -265,13 +280,15 @@ template <int P, typename T, int KB = 1, bool CAS = false> struct FarEval {
             b[Q] = T(ca) * b[gidx(K1 + 2, K2, K3 - 2)] + T(cb) * b[gidx(K1, K2 + 2, K3 - 2)];
         }
         gterm<N, (N - K3) - K1>(b[Q], G, accG);
-        if constexpr (K1 > 0) layer<N, K3, K1 - 1>(b, dh, c1, c2, G, accG);
+        if constexpr (K1 > 0) layer<N, K3, K1 - 1>(b, e, c2, G, accG);
     }
 
     // E contraction for the k of order N - 1 in layer K3 (needs layers K3, K3 + 1 of
-    // order N); E points at the E part of chunk (N, K3 + 1)
+    // order N); E points at the E part of chunk (N, K3 + 1).  The third component's
+    // factor k_3 + 1 is the same for the whole layer: its terms go to acc3 unscaled and
+    // the caller applies the factor once.
     template <int N, int K3, int K1>
-    STK_HD static void elayer(const T (&b)[NB], const T dh[3], Ptr __restrict__ E, T (*accF)[3]) {
+    STK_HD static void elayer(const T (&b)[NB], const T dh[3], Ptr __restrict__ E, T (*accF)[3], T *acc3) {
         constexpr int M = N - 1;
         constexpr int K2 = M - K3 - K1;
         constexpr int I = (M - K3) - K1;
@@ -281,9 +298,9 @@ template <int P, typename T, int KB = 1, bool CAS = false> struct FarEval {
             const T sig = dh[0] * Er[3 * I] + dh[1] * Er[3 * I + 1] + dh[2] * Er[3 * I + 2];
             accF[r][0] += b[gidx(K1 + 1, K2, K3)] * (T(K1 + 1) * sig);
             accF[r][1] += b[gidx(K1, K2 + 1, K3)] * (T(K2 + 1) * sig);
-            accF[r][2] += b[gidx(K1, K2, K3 + 1)] * (T(K3 + 1) * sig);
+            acc3[r] += b[gidx(K1, K2, K3 + 1)] * sig;
         }
-        if constexpr (K1 > 0) elayer<N, K3, K1 - 1>(b, dh, E, accF);
+        if constexpr (K1 > 0) elayer<N, K3, K1 - 1>(b, dh, E, accF, acc3);
     }
 
     // returns 0 through an asm the optimiser cannot see into.  Adding it to the block
@@ -302,13 +319,27 @@ template <int P, typename T, int KB = 1, bool CAS = false> struct FarEval {
     }
 
     template <int N, int J>
-    STK_HD static void layers_from(T (&b)[NB], const T dh[3], T c1, T c2, Ptr __restrict__ W, T (*accG)[3],
-                                   T (*accF)[3]) {
+    STK_HD static void layers_from(T (&b)[NB], const T dh[3], const T e[3], T c2, Ptr __restrict__ W,
+                                   T (*accG)[3], T (*accF)[3]) {
         if constexpr (J <= N) {
             Ptr __restrict__ chunk = W + stream_off(P, N, J) + fence(accG[0][0] + accF[0][0]);
-            layer<N, J, N - J>(b, dh, c1, c2, chunk, accG);
-            if constexpr (J >= 1) elayer<N, J - 1, N - J>(b, dh, chunk + stream_gpart(P, N, J), accF);
-            layers_from<N, J + 1>(b, dh, c1, c2, W, accG, accF);
+            layer<N, J, N - J>(b, e, c2, chunk, accG);
+            if constexpr (J == 1) {  // layer k_3 = 0: factor 1
+                T acc3[KB];
+#pragma unroll
+                for (int r = 0; r < KB; ++r) acc3[r] = accF[r][2];
+                elayer<N, 0, N - 1>(b, dh, chunk + stream_gpart(P, N, J), accF, acc3);
+#pragma unroll
+                for (int r = 0; r < KB; ++r) accF[r][2] = acc3[r];
+            } else if constexpr (J >= 2) {
+                T acc3[KB];
+#pragma unroll
+                for (int r = 0; r < KB; ++r) acc3[r] = T(0);
+                elayer<N, J - 1, N - J>(b, dh, chunk + stream_gpart(P, N, J), accF, acc3);
+#pragma unroll
+                for (int r = 0; r < KB; ++r) accF[r][2] += T(J) * acc3[r];
+            }
+            layers_from<N, J + 1>(b, dh, e, c2, W, accG, accF);
         }
     }
 
@@ -316,7 +347,8 @@ template <int P, typename T, int KB = 1, bool CAS = false> struct FarEval {
     STK_HD static void order(T (&b)[NB], const T dh[3], T t, Ptr __restrict__ W, T (*accG)[3], T (*accF)[3]) {
         const T c1 = T(2 * N - 1) / T(N) * t;
         const T c2 = T(N - 1) / T(N) * (t * t);
-        layers_from<N, 0>(b, dh, c1, c2, W, accG, accF);
+        const T e[3] = {c1 * dh[0], c1 * dh[1], c1 * dh[2]};
+        layers_from<N, 0>(b, dh, e, c2, W, accG, accF);
         if constexpr (N < PB) order<N + 1>(b, dh, t, W, accG, accF);
     }
 
