@@ -35,8 +35,45 @@ def nb_of(p):
 
 
 def far_flops_per_interaction(p, k=1):
-    # recurrence ~11 flops per b^q, 12-channel contraction 2 flops x 12 x K per b^q, 21 for
-    # the per-interaction set-up and the final combination (algorithmic count)
+    """Algorithmic flops of one far interaction (per target, per cluster) in the regrouped
+    form the far evaluator computes: the scaled recurrence for the layers k3 <= 1 of orders
+    1 .. p + 2 (per coefficient the direction-weighted sum of its parents, the sum of its
+    grandparents and one multiply-add), the harmonic fill of the layers k3 >= 2 (3 flops),
+    and per right-hand side the G terms (3 multiply-adds per coefficient of order <= p + 1),
+    the E contraction (per multi-index of order <= p + 1: d.E, then one multiply-add per
+    component, with a factor k_i + 1 where it is not 1; the third component's factor once
+    per layer), the velocity and the compensated per-target sums.  Set-up: d, R^2, 1/R, the
+    direction, t and three factors per order.  The recurrence is counted once however many
+    right-hand sides share it."""
+    pb = p + 2
+    rec = 14 + 6 * pb
+    per_rhs = 6 + 12
+    for n in range(1, pb + 1):
+        for k3 in range(0, n + 1):
+            for k1 in range(n - k3, -1, -1):
+                k2 = n - k3 - k1
+                if k3 <= 1:
+                    t1 = (k1 > 0) + (k2 > 0) + (k3 > 0)
+                    t2 = (k1 > 1) + (k2 > 1)
+                    rec += 2 * t1 - 1 + ((t2 - 1) + 2 if n > 1 and t2 > 0 else 0)
+                else:
+                    rec += 3
+                if n <= p + 1:
+                    per_rhs += 6
+    for m in range(0, p + 2):
+        for k3 in range(0, m + 1):
+            for k1 in range(m - k3, -1, -1):
+                k2 = m - k3 - k1
+                per_rhs += 5 + (2 + (k1 >= 1)) + (2 + (k2 >= 1)) + 2
+            if k3 >= 1:
+                per_rhs += 2
+    return rec + per_rhs * k
+
+
+def far_flops_12_channel(p, k=1):
+    # the 12-channel form (recurrence ~11 flops per b^q to order p + 2, contraction
+    # 2 flops x 12 channels x K per b^q, 21 for set-up and combination): the explicit
+    # contraction the regrouping replaces, kept for comparison
     nb = nb_of(p)
     return 11 * nb + 24 * nb * k + 21
 
@@ -141,6 +178,7 @@ def run_config(X, F, H, NU, p, theta, n0, prec, steps, warmup):
     near_lists = native.plan_lists(plan, "near")
     far_pc = np.bitwise_count(native.plan_lists(plan, "far")["mask"]).astype(np.int64)
     sparse_max, sparse_inter = native.plan_far_split(plan)
+    list_parts = native.plan_tiles(plan)["far_split"]
     del plan
     leaf_count = native.tree_export(native.build_tree(X, n0))["count"].astype(np.int64)
     # leaf-major items: each leaf's (target, leaf) incidences in waves of 64 lanes
@@ -155,18 +193,26 @@ def run_config(X, F, H, NU, p, theta, n0, prec, steps, warmup):
     far_ms = prof["far"][0] / prof["far"][1]
     near_ms = prof["near"][0] / prof["near"][1]
     far_flops = far_dense * far_flops_per_interaction(p)
+    far_flops_12 = far_dense * far_flops_12_channel(p)
     near_flops = pairs_total * NEAR_FLOPS_PER_PAIR
     peak = PEAK_FP32_VALU if prec == "mixed" else PEAK_FP64_VALU
     far_tf = far_flops / (far_ms * 1e-3)
     near_tf = near_flops / (near_ms * 1e-3)
     kname = f"k_far<{p},{'float' if prec == 'mixed' else 'double'},1>"
     traffic = profiled_traffic(kname) if (p == 8 and theta == 0.5 and n0 == 1000 and prec == "mixed") else None
-    # model work: the algorithmic count per interaction of the 12-channel form
+    # algorithmic work: the count per interaction of the regrouped form the kernel computes
+    # (the 12-channel form's count beside it)
     roofline = {"bound": "alu", "achieved": round(far_tf / 1e12, 3), "peak": peak / 1e12, "unit": "TFLOP/s",
                 "frac": round(far_tf / peak, 4), "traffic": traffic, "kernel": kname,
                 "far_interactions_per_launch": far_dense, "flops_per_interaction": far_flops_per_interaction(p),
+                "model_12_channel": {"flops_per_interaction": far_flops_12_channel(p),
+                                     "achieved": round(far_flops_12 / (far_ms * 1e-3) / 1e12, 3),
+                                     "frac": round(far_flops_12 / (far_ms * 1e-3) / peak, 4)},
                 "avg_launch_ms": round(far_ms, 4), "far_entries": dense_entries,
-                "lane_utilisation": round(far_dense / (64.0 * max(dense_entries, 1)), 4)}
+                "lane_utilisation": round(far_dense / (64.0 * max(dense_entries, 1)), 4),
+                # each group's far list in this many parts, a wave each; the far phase
+                # includes the kernel that adds the parts
+                "list_parts": list_parts}
     metric_point = p == 8 and theta == 0.5 and n0 == 1000 and prec == "mixed"
     vr = profiled_valu(kname) if metric_point else None
     if vr:
@@ -472,7 +518,9 @@ def multi_rhs_times(reps=3, force_tiles=None):
                      "ms": far_ms,
                      "tflops": round(far_i * far_flops_per_interaction(w.p, K) / (far_ms * 1e-3) / 1e12, 3),
                      "frac_of_fp32_peak": round(far_i * far_flops_per_interaction(w.p, K) / (far_ms * 1e-3)
-                                                / PEAK_FP32_VALU, 4)}}
+                                                / PEAK_FP32_VALU, 4),
+                     "model_12_channel_tflops": round(far_i * far_flops_12_channel(w.p, K) / (far_ms * 1e-3) / 1e12,
+                                                      3)}}
     f0, h0 = F[0].contiguous(), H[0].contiguous()
     _, ms1, _ = timed(f0, h0)
     S = torch.from_numpy(w.sample).to(dev)

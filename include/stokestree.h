@@ -227,13 +227,21 @@ stk_status stk_plan_export_lists(const stk_plan *plan, int32_t kind, int32_t *of
  *              terms added in the order of its own list; not with far_mfma; EINVAL from
  *              the evaluation if the plan has 2^31 - 64 or more far pairs);  2: only
  *              entries with at most 32 of their group's 64 targets, and only with one
- *              right-hand side.  With far_mfma, 0 means 2. */
+ *              right-hand side.  With far_mfma, 0 means 2.
+ *   far_split  parts of each group's far list in the group-major kernel, each run by a
+ *              wave of its own and summed in part order afterwards (more, shorter waves,
+ *              so the last round of waves idles less of the chip): 1 to 4, or 0
+ *              (automatic: the fewest parts that give at least twelve rounds of waves at four
+ *              waves per SIMD).  Not with far_mfma (0 or 1 only).  stk_plan_tiles reports
+ *              the number of parts the evaluation used (1 when every far entry ran
+ *              cluster major). */
 typedef struct stk_tiles {
     int32_t far_kb;
     int32_t near_kb;
     int32_t near_mfma;
     int32_t far_mfma;
     int32_t far_cm;
+    int32_t far_split;
 } stk_tiles;
 /* Record tiles for (current device's architecture, p, k_rhs, prec); NULL removes the
  * entry.  EINVAL if the tiles do not fit k_rhs and prec. */
@@ -248,8 +256,9 @@ stk_status stk_tiles_get(int32_t p, int32_t k_rhs, stk_precision prec, stk_tiles
 stk_status stk_autotune(int32_t p, int32_t k_rhs, stk_precision prec, int64_t n, double theta, int32_t n0,
                         stk_tiles *best, double *best_ms, void *stream);
 /* Write the table to / merge it from a text file (one "arch p K precision far_kb
- * near_kb near_mfma far_mfma far_cm" line per entry).  Load is all-or-nothing: EINVAL on a malformed
- * or invalid line, and nothing is merged. */
+ * near_kb near_mfma far_mfma far_cm far_split" line per entry; lines without far_split
+ * load as automatic).  Load is all-or-nothing: EINVAL on a malformed or invalid line, and
+ * nothing is merged. */
 stk_status stk_tiles_save(const char *path);
 stk_status stk_tiles_load(const char *path, int32_t *n_entries);
 /* The tiles a plan's evaluation used. */

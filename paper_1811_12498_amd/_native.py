@@ -70,11 +70,11 @@ _lib.stk_plan_far_split.argtypes = [_vp, _i32p, _i64p]
 class Tiles(ctypes.Structure):
     """stk_tiles: kernel variants of the far and near fields."""
     _fields_ = [("far_kb", ctypes.c_int32), ("near_kb", ctypes.c_int32), ("near_mfma", ctypes.c_int32),
-                ("far_mfma", ctypes.c_int32), ("far_cm", ctypes.c_int32)]
+                ("far_mfma", ctypes.c_int32), ("far_cm", ctypes.c_int32), ("far_split", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {"far_kb": self.far_kb, "near_kb": self.near_kb, "near_mfma": bool(self.near_mfma),
-                "far_mfma": bool(self.far_mfma), "far_cm": int(self.far_cm)}
+                "far_mfma": bool(self.far_mfma), "far_cm": int(self.far_cm), "far_split": int(self.far_split)}
 
 
 _lib.stk_tiles_set.argtypes = [_i32, _i32, ctypes.c_int, ctypes.POINTER(Tiles)]
@@ -318,9 +318,10 @@ def plan_lists(plan: Plan, kind: str) -> dict:
 
 
 def tiles_set(p: int, k_rhs: int, precision: str, far_kb: int = 1, near_kb: int = 1, near_mfma: bool = False,
-              far_mfma: bool = False, clear: bool = False, far_cm: int = 0) -> None:
-    """far_cm: 0 automatic, 1 every far entry cluster major, 2 only the sparse split."""
-    t = Tiles(far_kb, near_kb, int(near_mfma), int(far_mfma), int(far_cm))
+              far_mfma: bool = False, clear: bool = False, far_cm: int = 0, far_split: int = 0) -> None:
+    """far_cm: 0 automatic, 1 every far entry cluster major, 2 only the sparse split.
+    far_split: parts of each group's far list (1..4), 0 automatic."""
+    t = Tiles(far_kb, near_kb, int(near_mfma), int(far_mfma), int(far_cm), int(far_split))
     _check(_lib.stk_tiles_set(int(p), int(k_rhs), _prec(precision), None if clear else ctypes.byref(t)))
 
 

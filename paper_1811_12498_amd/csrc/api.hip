@@ -451,10 +451,11 @@ stk::Tiles from_abi(const stk_tiles &t) {
     r.near_mfma = t.near_mfma != 0;
     r.far_mfma = t.far_mfma != 0;
     r.far_cm = t.far_cm;
+    r.far_split = t.far_split;
     return r;
 }
 stk_tiles to_abi(const stk::Tiles &t) {
-    return stk_tiles{t.far_kb, t.near_kb, t.near_mfma ? 1 : 0, t.far_mfma ? 1 : 0, t.far_cm};
+    return stk_tiles{t.far_kb, t.near_kb, t.near_mfma ? 1 : 0, t.far_mfma ? 1 : 0, t.far_cm, t.far_split};
 }
 void check_tile_key(int32_t p, int32_t k_rhs, stk_precision prec) {
     stk::require(p >= 0 && p <= STK_P_MAX, "p must be in [0, STK_P_MAX]");

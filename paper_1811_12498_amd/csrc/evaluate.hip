@@ -7,6 +7,9 @@
 // (a near entry) and the lanes that descend (children pushed with their mask).  This
 // is exactly Algorithm 1 per target; the lists are built in two passes (count, scan,
 // fill) and kept in the plan for the adjoint.
+#include <map>
+#include <mutex>
+
 #include "far_kernels.hpp"
 #include "stk_internal.hpp"
 #include "stk_math.hpp"
@@ -259,6 +262,34 @@ __global__ void k_direct_reduce(const double *__restrict__ part, int64_t m, int 
 
 inline unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
 
+// compute units of the current device (looked up once per device)
+int device_cus() {
+    static std::mutex mu;
+    static std::map<int, int> cus;
+    int dev = 0;
+    STK_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cus.find(dev);
+    if (it != cus.end()) return it->second;
+    int n = 0;
+    STK_HIP(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev));
+    cus[dev] = n > 0 ? n : 1;
+    return cus[dev];
+}
+
+// the split far field's parts in order, plus the near part, in the caller's order
+__global__ void k_far_combine(const double *__restrict__ fpart, int32_t nsplit, const double *__restrict__ unear,
+                              const int32_t *__restrict__ tperm, int64_t m, int32_t K, double *__restrict__ u_out) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= m * K) return;
+    const int64_t r = i / m, t = i - r * m;
+    double u[3] = {0.0, 0.0, 0.0};
+    for (int32_t h = 0; h < nsplit; ++h)
+        for (int q = 0; q < 3; ++q) u[q] += fpart[((size_t(h) * K + r) * m + t) * 3 + q];
+    const int64_t o = tperm[t];
+    for (int q = 0; q < 3; ++q) u_out[(size_t(r) * m + o) * 3 + q] = u[q] + unear[(size_t(t) * K + r) * 3 + q];
+}
+
 template <typename T, int KB> void dispatch_far(int p, const FarArgs &a, hipStream_t s) {
     switch (p) {
         case 0: launch_far<0, T, KB>(a, s); break;
@@ -480,8 +511,21 @@ void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, dou
     const int sparse_max = all_cm ? 64 : (K == 1 && cm_fits ? FAR_SPARSE_MAX : 0);
     if (sparse_max > 0) far_sparse(t, pl, unear, sparse_max, s);
     pl.far_sparse_max = sparse_max;
+    // parts of each group's far list (tile far_split; automatically enough parts for
+    // FAR_SPLIT_ROUNDS rounds of waves, so the last round idles little of the chip)
+    int32_t nsplit = 1;
+    if (!all_cm && !pl.tiles.far_mfma && ng > 0) {
+        if (pl.tiles.far_split > 0) {
+            nsplit = pl.tiles.far_split;
+        } else {
+            const int64_t slots = int64_t(device_cus()) * 4 * 4;
+            while (nsplit < FAR_SPLIT_MAX && int64_t(ng) * nsplit < FAR_SPLIT_ROUNDS * slots) ++nsplit;
+        }
+    }
+    pl.tiles.far_split = nsplit;
+    double *fpart = nsplit > 1 ? reserve<double>(pl.far_part, size_t(nsplit) * K * size_t(m) * 3) : nullptr;
     FarArgs fa{tpos, m, foff, pl.far_node.as<int32_t>(), pl.far_mask.as<uint64_t>(), t.ncenter.as<double>(),
-               t.nrho.as<double>(), t.wblk.p, unear, tperm, u_out, ng, K, sparse_max};
+               t.nrho.as<double>(), t.wblk.p, unear, tperm, u_out, ng, K, sparse_max, nsplit, fpart};
     if (t.prec == STK_FP64)
         dispatch_far<double, 1>(t.p, fa, s);
     else if (pl.tiles.far_mfma)
@@ -492,6 +536,11 @@ void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, dou
         dispatch_far<float, 2>(t.p, fa, s);
     else
         dispatch_far<float, 1>(t.p, fa, s);
+    if (nsplit > 1 && m > 0) {
+        hipLaunchKernelGGL(k_far_combine, dim3(nblk(m * K, 256)), dim3(256), 0, s, fpart, nsplit, unear, tperm, m, K,
+                           u_out);
+        STK_CHECK_LAUNCH();
+    }
     prof_mark(STK_PHASE_FAR, s);
 }
 

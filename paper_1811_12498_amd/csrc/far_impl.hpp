@@ -9,7 +9,9 @@ namespace stk {
 // walks its group's far list once and shares each interaction's recurrence between the
 // block's KB streams.  All resident waves work on the same block, so the streams in use
 // at a time are KB per cluster (the cluster data of one block fits the XCD's L2 where
-// that of all K would not).
+// that of all K would not).  With nsplit > 1 the list is cut into nsplit contiguous parts
+// (grid z), each a wave of its own that writes its compensated sums to fpart: more, shorter
+// waves, so the last round of waves on a chip with few rounds leaves less of it idle.
 template <int P, typename T, int KB>
 __global__ __launch_bounds__(64) void k_far(FarArgs a) {
     constexpr int WS = 6 * nidx(P + 1);
@@ -30,7 +32,10 @@ __global__ __launch_bounds__(64) void k_far(FarArgs a) {
     constexpr bool CAS = sizeof(T) == 8;
     using Eval = FarEval<P, T, KB, CAS>;
     const typename Eval::Ptr __restrict__ wb = (typename Eval::Ptr)(a.wblk);
-    const int32_t e0 = a.off[g], e1 = a.off[g + 1];
+    const int32_t f0 = a.off[g], f1 = a.off[g + 1];
+    const int32_t h = int32_t(blockIdx.z);
+    const int32_t e0 = f0 + int32_t((int64_t(f1 - f0) * h) / a.nsplit);
+    const int32_t e1 = f0 + int32_t((int64_t(f1 - f0) * (h + 1)) / a.nsplit);
     const int K = a.K;
     {
         const int r0 = int(blockIdx.y) * KB;
@@ -58,20 +63,29 @@ __global__ __launch_bounds__(64) void k_far(FarArgs a) {
             }
         }
         if (valid) {
-            const int64_t o = a.tperm[t];
+            if (a.nsplit == 1) {
+                const int64_t o = a.tperm[t];
 #pragma unroll
-            for (int r = 0; r < KB; ++r)
+                for (int r = 0; r < KB; ++r)
 #pragma unroll
-                for (int i = 0; i < 3; ++i)
-                    a.u_out[(size_t(r0 + r) * a.m + o) * 3 + i] =
-                        acc[r][i].value() + a.unear[(size_t(t) * K + r0 + r) * 3 + i];
+                    for (int i = 0; i < 3; ++i)
+                        a.u_out[(size_t(r0 + r) * a.m + o) * 3 + i] =
+                            acc[r][i].value() + a.unear[(size_t(t) * K + r0 + r) * 3 + i];
+            } else {
+#pragma unroll
+                for (int r = 0; r < KB; ++r)
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+                        a.fpart[((size_t(h) * K + r0 + r) * a.m + t) * 3 + i] = acc[r][i].value();
+            }
         }
     }
 }
 
 template <int P, typename T, int KB> void launch_far(const FarArgs &a, hipStream_t s) {
     if (a.ngroups == 0) return;
-    hipLaunchKernelGGL((k_far<P, T, KB>), dim3(xcd_blocks(a.ngroups), unsigned(a.K / KB)), dim3(64), 0, s, a);
+    hipLaunchKernelGGL((k_far<P, T, KB>), dim3(xcd_blocks(a.ngroups), unsigned(a.K / KB), unsigned(a.nsplit)), dim3(64),
+                       0, s, a);
     STK_CHECK_LAUNCH();
 }
 

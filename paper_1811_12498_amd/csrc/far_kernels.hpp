@@ -27,6 +27,9 @@ struct FarArgs {
     int32_t ngroups;
     int32_t K;               // right-hand sides (a multiple of the kernel's block KB)
     int32_t sparse_max;      // entries with at most this many targets are done elsewhere (0: none)
+    int32_t nsplit;          // parts of each group's far list, one wave each (grid z); 1: the
+                             // wave adds the near part and writes u_out itself
+    double *fpart;           // nsplit > 1: (nsplit, K, m, 3) each part's sums, sorted targets
 };
 
 // cluster-major items of the sparse far entries (one right-hand side)

@@ -153,6 +153,7 @@ struct Tiles {
     bool near_mfma = false;  // near field on the matrix cores (FP32)
     bool far_mfma = false;   // far field on the matrix cores (FP32)
     int32_t far_cm = 0;      // FAR_CM_AUTO / FAR_CM_ON / FAR_CM_OFF
+    int32_t far_split = 0;   // parts of each group's far list, a wave each (1..FAR_SPLIT_MAX; 0: automatic)
 };
 
 // far_cm modes: every far entry cluster major when the group lists' lanes are less than
@@ -160,6 +161,9 @@ struct Tiles {
 // with one right-hand side)
 constexpr int32_t FAR_CM_AUTO = 0, FAR_CM_ON = 1, FAR_CM_OFF = 2;
 constexpr double FAR_CM_UTIL = 0.75;
+// far_split: at most this many parts; the automatic choice is the smallest number of parts
+// that gives at least FAR_SPLIT_ROUNDS waves per wave slot of four waves per SIMD
+constexpr int32_t FAR_SPLIT_MAX = 4, FAR_SPLIT_ROUNDS = 12;
 // cluster-major lists index incidences with int32
 constexpr int64_t CM_MAX_INC = (int64_t(1) << 31) - 64;
 
@@ -187,6 +191,7 @@ struct Plan {
     double reg_eps = -1.0;            // >= 0: the last evaluation used the regularized kernels with this eps
     Tiles force;
     AdjScratch adj;
+    DBuf far_part;                    // double (parts, K, m, 3): sums of the split group-major far field
     ~Plan();
 };
 

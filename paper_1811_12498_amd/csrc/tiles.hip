@@ -3,7 +3,8 @@
 // For a given (device architecture, Taylor order p, number of right-hand sides K,
 // precision) the far and near fields can run as VALU kernels that take 1, 2 or 4
 // right-hand sides per pass, or (FP32, several right-hand sides) run on the matrix
-// cores.  stk_autotune times every candidate on a synthetic problem of the
+// cores; the far field can run every entry cluster major, and its group-major lists can
+// be cut into up to four parts, a wave each.  stk_autotune times every candidate on a synthetic problem of the
 // caller's shape (uniform points in the unit cube generated on the device) and records
 // the fastest; evaluations look the table up and fall back to a fixed rule otherwise.
 // The table can be written to and read from a text file.
@@ -86,6 +87,8 @@ bool tiles_valid(const Tiles &t, int K, stk_precision prec) {
     if (prec == STK_FP64 && (t.far_kb != 1 || t.near_kb != 1 || t.near_mfma || t.far_mfma)) return false;
     if (t.far_cm != FAR_CM_AUTO && t.far_cm != FAR_CM_ON && t.far_cm != FAR_CM_OFF) return false;
     if (t.far_cm == FAR_CM_ON && t.far_mfma) return false;  // the matrix-core far kernel has no cluster-major split
+    if (t.far_split < 0 || t.far_split > FAR_SPLIT_MAX) return false;
+    if (t.far_mfma && t.far_split > 1) return false;  // nor split group lists
     return true;
 }
 
@@ -118,11 +121,11 @@ void tiles_save(const char *path) {
     std::lock_guard<std::mutex> lk(g_mu);
     FILE *fp = std::fopen(path, "w");
     if (!fp) throw Error(STK_EINVAL, std::string("cannot write ") + path);
-    std::fprintf(fp, "# arch p K precision far_kb near_kb near_mfma far_mfma far_cm\n");
+    std::fprintf(fp, "# arch p K precision far_kb near_kb near_mfma far_mfma far_cm far_split\n");
     for (const auto &e : g_table)
-        std::fprintf(fp, "%s %d %d %d %d %d %d %d %d\n", std::get<0>(e.first).c_str(), std::get<1>(e.first),
+        std::fprintf(fp, "%s %d %d %d %d %d %d %d %d %d\n", std::get<0>(e.first).c_str(), std::get<1>(e.first),
                      std::get<2>(e.first), std::get<3>(e.first), e.second.far_kb, e.second.near_kb,
-                     e.second.near_mfma ? 1 : 0, e.second.far_mfma ? 1 : 0, e.second.far_cm);
+                     e.second.near_mfma ? 1 : 0, e.second.far_mfma ? 1 : 0, e.second.far_cm, e.second.far_split);
     std::fclose(fp);
 }
 
@@ -136,9 +139,11 @@ int tiles_load(const char *path) {
         ++lineno;
         if (line[0] == '#' || line[0] == '\n') continue;
         char arch[128];
-        int p, K, prec, fkb, nkb, nm, fm, fc;
-        if (std::sscanf(line, "%127s %d %d %d %d %d %d %d %d", arch, &p, &K, &prec, &fkb, &nkb, &nm, &fm, &fc) != 9 ||
-            (prec != STK_FP64 && prec != STK_MIXED)) {
+        int p, K, prec, fkb, nkb, nm, fm, fc, fs = 0;
+        // far_split may be absent (tables written before it existed: automatic)
+        const int got = std::sscanf(line, "%127s %d %d %d %d %d %d %d %d %d", arch, &p, &K, &prec, &fkb, &nkb, &nm,
+                                    &fm, &fc, &fs);
+        if ((got != 9 && got != 10) || (prec != STK_FP64 && prec != STK_MIXED)) {
             std::fclose(fp);
             throw Error(STK_EINVAL, std::string(path) + ": malformed line " + std::to_string(lineno));
         }
@@ -148,6 +153,7 @@ int tiles_load(const char *path) {
         t.near_mfma = nm != 0;
         t.far_mfma = fm != 0;
         t.far_cm = fc;
+        t.far_split = got == 10 ? fs : 0;
         if (!tiles_valid(t, K, stk_precision(prec))) {
             std::fclose(fp);
             throw Error(STK_EINVAL, std::string(path) + ": invalid tiles on line " + std::to_string(lineno));
@@ -201,6 +207,14 @@ Tiles autotune(int p, int K, stk_precision prec, int64_t n, double theta, int32_
             t.far_cm = mode;
             if (tiles_valid(t, K, prec)) far_c.push_back(t);
         }
+    for (int split = 1; split <= FAR_SPLIT_MAX; ++split) {
+        // group-major far lists cut into `split` parts, a wave each
+        Tiles t = default_tiles(K, prec);
+        t.far_mfma = false;
+        t.far_cm = FAR_CM_OFF;
+        t.far_split = split;
+        if (tiles_valid(t, K, prec)) far_c.push_back(t);
+    }
     hipEvent_t e0, e1;
     STK_HIP(hipEventCreate(&e0));
     STK_HIP(hipEventCreate(&e1));

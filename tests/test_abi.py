@@ -37,21 +37,24 @@ def test_tiles_file_round_trip(tmp_path):
     and a malformed or invalid line rejects the whole file (no device needed)."""
     from paper_1811_12498_amd import native
     good = tmp_path / "tiles.txt"
-    good.write_text("# arch p K precision far_kb near_kb near_mfma far_mfma far_cm\n"
-                    "gfx950 8 16 1 4 4 1 1 0\n"
-                    "gfx950 6 1 0 1 1 0 0 1\n"
-                    "gfx950 5 4 1 2 2 0 0 2\n")
+    good.write_text("# arch p K precision far_kb near_kb near_mfma far_mfma far_cm far_split\n"
+                    "gfx950 8 16 1 4 4 1 1 0 0\n"
+                    "gfx950 6 1 0 1 1 0 0 1 3\n"
+                    "gfx950 5 4 1 2 2 0 0 2\n")    # written before far_split existed: automatic
     assert native.tiles_load(str(good)) == 3
     out = tmp_path / "saved.txt"
     native.tiles_save(str(out))
     lines = {ln for ln in out.read_text().splitlines() if not ln.startswith("#")}
-    assert {"gfx950 8 16 1 4 4 1 1 0", "gfx950 6 1 0 1 1 0 0 1", "gfx950 5 4 1 2 2 0 0 2"} <= lines
+    assert {"gfx950 8 16 1 4 4 1 1 0 0", "gfx950 6 1 0 1 1 0 0 1 3", "gfx950 5 4 1 2 2 0 0 2 0"} <= lines
     for bad in ("gfx950 8 16 1 4 4 1 1\n",      # too few fields
                 "gfx950 8 16 0 4 1 0 0 0\n",    # FP64 with 4 right-hand sides per pass
                 "gfx950 8 16 0 1 1 0 1 0\n",    # FP64 on the matrix cores
                 "gfx950 8 6 1 4 1 0 0 0\n",     # 4 does not divide K = 6
                 "gfx950 8 16 1 1 1 0 1 1\n",    # matrix-core far field with the cluster-major split
                 "gfx950 8 16 1 1 1 0 0 3\n",    # unknown far_cm mode
+                "gfx950 8 1 1 1 1 0 0 0 5\n",   # more than four far-list parts
+                "gfx950 8 1 1 1 1 0 0 0 -1\n",  # negative far-list parts
+                "gfx950 8 16 1 1 1 0 1 0 2\n",  # matrix-core far field with split lists
                 "gfx950 8 16 7 1 1 0 0 0\n"):   # unknown precision
         f = tmp_path / "bad.txt"
         f.write_text(bad)

@@ -101,7 +101,11 @@ def test_autotune_records_valid_tiles(nat):
     w = W.cube(20_000, seed=70, n0=200, k=K)
     X = _t(w.src)
     u, plan = nat.evaluate(X, X, _t(w.f), _t(w.h), _t(w.nu), p, 0.6, 200, "mixed", keep_plan=True)
-    assert nat.plan_tiles(plan) == best
+    used = nat.plan_tiles(plan)
+    # the plan reports the far-list parts it used (1 when every far entry ran cluster major)
+    assert {k: v for k, v in used.items() if k != "far_split"} == {k: v for k, v in best.items() if k != "far_split"}
+    all_cm = nat.plan_far_split(plan)[0] == 64
+    assert used["far_split"] == (1 if all_cm else (best["far_split"] or used["far_split"])) and used["far_split"] >= 1
     u64 = nat.evaluate(X, X, _t(w.f), _t(w.h), _t(w.nu), p, 0.6, 200, "fp64")
     assert float((u - u64).norm() / u64.norm()) < 1e-5
     nat.tiles_set(p, K, "mixed", clear=True)
@@ -199,3 +203,62 @@ def test_far_schedule_automatic_rule(nat, kind):
     assert nat.plan_tiles(plan)["far_cm"] == 0
     util = nat.plan_counts(plan)[0].sum() / (64.0 * nat.plan_info(plan)["far_entries"])
     assert nat.plan_far_split(plan)[0] == (64 if util < 0.75 else 32), util
+
+
+@pytest.mark.parametrize("K,prec", [(1, "fp64"), (1, "mixed"), (3, "fp64"), (4, "mixed")])
+def test_far_split_parts_agree(nat, K, prec):
+    """Tile far_split: each group's far list cut into 2, 3 or 4 parts (a wave each, the
+    parts' sums added in part order afterwards) gives the one-part result per right-hand
+    side; the plan reports the number of parts it used."""
+    p, theta, n0 = 6, 0.5, 400
+    w = W.cube(30_000, seed=120 + K, n0=n0, k=K)
+    X = _t(w.src)
+    F, H, NU = _t(w.f), _t(w.h), _t(w.nu)
+    us = {}
+    try:
+        for split in (1, 2, 3, 4):
+            nat.tiles_set(p, K, prec, far_kb=1, near_kb=1, far_cm=2, far_split=split)
+            us[split], pl = nat.evaluate(X, X, F, H, NU, p, theta, n0, prec, keep_plan=True)
+            assert nat.plan_tiles(pl)["far_split"] == split
+    finally:
+        nat.tiles_set(p, K, prec, clear=True)
+    ref = us[1] if K > 1 else us[1][None]
+    for split in (2, 3, 4):
+        u = us[split] if K > 1 else us[split][None]
+        for r in range(K):
+            e = float((u[r] - ref[r]).norm() / ref[r].norm())
+            assert e < (1e-14 if prec == "fp64" else 1e-6), (split, r, e)
+
+
+def test_far_split_fp64_matches_oracle(nat, orc):
+    """The group-major far field in three parts, FP64, against the oracle treecode
+    (disjoint targets, ragged last group)."""
+    n0, p, theta = 64, 7, 0.5
+    w = W.cube(5000, seed=123, n0=n0)
+    tg = np.random.default_rng(124).uniform(-0.1, 1.1, (1999, 3))
+    try:
+        nat.tiles_set(p, 1, "fp64", far_cm=2, far_split=3)
+        u = nat.evaluate(_t(tg), _t(w.src), _t(w.f[0]), _t(w.h[0]), _t(w.nu), p, theta, n0, "fp64")
+    finally:
+        nat.tiles_set(p, 1, "fp64", clear=True)
+    T = orc.build_tree(w.src, n0)
+    M, Mt = orc.moments(T, w.src, w.f[0], w.h[0], w.nu, p)
+    ref = orc.treecode(T, w.src, w.f[0], w.h[0], w.nu, M, Mt, p, theta, tg)
+    assert orc.rel_l2(u.cpu().numpy(), ref.u) < 1e-12
+
+
+def test_far_split_automatic_rule(nat):
+    """Tile far_split = 0: the fewest parts (at most four) that give at least twelve waves per
+    wave slot of four waves per SIMD; 1 when every far entry runs cluster major."""
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    w = W.sphere(200_000, seed=125, n0=1000)
+    X = _t(w.src)
+    _, plan = nat.evaluate(X, X, _t(w.f[0]), _t(w.h[0]), _t(w.nu), 8, 0.5, w.n0, "mixed", keep_plan=True)
+    ng = (w.n + 63) // 64
+    want = 1
+    while want < 4 and ng * want < 12 * cus * 16:
+        want += 1
+    if nat.plan_far_split(plan)[0] == 64:
+        want = 1
+    assert nat.plan_tiles(plan)["far_split"] == want, (ng, cus)
