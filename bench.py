@@ -602,6 +602,48 @@ def tune_c3(targets=(1e-3, 1e-4, 1e-5)):
             "best": best, "table": [c.__dict__ for c in table]}
 
 
+def far_split_times(reps=6):
+    """The group-major far field with each group's list in 1..4 parts (tile far_split
+    forced; 0 = the automatic choice) on the 1M sphere, at the metric's parameters and at
+    the at-error-bar ones: ms per evaluation and the far phase (the far kernel and the sum of
+    the parts) from the library's HIP events, mean of `reps` evaluations after two warm-ups."""
+    import torch
+
+    from paper_1811_12498_amd import native, workloads
+    w = workloads.c3_sphere_1m()
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    X, F, H, NU = t(w.src), t(w.f[0]), t(w.h[0]), t(w.nu)
+    rows = []
+    for p, theta, n0 in ((w.p, w.theta, w.n0), AT_ERROR_BAR):
+        for split in (0, 1, 2, 3, 4):
+            if split:
+                native.tiles_set(p, 1, "mixed", far_split=split)
+            else:
+                native.tiles_set(p, 1, "mixed", clear=True)
+            try:
+                for _ in range(2):
+                    native.evaluate(X, X, F, H, NU, p, theta, n0, "mixed")
+                torch.cuda.synchronize()
+                native.profile_read()
+                native.profile_enable(True)
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    native.evaluate(X, X, F, H, NU, p, theta, n0, "mixed")
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                native.profile_enable(False)
+                prof = native.profile_read()
+                _, plan = native.evaluate(X, X, F, H, NU, p, theta, n0, "mixed", keep_plan=True)
+                parts = native.plan_tiles(plan)["far_split"]
+                del plan
+            finally:
+                native.tiles_set(p, 1, "mixed", clear=True)
+            rows.append({"p": p, "theta": theta, "n0": n0, "far_split": split, "parts": parts,
+                         "ms": round((t1 - t0) * 1e3 / reps, 3), "far_ms": round(prof["far"][0] / prof["far"][1], 3)})
+    return {"workload": "sphere N=1e6 (normalised Gaussians), nu=normal, h=f, mixed", "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -616,7 +658,8 @@ def main():
                                     "e.g. far_mfma=1,near_mfma=1,far_kb=4,near_kb=4 (for profiling)")
     ap.add_argument("--params", nargs=3, metavar=("P", "THETA", "N0"),
                     help="evaluate the metric's points at these treecode parameters instead (for profiling)")
-    ap.add_argument("--only", choices=["fwd_adjoint", "multi_rhs", "table1", "tune", "c2", "regularized"],
+    ap.add_argument("--only", choices=["fwd_adjoint", "multi_rhs", "table1", "tune", "c2", "regularized",
+                                       "far_split"],
                     help="run only this secondary measurement and print its JSON object (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -636,7 +679,7 @@ def main():
     if args.only:
         res = {"fwd_adjoint": fwd_adjoint_times, "multi_rhs": multi_rhs_times,
                "table1": table1_icosphere, "tune": tune_c3, "c2": c2_grid,
-               "regularized": regularized_times}[args.only]()
+               "regularized": regularized_times, "far_split": far_split_times}[args.only]()
         print(json.dumps(res), flush=True)
         return
 
