@@ -443,6 +443,8 @@ stk_status stk_plan_export_lists(const stk_plan *plan, int32_t kind, int32_t *of
     });
 }
 
+}  // extern "C"
+
 namespace {
 stk::Tiles from_abi(const stk_tiles &t) {
     stk::Tiles r;
@@ -463,6 +465,8 @@ void check_tile_key(int32_t p, int32_t k_rhs, stk_precision prec) {
     stk::require(prec == STK_FP64 || prec == STK_MIXED, "unknown precision");
 }
 }  // namespace
+
+extern "C" {
 
 stk_status stk_tiles_set(int32_t p, int32_t k_rhs, stk_precision prec, const stk_tiles *tiles) {
     return guarded([&] {

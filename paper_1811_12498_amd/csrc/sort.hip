@@ -2,9 +2,9 @@
 //
 // Each pass handles 8 key bits: (1) per-tile digit histograms, (2) an exclusive scan of
 // each digit's row of tile counts plus a scan of the digit totals, (3) a stable scatter
-// in which every
-// tile ranks its keys round by round (256 keys per round, wave64 ballots find the
-// lanes sharing a digit, wave counts are combined in LDS in wave order).  Ties keep
+// in which every tile ranks its keys round by round (256 keys per round, wave64 ballots
+// find the lanes sharing a digit, wave counts are combined in LDS in wave order), lays
+// the tile out in digit order in LDS and writes each digit's run contiguously.  Ties keep
 // their input order, so sorting (key, index) pairs yields the order of a
 // lexicographic (key, index) sort.
 #include "stk_internal.hpp"
@@ -34,46 +34,85 @@ __global__ __launch_bounds__(ST) void k_hist(const uint64_t *__restrict__ keys, 
     hist[int64_t(tid) * ntiles + blockIdx.x] = cnt[tid];
 }
 
+// exclusive scan over the RADIX (= ST) values v of the block's threads, in thread order
+__device__ inline int32_t block_excl_radix(int32_t v, int32_t *ws) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) ws[wave] = x;
+    __syncthreads();
+    int32_t before = 0;
+    for (int w = 0; w < wave; ++w) before += ws[w];
+    return before + x - v;
+}
+
+// One tile per block.  The keys are ranked round by round as in a direct scatter (stable),
+// but placed at their position within the tile's digit-ordered layout in LDS; the tile is
+// then written out in that order, so each digit's run goes to consecutive addresses.
 __global__ __launch_bounds__(ST) void k_scatter(const uint64_t *__restrict__ kin, const int32_t *__restrict__ vin,
                                                 uint64_t *__restrict__ kout, int32_t *__restrict__ vout, int64_t n,
                                                 int shift, const int32_t *__restrict__ off, int32_t ntiles,
                                                 const int32_t *__restrict__ dbase) {
-    __shared__ int32_t base[RADIX];
+    static_assert(RADIX == ST, "one thread per digit");
+    __shared__ uint64_t lk[TILE];
+    __shared__ int32_t lv[TILE];
+    __shared__ int32_t gbase[RADIX];   // global start of this tile's run of each digit
+    __shared__ int32_t tstart[RADIX];  // start of each digit's run within the tile
+    __shared__ int32_t run[RADIX];     // keys of each digit placed so far
     __shared__ int32_t wcnt[NWAVE][RADIX];
+    __shared__ int32_t ws[NWAVE];
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
-    base[tid] = off[int64_t(tid) * ntiles + blockIdx.x] + dbase[tid];
+    const int32_t tile = blockIdx.x;
+    const int64_t tbase = int64_t(tile) * TILE;
+    const int32_t tn = int32_t(n - tbase < TILE ? n - tbase : TILE);
+    // this tile's count of digit tid: the difference of the scanned histogram row, the
+    // last tile against the digit's total
+    const int32_t o = off[int64_t(tid) * ntiles + tile];
+    int32_t total_d;
+    if (tid + 1 < RADIX)
+        total_d = dbase[tid + 1] - dbase[tid];
+    else
+        total_d = int32_t(n) - dbase[tid];
+    const int32_t cnt = (tile + 1 < ntiles ? off[int64_t(tid) * ntiles + tile + 1] : total_d) - o;
+    gbase[tid] = dbase[tid] + o;
+    tstart[tid] = block_excl_radix(cnt, ws);
+    run[tid] = 0;
     for (int w = 0; w < NWAVE; ++w) wcnt[w][tid] = 0;
     __syncthreads();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int64_t tbase = int64_t(blockIdx.x) * TILE;
     for (int it = 0; it < ITEMS; ++it) {
-        const int64_t i = tbase + int64_t(it) * ST + tid;
-        const bool valid = i < n;
+        const int32_t li = it * ST + tid;
+        const bool valid = li < tn;
         uint64_t key = 0;
         int32_t val = 0;
         int dig = 0;
         if (valid) {
-            key = kin[i];
-            val = vin[i];
+            key = kin[tbase + li];
+            val = vin[tbase + li];
             dig = int((key >> shift) & (RADIX - 1));
         }
         uint64_t match = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < RB; ++b) {
-            const bool bit = (dig >> b) & 1;
+        for (int bt = 0; bt < RB; ++bt) {
+            const bool bit = (dig >> bt) & 1;
             const uint64_t bb = __ballot(bit);
             match &= bit ? bb : ~bb;
         }
         const int rank = __popcll(match & lt);
         if (valid && rank == 0) wcnt[wave][dig] = __popcll(match);
         __syncthreads();
-        int dest = 0;
         if (valid) {
             int before = 0;
             for (int w = 0; w < wave; ++w) before += wcnt[w][dig];
-            dest = base[dig] + before + rank;
+            const int32_t lp = tstart[dig] + run[dig] + before + rank;
+            lk[lp] = key;
+            lv[lp] = val;
         }
         __syncthreads();
         {
@@ -82,12 +121,20 @@ __global__ __launch_bounds__(ST) void k_scatter(const uint64_t *__restrict__ kin
                 tot += wcnt[w][tid];
                 wcnt[w][tid] = 0;
             }
-            base[tid] += tot;
+            run[tid] += tot;
         }
         __syncthreads();
-        if (valid) {
+    }
+    // the tile in digit order: consecutive positions of one digit go to consecutive
+    // addresses
+    for (int it = 0; it < ITEMS; ++it) {
+        const int32_t li = it * ST + tid;
+        if (li < tn) {
+            const uint64_t key = lk[li];
+            const int dig = int((key >> shift) & (RADIX - 1));
+            const int64_t dest = int64_t(gbase[dig]) + (li - tstart[dig]);
             kout[dest] = key;
-            vout[dest] = val;
+            vout[dest] = lv[li];
         }
     }
 }
