@@ -495,8 +495,12 @@ void transpose(Tree &t, const DBuf &goff, const DBuf &gnode, int64_t ne, int32_t
     STK_CHECK_LAUNCH();
     scan_exclusive_i32(cnt, ioff, nn, t.s_scan, s);
     int32_t nitems = 0;
-    STK_HIP(hipMemcpyAsync(&nitems, ioff + nn, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    STK_HIP(hipStreamSynchronize(s));
+    {
+        const PeekSrc src{ioff + nn, 4};
+        int64_t v = 0;
+        peek(t.peek, s, 1, &src, &v);
+        nitems = int32_t(v);
+    }
     tr.nitems = nitems;
     int32_t *inode = reserve<int32_t>(tr.item_node, size_t(nitems) + 1);
     int32_t *ia = reserve<int32_t>(tr.item_a, size_t(nitems) + 1);
@@ -520,11 +524,11 @@ void adjoint(Plan &pl, const double *w, double *gf, double *gh, double *gt, doub
     prof_mark(-1, s);
 
     double *ws = reserve<double>(A.ws, size_t(m) * 3);
-    hipLaunchKernelGGL(k_gather_w, dim3(nblk(m, 256)), dim3(256), 0, s, w, pl.tperm.as<int32_t>(), m, ws);
+    hipLaunchKernelGGL(k_gather_w, dim3(nblk(m, 256)), dim3(256), 0, s, w, pl.tperm_p, m, ws);
     STK_CHECK_LAUNCH();
 
     NearAdjArgs na{};
-    na.tpos = pl.tpos.as<double>();
+    na.tpos = pl.tpos_p;
     na.ws = ws;
     na.m = m;
     na.off = pl.near_off.as<int32_t>();
@@ -541,7 +545,7 @@ void adjoint(Plan &pl, const double *w, double *gf, double *gh, double *gt, doub
         gtn = reserve<double>(A.gt_near, size_t(m) * 3);
         gtf = reserve<double>(A.gt_far, size_t(m) * 3);
         na.gt = gtn;
-        NearTgradArgs nt{pl.tpos.as<double>(), ws, pl.ncm.item_node.as<int32_t>(), pl.ncm.item_i0.as<int32_t>(),
+        NearTgradArgs nt{pl.tpos_p, ws, pl.ncm.item_node.as<int32_t>(), pl.ncm.item_i0.as<int32_t>(),
                          pl.ncm.item_i1.as<int32_t>(), pl.ncm.inc_tgt.as<int32_t>(), pl.ncm.inc_slot.as<int32_t>(),
                          t.nstart.as<int32_t>(), t.ncount.as<int32_t>(), t.geo.as<double>(), t.wts.p,
                          pl.ncm.part.p, pl.ncm.n_items};
@@ -586,8 +590,12 @@ void adjoint(Plan &pl, const double *w, double *gf, double *gh, double *gt, doub
         STK_CHECK_LAUNCH();
         scan_exclusive_i32(cnt, ioff, nn, t.s_scan, s);
         int32_t nitems = 0;
-        STK_HIP(hipMemcpyAsync(&nitems, ioff + nn, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        STK_HIP(hipStreamSynchronize(s));
+        {
+            const PeekSrc src{ioff + nn, 4};
+            int64_t v = 0;
+            peek(t.peek, s, 1, &src, &v);
+            nitems = int32_t(v);
+        }
         TransposedLists &tr = A.far_t;
         tr.nitems = nitems;
         int32_t *inode = reserve<int32_t>(tr.item_node, size_t(nitems) + 1);
@@ -600,7 +608,7 @@ void adjoint(Plan &pl, const double *w, double *gf, double *gh, double *gt, doub
         }
         double *lam = reserve<double>(A.lambda, size_t(nn) * 6 * ngc);
         STK_HIP(hipMemsetAsync(lam, 0, sizeof(double) * size_t(nn) * 6 * ngc, s));
-        la.tpos = pl.tpos.as<double>();
+        la.tpos = pl.tpos_p;
         la.ws = ws;
         la.m = m;
         la.item_node = inode;
@@ -616,7 +624,7 @@ void adjoint(Plan &pl, const double *w, double *gf, double *gh, double *gt, doub
     }
     if (gt) {
         const size_t tsz = fp64 ? sizeof(double) : sizeof(float);
-        ta.tpos = pl.tpos.as<double>();
+        ta.tpos = pl.tpos_p;
         ta.ws = ws;
         ta.item_node = fc.item_node.as<int32_t>();
         ta.item_i0 = fc.item_i0.as<int32_t>();
@@ -683,7 +691,7 @@ void adjoint(Plan &pl, const double *w, double *gf, double *gh, double *gt, doub
         STK_CHECK_LAUNCH();
     }
     if (gt) {
-        hipLaunchKernelGGL(k_tgt_total, dim3(nblk(m, 256)), dim3(256), 0, s, gtf, gtn, m, pl.tperm.as<int32_t>(), gt);
+        hipLaunchKernelGGL(k_tgt_total, dim3(nblk(m, 256)), dim3(256), 0, s, gtf, gtn, m, pl.tperm_p, gt);
         STK_CHECK_LAUNCH();
     }
     prof_mark(STK_PHASE_ADJOINT, s);

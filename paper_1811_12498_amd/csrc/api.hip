@@ -70,32 +70,30 @@ hipStream_t side_stream(int dev) {
 
 // Tree on the caller's stream, then the moments on the side stream (after the tree and
 // everything queued before it) while the evaluation proceeds; the evaluation waits for
-// them before its near field.
+// the source records before its near field and for the moments before its far field.
 void tree_moments_evaluate(stk::Tree &tree, stk::Plan &pl, const double *targets, int64_t m, const double *sources,
                            int64_t n, const double *f, const double *h, const double *nu, int32_t k_rhs, int32_t p,
                            double theta, int32_t n0, stk_precision prec, double *u_out, bool same, hipStream_t s) {
     stk::build_tree(tree, sources, n, n0, s);
     hipStream_t s2 = side_stream(tree.device);
-    hipEvent_t built = nullptr, ready = nullptr;
-    STK_HIP(hipEventCreateWithFlags(&built, hipEventDisableTiming));
-    STK_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // tree built, records written, moments done
+    for (hipEvent_t &e : ev) STK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     try {
-        STK_HIP(hipEventRecord(built, s));
-        STK_HIP(hipStreamWaitEvent(s2, built, 0));
-        stk::compute_moments(tree, f, h, nu, k_rhs, p, prec, s2);
-        STK_HIP(hipEventRecord(ready, s2));
-        pl.moments_ready = ready;
+        STK_HIP(hipEventRecord(ev[0], s));
+        STK_HIP(hipStreamWaitEvent(s2, ev[0], 0));
+        stk::compute_moments(tree, f, h, nu, k_rhs, p, prec, s2, ev[1]);
+        STK_HIP(hipEventRecord(ev[2], s2));
+        pl.records_ready = ev[1];
+        pl.moments_ready = ev[2];
         stk::evaluate(tree, pl, targets, m, theta, u_out, same, s);
     } catch (...) {
-        pl.moments_ready = nullptr;
+        pl.records_ready = pl.moments_ready = nullptr;
         (void)hipStreamSynchronize(s2);
-        (void)hipEventDestroy(built);
-        (void)hipEventDestroy(ready);
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
         throw;
     }
-    pl.moments_ready = nullptr;
-    (void)hipEventDestroy(built);
-    (void)hipEventDestroy(ready);
+    pl.records_ready = pl.moments_ready = nullptr;
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
 }
 
 // Plans that own their tree, parked by stk_plan_destroy for the next stk_evaluate with
@@ -178,6 +176,7 @@ stk_status stk_build_tree(const double *src, int64_t n, int32_t n0, void *stream
         try {
             STK_HIP(hipGetDevice(&h->t.device));
             stk::build_tree(h->t, src, n, n0, as_stream(stream));
+            STK_HIP(hipStreamSynchronize(as_stream(stream)));
         } catch (...) {
             delete h;
             throw;
@@ -403,7 +402,7 @@ stk_status stk_plan_counts(const stk_plan *plan, int64_t *nfar, int64_t *nnear, 
         const size_t m = size_t(P.m);
         std::vector<int32_t> perm(m), a(m), b(m), c(m);
         STK_HIP(hipDeviceSynchronize());
-        STK_HIP(hipMemcpy(perm.data(), P.tperm.p, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
+        if (m) STK_HIP(hipMemcpy(perm.data(), P.tperm_p, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
         STK_HIP(hipMemcpy(a.data(), P.cnt_far.p, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
         STK_HIP(hipMemcpy(b.data(), P.cnt_near.p, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
         STK_HIP(hipMemcpy(c.data(), P.cnt_pairs.p, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
@@ -439,7 +438,7 @@ stk_status stk_plan_export_lists(const stk_plan *plan, int32_t kind, int32_t *of
         cp(off, kind == 0 ? P.far_off : P.near_off, sizeof(int32_t) * size_t(P.ngroups + 1));
         cp(node, kind == 0 ? P.far_node : P.near_node, sizeof(int32_t) * ne);
         cp(mask, kind == 0 ? P.far_mask : P.near_mask, sizeof(uint64_t) * ne);
-        cp(tperm, P.tperm, sizeof(int32_t) * size_t(P.m));
+        if (tperm && P.m) STK_HIP(hipMemcpy(tperm, P.tperm_p, sizeof(int32_t) * size_t(P.m), hipMemcpyDeviceToHost));
     });
 }
 

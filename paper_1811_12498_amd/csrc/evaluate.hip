@@ -5,8 +5,11 @@
 // applies the MAC (eq. MAC) to its own target, and the wave splits the cluster into
 // the lanes that accept it (a far entry with their mask), the lanes that reach a leaf
 // (a near entry) and the lanes that descend (children pushed with their mask).  This
-// is exactly Algorithm 1 per target; the lists are built in two passes (count, scan,
-// fill) and kept in the plan for the adjoint.
+// is exactly Algorithm 1 per target.  The lists are built in one pass into per-group
+// slots plus a compaction (two passes, count then fill at the scanned offsets, when the
+// slots would not hold them) and kept in the plan for the adjoint.
+#include <algorithm>
+#include <climits>
 #include <map>
 #include <mutex>
 
@@ -20,6 +23,10 @@ namespace stk {
 namespace {
 
 constexpr int STACK = 256;  // >= 1 + 7 * STK_MAX_LEVEL
+// per-group list slots of the one-pass traversal: at least these many entries, at most
+// this many bytes in all (else two passes)
+constexpr int32_t TRAV_SLOT_FAR_MIN = 256, TRAV_SLOT_NEAR_MIN = 64;
+constexpr size_t TRAV_SLOT_BYTES_MAX = size_t(2) << 30;
 
 __device__ inline uint64_t rfl64(uint64_t v) {
     const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(v));
@@ -30,9 +37,7 @@ __device__ inline uint64_t rfl64(uint64_t v) {
 struct TravArgs {
     const double *tpos;
     int64_t m;
-    const double *center;
-    const double *radius;
-    const int32_t *child0, *nchild, *count;
+    const TravNode *node;
     double theta;
     // count pass outputs
     int32_t *gfar, *gnear;              // per group entry counts
@@ -42,9 +47,19 @@ struct TravArgs {
     const int32_t *far_off, *near_off;
     int32_t *far_node, *near_node;
     uint64_t *far_mask, *near_mask;
+    // one-pass mode: each group's entries at g * slot_far (slot_near) in the slot arrays,
+    // at most that many (the counts are exact either way)
+    int32_t slot_far, slot_near;
+    int32_t *sfar_node, *snear_node;
+    uint64_t *sfar_mask, *snear_mask;
 };
 
-template <bool FILL> __global__ __launch_bounds__(64) void k_traverse(TravArgs a) {
+// COUNT: counts only; FILL: entries at the scanned offsets; SLOT: counts, and entries into
+// fixed per-group slots (compacted afterwards)
+enum TravMode { TRAV_COUNT = 0, TRAV_FILL = 1, TRAV_SLOT = 2 };
+
+template <int MODE> __global__ __launch_bounds__(64) void k_traverse(TravArgs a) {
+    constexpr bool FILL = MODE == TRAV_FILL, SLOT = MODE == TRAV_SLOT;
     __shared__ int32_t st_node[STACK];
     __shared__ uint64_t st_mask[STACK];
     const int32_t g = blockIdx.x;
@@ -63,13 +78,13 @@ template <bool FILL> __global__ __launch_bounds__(64) void k_traverse(TravArgs a
         fo = a.far_off[g];
         no = a.near_off[g];
     }
-    // the node table is read only: through the constant address space its loads at the
-    // wave-uniform node index stay scalar even in the fill pass, which stores lists
-    const STK_CONST_AS double *cen = (const STK_CONST_AS double *)(a.center);
-    const STK_CONST_AS double *rad = (const STK_CONST_AS double *)(a.radius);
-    const STK_CONST_AS int32_t *nch = (const STK_CONST_AS int32_t *)(a.nchild);
-    const STK_CONST_AS int32_t *ch0 = (const STK_CONST_AS int32_t *)(a.child0);
-    const STK_CONST_AS int32_t *cnt = (const STK_CONST_AS int32_t *)(a.count);
+    int32_t *const sfn = SLOT ? a.sfar_node + int64_t(g) * a.slot_far : nullptr;
+    uint64_t *const sfm = SLOT ? a.sfar_mask + int64_t(g) * a.slot_far : nullptr;
+    int32_t *const snn = SLOT ? a.snear_node + int64_t(g) * a.slot_near : nullptr;
+    uint64_t *const snm = SLOT ? a.snear_mask + int64_t(g) * a.slot_near : nullptr;
+    // the node records are read only: through the constant address space the load at the
+    // wave-uniform node index stays scalar even in the fill pass, which stores lists
+    const STK_CONST_AS TravNode *nodes = (const STK_CONST_AS TravNode *)(a.node);
     const uint64_t vmask = __ballot(valid);
     if (lane == 0) {
         st_node[0] = 0;
@@ -82,9 +97,13 @@ template <bool FILL> __global__ __launch_bounds__(64) void k_traverse(TravArgs a
         const int32_t c = __builtin_amdgcn_readfirstlane(st_node[sp]);
         const uint64_t mk = rfl64(st_mask[sp]);
         __syncthreads();
-        // every field of the node is requested at once: one round trip per visit
-        const double y0 = cen[3 * c], y1 = cen[3 * c + 1], y2 = cen[3 * c + 2], rc = rad[c];
-        const int32_t k = nch[c], c0 = ch0[c], nc = cnt[c];
+        // the node's whole record in one load: one round trip per visit
+        const TravNode nd = nodes[c];
+        const double y0 = nd.c[0], y1 = nd.c[1], y2 = nd.c[2], rc = nd.r;
+        const int32_t k = nd.nchild, c0 = nd.child0, nc = nd.count;
+        // the integer fields are consumed here, so the compiler issues them with the centre
+        // and radius instead of sinking their load into the descend branch
+        asm volatile("" ::"s"(k), "s"(c0), "s"(nc));
         const bool in = (mk >> lane) & 1ull;
         bool accept = false;
         {
@@ -100,6 +119,10 @@ template <bool FILL> __global__ __launch_bounds__(64) void k_traverse(TravArgs a
                 a.far_node[fo] = c;
                 a.far_mask[fo] = am;
             }
+            if (SLOT && lane == 0 && fo < a.slot_far) {
+                sfn[fo] = c;
+                sfm[fo] = am;
+            }
             ++fo;
             nf += accept;
         }
@@ -108,6 +131,10 @@ template <bool FILL> __global__ __launch_bounds__(64) void k_traverse(TravArgs a
                 if (FILL && lane == 0) {
                     a.near_node[no] = c;
                     a.near_mask[no] = rm;
+                }
+                if (SLOT && lane == 0 && no < a.slot_near) {
+                    snn[no] = c;
+                    snm[no] = rm;
                 }
                 ++no;
                 if ((rm >> lane) & 1ull) {
@@ -146,28 +173,49 @@ template <bool FILL> __global__ __launch_bounds__(64) void k_traverse(TravArgs a
     }
 }
 
-// one block: out[0] = sum of a[0..n), out[1] = sum of b[0..n), in int64
+// one block: out[0] = sum of a[0..n), out[1] = sum of b[0..n) (int64), out[2] = max of
+// c[0..n), out[3] = max of d[0..n)
 __global__ __launch_bounds__(1024) void k_sum2_i64(const int32_t *__restrict__ a, const int32_t *__restrict__ b,
+                                                   const int32_t *__restrict__ c, const int32_t *__restrict__ d,
                                                    int32_t n, long long *__restrict__ out) {
-    __shared__ long long red[2][1024];
-    long long sa = 0, sb = 0;
+    __shared__ long long red[4][1024];
+    long long sa = 0, sb = 0, mc = 0, md = 0;
     for (int32_t i = threadIdx.x; i < n; i += 1024) {
         sa += a[i];
         sb += b[i];
+        mc = c[i] > mc ? c[i] : mc;
+        md = d[i] > md ? d[i] : md;
     }
     red[0][threadIdx.x] = sa;
     red[1][threadIdx.x] = sb;
+    red[2][threadIdx.x] = mc;
+    red[3][threadIdx.x] = md;
     __syncthreads();
     for (int o = 512; o > 0; o >>= 1) {
         if (int(threadIdx.x) < o) {
             red[0][threadIdx.x] += red[0][threadIdx.x + o];
             red[1][threadIdx.x] += red[1][threadIdx.x + o];
+            red[2][threadIdx.x] = red[2][threadIdx.x + o] > red[2][threadIdx.x] ? red[2][threadIdx.x + o]
+                                                                                 : red[2][threadIdx.x];
+            red[3][threadIdx.x] = red[3][threadIdx.x + o] > red[3][threadIdx.x] ? red[3][threadIdx.x + o]
+                                                                                 : red[3][threadIdx.x];
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        out[0] = red[0][0];
-        out[1] = red[1][0];
+    if (threadIdx.x < 4) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+// grid (groups): a group's slot entries to its place in the scanned lists
+__global__ __launch_bounds__(256) void k_slot_compact(const int32_t *__restrict__ cnt, const int32_t *__restrict__ off,
+                                                      int32_t slot, const int32_t *__restrict__ snode,
+                                                      const uint64_t *__restrict__ smask, int32_t *__restrict__ node,
+                                                      uint64_t *__restrict__ mask) {
+    const int32_t g = blockIdx.x;
+    const int32_t n = cnt[g], o = off[g];
+    const int64_t base = int64_t(g) * slot;
+    for (int32_t j = threadIdx.x; j < n; j += 256) {
+        node[o + j] = snode[base + j];
+        mask[o + j] = smask[base + j];
     }
 }
 
@@ -376,7 +424,7 @@ void far_sparse(Tree &t, Plan &pl, double *unear, int max_pc, hipStream_t s) {
                   pl.n_far_entries, pl.ngroups, m, max_pc, max_pc >= 64 ? pl.cnt_far.as<int32_t>() : nullptr, s);
     const size_t tsz = t.prec == STK_FP64 ? sizeof(double) : sizeof(float);
     void *part = reserve<unsigned char>(cm.part, tsz * 3 * size_t(K) * size_t(cm.n_inc) + tsz);
-    FarSparseArgs sa{pl.tpos.as<double>(), cm.item_node.as<int32_t>(), cm.item_i0.as<int32_t>(),
+    FarSparseArgs sa{pl.tpos_p, cm.item_node.as<int32_t>(), cm.item_i0.as<int32_t>(),
                      cm.item_i1.as<int32_t>(), cm.inc_tgt.as<int32_t>(), cm.inc_slot.as<int32_t>(),
                      t.ncenter.as<double>(), t.nrho.as<double>(), t.wblk.p, part, cm.n_items, K};
     const int kb = pl.tiles.far_kb;
@@ -414,12 +462,14 @@ void build_lists(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, 
     prof_mark(-1, s);
 
     // targets in Morton order of the tree's root cube
-    int32_t *tperm = reserve<int32_t>(pl.tperm, size_t(m));
-    double *tpos = reserve<double>(pl.tpos, size_t(m) * 3);
     if (same_as_sources) {
-        STK_HIP(hipMemcpyAsync(tperm, t.perm.p, sizeof(int32_t) * m, hipMemcpyDeviceToDevice, s));
-        STK_HIP(hipMemcpyAsync(tpos, t.pos.p, sizeof(double) * 3 * m, hipMemcpyDeviceToDevice, s));
+        pl.tperm_p = t.perm.as<int32_t>();
+        pl.tpos_p = t.pos.as<double>();
     } else {
+        int32_t *tperm = reserve<int32_t>(pl.tperm, size_t(m));
+        double *tpos = reserve<double>(pl.tpos, size_t(m) * 3);
+        pl.tperm_p = tperm;
+        pl.tpos_p = tpos;
         uint64_t *keys = reserve<uint64_t>(t.s_keys, size_t(m));
         hipLaunchKernelGGL(k_tkeys, dim3(nblk(m, 256)), dim3(256), 0, s, tgt, m, t.lo[0], t.lo[1], t.lo[2],
                            t.scale, keys, tperm);
@@ -432,13 +482,9 @@ void build_lists(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, 
 
     // interaction lists: count, scan, fill
     TravArgs ta{};
-    ta.tpos = tpos;
+    ta.tpos = pl.tpos_p;
     ta.m = m;
-    ta.center = t.ncenter.as<double>();
-    ta.radius = t.nradius.as<double>();
-    ta.child0 = t.nchild0.as<int32_t>();
-    ta.nchild = t.nnchild.as<int32_t>();
-    ta.count = t.ncount.as<int32_t>();
+    ta.node = t.trav.as<TravNode>();
     ta.theta = theta;
     int32_t *gcnt = reserve<int32_t>(t.s_vals, size_t(ng) * 4);
     ta.gfar = gcnt;
@@ -448,21 +494,47 @@ void build_lists(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, 
     ta.cnt_far = reserve<int32_t>(pl.cnt_far, size_t(m));
     ta.cnt_near = reserve<int32_t>(pl.cnt_near, size_t(m));
     ta.cnt_pairs = reserve<int32_t>(pl.cnt_pairs, size_t(m));
-    hipLaunchKernelGGL(k_traverse<false>, dim3(ng), dim3(64), 0, s, ta);
+    // One pass when the per-group slots fit: the traversal counts and writes each group's
+    // entries into slots of the last evaluation's longest list (plus a quarter), which are
+    // then compacted into the scanned lists.  If a group overflowed its slots (or on the
+    // first evaluation at a larger size), a second pass writes the lists at the scanned
+    // offsets, as the two-pass build always does when the slots would not fit.
+    const int32_t sf = std::max(pl.slot_far, TRAV_SLOT_FAR_MIN), sn = std::max(pl.slot_near, TRAV_SLOT_NEAR_MIN);
+    const bool one_pass = ng > 0 && size_t(ng) * size_t(sf + sn) * 12 <= TRAV_SLOT_BYTES_MAX;
+    if (one_pass) {
+        unsigned char *sb = reserve<unsigned char>(t.s_slot, size_t(ng) * size_t(sf + sn) * 12);
+        ta.slot_far = sf;
+        ta.slot_near = sn;
+        ta.sfar_mask = reinterpret_cast<uint64_t *>(sb);
+        ta.snear_mask = ta.sfar_mask + size_t(ng) * sf;
+        ta.sfar_node = reinterpret_cast<int32_t *>(ta.snear_mask + size_t(ng) * sn);
+        ta.snear_node = ta.sfar_node + size_t(ng) * sf;
+        hipLaunchKernelGGL(k_traverse<TRAV_SLOT>, dim3(ng), dim3(64), 0, s, ta);
+    } else {
+        hipLaunchKernelGGL(k_traverse<TRAV_COUNT>, dim3(ng), dim3(64), 0, s, ta);
+    }
     STK_CHECK_LAUNCH();
-    long long *inc_d = reserve<long long>(pl.far_inc, 2);
-    hipLaunchKernelGGL(k_sum2_i64, dim3(1), dim3(1024), 0, s, ta.gpf, ta.gpn, ng, inc_d);
+    long long *inc_d = reserve<long long>(pl.far_inc, 4);
+    hipLaunchKernelGGL(k_sum2_i64, dim3(1), dim3(1024), 0, s, ta.gpf, ta.gpn, ta.gfar, ta.gnear, ng, inc_d);
     STK_CHECK_LAUNCH();
     int32_t *foff = reserve<int32_t>(pl.far_off, size_t(ng) + 1);
     int32_t *noff = reserve<int32_t>(pl.near_off, size_t(ng) + 1);
     scan_exclusive_i32(ta.gfar, foff, ng, t.s_scan, s);
     scan_exclusive_i32(ta.gnear, noff, ng, t.s_scan, s);
     int32_t tot[2];
-    long long inc[2] = {0, 0};
-    STK_HIP(hipMemcpyAsync(&tot[0], foff + ng, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    STK_HIP(hipMemcpyAsync(&tot[1], noff + ng, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    STK_HIP(hipMemcpyAsync(inc, inc_d, sizeof(inc), hipMemcpyDeviceToHost, s));
-    STK_HIP(hipStreamSynchronize(s));
+    int64_t inc[2], longest[2];
+    {
+        const PeekSrc src[6] = {{foff + ng, 4}, {noff + ng, 4}, {inc_d, 8}, {inc_d + 1, 8}, {inc_d + 2, 8},
+                                {inc_d + 3, 8}};
+        int64_t v[6];
+        peek(t.peek, s, 6, src, v);
+        tot[0] = int32_t(v[0]);
+        tot[1] = int32_t(v[1]);
+        inc[0] = v[2];
+        inc[1] = v[3];
+        longest[0] = v[4];
+        longest[1] = v[5];
+    }
     pl.n_far_entries = tot[0];
     pl.n_near_entries = tot[1];
     pl.n_far_inc = int64_t(inc[0]);
@@ -475,8 +547,19 @@ void build_lists(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, 
     ta.far_mask = reserve<uint64_t>(pl.far_mask, size_t(tot[0]) + 1);
     ta.near_node = reserve<int32_t>(pl.near_node, size_t(tot[1]) + 1);
     ta.near_mask = reserve<uint64_t>(pl.near_mask, size_t(tot[1]) + 1);
-    hipLaunchKernelGGL(k_traverse<true>, dim3(ng), dim3(64), 0, s, ta);
-    STK_CHECK_LAUNCH();
+    if (one_pass && longest[0] <= sf && longest[1] <= sn) {
+        hipLaunchKernelGGL(k_slot_compact, dim3(ng), dim3(256), 0, s, ta.gfar, foff, sf, ta.sfar_node, ta.sfar_mask,
+                           ta.far_node, ta.far_mask);
+        STK_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_slot_compact, dim3(ng), dim3(256), 0, s, ta.gnear, noff, sn, ta.snear_node,
+                           ta.snear_mask, ta.near_node, ta.near_mask);
+        STK_CHECK_LAUNCH();
+    } else if (ng > 0) {
+        hipLaunchKernelGGL(k_traverse<TRAV_FILL>, dim3(ng), dim3(64), 0, s, ta);
+        STK_CHECK_LAUNCH();
+    }
+    pl.slot_far = int32_t(std::min<int64_t>(longest[0] + longest[0] / 4 + 1, INT32_MAX / 2));
+    pl.slot_near = int32_t(std::min<int64_t>(longest[1] + longest[1] / 4 + 1, INT32_MAX / 2));
 }
 
 void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, double *u_out, bool same_as_sources,
@@ -484,8 +567,8 @@ void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, dou
     pl.reg_eps = -1.0;
     build_lists(t, pl, tgt, m, theta, same_as_sources, s);
     const int32_t ng = pl.ngroups;
-    const double *tpos = pl.tpos.as<double>();
-    const int32_t *tperm = pl.tperm.as<int32_t>();
+    const double *tpos = pl.tpos_p;
+    const int32_t *tperm = pl.tperm_p;
     const int32_t *foff = pl.far_off.as<int32_t>();
 
     // kernel variants: right-hand sides per pass, matrix cores
@@ -509,6 +592,12 @@ void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, dou
     if (pl.tiles.far_cm == FAR_CM_ON && !cm_fits)
         throw Error(STK_EINVAL, "far_cm: too many far interactions for the cluster-major lists");
     const int sparse_max = all_cm ? 64 : (K == 1 && cm_fits ? FAR_SPARSE_MAX : 0);
+    // moments computed beside the lists and the near field (on another stream) must be
+    // complete from here on: the far kernels read the clusters' streams
+    if (pl.moments_ready) {
+        STK_HIP(hipStreamWaitEvent(s, pl.moments_ready, 0));
+        pl.moments_ready = nullptr;
+    }
     if (sparse_max > 0) far_sparse(t, pl, unear, sparse_max, s);
     pl.far_sparse_max = sparse_max;
     // parts of each group's far list (tile far_split; automatically enough parts for

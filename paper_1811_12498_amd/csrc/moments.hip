@@ -283,7 +283,7 @@ static void launch_moments(Tree &t, int K, int p, int nm, const double *w12, dou
 }
 
 void compute_moments(Tree &t, const double *f, const double *h, const double *nu, int32_t K, int32_t p,
-                     stk_precision prec, hipStream_t s) {
+                     stk_precision prec, hipStream_t s, hipEvent_t records_done) {
     const int nm = nidx(p), ng = nidx(p + 1);
     const int32_t nn = t.nnodes;
     prof_mark(-1, s);
@@ -299,6 +299,7 @@ void compute_moments(Tree &t, const double *f, const double *h, const double *nu
         hipLaunchKernelGGL(k_records<float>, dim3(nblk(t.n, 256)), dim3(256), 0, s, t.pos.as<double>(),
                            t.perm.as<int32_t>(), t.n, K, f, h, nu, t.geo.as<double>(), t.wts.as<float>(), w12);
     STK_CHECK_LAUNCH();
+    if (records_done) STK_HIP(hipEventRecord(records_done, s));
 
     double *part = reserve<double>(t.mom_part, size_t(t.nleafchunks) * K * nm * 12 + 1);
     const int A = (nm + 63) / 64;

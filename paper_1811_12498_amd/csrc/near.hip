@@ -599,12 +599,10 @@ void cluster_major(Tree &t, ClusterMajor &cm, const int32_t *off, const int32_t 
         hipLaunchKernelGGL(k_cm_flag, dim3(nblk(ne, 256)), dim3(256), 0, s, mask, ne, max_pc, flag);
         STK_CHECK_LAUNCH();
         scan_exclusive_i32(flag, fpos, ne, t.s_scan, s);
-        int32_t nkept = 0;
-        STK_HIP(hipMemcpyAsync(&nkept, fpos + ne, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         hipLaunchKernelGGL(k_cm_compact, dim3(nblk(ne, 256)), dim3(256), 0, s, node, mask, ne, max_pc, fpos, keys, ent);
         STK_CHECK_LAUNCH();
-        STK_HIP(hipStreamSynchronize(s));
-        nk = nkept;
+        const PeekSrc src{fpos + ne, 4};
+        peek(t.peek, s, 1, &src, &nk);
         radix_sort_pairs(t, keys, ent, nk, bits, s);
     } else if (ne > 0) {
         hipLaunchKernelGGL(k_cm_keys, dim3(nblk(ne, 256)), dim3(256), 0, s, node, mask, ne, nn, max_pc, keys, ent);
@@ -639,11 +637,11 @@ void cluster_major(Tree &t, ClusterMajor &cm, const int32_t *off, const int32_t 
     hipLaunchKernelGGL(k_item_count, dim3(nblk(nn, 256)), dim3(256), 0, s, loff, nn, 64, icnt);
     STK_CHECK_LAUNCH();
     scan_exclusive_i32(icnt, ioff, nn, t.s_scan, s);
-    int32_t tot[3];
-    STK_HIP(hipMemcpyAsync(&tot[0], incoff + nk, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    STK_HIP(hipMemcpyAsync(&tot[1], ioff + nn, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    STK_HIP(hipMemcpyAsync(&tot[2], toff + m, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    STK_HIP(hipStreamSynchronize(s));
+    int64_t tot[3];
+    {
+        const PeekSrc src[3] = {{incoff + nk, 4}, {ioff + nn, 4}, {toff + m, 4}};
+        peek(t.peek, s, 3, src, tot);
+    }
     if (tot[0] != tot[2]) throw Error(STK_EDEVICE, "lists: incidence count differs from the per-target counts");
     cm.n_inc = tot[0];
     cm.n_items = tot[1];
@@ -670,11 +668,11 @@ void near_field(Tree &t, Plan &pl, double *unear, hipStream_t s) {
     cluster_major(t, cm, pl.near_off.as<int32_t>(), pl.near_node.as<int32_t>(), pl.near_mask.as<uint64_t>(),
                   pl.n_near_entries, pl.ngroups, m, 64, pl.cnt_near.as<int32_t>(), s);
     prof_mark(STK_PHASE_LISTS, s);
-    // moments computed beside the lists (on another stream) must be complete from here on:
-    // the near field reads their source records, the far field their streams
-    if (pl.moments_ready) {
-        STK_HIP(hipStreamWaitEvent(s, pl.moments_ready, 0));
-        pl.moments_ready = nullptr;
+    // source records computed beside the lists (on another stream) must be complete from
+    // here on
+    if (pl.records_ready) {
+        STK_HIP(hipStreamWaitEvent(s, pl.records_ready, 0));
+        pl.records_ready = nullptr;
     }
     const int32_t *ileaf = cm.item_node.as<int32_t>(), *i0 = cm.item_i0.as<int32_t>(), *i1 = cm.item_i1.as<int32_t>();
     const int32_t *inc_tgt = cm.inc_tgt.as<int32_t>(), *inc_slot = cm.inc_slot.as<int32_t>();
@@ -683,7 +681,7 @@ void near_field(Tree &t, Plan &pl, double *unear, hipStream_t s) {
     const int K = t.k_rhs;
     const size_t tsz = t.prec == STK_FP64 ? sizeof(double) : sizeof(float);
     void *part = reserve<unsigned char>(cm.part, tsz * 3 * size_t(cm.n_inc) * K + tsz);
-    NearArgs na{pl.tpos.as<double>(), ileaf, i0, i1, inc_tgt, inc_slot, t.nstart.as<int32_t>(),
+    NearArgs na{pl.tpos_p, ileaf, i0, i1, inc_tgt, inc_slot, t.nstart.as<int32_t>(),
                 t.ncount.as<int32_t>(), t.nbmin.as<double>(), t.nbmax.as<double>(), t.geo.as<double>(), t.wts.p,
                 part, cm.n_items, K};
     const int64_t mk = m * K;

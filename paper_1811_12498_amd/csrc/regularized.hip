@@ -80,19 +80,23 @@ void evaluate_regularized(Tree &t, Plan &pl, const double *tgt, int64_t m, doubl
     prof_mark(STK_PHASE_LISTS, s);  // the lists transposed
     double *part = reserve<double>(cm.part, 3 * size_t(cm.n_inc) + 1);
     double *wreg = reserve<double>(t.wreg, size_t(t.nnodes) * reg_stream_len(t.p));
+    if (pl.moments_ready) {  // moments computed on another stream
+        STK_HIP(hipStreamWaitEvent(s, pl.moments_ready, 0));
+        pl.moments_ready = nullptr;
+    }
     if (t.nnodes > 0) {
         hipLaunchKernelGGL(k_reg_stream, dim3(unsigned(t.nnodes)), dim3(64), 0, s, t.mom.as<double>(), t.p,
                            nidx(t.p), wreg);
         STK_CHECK_LAUNCH();
     }
     prof_mark(STK_PHASE_MOMENTS, s);  // the clusters' streams, like the channel blocks
-    RegFarArgs ra{pl.tpos.as<double>(), cm.item_node.as<int32_t>(), cm.item_i0.as<int32_t>(),
+    RegFarArgs ra{pl.tpos_p, cm.item_node.as<int32_t>(), cm.item_i0.as<int32_t>(),
                   cm.item_i1.as<int32_t>(), cm.inc_tgt.as<int32_t>(), cm.inc_slot.as<int32_t>(),
                   t.ncenter.as<double>(), wreg, part, eps * eps, cm.n_items};
     dispatch_reg_far(t.p, ra, s);
     if (m > 0) {
         hipLaunchKernelGGL(k_reg_finish, dim3(unsigned((m + 255) / 256)), dim3(256), 0, s, part,
-                           cm.toff.as<int32_t>(), unear, pl.tperm.as<int32_t>(), m, u_out);
+                           cm.toff.as<int32_t>(), unear, pl.tperm_p, m, u_out);
         STK_CHECK_LAUNCH();
     }
     prof_mark(STK_PHASE_FAR, s);

@@ -268,6 +268,47 @@ void scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, DBuf &scratc
     STK_HIP(hipMemcpyAsync(out + n, offs + ntiles, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
 }
 
+namespace {
+struct PeekArgs {
+    const void *p[PEEK_MAX];
+    int32_t bytes[PEEK_MAX];
+    int32_t n;
+};
+
+__global__ void k_peek(PeekArgs a, int64_t *__restrict__ dst) {
+    const int i = threadIdx.x;
+    if (i < a.n)
+        dst[i] = a.bytes[i] == 8 ? *static_cast<const int64_t *>(a.p[i])
+                                 : int64_t(*static_cast<const int32_t *>(a.p[i]));
+}
+}  // namespace
+
+void peek(HostPeek &pk, hipStream_t s, int n, const PeekSrc *src, int64_t *out) {
+    if (n < 1 || n > PEEK_MAX) throw Error(STK_EINVAL, "peek: 1 to PEEK_MAX values");
+    if (!pk.h) {
+        void *h = nullptr, *d = nullptr;
+        STK_HIP(hipHostMalloc(&h, sizeof(int64_t) * PEEK_MAX, hipHostMallocMapped | hipHostMallocCoherent));
+        const hipError_t e = hipHostGetDevicePointer(&d, h, 0);
+        if (e != hipSuccess) {
+            (void)hipHostFree(h);
+            STK_HIP(e);
+        }
+        pk.h = static_cast<int64_t *>(h);
+        pk.d = static_cast<int64_t *>(d);
+    }
+    PeekArgs a{};
+    a.n = n;
+    for (int i = 0; i < n; ++i) {
+        if (src[i].bytes != 4 && src[i].bytes != 8) throw Error(STK_EINVAL, "peek: 4- or 8-byte values");
+        a.p[i] = src[i].p;
+        a.bytes[i] = src[i].bytes;
+    }
+    hipLaunchKernelGGL(k_peek, dim3(1), dim3(64), 0, s, a, pk.d);
+    STK_CHECK_LAUNCH();
+    STK_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < n; ++i) out[i] = pk.h[i];
+}
+
 void radix_sort_pairs(Tree &t, uint64_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t s) {
     if (n <= 1) return;
     const int32_t ntiles = int32_t((n + TILE - 1) / TILE);

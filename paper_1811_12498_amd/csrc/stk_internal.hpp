@@ -63,6 +63,31 @@ struct DBuf {
     template <class T> T *as() const { return static_cast<T *>(p); }
 };
 
+// ---------------------------------------------------------------------------------
+// small device-to-host reads: the sizes the host needs before its next launch (list
+// lengths, node and chunk counts).  One kernel copies up to PEEK_MAX 4- or 8-byte device
+// values into pinned host slots, then one stream synchronisation (a pageable copy would
+// cost a round trip of its own per value).
+// ---------------------------------------------------------------------------------
+constexpr int PEEK_MAX = 8;
+struct HostPeek {
+    int64_t *h = nullptr;  // pinned, PEEK_MAX slots (allocated on first use, kept with the owner)
+    int64_t *d = nullptr;  // the same slots as the device sees them
+    HostPeek() = default;
+    HostPeek(const HostPeek &) = delete;
+    HostPeek &operator=(const HostPeek &) = delete;
+    ~HostPeek() {
+        if (h) (void)hipHostFree(h);
+    }
+};
+struct PeekSrc {
+    const void *p;  // device address
+    int bytes;      // 4: int32 (sign-extended); 8: int64 or double (raw bits)
+};
+// Enqueue the copy of src[0..n) (1 <= n <= PEEK_MAX) on s, synchronise s, and return the
+// values in out[0..n).
+void peek(HostPeek &pk, hipStream_t s, int n, const PeekSrc *src, int64_t *out);
+
 template <class T> inline T *reserve(DBuf &b, size_t n) {
     b.reserve(n * sizeof(T));
     return b.as<T>();
@@ -71,6 +96,13 @@ template <class T> inline T *reserve(DBuf &b, size_t n) {
 // ---------------------------------------------------------------------------------
 // tree handle
 // ---------------------------------------------------------------------------------
+// One record per node for the MAC traversal: everything a visit reads, in one 64-byte line.
+struct alignas(64) TravNode {
+    double c[3];  // centre
+    double r;     // radius
+    int32_t nchild, child0, count, pad[5];
+};
+
 struct Tree {
     int device = 0;
     int64_t n = 0;
@@ -87,6 +119,7 @@ struct Tree {
     DBuf nlevel, nparent, nchild0, nnchild, nstart, ncount;   // int32
     DBuf nbmin, nbmax, ncenter;  // double (nn,3)
     DBuf nradius, nrho;          // double (nn)
+    DBuf trav;                   // TravNode (nn): the fields above that the traversal reads
     // work chunks over (node, particle range) for per-node reductions
     DBuf chunk_off;              // int32 (nn + 1): first chunk of each node
     int32_t nchunks = 0;
@@ -109,7 +142,9 @@ struct Tree {
     // reusable scratch for evaluation
     DBuf s_keys, s_vals, s_keys2, s_vals2, s_hist, s_tmp;
     DBuf s_scan;                   // tile sums of scan_exclusive_i32
+    DBuf s_slot;                   // per-group list slots of the one-pass traversal
     DBuf s_bm;                     // operand blocks of the matrix-core far field
+    HostPeek peek;                 // host slots for the sizes read back during a build or evaluation
 };
 
 // lists re-sorted by node (cluster-major / leaf-major) and their work items
@@ -175,11 +210,15 @@ struct Plan {
     int32_t ngroups = 0;
     DBuf tpos;                     // double (m,3) targets in Morton order
     DBuf tperm;                    // int32 sorted -> caller index
+    // the targets in use: tpos / tperm, or the tree's sorted sources and their permutation
+    // when the targets are the sources
+    const double *tpos_p = nullptr;
+    const int32_t *tperm_p = nullptr;
     DBuf far_off, near_off;        // int32 (ngroups + 1)
     DBuf far_node, near_node;      // int32 entries
     DBuf far_mask, near_mask;      // uint64 entries (lane masks of the 64-target group)
     DBuf cnt_far, cnt_near, cnt_pairs;  // int32 per sorted target
-    DBuf far_inc;                       // int64 (2): far (target, cluster) and near (target, leaf) pairs
+    DBuf far_inc;                       // int64 (4): far (target, cluster) and near (target, leaf) pairs, longest far and near group lists
     int64_t n_far_entries = 0, n_near_entries = 0, n_far_inc = 0;
     // cluster-major views of the group lists: the near field (every near entry) and, for
     // one right-hand side, the far entries that apply to few targets of their group
@@ -187,11 +226,17 @@ struct Plan {
     int32_t far_sparse_max = 0;       // threshold of the last evaluation's sparse far split
     Tiles tiles;                      // kernel variants used by the last evaluation
     bool forced = false;              // use `force` instead of the table (autotuning)
-    hipEvent_t moments_ready = nullptr;  // if set, the evaluation's stream waits on it before the near field
+    // if set, computed on another stream: the evaluation's stream waits on records_ready
+    // before the near field (which reads the source records) and on moments_ready before
+    // the far field (which reads the clusters' streams)
+    hipEvent_t records_ready = nullptr, moments_ready = nullptr;
     double reg_eps = -1.0;            // >= 0: the last evaluation used the regularized kernels with this eps
     Tiles force;
     AdjScratch adj;
     DBuf far_part;                    // double (parts, K, m, 3): sums of the split group-major far field
+    // slot capacity of the one-pass traversal: a quarter above the longest group lists of
+    // the last evaluation (0: not yet known)
+    int32_t slot_far = 0, slot_near = 0;
     ~Plan();
 };
 
@@ -209,8 +254,10 @@ void radix_sort_pairs(Tree &t, uint64_t *keys, int32_t *vals, int64_t n, int bit
 void scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, DBuf &scratch, hipStream_t s);
 
 void build_tree(Tree &t, const double *src, int64_t n, int32_t n0, hipStream_t s);
+// records_done, if given, is recorded on s once the per-source records (what the near
+// field reads) are written, before the moments themselves
 void compute_moments(Tree &t, const double *f, const double *h, const double *nu, int32_t k, int32_t p,
-                     stk_precision prec, hipStream_t s);
+                     stk_precision prec, hipStream_t s, hipEvent_t records_done = nullptr);
 // same_as_sources: the targets are exactly the tree's sources (same array), so their
 // Morton order is the tree's and they are not sorted again
 void evaluate(Tree &t, Plan &plan, const double *tgt, int64_t m, double theta, double *u_out, bool same_as_sources,

@@ -109,34 +109,66 @@ __global__ void k_gather3(const double *__restrict__ src, const int32_t *__restr
 }
 
 // ---- subdivision -----------------------------------------------------------------------
-// first index in [b, e) whose 3-bit digit at `shift` is >= c (keys sorted, prefix shared)
-__device__ inline int32_t lower_digit(const uint64_t *__restrict__ keys, int32_t b, int32_t e, int shift, int c) {
-    while (b < e) {
-        const int32_t m = b + ((e - b) >> 1);
-        if (int((keys[m] >> shift) & 7) < c)
-            b = m + 1;
-        else
-            e = m;
+// the root: every point, no children yet
+__global__ void k_root(int32_t n, int32_t *__restrict__ level, int32_t *__restrict__ parent,
+                       int32_t *__restrict__ child0, int32_t *__restrict__ nchild, int32_t *__restrict__ start,
+                       int32_t *__restrict__ count) {
+    if (threadIdx.x == 0) {
+        level[0] = 0;
+        parent[0] = -1;
+        child0[0] = -1;
+        nchild[0] = 0;
+        start[0] = 0;
+        count[0] = n;
     }
-    return b;
 }
 
-__global__ void k_split_count(const uint64_t *__restrict__ keys, const int32_t *__restrict__ start,
-                              const int32_t *__restrict__ count, int32_t lb, int32_t nlev, int shift, int32_t n0,
-                              int32_t *__restrict__ nch, int32_t *__restrict__ bnd) {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+// One wavefront per node of the level.  A node with more than n0 points splits at the
+// boundaries b_d = first index in [s, s + c) whose 3-bit digit at `shift` is >= d,
+// d = 1..7 (the node's keys are sorted and share the bits above the digit, so the digits
+// rise along the node).  The seven searches run together: lanes 9(d-1) .. 9(d-1)+8 probe
+// nine points of the interval still holding b_d, which shrinks about tenfold per round.
+// bnd[9 i + d] = b_d (b_0 = s, b_8 = s + c); nch[i] = number of non-empty octants.
+__global__ __launch_bounds__(BT) void k_split_count(const uint64_t *__restrict__ keys,
+                                                    const int32_t *__restrict__ start,
+                                                    const int32_t *__restrict__ count, int32_t lb, int32_t nlev,
+                                                    int shift, int32_t n0, int32_t *__restrict__ nch,
+                                                    int32_t *__restrict__ bnd) {
+    const int32_t i = int32_t((int64_t(blockIdx.x) * BT + threadIdx.x) >> 6);  // uniform per wave
+    const int lane = threadIdx.x & 63;
     if (i >= nlev) return;
     const int32_t s = start[lb + i], c = count[lb + i];
-    int32_t k = 0;
-    if (c > n0) {
-        int32_t b[9];
-        b[0] = s;
-        b[8] = s + c;
-        for (int d = 1; d < 8; ++d) b[d] = lower_digit(keys, b[d - 1], s + c, shift, d);
-        for (int d = 0; d < 9; ++d) bnd[9 * i + d] = b[d];
-        for (int d = 0; d < 8; ++d) k += b[d + 1] > b[d];
+    if (c <= n0) {
+        if (lane == 0) nch[i] = 0;
+        return;
     }
-    nch[i] = k;
+    const int g = lane / 9, k = lane - 9 * g;  // boundary d = g + 1; lane 63 (g = 7) idles
+    int32_t lo = s, hi = g < 7 ? s + c : s;    // b_d lies in [lo, hi]
+    while (__ballot(lo < hi) != 0) {
+        const int32_t len = hi - lo;
+        const int np = len > 9 ? 9 : len;
+        // probes: lo + (k + 1) len / 10 for an interval of ten or more, else every point
+        const int32_t pos = len > 9 ? lo + int32_t(int64_t(k + 1) * len / 10) : lo + k;
+        const bool ge = len > 0 && k < np && int((keys[pos] >> shift) & 7) >= g + 1;
+        const uint64_t bal = __ballot(ge);
+        if (len > 0) {
+            const uint32_t gb = uint32_t(bal >> (9 * g)) & 0x1ffu;
+            const int j = gb ? __builtin_ctz(gb) : np;  // probes below the boundary
+            if (len <= 9) {
+                lo = hi = lo + j;
+            } else {
+                const int32_t nlo = j > 0 ? lo + int32_t(int64_t(j) * len / 10) + 1 : lo;
+                hi = j < 9 ? lo + int32_t(int64_t(j + 1) * len / 10) : hi;
+                lo = nlo;
+            }
+        }
+    }
+    const int32_t bd = __shfl(lo, lane >= 1 && lane <= 7 ? 9 * (lane - 1) : 0, 64);
+    const int32_t b = lane == 0 ? s : (lane == 8 ? s + c : bd);
+    if (lane < 9) bnd[9 * i + lane] = b;
+    const int32_t next = __shfl(b, lane < 63 ? lane + 1 : 63, 64);
+    const uint64_t occupied = __ballot(lane < 8 && next > b);
+    if (lane == 0) nch[i] = int32_t(__popcll(occupied));
 }
 
 __global__ void k_split_emit(int32_t lb, int32_t nlev, int32_t le, int32_t lev, const int32_t *__restrict__ nch,
@@ -280,12 +312,25 @@ __global__ __launch_bounds__(BT) void k_radius(const double *__restrict__ pos, c
     if (threadIdx.x == 0) atomic_max_nonneg(&r2max[node], red[0]);
 }
 
-__global__ void k_radius_final(int32_t nn, double *__restrict__ r, double *__restrict__ rho) {
+// radii from the largest squared distances, the far field's power-of-two scale, and each
+// node's traversal record
+__global__ void k_radius_final(int32_t nn, double *__restrict__ r, double *__restrict__ rho,
+                               const double *__restrict__ center, const int32_t *__restrict__ nchild,
+                               const int32_t *__restrict__ child0, const int32_t *__restrict__ count,
+                               TravNode *__restrict__ trav) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nn) return;
     const double v = sqrt(r[i]);
     r[i] = v;
     rho[i] = rho_of(v);
+    TravNode t;
+    for (int a = 0; a < 3; ++a) t.c[a] = center[3 * i + a];
+    t.r = v;
+    t.nchild = nchild[i];
+    t.child0 = child0[i];
+    t.count = count[i];
+    for (int a = 0; a < 5; ++a) t.pad[a] = 0;
+    trav[i] = t;
 }
 
 inline unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
@@ -318,8 +363,13 @@ void build_tree(Tree &t, const double *src, int64_t n, int32_t n0, hipStream_t s
     hipLaunchKernelGGL(k_bounds_final, dim3(1), dim3(BT), 0, s, part, nbb, part + size_t(nbb) * 6);
     STK_CHECK_LAUNCH();
     double b6[6];
-    STK_HIP(hipMemcpyAsync(b6, part + size_t(nbb) * 6, sizeof(b6), hipMemcpyDeviceToHost, s));
-    STK_HIP(hipStreamSynchronize(s));
+    {
+        PeekSrc src[6];
+        int64_t raw[6];
+        for (int a = 0; a < 6; ++a) src[a] = {part + size_t(nbb) * 6 + a, 8};
+        peek(t.peek, s, 6, src, raw);
+        std::memcpy(b6, raw, sizeof(b6));
+    }
     double L = 0.0;
     for (int a = 0; a < 3; ++a) {
         t.lo[a] = b6[a];
@@ -348,37 +398,42 @@ void build_tree(Tree &t, const double *src, int64_t n, int32_t n0, hipStream_t s
             b->reserve(cap * sizeof(int32_t));
         }
     }
-    {
-        const int32_t root[6] = {0, -1, -1, 0, 0, int32_t(n)};
-        DBuf *dst[6] = {&t.nlevel, &t.nparent, &t.nchild0, &t.nnchild, &t.nstart, &t.ncount};
-        for (int k = 0; k < 6; ++k)
-            STK_HIP(hipMemcpyAsync(dst[k]->p, &root[k], sizeof(int32_t), hipMemcpyHostToDevice, s));
-    }
+    hipLaunchKernelGGL(k_root, dim3(1), dim3(64), 0, s, int32_t(n), t.nlevel.as<int32_t>(), t.nparent.as<int32_t>(),
+                       t.nchild0.as<int32_t>(), t.nnchild.as<int32_t>(), t.nstart.as<int32_t>(),
+                       t.ncount.as<int32_t>());
+    STK_CHECK_LAUNCH();
     int32_t nnodes = 1, lb = 0, le = 1, lev = 0;
     t.level_begin.assign(1, 0);
     while (!t.degenerate && lev < STK_MAX_LEVEL) {
         const int32_t nlev = le - lb;
-        int32_t *nch = reserve<int32_t>(t.s_vals, size_t(nlev) * 11 + 2);
-        int32_t *choff = nch + nlev;
-        int32_t *bnd = reserve<int32_t>(t.s_vals2, size_t(nlev) * 9);
-        hipLaunchKernelGGL(k_split_count, dim3(nblk(nlev, BT)), dim3(BT), 0, s, keys, t.nstart.as<int32_t>(),
-                           t.ncount.as<int32_t>(), lb, nlev, 3 * (STK_MAX_LEVEL - 1 - lev), n0, nch, bnd);
-        STK_CHECK_LAUNCH();
-        scan_exclusive_i32(nch, choff, nlev, t.s_scan, s);
-        int32_t total = 0;
-        STK_HIP(hipMemcpyAsync(&total, choff + nlev, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        STK_HIP(hipStreamSynchronize(s));
-        if (total > 0 && size_t(nnodes + total) > cap) {
+        // room for every child the level can make (at most eight per node), so the
+        // children are written before the host reads how many there are
+        if (size_t(nnodes) + 8 * size_t(nlev) > cap) {
             size_t ncap = cap;
-            while (ncap < size_t(nnodes + total)) ncap *= 2;
+            while (ncap < size_t(nnodes) + 8 * size_t(nlev)) ncap *= 2;
             for (DBuf *b : {&t.nlevel, &t.nparent, &t.nchild0, &t.nnchild, &t.nstart, &t.ncount})
                 grow_keep(*b, size_t(nnodes) * sizeof(int32_t), ncap * sizeof(int32_t), s);
             cap = ncap;
         }
+        int32_t *nch = reserve<int32_t>(t.s_vals, size_t(nlev) * 11 + 2);
+        int32_t *choff = nch + nlev;
+        int32_t *bnd = reserve<int32_t>(t.s_vals2, size_t(nlev) * 9);
+        hipLaunchKernelGGL(k_split_count, dim3(nblk(int64_t(nlev) * 64, BT)), dim3(BT), 0, s, keys,
+                           t.nstart.as<int32_t>(), t.ncount.as<int32_t>(), lb, nlev, 3 * (STK_MAX_LEVEL - 1 - lev),
+                           n0, nch, bnd);
+        STK_CHECK_LAUNCH();
+        scan_exclusive_i32(nch, choff, nlev, t.s_scan, s);
         hipLaunchKernelGGL(k_split_emit, dim3(nblk(nlev, BT)), dim3(BT), 0, s, lb, nlev, le, lev, nch, choff, bnd,
                            t.nlevel.as<int32_t>(), t.nparent.as<int32_t>(), t.nchild0.as<int32_t>(),
                            t.nnchild.as<int32_t>(), t.nstart.as<int32_t>(), t.ncount.as<int32_t>());
         STK_CHECK_LAUNCH();
+        int32_t total = 0;
+        {
+            const PeekSrc src{choff + nlev, 4};
+            int64_t v = 0;
+            peek(t.peek, s, 1, &src, &v);
+            total = int32_t(v);
+        }
         t.level_begin.push_back(le);
         if (total == 0) break;
         nnodes += total;
@@ -410,25 +465,30 @@ void build_tree(Tree &t, const double *src, int64_t n, int32_t n0, hipStream_t s
     hipLaunchKernelGGL(k_chunk_count, dim3(nblk(nnodes, BT)), dim3(BT), 0, s, t.ncount.as<int32_t>(), nnodes, cnt);
     STK_CHECK_LAUNCH();
     scan_exclusive_i32(cnt, coff, nnodes, t.s_scan, s);
-    STK_HIP(hipMemcpyAsync(&t.nchunks, coff + nnodes, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     int32_t *lcnt = reserve<int32_t>(t.s_vals2, size_t(nnodes));
     int32_t *lcoff = reserve<int32_t>(t.leaf_coff, size_t(nnodes) + 1);
     hipLaunchKernelGGL(k_leaf_chunk_count, dim3(nblk(nnodes, BT)), dim3(BT), 0, s, t.ncount.as<int32_t>(),
                        t.nnchild.as<int32_t>(), nnodes, lcnt);
     STK_CHECK_LAUNCH();
     scan_exclusive_i32(lcnt, lcoff, nnodes, t.s_scan, s);
-    STK_HIP(hipMemcpyAsync(&t.nleafchunks, lcoff + nnodes, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     double *rad = reserve<double>(t.nradius, size_t(nnodes));
     double *rho = reserve<double>(t.nrho, size_t(nnodes));
     STK_HIP(hipMemsetAsync(rad, 0, sizeof(double) * nnodes, s));
-    STK_HIP(hipStreamSynchronize(s));
+    {
+        const PeekSrc src[2] = {{coff + nnodes, 4}, {lcoff + nnodes, 4}};
+        int64_t v[2];
+        peek(t.peek, s, 2, src, v);
+        t.nchunks = int32_t(v[0]);
+        t.nleafchunks = int32_t(v[1]);
+    }
     hipLaunchKernelGGL(k_radius, dim3(t.nchunks), dim3(BT), 0, s, pos, t.nstart.as<int32_t>(),
                        t.ncount.as<int32_t>(), coff, nnodes, cen, rad);
     STK_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_radius_final, dim3(nblk(nnodes, BT)), dim3(BT), 0, s, nnodes, rad, rho);
+    TravNode *trav = reserve<TravNode>(t.trav, size_t(nnodes));
+    hipLaunchKernelGGL(k_radius_final, dim3(nblk(nnodes, BT)), dim3(BT), 0, s, nnodes, rad, rho, cen,
+                       t.nnchild.as<int32_t>(), t.nchild0.as<int32_t>(), t.ncount.as<int32_t>(), trav);
     STK_CHECK_LAUNCH();
     prof_mark(STK_PHASE_TREE, s);
-    STK_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace stk

@@ -155,6 +155,37 @@ def test_interaction_lists_match_oracle(nat, orc, kind, n, seed, n0, p, theta, h
         assert np.array_equal(n_gpu, n_ref[order]), kind_
 
 
+def test_list_build_one_pass_and_second_pass(nat, orc):
+    """The lists are written in one traversal into per-group slots sized from the plan's
+    previous evaluation (a quarter above its longest group lists), then compacted; a group
+    whose lists outgrow their slots (a fresh plan starts at 256 far and 64 near entries)
+    makes the build fall back to a second traversal at the scanned offsets.  N = 20,000 in
+    the unit cube, N0 = 16, theta = 0.35: the longest group lists (1464 far, 139 near
+    entries, from the oracle's per-target lists) exceed a fresh plan's slots, so its first
+    evaluation takes the second pass and its next one the slots.  Both give every target's
+    far clusters and near leaves of Algorithm 1."""
+    w = W.cube(20_000, seed=12, n0=16)
+    theta, p, n0 = 0.35, 2, 16
+    T = orc.build_tree(w.src, n0)
+    L = orc.lists(T, theta, w.src)
+    X = _t(w.src)
+    nat.plan_cache_clear()
+    for call in range(2):
+        _, plan = nat.evaluate(X, X, _t(w.f[0]), _t(w.h[0]), _t(w.nu), p, theta, n0, "fp64", keep_plan=True)
+        for kind_, ptr, nodes, first_slots in (("far", L.far_ptr, L.far_nodes, 256),
+                                               ("near", L.near_ptr, L.near_nodes, 64)):
+            lists = nat.plan_lists(plan, kind_)
+            if call == 0:
+                assert np.diff(lists["off"]).max() > first_slots, kind_
+            t_gpu, n_gpu = _per_target(lists, w.n)
+            t_ref = np.repeat(np.arange(w.n), np.diff(ptr))
+            n_ref = nodes[: int(ptr[-1])]
+            order = np.lexsort((n_ref, t_ref))
+            assert np.array_equal(t_gpu, t_ref[order]), (call, kind_)
+            assert np.array_equal(n_gpu, n_ref[order]), (call, kind_)
+        del plan
+
+
 def test_large_plan_matches_oracle(nat, orc):
     """150,000 targets (= sources) with small leaves: the device-wide scans of the list
     build take their multi-tile path (more than 65,536 entries); counts, lists and the
