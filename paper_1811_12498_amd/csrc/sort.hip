@@ -15,7 +15,7 @@ namespace {
 constexpr int RB = 8;                 // bits per pass
 constexpr int RADIX = 1 << RB;
 constexpr int ST = 256;               // threads per block (4 waves)
-constexpr int ITEMS = 16;             // rounds per tile
+constexpr int ITEMS = 8;              // rounds per tile
 constexpr int TILE = ST * ITEMS;
 constexpr int NWAVE = ST / 64;
 
