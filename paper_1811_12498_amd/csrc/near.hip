@@ -196,7 +196,33 @@ __global__ void k_cm_pos(const int32_t *__restrict__ ent, const uint64_t *__rest
     pos[e] = int32_t(k);
 }
 
-// per target: number of kept entries of its group that apply to it
+__device__ inline uint64_t shfl_u64(uint64_t v, int src) {
+    return (uint64_t(uint32_t(__shfl(int(v >> 32), src, 64))) << 32) | uint32_t(__shfl(int(uint32_t(v)), src, 64));
+}
+__device__ inline uint64_t shfl_xor_u64(uint64_t v, int m) {
+    return (uint64_t(uint32_t(__shfl_xor(int(v >> 32), m, 64))) << 32) |
+           uint32_t(__shfl_xor(int(uint32_t(v)), m, 64));
+}
+
+// 64 x 64 bit transpose over a wave (every lane calls it): lane j holds row j; on return
+// lane l holds column l, whose bit j is bit l of row j.  Six steps, each swapping the
+// off-diagonal blocks of half the previous size between lanes s apart.
+__device__ inline uint64_t wave_transpose64(uint64_t row) {
+    const int lane = threadIdx.x & 63;
+    constexpr uint64_t keep[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                                  0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int s = 32 >> k;
+        const uint64_t p = shfl_xor_u64(row, s), m = keep[k];
+        row = (lane & s) == 0 ? ((row & m) | ((p & m) << s)) : ((row & ~m) | ((p & ~m) >> s));
+    }
+    return row;
+}
+
+// per target: number of kept entries of its group that apply to it.  The group's masks are
+// read 64 at a time, one per lane; the transposed bit matrix gives each lane the entries
+// that include its target.
 __global__ __launch_bounds__(64) void k_cm_tcount(const int32_t *__restrict__ off, const uint64_t *__restrict__ mask,
                                                   int64_t m, int max_pc, int32_t *__restrict__ tcnt) {
     const int32_t g = blockIdx.x;
@@ -204,18 +230,11 @@ __global__ __launch_bounds__(64) void k_cm_tcount(const int32_t *__restrict__ of
     const int64_t t = int64_t(g) * 64 + lane;
     int32_t c = 0;
     const int32_t e0 = off[g], e1 = off[g + 1];
-    int32_t e = e0;
-    for (; e + 8 <= e1; e += 8) {  // eight masks per round: one wait on the scalar cache
-        uint64_t mk[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) mk[u] = mask[e + u];
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (kept(mk[u], max_pc) && ((mk[u] >> lane) & 1ull)) ++c;
-    }
-    for (; e < e1; ++e) {
-        const uint64_t mk = mask[e];
-        if (kept(mk, max_pc) && ((mk >> lane) & 1ull)) ++c;
+    for (int32_t eb = e0; eb < e1; eb += 64) {
+        const int nb = e1 - eb < 64 ? e1 - eb : 64;
+        const uint64_t mj = lane < nb ? mask[eb + lane] : 0ull;
+        const uint64_t kb = __ballot(lane < nb && kept(mj, max_pc));
+        c += __popcll(wave_transpose64(mj) & kb);
     }
     if (t < m) tcnt[t] = c;
 }
@@ -228,8 +247,10 @@ __global__ void k_cm_loff(const int32_t *__restrict__ eoff, const int32_t *__res
     loff[c] = incoff[eoff[c]];
 }
 
-// one wave per group: lane l walks the group's kept entries in list order and places each
-// of its incidences (target, slot) at the incidence's node-major position
+// one wave per group: lane l walks the group's kept entries that include its target, in
+// list order, and places each incidence (target, slot) at its node-major position.  The
+// entries are read 64 at a time, one per lane (mask, and the first incidence of a kept
+// entry); the transposed bit matrix gives each lane its entries of the batch.
 __global__ __launch_bounds__(64) void k_cm_fill(const int32_t *__restrict__ off, const uint64_t *__restrict__ mask,
                                                 int max_pc, const int32_t *__restrict__ pos,
                                                 const int32_t *__restrict__ incoff, const int32_t *__restrict__ toff,
@@ -241,29 +262,30 @@ __global__ __launch_bounds__(64) void k_cm_fill(const int32_t *__restrict__ off,
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     int32_t slot = t < m ? toff[t] : 0;
     const int32_t e0 = off[g], e1 = off[g + 1];
-    int32_t e = e0;
-    for (; e + 8 <= e1; e += 8) {  // eight entries per round: one wait on the scalar cache
-        uint64_t mk[8];
-        int32_t ps[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            mk[u] = mask[e + u];
-            ps[u] = pos[e + u];
+    for (int32_t eb = e0; eb < e1; eb += 64) {
+        const int nb = e1 - eb < 64 ? e1 - eb : 64;
+        uint64_t mj = 0ull;
+        int32_t pj = 0;
+        if (lane < nb) {
+            mj = mask[eb + lane];
+            pj = pos[eb + lane];
         }
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (kept(mk[u], max_pc) && ((mk[u] >> lane) & 1ull)) {
-                const int32_t q = incoff[ps[u]] + __popcll(mk[u] & lt);
+        const bool kj = lane < nb && kept(mj, max_pc);
+        // an entry that is not kept has no sorted position: its lane reads incoff[0] and
+        // the value is not used
+        const int32_t ij = incoff[kj ? pj : 0];
+        uint64_t mine = wave_transpose64(mj) & __ballot(kj);
+        while (__ballot(mine != 0ull) != 0ull) {  // every lane takes part in the shuffles
+            const bool have = mine != 0ull;
+            const int j = have ? __builtin_ctzll(mine) : 0;
+            mine &= mine - 1ull;
+            const uint64_t mk = shfl_u64(mj, j);
+            const int32_t io = __shfl(ij, j, 64);
+            if (have) {
+                const int32_t q = io + __popcll(mk & lt);
                 inc_tgt[q] = int32_t(t);
                 inc_slot[q] = slot++;
             }
-    }
-    for (; e < e1; ++e) {
-        const uint64_t mk = mask[e];
-        if (kept(mk, max_pc) && ((mk >> lane) & 1ull)) {
-            const int32_t q = incoff[pos[e]] + __popcll(mk & lt);
-            inc_tgt[q] = int32_t(t);
-            inc_slot[q] = slot++;
         }
     }
 }

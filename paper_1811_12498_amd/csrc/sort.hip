@@ -283,8 +283,7 @@ __global__ void k_peek(PeekArgs a, int64_t *__restrict__ dst) {
 }
 }  // namespace
 
-void peek(HostPeek &pk, hipStream_t s, int n, const PeekSrc *src, int64_t *out) {
-    if (n < 1 || n > PEEK_MAX) throw Error(STK_EINVAL, "peek: 1 to PEEK_MAX values");
+int64_t *peek_slots(HostPeek &pk) {
     if (!pk.h) {
         void *h = nullptr, *d = nullptr;
         STK_HIP(hipHostMalloc(&h, sizeof(int64_t) * PEEK_MAX, hipHostMallocMapped | hipHostMallocCoherent));
@@ -296,6 +295,18 @@ void peek(HostPeek &pk, hipStream_t s, int n, const PeekSrc *src, int64_t *out) 
         pk.h = static_cast<int64_t *>(h);
         pk.d = static_cast<int64_t *>(d);
     }
+    return pk.d;
+}
+
+void peek_wait(HostPeek &pk, hipStream_t s, int n, int64_t *out) {
+    if (n < 1 || n > PEEK_MAX || !pk.h) throw Error(STK_EINVAL, "peek_wait: 1 to PEEK_MAX allocated slots");
+    STK_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < n; ++i) out[i] = pk.h[i];
+}
+
+void peek(HostPeek &pk, hipStream_t s, int n, const PeekSrc *src, int64_t *out) {
+    if (n < 1 || n > PEEK_MAX) throw Error(STK_EINVAL, "peek: 1 to PEEK_MAX values");
+    peek_slots(pk);
     PeekArgs a{};
     a.n = n;
     for (int i = 0; i < n; ++i) {
@@ -305,8 +316,7 @@ void peek(HostPeek &pk, hipStream_t s, int n, const PeekSrc *src, int64_t *out) 
     }
     hipLaunchKernelGGL(k_peek, dim3(1), dim3(64), 0, s, a, pk.d);
     STK_CHECK_LAUNCH();
-    STK_HIP(hipStreamSynchronize(s));
-    for (int i = 0; i < n; ++i) out[i] = pk.h[i];
+    peek_wait(pk, s, n, out);
 }
 
 void radix_sort_pairs(Tree &t, uint64_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t s) {

@@ -69,7 +69,7 @@ struct DBuf {
 // values into pinned host slots, then one stream synchronisation (a pageable copy would
 // cost a round trip of its own per value).
 // ---------------------------------------------------------------------------------
-constexpr int PEEK_MAX = 8;
+constexpr int PEEK_MAX = 32;
 struct HostPeek {
     int64_t *h = nullptr;  // pinned, PEEK_MAX slots (allocated on first use, kept with the owner)
     int64_t *d = nullptr;  // the same slots as the device sees them
@@ -87,6 +87,10 @@ struct PeekSrc {
 // Enqueue the copy of src[0..n) (1 <= n <= PEEK_MAX) on s, synchronise s, and return the
 // values in out[0..n).
 void peek(HostPeek &pk, hipStream_t s, int n, const PeekSrc *src, int64_t *out);
+// The slots as the device sees them (allocated if needed), for a kernel that writes its
+// results there itself; peek_wait then synchronises s and returns slots [0, n).
+int64_t *peek_slots(HostPeek &pk);
+void peek_wait(HostPeek &pk, hipStream_t s, int n, int64_t *out);
 
 template <class T> inline T *reserve(DBuf &b, size_t n) {
     b.reserve(n * sizeof(T));

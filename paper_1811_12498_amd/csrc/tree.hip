@@ -123,25 +123,15 @@ __global__ void k_root(int32_t n, int32_t *__restrict__ level, int32_t *__restri
     }
 }
 
-// One wavefront per node of the level.  A node with more than n0 points splits at the
-// boundaries b_d = first index in [s, s + c) whose 3-bit digit at `shift` is >= d,
-// d = 1..7 (the node's keys are sorted and share the bits above the digit, so the digits
-// rise along the node).  The seven searches run together: lanes 9(d-1) .. 9(d-1)+8 probe
-// nine points of the interval still holding b_d, which shrinks about tenfold per round.
-// bnd[9 i + d] = b_d (b_0 = s, b_8 = s + c); nch[i] = number of non-empty octants.
-__global__ __launch_bounds__(BT) void k_split_count(const uint64_t *__restrict__ keys,
-                                                    const int32_t *__restrict__ start,
-                                                    const int32_t *__restrict__ count, int32_t lb, int32_t nlev,
-                                                    int shift, int32_t n0, int32_t *__restrict__ nch,
-                                                    int32_t *__restrict__ bnd) {
-    const int32_t i = int32_t((int64_t(blockIdx.x) * BT + threadIdx.x) >> 6);  // uniform per wave
+// The octant split of one node [s, s + c) by one wavefront (every lane calls it): the
+// boundaries b_d = first index whose 3-bit digit at `shift` is >= d, d = 1..7 (the node's
+// keys are sorted and share the bits above the digit, so the digits rise along the node).
+// The seven searches run together: lanes 9(d-1) .. 9(d-1)+8 probe nine points of the
+// interval still holding b_d, which shrinks about tenfold per round.  Lanes 0..8 write
+// bnd9[d] = b_d (b_0 = s, b_8 = s + c); returns the number of non-empty octants.
+__device__ inline int32_t split_node(const uint64_t *__restrict__ keys, int32_t s, int32_t c, int shift,
+                                     int32_t *bnd9) {
     const int lane = threadIdx.x & 63;
-    if (i >= nlev) return;
-    const int32_t s = start[lb + i], c = count[lb + i];
-    if (c <= n0) {
-        if (lane == 0) nch[i] = 0;
-        return;
-    }
     const int g = lane / 9, k = lane - 9 * g;  // boundary d = g + 1; lane 63 (g = 7) idles
     int32_t lo = s, hi = g < 7 ? s + c : s;    // b_d lies in [lo, hi]
     while (__ballot(lo < hi) != 0) {
@@ -165,10 +155,56 @@ __global__ __launch_bounds__(BT) void k_split_count(const uint64_t *__restrict__
     }
     const int32_t bd = __shfl(lo, lane >= 1 && lane <= 7 ? 9 * (lane - 1) : 0, 64);
     const int32_t b = lane == 0 ? s : (lane == 8 ? s + c : bd);
-    if (lane < 9) bnd[9 * i + lane] = b;
+    if (lane < 9) bnd9[lane] = b;
     const int32_t next = __shfl(b, lane < 63 ? lane + 1 : 63, 64);
-    const uint64_t occupied = __ballot(lane < 8 && next > b);
-    if (lane == 0) nch[i] = int32_t(__popcll(occupied));
+    return int32_t(__popcll(__ballot(lane < 8 && next > b)));
+}
+
+// Node `node` (at level lev) gets its k children, the first at index c, one per non-empty
+// octant of bnd9.  cs / cc, if given, also receive each child's (start, count) at its
+// index relative to c0.
+__device__ inline void emit_node(int32_t node, int32_t k, int32_t c, int32_t c0, const int32_t *bnd9, int32_t lev,
+                                 int32_t *__restrict__ level, int32_t *__restrict__ parent,
+                                 int32_t *__restrict__ child0, int32_t *__restrict__ nchild,
+                                 int32_t *__restrict__ start, int32_t *__restrict__ count, int32_t *cs, int32_t *cc) {
+    if (k == 0) {
+        child0[node] = -1;
+        nchild[node] = 0;
+        return;
+    }
+    child0[node] = c;
+    nchild[node] = k;
+    for (int d = 0; d < 8; ++d) {
+        const int32_t b = bnd9[d], e = bnd9[d + 1];
+        if (e > b) {
+            level[c] = lev + 1;
+            parent[c] = node;
+            child0[c] = -1;
+            nchild[c] = 0;
+            start[c] = b;
+            count[c] = e - b;
+            if (cs) {
+                cs[c - c0] = b;
+                cc[c - c0] = e - b;
+            }
+            ++c;
+        }
+    }
+}
+
+// One wavefront per node of the level: nodes with more than n0 points are split
+// (bnd[9 i ..] their octant bounds), nch[i] = number of children.
+__global__ __launch_bounds__(BT) void k_split_count(const uint64_t *__restrict__ keys,
+                                                    const int32_t *__restrict__ start,
+                                                    const int32_t *__restrict__ count, int32_t lb, int32_t nlev,
+                                                    int shift, int32_t n0, int32_t *__restrict__ nch,
+                                                    int32_t *__restrict__ bnd) {
+    const int32_t i = int32_t((int64_t(blockIdx.x) * BT + threadIdx.x) >> 6);  // uniform per wave
+    const int lane = threadIdx.x & 63;
+    if (i >= nlev) return;
+    const int32_t s = start[lb + i], c = count[lb + i];
+    const int32_t k = c > n0 ? split_node(keys, s, c, shift, bnd + 9 * i) : 0;
+    if (lane == 0) nch[i] = k;
 }
 
 __global__ void k_split_emit(int32_t lb, int32_t nlev, int32_t le, int32_t lev, const int32_t *__restrict__ nch,
@@ -177,27 +213,78 @@ __global__ void k_split_emit(int32_t lb, int32_t nlev, int32_t le, int32_t lev, 
                              int32_t *__restrict__ nchild, int32_t *__restrict__ start, int32_t *__restrict__ count) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nlev) return;
-    const int32_t node = lb + i;
-    const int32_t k = nch[i];
-    if (k == 0) {
-        child0[node] = -1;
-        nchild[node] = 0;
-        return;
+    emit_node(lb + i, nch[i], le + choff[i], 0, bnd + 9 * i, lev, level, parent, child0, nchild, start, count,
+              nullptr, nullptr);
+}
+
+// The levels of at most TOP_NODES nodes from the root down, in one block: its waves split
+// a level's nodes, wave 0 scans the child counts, its threads emit the children, and the
+// next level's (start, count) stay in LDS.  out (the host's pinned slots): out[0] = levels
+// done, out[1] = the level reached, out[2] / out[3] = its first node / one past its last,
+// out[4] = 1 if no node of the last level done split (the tree is complete), out[5 + j] =
+// the first node of level j + 1 for each level j done.
+constexpr int TOP_T = 1024;
+constexpr int TOP_NODES = 128;
+
+__global__ __launch_bounds__(TOP_T) void k_split_top(const uint64_t *__restrict__ keys, int32_t n, int32_t n0,
+                                                     int32_t *__restrict__ level, int32_t *__restrict__ parent,
+                                                     int32_t *__restrict__ child0, int32_t *__restrict__ nchild,
+                                                     int32_t *__restrict__ start, int32_t *__restrict__ count,
+                                                     int64_t *__restrict__ out) {
+    __shared__ int32_t cs[8 * TOP_NODES], cc[8 * TOP_NODES];  // the level's nodes: start, count
+    __shared__ int32_t nch[TOP_NODES], choff[TOP_NODES + 1], bnd[9 * TOP_NODES];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    if (tid == 0) {
+        cs[0] = 0;
+        cc[0] = n;
     }
-    int32_t c = le + choff[i];
-    child0[node] = c;
-    nchild[node] = k;
-    for (int d = 0; d < 8; ++d) {
-        const int32_t b = bnd[9 * i + d], e = bnd[9 * i + d + 1];
-        if (e > b) {
-            level[c] = lev + 1;
-            parent[c] = node;
-            child0[c] = -1;
-            nchild[c] = 0;
-            start[c] = b;
-            count[c] = e - b;
-            ++c;
+    __syncthreads();
+    int32_t lb = 0, le = 1, lev = 0, done = 0, nlv = 0;  // the same in every thread
+    while (lev < STK_MAX_LEVEL && le - lb <= TOP_NODES) {
+        const int32_t nlev = le - lb;
+        for (int32_t i = wave; i < nlev; i += TOP_T / 64) {
+            const int32_t c = cc[i];
+            const int32_t k = c > n0 ? split_node(keys, cs[i], c, 3 * (STK_MAX_LEVEL - 1 - lev), bnd + 9 * i) : 0;
+            if (lane == 0) nch[i] = k;
         }
+        __syncthreads();
+        if (wave == 0) {  // exclusive scan of nch[0, nlev), two per lane
+            static_assert(TOP_NODES <= 128, "two counts per lane of one wave");
+            const int32_t a0 = 2 * lane < nlev ? nch[2 * lane] : 0;
+            const int32_t a1 = 2 * lane + 1 < nlev ? nch[2 * lane + 1] : 0;
+            int32_t x = a0 + a1;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int32_t y = __shfl_up(x, o, 64);
+                if (lane >= o) x += y;
+            }
+            const int32_t ex = x - a0 - a1;
+            if (2 * lane < nlev) choff[2 * lane] = ex;
+            if (2 * lane + 1 < nlev) choff[2 * lane + 1] = ex + a0;
+            if (lane == 63) choff[TOP_NODES] = x;
+        }
+        __syncthreads();
+        const int32_t total = choff[TOP_NODES];
+        if (tid < nlev)
+            emit_node(lb + tid, nch[tid], le + choff[tid], le, bnd + 9 * tid, lev, level, parent, child0, nchild,
+                      start, count, cs, cc);
+        __syncthreads();
+        if (tid == 0) out[5 + nlv] = le;
+        ++nlv;
+        if (total == 0) {
+            done = 1;
+            break;
+        }
+        lb = le;
+        le += total;
+        ++lev;
+    }
+    if (tid == 0) {
+        out[0] = nlv;
+        out[1] = lev;
+        out[2] = lb;
+        out[3] = le;
+        out[4] = done;
     }
 }
 
@@ -398,13 +485,40 @@ void build_tree(Tree &t, const double *src, int64_t n, int32_t n0, hipStream_t s
             b->reserve(cap * sizeof(int32_t));
         }
     }
+    // room for every node the top-levels kernel can make
+    const size_t top_max = 1 + size_t(STK_MAX_LEVEL) * 8 * TOP_NODES;
+    if (!t.degenerate && top_max > cap) {
+        size_t ncap = cap;
+        while (ncap < top_max) ncap *= 2;
+        for (DBuf *b : {&t.nlevel, &t.nparent, &t.nchild0, &t.nnchild, &t.nstart, &t.ncount})
+            grow_keep(*b, 0, ncap * sizeof(int32_t), s);
+        cap = ncap;
+    }
     hipLaunchKernelGGL(k_root, dim3(1), dim3(64), 0, s, int32_t(n), t.nlevel.as<int32_t>(), t.nparent.as<int32_t>(),
                        t.nchild0.as<int32_t>(), t.nnchild.as<int32_t>(), t.nstart.as<int32_t>(),
                        t.ncount.as<int32_t>());
     STK_CHECK_LAUNCH();
     int32_t nnodes = 1, lb = 0, le = 1, lev = 0;
     t.level_begin.assign(1, 0);
-    while (!t.degenerate && lev < STK_MAX_LEVEL) {
+    bool complete = t.degenerate;
+    if (!t.degenerate) {
+        // the sparse top levels in one block, then the host walks the rest level by level
+        static_assert(5 + STK_MAX_LEVEL <= PEEK_MAX, "the top kernel's results fit the host slots");
+        int64_t *slots = peek_slots(t.peek);
+        hipLaunchKernelGGL(k_split_top, dim3(1), dim3(TOP_T), 0, s, keys, int32_t(n), n0, t.nlevel.as<int32_t>(),
+                           t.nparent.as<int32_t>(), t.nchild0.as<int32_t>(), t.nnchild.as<int32_t>(),
+                           t.nstart.as<int32_t>(), t.ncount.as<int32_t>(), slots);
+        STK_CHECK_LAUNCH();
+        int64_t r[5 + STK_MAX_LEVEL];
+        peek_wait(t.peek, s, 5 + STK_MAX_LEVEL, r);
+        for (int64_t j = 0; j < r[0]; ++j) t.level_begin.push_back(int32_t(r[5 + j]));
+        lev = int32_t(r[1]);
+        lb = int32_t(r[2]);
+        le = int32_t(r[3]);
+        nnodes = le;
+        complete = r[4] != 0;
+    }
+    while (!complete && lev < STK_MAX_LEVEL) {
         const int32_t nlev = le - lb;
         // room for every child the level can make (at most eight per node), so the
         // children are written before the host reads how many there are

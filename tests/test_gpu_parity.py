@@ -40,11 +40,18 @@ def _case(kind, n, seed, n0):
         w = W.cube(n, seed=seed, n0=n0)
         w.src[n // 2:] = w.src[: n - n // 2]
         return w
+    if kind == "chain":  # all but ten points coincident: single-child nodes down to the last level
+        w = W.cube(n, seed=seed, n0=n0)
+        w.src[10:] = w.src[0]
+        return w
     raise ValueError(kind)
 
 
+# level sizes (oracle): the 20,000-point sphere 1, 8, 56, 264, 575 (the sparse top levels
+# and the level-by-level build both run); the chain one node per level from level 2 to the
+# last (21)
 TREE_CASES = [("cube", 1000, 1, 50), ("cube", 5003, 2, 64), ("sphere", 20000, 3, 100), ("cube_pm1", 7777, 4, 500),
-              ("dups", 3000, 5, 40), ("cube", 70, 6, 1000)]
+              ("dups", 3000, 5, 40), ("cube", 70, 6, 1000), ("chain", 300, 8, 20)]
 
 
 @pytest.mark.parametrize("kind,n,seed,n0", TREE_CASES)
