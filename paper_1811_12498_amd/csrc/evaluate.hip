@@ -173,38 +173,6 @@ template <int MODE> __global__ __launch_bounds__(64) void k_traverse(TravArgs a)
     }
 }
 
-// one block: out[0] = sum of a[0..n), out[1] = sum of b[0..n) (int64), out[2] = max of
-// c[0..n), out[3] = max of d[0..n)
-__global__ __launch_bounds__(1024) void k_sum2_i64(const int32_t *__restrict__ a, const int32_t *__restrict__ b,
-                                                   const int32_t *__restrict__ c, const int32_t *__restrict__ d,
-                                                   int32_t n, long long *__restrict__ out) {
-    __shared__ long long red[4][1024];
-    long long sa = 0, sb = 0, mc = 0, md = 0;
-    for (int32_t i = threadIdx.x; i < n; i += 1024) {
-        sa += a[i];
-        sb += b[i];
-        mc = c[i] > mc ? c[i] : mc;
-        md = d[i] > md ? d[i] : md;
-    }
-    red[0][threadIdx.x] = sa;
-    red[1][threadIdx.x] = sb;
-    red[2][threadIdx.x] = mc;
-    red[3][threadIdx.x] = md;
-    __syncthreads();
-    for (int o = 512; o > 0; o >>= 1) {
-        if (int(threadIdx.x) < o) {
-            red[0][threadIdx.x] += red[0][threadIdx.x + o];
-            red[1][threadIdx.x] += red[1][threadIdx.x + o];
-            red[2][threadIdx.x] = red[2][threadIdx.x + o] > red[2][threadIdx.x] ? red[2][threadIdx.x + o]
-                                                                                 : red[2][threadIdx.x];
-            red[3][threadIdx.x] = red[3][threadIdx.x + o] > red[3][threadIdx.x] ? red[3][threadIdx.x + o]
-                                                                                 : red[3][threadIdx.x];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x < 4) out[threadIdx.x] = red[threadIdx.x][0];
-}
-
 // grid (groups): a group's slot entries to its place in the scanned lists
 __global__ __launch_bounds__(256) void k_slot_compact(const int32_t *__restrict__ cnt, const int32_t *__restrict__ off,
                                                       int32_t slot, const int32_t *__restrict__ snode,
@@ -515,12 +483,10 @@ void build_lists(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, 
     }
     STK_CHECK_LAUNCH();
     long long *inc_d = reserve<long long>(pl.far_inc, 4);
-    hipLaunchKernelGGL(k_sum2_i64, dim3(1), dim3(1024), 0, s, ta.gpf, ta.gpn, ta.gfar, ta.gnear, ng, inc_d);
-    STK_CHECK_LAUNCH();
     int32_t *foff = reserve<int32_t>(pl.far_off, size_t(ng) + 1);
     int32_t *noff = reserve<int32_t>(pl.near_off, size_t(ng) + 1);
-    scan_exclusive_i32(ta.gfar, foff, ng, t.s_scan, s);
-    scan_exclusive_i32(ta.gnear, noff, ng, t.s_scan, s);
+    // list offsets, pair totals and the longest group lists
+    scan2_stats(ta.gfar, foff, ta.gnear, noff, ta.gpf, ta.gpn, ng, inc_d, t.s_scan, s);
     int32_t tot[2];
     int64_t inc[2], longest[2];
     {

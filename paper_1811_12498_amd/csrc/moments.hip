@@ -3,8 +3,8 @@
 //   M_j^k(C) = sum_{y in C} (y - y_c)^k f_j,   Mt_jl^k(C) = sum_{y in C} (y - y_c)^k h_j nu_l
 //
 // in FP64.  A leaf's moments are summed directly from its points: work items are (leaf,
-// chunk of <= CHUNK points), each writes a partial sum and a second kernel adds a leaf's
-// partials in chunk order.  An inner node's moments are its children's, moved to its
+// chunk of <= CHUNK points), each writes a partial sum, and the leaf's block in the
+// level-by-level pass adds them in chunk order.  An inner node's moments are its children's, moved to its
 // centre by the binomial expansion
 //   (y - c)^k = sum_{j <= k} C(k, j) (c' - c)^(k - j) (y - c')^j    (c' a child's centre),
 // exact in exact arithmetic, level by level from the leaves up; children and terms are
@@ -32,10 +32,10 @@ __device__ inline int32_t node_of_chunk(const int32_t *__restrict__ off, int32_t
 }
 
 // One wavefront per (node, chunk of <= CHUNK points) and right-hand side r (grid
-// (nchunks, K)).  Lane L owns the multi-indices a = L + 64 j.  For each point the wave
-// reads its 12 weights (f_j, h_j nu_l; uniform, so through the scalar cache) and the
-// powers (y - y_c)_axis^e from a small LDS table, and each lane adds
-// (y - y_c)^k * weight to its 12 accumulators per multi-index.  Powers and the monomial
+// (nchunks, K)).  Lane L owns the multi-indices a = L + 64 j.  The points are taken
+// STAGE at a time: the wave stages their powers (y - y_c)_axis^e and their 12 weights
+// (f_j, h_j nu_l) in LDS, then for each point each lane adds (y - y_c)^k * weight to its
+// 12 accumulators per multi-index.  Powers and the monomial
 // are formed by repeated multiplication in the same order as the oracle.
 // part[((chunk * K + r) * nm + a) * 12 + c]
 template <int A>
@@ -45,6 +45,7 @@ __global__ __launch_bounds__(64) void k_moments(const double *__restrict__ pos, 
                                                 const double *__restrict__ w12, int p, int nm,
                                                 double *__restrict__ part) {
     __shared__ double pw[STAGE][3][STK_P_MAX + 1];
+    __shared__ double wl[STAGE][12];
     const int32_t ch = blockIdx.x;
     const int r = blockIdx.y;
     const int K = gridDim.y;
@@ -79,12 +80,15 @@ __global__ __launch_bounds__(64) void k_moments(const double *__restrict__ pos, 
                 v *= d;
             }
         }
+        for (int q = lane; q < 12 * cnt; q += 64) {
+            const int pt = q / 12, c = q - 12 * pt;
+            wl[pt][c] = w12[(size_t(b + pt) * K + r) * 12 + c];
+        }
         __syncthreads();
         for (int pt = 0; pt < cnt; ++pt) {
-            const double *__restrict__ w = w12 + (size_t(b + pt) * K + r) * 12;
             double wv[12];
 #pragma unroll
-            for (int c = 0; c < 12; ++c) wv[c] = w[c];
+            for (int c = 0; c < 12; ++c) wv[c] = wl[pt][c];
 #pragma unroll
             for (int j = 0; j < A; ++j) {
                 const double mono = pw[pt][0][e1[j]] * pw[pt][1][e2[j]] * pw[pt][2][e3[j]];
@@ -103,36 +107,11 @@ __global__ __launch_bounds__(64) void k_moments(const double *__restrict__ pos, 
     }
 }
 
-// grid (nnodes, K, ceil(12 nm / MT)): mom[(node * nm + a) * 12K + 12 r + c] = sum of the
-// node's chunk partials in chunk order
-__global__ __launch_bounds__(MT) void k_moments_reduce(const double *__restrict__ part, const int32_t *__restrict__ coff,
-                                                       int nm, double *__restrict__ mom) {
-    const int32_t node = blockIdx.x;
-    const int r = blockIdx.y, K = gridDim.y;
-    const int q = blockIdx.z * MT + threadIdx.x;
-    if (q >= nm * 12) return;
-    const int32_t c0 = coff[node], c1 = coff[node + 1];
-    const size_t stride = size_t(K) * nm * 12;
-    const double *src = part + (size_t(c0) * K + r) * nm * 12 + q;
-    double s = 0.0;
-    int32_t ch = c0;
-    for (; ch + 4 <= c1; ch += 4, src += 4 * stride) {
-        const double v0 = src[0], v1 = src[stride], v2 = src[2 * stride], v3 = src[3 * stride];
-        s += v0;
-        s += v1;
-        s += v2;
-        s += v3;
-    }
-    for (; ch < c1; ++ch, src += stride) s += src[0];
-    const int a = q / 12, c = q % 12;
-    mom[(size_t(node) * nm + a) * 12 * K + 12 * r + c] = s;
-}
-
 // grid (nodes of one level, K), MT threads, 2 nm * 12 doubles of dynamic LDS; one launch
 // per level from the deepest up.  A block first completes its node's moments (an inner
 // node: the sum of its children's moments moved to its centre, children in order; a leaf:
-// its direct moments), then moves them to its parent's centre for the level above, one
-// axis at a time,
+// the sum of its chunks' partial moments, in chunk order), then moves them to its parent's
+// centre for the level above, one axis at a time,
 //   M'(k) = sum_{j <= k_i} C(k_i, j) d_i^(k_i - j) M(k with k_i -> j)   (i = x, y, z),
 // which composes to the binomial expansion and keeps every index within ||k|| <= p.  A
 // thread takes whole lines along the axis (the other two components and the channel
@@ -144,6 +123,7 @@ __device__ inline int m2m_index(int ax, int kl, int u, int v) {
 
 __global__ __launch_bounds__(MT) void k_m2m(const double *__restrict__ center, const int32_t *__restrict__ child0,
                                             const int32_t *__restrict__ nchild, const int32_t *__restrict__ parent,
+                                            const double *__restrict__ part, const int32_t *__restrict__ leaf_coff,
                                             int32_t lev_begin, int p, int nm, double *__restrict__ mom,
                                             double *__restrict__ up) {
     extern __shared__ double m2m_lds[];
@@ -164,7 +144,16 @@ __global__ __launch_bounds__(MT) void k_m2m(const double *__restrict__ center, c
             buf0[q] = s;
         }
     } else {
-        for (int q = tid; q < nq; q += MT) buf0[q] = mom[at(node, q)];
+        // part[((chunk * K + r) * nm + a) * 12 + c], the leaf's chunks c0 .. c1 - 1
+        const int32_t c0 = leaf_coff[node], c1 = leaf_coff[node + 1];
+        const size_t stride = size_t(K) * nm * 12;
+        for (int q = tid; q < nq; q += MT) {
+            const double *src = part + (size_t(c0) * K + r) * nm * 12 + q;
+            double v = 0.0;
+            for (int32_t ch = c0; ch < c1; ++ch, src += stride) v += *src;
+            mom[at(node, q)] = v;
+            buf0[q] = v;
+        }
     }
     const int32_t par = parent[node];
     if (par < 0) return;  // the root
@@ -312,9 +301,6 @@ void compute_moments(Tree &t, const double *f, const double *h, const double *nu
         default: throw Error(STK_EINVAL, "p too large for the moment kernel");
     }
     double *mom = reserve<double>(t.mom, size_t(nn) * nm * 12 * K);
-    hipLaunchKernelGGL(k_moments_reduce, dim3(nn, K, (nm * 12 + MT - 1) / MT), dim3(MT), 0, s, part,
-                       t.leaf_coff.as<int32_t>(), nm, mom);
-    STK_CHECK_LAUNCH();
     // every level from the deepest up: complete inner nodes from their children, move each
     // node's moments to its parent's centre
     double *up = reserve<double>(t.mom_up, size_t(nn) * nm * 12 * K);
@@ -323,7 +309,7 @@ void compute_moments(Tree &t, const double *f, const double *h, const double *nu
         if (e > b) {
             hipLaunchKernelGGL(k_m2m, dim3(e - b, K), dim3(MT), sizeof(double) * 2 * nm * 12, s,
                                t.ncenter.as<double>(), t.nchild0.as<int32_t>(), t.nnchild.as<int32_t>(),
-                               t.nparent.as<int32_t>(), b, p, nm, mom, up);
+                               t.nparent.as<int32_t>(), part, t.leaf_coff.as<int32_t>(), b, p, nm, mom, up);
             STK_CHECK_LAUNCH();
         }
     }

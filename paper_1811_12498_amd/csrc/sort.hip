@@ -191,6 +191,47 @@ __global__ __launch_bounds__(SCAN_T) void k_scan(const int32_t *__restrict__ in,
     if (threadIdx.x == 0) out[n] = tot;
 }
 
+// Blocks base + blockIdx.x: 0 scans a into oa (oa[n] = its total), 1 scans b into ob, 2
+// writes stats = {sum of c, sum of d (int64), max of a, max of b}.
+__global__ __launch_bounds__(SCAN_T) void k_scan2_stats(const int32_t *__restrict__ a, int32_t *__restrict__ oa,
+                                                        const int32_t *__restrict__ b, int32_t *__restrict__ ob,
+                                                        const int32_t *__restrict__ c, const int32_t *__restrict__ d,
+                                                        int64_t n, int base, long long *__restrict__ stats) {
+    const int role = base + int(blockIdx.x);
+    if (role < 2) {
+        const int32_t *in = role == 0 ? a : b;
+        int32_t *out = role == 0 ? oa : ob;
+        const int32_t tot = block_scan_excl<SCAN_T>(in, out, n);
+        if (threadIdx.x == 0) out[n] = tot;
+        return;
+    }
+    __shared__ long long red[4][SCAN_T];
+    long long sc = 0, sd = 0, ma = 0, mb = 0;
+    for (int64_t i = threadIdx.x; i < n; i += SCAN_T) {
+        sc += c[i];
+        sd += d[i];
+        ma = a[i] > ma ? a[i] : ma;
+        mb = b[i] > mb ? b[i] : mb;
+    }
+    red[0][threadIdx.x] = sc;
+    red[1][threadIdx.x] = sd;
+    red[2][threadIdx.x] = ma;
+    red[3][threadIdx.x] = mb;
+    __syncthreads();
+    for (int o = SCAN_T / 2; o > 0; o >>= 1) {
+        if (int(threadIdx.x) < o) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + o];
+            red[1][threadIdx.x] += red[1][threadIdx.x + o];
+            red[2][threadIdx.x] = red[2][threadIdx.x + o] > red[2][threadIdx.x] ? red[2][threadIdx.x + o]
+                                                                                 : red[2][threadIdx.x];
+            red[3][threadIdx.x] = red[3][threadIdx.x + o] > red[3][threadIdx.x] ? red[3][threadIdx.x + o]
+                                                                                 : red[3][threadIdx.x];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) stats[threadIdx.x] = red[threadIdx.x][0];
+}
+
 // device-wide scan for long inputs: tile sums, a single-block scan of them, then each
 // tile scanned from its offset
 constexpr int STILE_T = 256;
@@ -215,11 +256,13 @@ __global__ __launch_bounds__(STILE_T) void k_tile_sums(const int32_t *__restrict
     }
 }
 
+// each tile scanned from its offset; the first block also writes the total, out[n]
 __global__ __launch_bounds__(STILE_T) void k_tile_scan(const int32_t *__restrict__ in, int64_t n,
                                                        const int32_t *__restrict__ offs, int32_t *__restrict__ out) {
     const int64_t base = int64_t(blockIdx.x) * STILE;
     const int64_t len = n - base < STILE ? n - base : STILE;
     block_scan_excl<STILE_T>(in + base, out + base, len, offs[blockIdx.x]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = offs[gridDim.x];
 }
 
 // radix histogram table hist[digit * ntiles + tile]: block d scans row d in place and
@@ -265,7 +308,6 @@ void scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, DBuf &scratc
     STK_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_tile_scan, dim3(unsigned(ntiles)), dim3(STILE_T), 0, s, in, n, offs, out);
     STK_CHECK_LAUNCH();
-    STK_HIP(hipMemcpyAsync(out + n, offs + ntiles, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
 }
 
 namespace {
@@ -317,6 +359,19 @@ void peek(HostPeek &pk, hipStream_t s, int n, const PeekSrc *src, int64_t *out) 
     hipLaunchKernelGGL(k_peek, dim3(1), dim3(64), 0, s, a, pk.d);
     STK_CHECK_LAUNCH();
     peek_wait(pk, s, n, out);
+}
+
+void scan2_stats(const int32_t *a, int32_t *oa, const int32_t *b, int32_t *ob, const int32_t *c, const int32_t *d,
+                 int64_t n, long long *stats, DBuf &scratch, hipStream_t s) {
+    if (n <= 16 * 4 * SCAN_T) {  // the two scans and the statistics in one launch
+        hipLaunchKernelGGL(k_scan2_stats, dim3(3), dim3(SCAN_T), 0, s, a, oa, b, ob, c, d, n, 0, stats);
+        STK_CHECK_LAUNCH();
+        return;
+    }
+    scan_exclusive_i32(a, oa, n, scratch, s);
+    scan_exclusive_i32(b, ob, n, scratch, s);
+    hipLaunchKernelGGL(k_scan2_stats, dim3(1), dim3(SCAN_T), 0, s, a, oa, b, ob, c, d, n, 2, stats);
+    STK_CHECK_LAUNCH();
 }
 
 void radix_sort_pairs(Tree &t, uint64_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t s) {

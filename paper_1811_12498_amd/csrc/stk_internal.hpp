@@ -256,6 +256,10 @@ void radix_sort_pairs(Tree &t, uint64_t *keys, int32_t *vals, int64_t n, int bit
 // exclusive scan of int32 in[0..n) into out[0..n]; out[n] = total.  Long inputs use
 // `scratch` for per-tile sums (in and out must not overlap).
 void scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, DBuf &scratch, hipStream_t s);
+// exclusive scans of a and b (length n) into oa and ob (oa[n], ob[n] = the totals), and
+// stats = {sum of c, sum of d (int64), max of a, max of b}; one launch for n <= 65,536
+void scan2_stats(const int32_t *a, int32_t *oa, const int32_t *b, int32_t *ob, const int32_t *c, const int32_t *d,
+                 int64_t n, long long *stats, DBuf &scratch, hipStream_t s);
 
 void build_tree(Tree &t, const double *src, int64_t n, int32_t n0, hipStream_t s);
 // records_done, if given, is recorded on s once the per-source records (what the near

@@ -326,12 +326,9 @@ __global__ __launch_bounds__(BT) void k_leaf_box(const double *__restrict__ pos,
     }
 }
 
-__global__ void k_inner_box(int32_t lb, int32_t nlev, const int32_t *__restrict__ child0,
-                            const int32_t *__restrict__ nchild, double *__restrict__ bmin, double *__restrict__ bmax,
-                            double *__restrict__ center) {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nlev) return;
-    const int32_t node = lb + i;
+// an inner node's box: the union of its children's, centre its midpoint
+__device__ inline void inner_box(int32_t node, const int32_t *__restrict__ child0, const int32_t *__restrict__ nchild,
+                                 double *__restrict__ bmin, double *__restrict__ bmax, double *__restrict__ center) {
     const int32_t k = nchild[node];
     if (k == 0) return;
     const int32_t c0 = child0[node];
@@ -344,6 +341,29 @@ __global__ void k_inner_box(int32_t lb, int32_t nlev, const int32_t *__restrict_
         bmin[3 * node + a] = l;
         bmax[3 * node + a] = h;
         center[3 * node + a] = 0.5 * (l + h);
+    }
+}
+
+__global__ void k_inner_box(int32_t lb, int32_t nlev, const int32_t *__restrict__ child0,
+                            const int32_t *__restrict__ nchild, double *__restrict__ bmin, double *__restrict__ bmax,
+                            double *__restrict__ center) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nlev) inner_box(lb + i, child0, nchild, bmin, bmax, center);
+}
+
+// the boxes of levels top, top - 1, .., 0 (each of at most TOP_BOX_NODES nodes) by one
+// block, level by level: a level's boxes are read by the next only after the barrier
+constexpr int TOP_BOX_NODES = 4096;
+struct LevelBegins {
+    int32_t b[STK_MAX_LEVEL + 2];
+};
+__global__ __launch_bounds__(1024) void k_inner_box_top(int32_t top, LevelBegins lv, const int32_t *__restrict__ child0,
+                                                        const int32_t *__restrict__ nchild, double *__restrict__ bmin,
+                                                        double *__restrict__ bmax, double *__restrict__ center) {
+    for (int32_t l = top; l >= 0; --l) {
+        for (int32_t node = lv.b[l] + int32_t(threadIdx.x); node < lv.b[l + 1]; node += 1024)
+            inner_box(node, child0, nchild, bmin, bmax, center);
+        __syncthreads();
     }
 }
 
@@ -566,11 +586,24 @@ void build_tree(Tree &t, const double *src, int64_t n, int32_t n0, hipStream_t s
     hipLaunchKernelGGL(k_leaf_box, dim3(nnodes), dim3(BT), 0, s, pos, t.nstart.as<int32_t>(),
                        t.ncount.as<int32_t>(), t.nnchild.as<int32_t>(), bmin, bmax, cen);
     STK_CHECK_LAUNCH();
-    for (int l = t.nlevels - 2; l >= 0; --l) {
-        const int32_t b = t.level_begin[l], e = t.level_begin[l + 1];
-        hipLaunchKernelGGL(k_inner_box, dim3(nblk(e - b, BT)), dim3(BT), 0, s, b, e - b,
-                           t.nchild0.as<int32_t>(), t.nnchild.as<int32_t>(), bmin, bmax, cen);
-        STK_CHECK_LAUNCH();
+    {
+        // levels above `top` are all small: one block takes them, the others a launch each
+        int top = t.nlevels - 2;
+        int small = -1;  // the deepest level from which every level up to the root is small
+        for (int l = 0; l <= top && t.level_begin[l + 1] - t.level_begin[l] <= TOP_BOX_NODES; ++l) small = l;
+        for (int l = top; l > small; --l) {
+            const int32_t b = t.level_begin[l], e = t.level_begin[l + 1];
+            hipLaunchKernelGGL(k_inner_box, dim3(nblk(e - b, BT)), dim3(BT), 0, s, b, e - b,
+                               t.nchild0.as<int32_t>(), t.nnchild.as<int32_t>(), bmin, bmax, cen);
+            STK_CHECK_LAUNCH();
+        }
+        if (small >= 0) {
+            LevelBegins lv{};
+            for (int l = 0; l <= small + 1; ++l) lv.b[l] = t.level_begin[l];
+            hipLaunchKernelGGL(k_inner_box_top, dim3(1), dim3(1024), 0, s, small, lv, t.nchild0.as<int32_t>(),
+                               t.nnchild.as<int32_t>(), bmin, bmax, cen);
+            STK_CHECK_LAUNCH();
+        }
     }
 
     // work chunks and radii
