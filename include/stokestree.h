@@ -270,7 +270,7 @@ stk_status stk_plan_tiles(const stk_plan *plan, stk_tiles *out);
  * per phase since the last read (host arrays of STK_NPHASES entries; either may be
  * NULL), and clears the record.  Timing is process-wide; calls on several streams
  * at once are not separated. */
-#define STK_NPHASES 9
+#define STK_NPHASES 10
 enum {
     STK_PHASE_TREE = 0,     /* root cube, Morton keys, sort, subdivision, boxes, radii */
     STK_PHASE_MOMENTS = 1,  /* moments, channel blocks, near-field records            */
@@ -280,7 +280,9 @@ enum {
     STK_PHASE_FAR = 5,      /* far-field kernel                                         */
     STK_PHASE_DIRECT = 6,   /* FP64 direct sum                                          */
     STK_PHASE_ADJOINT = 7,  /* adjoint kernels                                          */
-    STK_PHASE_FAR_SPARSE = 8 /* far entries applying to few targets, cluster major (K = 1) */
+    STK_PHASE_FAR_SPARSE = 8, /* far entries applying to few targets, cluster major (K = 1) */
+    STK_PHASE_FINISH = 9    /* per-target sums of the near and sparse far partials and of
+                               the far field's parts, when it runs in parts                */
 };
 stk_status stk_profile_enable(int on);
 stk_status stk_profile_read(double *ms, int64_t *count);

@@ -31,7 +31,7 @@ EXPORTS = ["stk_build_tree", "stk_compute_moments", "stk_evaluate_tree", "stk_ev
            "stk_profile_enable", "stk_profile_read", "stk_tree_destroy", "stk_plan_destroy",
            "stk_plan_cache_clear", "stk_last_error"]
 
-PHASES = ["tree", "moments", "targets", "lists", "near", "far", "direct", "adjoint", "far_sparse"]
+PHASES = ["tree", "moments", "targets", "lists", "near", "far", "direct", "adjoint", "far_sparse", "finish"]
 
 
 class StkError(RuntimeError):

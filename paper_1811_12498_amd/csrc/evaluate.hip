@@ -293,17 +293,39 @@ int device_cus() {
     return cus[dev];
 }
 
-// the split far field's parts in order, plus the near part, in the caller's order
-__global__ void k_far_combine(const double *__restrict__ fpart, int32_t nsplit, const double *__restrict__ unear,
-                              const int32_t *__restrict__ tperm, int64_t m, int32_t K, double *__restrict__ u_out) {
+// Per (target, right-hand side), when the group-major far field ran in parts: the near
+// partials in near-list order (compensated), plus the sparse far partials in their list
+// order (compensated; spart may be null), then the far parts in order, written in the
+// caller's order.  The arithmetic of a separate near reduction, sparse addition and
+// combination, in one pass.
+template <typename T>
+__global__ void k_finish(const T *__restrict__ npart, const int32_t *__restrict__ ntoff, const T *__restrict__ spart,
+                         const int32_t *__restrict__ stoff, const double *__restrict__ fpart, int32_t nsplit,
+                         const int32_t *__restrict__ tperm, int64_t m, int32_t K, double *__restrict__ u_out) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= m * K) return;
     const int64_t r = i / m, t = i - r * m;
+    double un[3];
+    {
+        Comp<T> acc[3];
+        for (int32_t k = ntoff[t]; k < ntoff[t + 1]; ++k)
+            for (int q = 0; q < 3; ++q) acc[q].add(npart[(int64_t(k) * K + r) * 3 + q]);
+        for (int q = 0; q < 3; ++q) un[q] = acc[q].value();
+    }
+    if (spart) {
+        const int32_t k0 = stoff[t], k1 = stoff[t + 1];
+        if (k0 != k1) {
+            Comp<T> acc[3];
+            for (int32_t k = k0; k < k1; ++k)
+                for (int q = 0; q < 3; ++q) acc[q].add(spart[3 * (int64_t(k) * K + r) + q]);
+            for (int q = 0; q < 3; ++q) un[q] += acc[q].value();
+        }
+    }
     double u[3] = {0.0, 0.0, 0.0};
     for (int32_t h = 0; h < nsplit; ++h)
         for (int q = 0; q < 3; ++q) u[q] += fpart[((size_t(h) * K + r) * m + t) * 3 + q];
     const int64_t o = tperm[t];
-    for (int q = 0; q < 3; ++q) u_out[(size_t(r) * m + o) * 3 + q] = u[q] + unear[(size_t(t) * K + r) * 3 + q];
+    for (int q = 0; q < 3; ++q) u_out[(size_t(r) * m + o) * 3 + q] = u[q] + un[q];
 }
 
 template <typename T, int KB> void dispatch_far(int p, const FarArgs &a, hipStream_t s) {
@@ -384,7 +406,7 @@ void dispatch_far_mfma(int p, const FarArgs &a, DBuf &bm, int32_t nn, hipStream_
 
 }  // namespace
 
-void far_sparse(Tree &t, Plan &pl, double *unear, int max_pc, hipStream_t s) {
+void far_sparse(Tree &t, Plan &pl, double *unear, int max_pc, hipStream_t s, bool add) {
     const int64_t m = pl.m;
     const int K = t.k_rhs;
     ClusterMajor &cm = pl.fcm;
@@ -404,7 +426,7 @@ void far_sparse(Tree &t, Plan &pl, double *unear, int max_pc, hipStream_t s) {
         dispatch_far_sparse<float, 2>(t.p, sa, s);
     else
         dispatch_far_sparse<float, 1>(t.p, sa, s);
-    if (m > 0 && cm.n_inc > 0) {
+    if (add && m > 0 && cm.n_inc > 0) {
         if (t.prec == STK_FP64)
             hipLaunchKernelGGL(k_cm_add<double>, dim3(nblk(m * K, 256)), dim3(256), 0, s,
                                static_cast<const double *>(part), cm.toff.as<int32_t>(), m, K, unear);
@@ -543,14 +565,10 @@ void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, dou
     if (!tiles_valid(pl.tiles, K, t.prec)) throw Error(STK_EINVAL, "kernel tiles do not fit this evaluation");
     const int kb = pl.tiles.far_kb;
 
-    // near field (its leaf-major lists close the lists phase), then far field (which adds
-    // the near part and un-permutes)
-    double *unear = reserve<double>(t.s_tmp, size_t(m) * K * 3);
-    near_field(t, pl, unear, s);
     // far entries that apply to few targets of their group (one right-hand side), or every
     // far entry (tile far_cm, or automatically when the group lists' lanes are mostly
-    // idle), run cluster major (their velocities are added to unear); the group-major
-    // kernel skips them
+    // idle), run cluster major (their velocities are added to the near part); the
+    // group-major kernel skips them
     const double util = pl.n_far_entries > 0 ? double(pl.n_far_inc) / (64.0 * double(pl.n_far_entries)) : 1.0;
     const bool cm_fits = pl.n_far_inc < CM_MAX_INC;
     const bool all_cm = !pl.tiles.far_mfma && cm_fits &&
@@ -558,13 +576,6 @@ void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, dou
     if (pl.tiles.far_cm == FAR_CM_ON && !cm_fits)
         throw Error(STK_EINVAL, "far_cm: too many far interactions for the cluster-major lists");
     const int sparse_max = all_cm ? 64 : (K == 1 && cm_fits ? FAR_SPARSE_MAX : 0);
-    // moments computed beside the lists and the near field (on another stream) must be
-    // complete from here on: the far kernels read the clusters' streams
-    if (pl.moments_ready) {
-        STK_HIP(hipStreamWaitEvent(s, pl.moments_ready, 0));
-        pl.moments_ready = nullptr;
-    }
-    if (sparse_max > 0) far_sparse(t, pl, unear, sparse_max, s);
     pl.far_sparse_max = sparse_max;
     // parts of each group's far list (tile far_split; automatically enough parts for
     // FAR_SPLIT_ROUNDS rounds of waves, so the last round idles little of the chip)
@@ -578,6 +589,21 @@ void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, dou
         }
     }
     pl.tiles.far_split = nsplit;
+    // with the far field in parts, one final pass adds the near partials, the sparse far
+    // partials and the parts; otherwise the near part is reduced into unear, the sparse
+    // partials added to it, and the far kernel adds it
+    const bool finish = nsplit > 1 && m > 0;
+
+    // near field (its leaf-major lists close the lists phase), then far field
+    double *unear = reserve<double>(t.s_tmp, size_t(m) * K * 3);
+    near_field(t, pl, unear, s, !finish);
+    // moments computed beside the lists and the near field (on another stream) must be
+    // complete from here on: the far kernels read the clusters' streams
+    if (pl.moments_ready) {
+        STK_HIP(hipStreamWaitEvent(s, pl.moments_ready, 0));
+        pl.moments_ready = nullptr;
+    }
+    if (sparse_max > 0) far_sparse(t, pl, unear, sparse_max, s, !finish);
     double *fpart = nsplit > 1 ? reserve<double>(pl.far_part, size_t(nsplit) * K * size_t(m) * 3) : nullptr;
     FarArgs fa{tpos, m, foff, pl.far_node.as<int32_t>(), pl.far_mask.as<uint64_t>(), t.ncenter.as<double>(),
                t.nrho.as<double>(), t.wblk.p, unear, tperm, u_out, ng, K, sparse_max, nsplit, fpart};
@@ -591,12 +617,21 @@ void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, dou
         dispatch_far<float, 2>(t.p, fa, s);
     else
         dispatch_far<float, 1>(t.p, fa, s);
-    if (nsplit > 1 && m > 0) {
-        hipLaunchKernelGGL(k_far_combine, dim3(nblk(m * K, 256)), dim3(256), 0, s, fpart, nsplit, unear, tperm, m, K,
-                           u_out);
-        STK_CHECK_LAUNCH();
-    }
     prof_mark(STK_PHASE_FAR, s);
+    if (finish) {
+        const ClusterMajor &nc = pl.ncm, &fc = pl.fcm;
+        const int32_t *stoff = sparse_max > 0 ? fc.toff.as<int32_t>() : nullptr;
+        if (t.prec == STK_FP64)
+            hipLaunchKernelGGL(k_finish<double>, dim3(nblk(m * K, 256)), dim3(256), 0, s, nc.part.as<double>(),
+                               nc.toff.as<int32_t>(), sparse_max > 0 ? fc.part.as<double>() : nullptr, stoff, fpart,
+                               nsplit, tperm, m, K, u_out);
+        else
+            hipLaunchKernelGGL(k_finish<float>, dim3(nblk(m * K, 256)), dim3(256), 0, s, nc.part.as<float>(),
+                               nc.toff.as<int32_t>(), sparse_max > 0 ? fc.part.as<float>() : nullptr, stoff, fpart,
+                               nsplit, tperm, m, K, u_out);
+        STK_CHECK_LAUNCH();
+        prof_mark(STK_PHASE_FINISH, s);
+    }
 }
 
 DirectShape direct_shape(int64_t m, int64_t n) {

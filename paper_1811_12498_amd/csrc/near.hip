@@ -684,7 +684,7 @@ void cluster_major(Tree &t, ClusterMajor &cm, const int32_t *off, const int32_t 
     }
 }
 
-void near_field(Tree &t, Plan &pl, double *unear, hipStream_t s) {
+void near_field(Tree &t, Plan &pl, double *unear, hipStream_t s, bool reduce) {
     const int64_t m = pl.m;
     ClusterMajor &cm = pl.ncm;
     cluster_major(t, cm, pl.near_off.as<int32_t>(), pl.near_node.as<int32_t>(), pl.near_mask.as<uint64_t>(),
@@ -714,14 +714,14 @@ void near_field(Tree &t, Plan &pl, double *unear, hipStream_t s) {
             hipLaunchKernelGGL(k_near_reg, dim3(xcd_item_blocks<XCD_CHUNK_NEAR>(na.nitems)), dim3(64), 0, s, na);
             STK_CHECK_LAUNCH();
         }
-        if (mk > 0) {
+        if (reduce && mk > 0) {
             hipLaunchKernelGGL(k_near_reduce<double>, dim3(nblk(mk, 256)), dim3(256), 0, s,
                                static_cast<const double *>(part), toff, m, K, unear);
             STK_CHECK_LAUNCH();
         }
     } else if (t.prec == STK_FP64) {
         launch_near<double, 1>(na, s);
-        if (mk > 0) {
+        if (reduce && mk > 0) {
             hipLaunchKernelGGL(k_near_reduce<double>, dim3(nblk(mk, 256)), dim3(256), 0, s,
                                static_cast<const double *>(part), toff, m, K, unear);
             STK_CHECK_LAUNCH();
@@ -738,7 +738,7 @@ void near_field(Tree &t, Plan &pl, double *unear, hipStream_t s) {
             launch_near<float, 2>(na, s);
         else
             launch_near<float, 1>(na, s);
-        if (mk > 0) {
+        if (reduce && mk > 0) {
             hipLaunchKernelGGL(k_near_reduce<float>, dim3(nblk(mk, 256)), dim3(256), 0, s,
                                static_cast<const float *>(part), toff, m, K, unear);
             STK_CHECK_LAUNCH();

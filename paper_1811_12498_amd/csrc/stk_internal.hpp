@@ -298,13 +298,16 @@ void cluster_major(Tree &t, ClusterMajor &cm, const int32_t *off, const int32_t 
                    int64_t ne, int32_t ng, int64_t m, int max_pc, const int32_t *tcount, hipStream_t s);
 // near field of a plan whose group-major near lists are filled: unear (m,K,3), sorted
 // target order, K = the tree's right-hand sides
-void near_field(Tree &t, Plan &plan, double *unear, hipStream_t s);
+// reduce = false leaves the per-target sums of the partials to a later pass (the partials
+// stay in plan.ncm.part)
+void near_field(Tree &t, Plan &plan, double *unear, hipStream_t s, bool reduce = true);
 // far entries with at most max_pc targets, cluster major: adds their velocities (every
 // right-hand side) to unear (m,K,3); the group-major far kernel then skips entries of at
 // most max_pc targets.  FAR_SPARSE_MAX is the split used by default with one right-hand
 // side; max_pc = 64 takes every far entry.
 constexpr int FAR_SPARSE_MAX = 32;
-void far_sparse(Tree &t, Plan &plan, double *unear, int max_pc, hipStream_t s);
+// add = false leaves the per-target sums to a later pass (the partials stay in plan.fcm.part)
+void far_sparse(Tree &t, Plan &plan, double *unear, int max_pc, hipStream_t s, bool add = true);
 // FP64 direct sum: k_direct sums `chunk` consecutive sources per wave for 64 targets into
 // partial velocities (3 m nch doubles), k_direct_reduce adds them in chunk order; the shape
 // depends only on (m, n)
