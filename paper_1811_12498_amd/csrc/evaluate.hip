@@ -25,7 +25,7 @@ namespace {
 constexpr int STACK = 256;  // >= 1 + 7 * STK_MAX_LEVEL
 // per-group list slots of the one-pass traversal: at least these many entries, at most
 // this many bytes in all (else two passes)
-constexpr int32_t TRAV_SLOT_FAR_MIN = 256, TRAV_SLOT_NEAR_MIN = 64;
+constexpr int32_t TRAV_SLOT_FAR_MIN = 512, TRAV_SLOT_NEAR_MIN = 256;
 constexpr size_t TRAV_SLOT_BYTES_MAX = size_t(2) << 30;
 
 __device__ inline uint64_t rfl64(uint64_t v) {
@@ -485,11 +485,11 @@ void build_lists(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, 
     ta.cnt_near = reserve<int32_t>(pl.cnt_near, size_t(m));
     ta.cnt_pairs = reserve<int32_t>(pl.cnt_pairs, size_t(m));
     // One pass when the per-group slots fit: the traversal counts and writes each group's
-    // entries into slots of the last evaluation's longest list (plus a quarter), which are
-    // then compacted into the scanned lists.  If a group overflowed its slots (or on the
-    // first evaluation at a larger size), a second pass writes the lists at the scanned
-    // offsets, as the two-pass build always does when the slots would not fit.
-    const int32_t sf = std::max(pl.slot_far, TRAV_SLOT_FAR_MIN), sn = std::max(pl.slot_near, TRAV_SLOT_NEAR_MIN);
+    // entries into slots sized from the longest lists of the tree's last evaluation (plus a
+    // quarter; at least 512 far and 256 near entries), which are then compacted into the
+    // scanned lists.  If a group overflowed its slots, a second pass writes the lists at the
+    // scanned offsets, as the two-pass build always does when the slots would not fit.
+    const int32_t sf = std::max(t.slot_far, TRAV_SLOT_FAR_MIN), sn = std::max(t.slot_near, TRAV_SLOT_NEAR_MIN);
     const bool one_pass = ng > 0 && size_t(ng) * size_t(sf + sn) * 12 <= TRAV_SLOT_BYTES_MAX;
     if (one_pass) {
         unsigned char *sb = reserve<unsigned char>(t.s_slot, size_t(ng) * size_t(sf + sn) * 12);
@@ -546,8 +546,8 @@ void build_lists(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, 
         hipLaunchKernelGGL(k_traverse<TRAV_FILL>, dim3(ng), dim3(64), 0, s, ta);
         STK_CHECK_LAUNCH();
     }
-    pl.slot_far = int32_t(std::min<int64_t>(longest[0] + longest[0] / 4 + 1, INT32_MAX / 2));
-    pl.slot_near = int32_t(std::min<int64_t>(longest[1] + longest[1] / 4 + 1, INT32_MAX / 2));
+    t.slot_far = int32_t(std::min<int64_t>(longest[0] + longest[0] / 4 + 1, INT32_MAX / 2));
+    t.slot_near = int32_t(std::min<int64_t>(longest[1] + longest[1] / 4 + 1, INT32_MAX / 2));
 }
 
 void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, double *u_out, bool same_as_sources,

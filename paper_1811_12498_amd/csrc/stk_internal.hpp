@@ -147,6 +147,9 @@ struct Tree {
     DBuf s_keys, s_vals, s_keys2, s_vals2, s_hist, s_tmp;
     DBuf s_scan;                   // tile sums of scan_exclusive_i32
     DBuf s_slot;                   // per-group list slots of the one-pass traversal
+    // their capacity: a quarter above the longest group lists of the last evaluation with
+    // this tree (0: none yet)
+    int32_t slot_far = 0, slot_near = 0;
     DBuf s_bm;                     // operand blocks of the matrix-core far field
     HostPeek peek;                 // host slots for the sizes read back during a build or evaluation
 };
@@ -238,9 +241,7 @@ struct Plan {
     Tiles force;
     AdjScratch adj;
     DBuf far_part;                    // double (parts, K, m, 3): sums of the split group-major far field
-    // slot capacity of the one-pass traversal: a quarter above the longest group lists of
-    // the last evaluation (0: not yet known)
-    int32_t slot_far = 0, slot_near = 0;
+
     ~Plan();
 };
 

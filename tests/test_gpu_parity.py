@@ -163,14 +163,14 @@ def test_interaction_lists_match_oracle(nat, orc, kind, n, seed, n0, p, theta, h
 
 
 def test_list_build_one_pass_and_second_pass(nat, orc):
-    """The lists are written in one traversal into per-group slots sized from the plan's
+    """The lists are written in one traversal into per-group slots sized from the tree's
     previous evaluation (a quarter above its longest group lists), then compacted; a group
-    whose lists outgrow their slots (a fresh plan starts at 256 far and 64 near entries)
+    whose lists outgrow their slots (a fresh tree starts at 512 far and 256 near entries)
     makes the build fall back to a second traversal at the scanned offsets.  N = 20,000 in
-    the unit cube, N0 = 16, theta = 0.35: the longest group lists (1464 far, 139 near
-    entries, from the oracle's per-target lists) exceed a fresh plan's slots, so its first
-    evaluation takes the second pass and its next one the slots.  Both give every target's
-    far clusters and near leaves of Algorithm 1."""
+    the unit cube, N0 = 16, theta = 0.35: the longest group far list (1464 entries, from the
+    oracle's per-target lists) exceeds a fresh tree's slots, so a fresh plan's first
+    evaluation takes the second pass and the same plan's next one the slots.  Both give
+    every target's far clusters and near leaves of Algorithm 1."""
     w = W.cube(20_000, seed=12, n0=16)
     theta, p, n0 = 0.35, 2, 16
     T = orc.build_tree(w.src, n0)
@@ -179,11 +179,10 @@ def test_list_build_one_pass_and_second_pass(nat, orc):
     nat.plan_cache_clear()
     for call in range(2):
         _, plan = nat.evaluate(X, X, _t(w.f[0]), _t(w.h[0]), _t(w.nu), p, theta, n0, "fp64", keep_plan=True)
-        for kind_, ptr, nodes, first_slots in (("far", L.far_ptr, L.far_nodes, 256),
-                                               ("near", L.near_ptr, L.near_nodes, 64)):
+        for kind_, ptr, nodes in (("far", L.far_ptr, L.far_nodes), ("near", L.near_ptr, L.near_nodes)):
             lists = nat.plan_lists(plan, kind_)
-            if call == 0:
-                assert np.diff(lists["off"]).max() > first_slots, kind_
+            if call == 0 and kind_ == "far":
+                assert np.diff(lists["off"]).max() > 512
             t_gpu, n_gpu = _per_target(lists, w.n)
             t_ref = np.repeat(np.arange(w.n), np.diff(ptr))
             n_ref = nodes[: int(ptr[-1])]
