@@ -55,15 +55,17 @@ void check_common(const double *pts, int64_t n, const char *what) {
     stk::require(n < (int64_t(1) << 31) / 8, std::string(what) + ": count too large (int32 indexing)");
 }
 
-// A second stream per device, on which stk_evaluate computes the moments while the caller's
-// stream sorts the targets and builds the interaction lists (default priority; created on
-// first use, kept until the process exits).
-hipStream_t side_stream(int dev) {
+// Two more streams per device (default priority; created on first use, kept until the
+// process exits): on the first stk_evaluate computes the moments while the caller's stream
+// sorts the targets and builds the interaction lists, on the second it builds the sparse
+// far entries' cluster-major view while the caller's stream builds the near field's.
+hipStream_t side_stream(int dev, int which = 0) {
     static std::mutex mu;
     static std::vector<hipStream_t> *streams = new std::vector<hipStream_t>();
     std::lock_guard<std::mutex> lk(mu);
-    if (size_t(dev) >= streams->size()) streams->resize(size_t(dev) + 1, nullptr);
-    hipStream_t &sd = (*streams)[size_t(dev)];
+    const size_t k = 2 * size_t(dev) + size_t(which);
+    if (k >= streams->size()) streams->resize(k + 1, nullptr);
+    hipStream_t &sd = (*streams)[k];
     if (!sd) STK_HIP(hipStreamCreateWithFlags(&sd, hipStreamNonBlocking));
     return sd;
 }
@@ -85,14 +87,18 @@ void tree_moments_evaluate(stk::Tree &tree, stk::Plan &pl, const double *targets
         STK_HIP(hipEventRecord(ev[2], s2));
         pl.records_ready = ev[1];
         pl.moments_ready = ev[2];
+        pl.aux = side_stream(tree.device, 1);
         stk::evaluate(tree, pl, targets, m, theta, u_out, same, s);
     } catch (...) {
         pl.records_ready = pl.moments_ready = nullptr;
         (void)hipStreamSynchronize(s2);
+        if (pl.aux) (void)hipStreamSynchronize(pl.aux);
+        pl.aux = nullptr;
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
         throw;
     }
     pl.records_ready = pl.moments_ready = nullptr;
+    pl.aux = nullptr;
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
 }
 

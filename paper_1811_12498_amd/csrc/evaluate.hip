@@ -406,12 +406,30 @@ void dispatch_far_mfma(int p, const FarArgs &a, DBuf &bm, int32_t nn, hipStream_
 
 }  // namespace
 
+namespace {
+CmInput far_cm_input(Plan &pl, int max_pc) {
+    return CmInput{pl.far_off.as<int32_t>(), pl.far_node.as<int32_t>(), pl.far_mask.as<uint64_t>(), pl.n_far_entries,
+                   pl.ngroups, pl.m, max_pc, max_pc >= 64 ? pl.cnt_far.as<int32_t>() : nullptr};
+}
+CmInput near_cm_input(Plan &pl) {
+    return CmInput{pl.near_off.as<int32_t>(), pl.near_node.as<int32_t>(), pl.near_mask.as<uint64_t>(),
+                   pl.n_near_entries, pl.ngroups, pl.m, 64, pl.cnt_near.as<int32_t>()};
+}
+}  // namespace
+
 void far_sparse(Tree &t, Plan &pl, double *unear, int max_pc, hipStream_t s, bool add) {
+    const CmInput in = far_cm_input(pl, max_pc);
+    cm_stage1(t, pl.fcm, in, s);
+    cm_stage2(t, pl.fcm, in, s);
+    cm_stage3(t, pl.fcm, in, s);
+    far_sparse_run(t, pl, unear, max_pc, s, add);
+}
+
+void far_sparse_run(Tree &t, Plan &pl, double *unear, int max_pc, hipStream_t s, bool add) {
+    (void)max_pc;
     const int64_t m = pl.m;
     const int K = t.k_rhs;
     ClusterMajor &cm = pl.fcm;
-    cluster_major(t, cm, pl.far_off.as<int32_t>(), pl.far_node.as<int32_t>(), pl.far_mask.as<uint64_t>(),
-                  pl.n_far_entries, pl.ngroups, m, max_pc, max_pc >= 64 ? pl.cnt_far.as<int32_t>() : nullptr, s);
     const size_t tsz = t.prec == STK_FP64 ? sizeof(double) : sizeof(float);
     void *part = reserve<unsigned char>(cm.part, tsz * 3 * size_t(K) * size_t(cm.n_inc) + tsz);
     FarSparseArgs sa{pl.tpos_p, cm.item_node.as<int32_t>(), cm.item_i0.as<int32_t>(),
@@ -439,6 +457,8 @@ void far_sparse(Tree &t, Plan &pl, double *unear, int max_pc, hipStream_t s, boo
 }
 
 Plan::~Plan() {
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
     if (owns_tree) delete tree;
 }
 
@@ -594,16 +614,42 @@ void evaluate(Tree &t, Plan &pl, const double *tgt, int64_t m, double theta, dou
     // partials added to it, and the far kernel adds it
     const bool finish = nsplit > 1 && m > 0;
 
-    // near field (its leaf-major lists close the lists phase), then far field
+    // The near field's leaf-major view and the sparse far entries' cluster-major view (each
+    // a chain of small sorts and scans with host readbacks between them, and each with its
+    // own scratch): on two streams when the plan names a second one, their stages
+    // interleaved so that one view's kernels run while the host waits for the other's
+    // readback.  Then the near field, then the far field.
     double *unear = reserve<double>(t.s_tmp, size_t(m) * K * 3);
-    near_field(t, pl, unear, s, !finish);
+    const bool two = sparse_max > 0 && pl.aux && pl.aux != s;
+    hipStream_t s3 = two ? pl.aux : s;
+    if (two) {
+        for (hipEvent_t &e : pl.ev)
+            if (!e) STK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        STK_HIP(hipEventRecord(pl.ev[0], s));  // the lists
+        STK_HIP(hipStreamWaitEvent(s3, pl.ev[0], 0));
+    }
+    const CmInput nin = near_cm_input(pl), fin = far_cm_input(pl, sparse_max);
+    cm_stage1(t, pl.ncm, nin, s);
+    if (sparse_max > 0) cm_stage1(t, pl.fcm, fin, s3);
+    cm_stage2(t, pl.ncm, nin, s);
+    if (sparse_max > 0) cm_stage2(t, pl.fcm, fin, s3);
+    cm_stage3(t, pl.ncm, nin, s);
+    prof_mark(STK_PHASE_LISTS, s);
+    if (sparse_max > 0) {
+        cm_stage3(t, pl.fcm, fin, s3);
+        if (two) STK_HIP(hipEventRecord(pl.ev[1], s3));  // the sparse far entries' view
+    }
+    near_kernels(t, pl, unear, s, !finish);
     // moments computed beside the lists and the near field (on another stream) must be
     // complete from here on: the far kernels read the clusters' streams
     if (pl.moments_ready) {
         STK_HIP(hipStreamWaitEvent(s, pl.moments_ready, 0));
         pl.moments_ready = nullptr;
     }
-    if (sparse_max > 0) far_sparse(t, pl, unear, sparse_max, s, !finish);
+    if (sparse_max > 0) {
+        if (two) STK_HIP(hipStreamWaitEvent(s, pl.ev[1], 0));
+        far_sparse_run(t, pl, unear, sparse_max, s, !finish);
+    }
     double *fpart = nsplit > 1 ? reserve<double>(pl.far_part, size_t(nsplit) * K * size_t(m) * 3) : nullptr;
     FarArgs fa{tpos, m, foff, pl.far_node.as<int32_t>(), pl.far_mask.as<uint64_t>(), t.ncenter.as<double>(),
                t.nrho.as<double>(), t.wblk.p, unear, tperm, u_out, ng, K, sparse_max, nsplit, fpart};

@@ -604,49 +604,86 @@ template <typename T, int KB> void launch_near(const NearArgs &na, hipStream_t s
 
 void cluster_major(Tree &t, ClusterMajor &cm, const int32_t *off, const int32_t *node, const uint64_t *mask,
                    int64_t ne, int32_t ng, int64_t m, int max_pc, const int32_t *tcount, hipStream_t s) {
-    const int32_t nn = int32_t(t.nnodes);
-    // kept entries sorted by node (stable: group order within a node), the others last
-    uint64_t *keys = reserve<uint64_t>(cm.keys, size_t(ne) + 1);
-    int32_t *ent = reserve<int32_t>(cm.ent, size_t(ne) + 1);
-    int32_t *pc = reserve<int32_t>(cm.pc, size_t(ne) + 1);
-    int32_t *pos = reserve<int32_t>(cm.pos, size_t(ne) + 1);
-    int32_t *incoff = reserve<int32_t>(cm.incoff, size_t(ne) + 1);
+    const CmInput in{off, node, mask, ne, ng, m, max_pc, tcount};
+    cm_stage1(t, cm, in, s);
+    cm_stage2(t, cm, in, s);
+    cm_stage3(t, cm, in, s);
+}
+
+namespace {
+int cm_key_bits(int32_t nn) {
     int bits = 1;
     while ((int64_t(1) << bits) <= int64_t(nn)) ++bits;
-    int64_t nk = ne;  // entries in the sorted array
-    if (ne > 0 && max_pc < 64) {
+    return bits;
+}
+}  // namespace
+
+// stage 1: the sort keys of the kept entries (node, entry); when few are kept (max_pc < 64)
+// they are compacted first and their number is requested
+void cm_stage1(Tree &t, ClusterMajor &cm, const CmInput &in, hipStream_t s) {
+    const int32_t nn = int32_t(t.nnodes);
+    const int64_t ne = in.ne;
+    uint64_t *keys = reserve<uint64_t>(cm.keys, size_t(ne) + 1);
+    int32_t *ent = reserve<int32_t>(cm.ent, size_t(ne) + 1);
+    reserve<int32_t>(cm.pc, size_t(ne) + 1);
+    reserve<int32_t>(cm.pos, size_t(ne) + 1);
+    reserve<int32_t>(cm.incoff, size_t(ne) + 1);
+    cm.nk = ne;
+    cm.nk_pending = false;
+    if (ne > 0 && in.max_pc < 64) {
         // few entries kept: compact them, then sort only those
-        int32_t *flag = reserve<int32_t>(cm.pc, size_t(ne) + 1);
-        int32_t *fpos = reserve<int32_t>(cm.incoff, size_t(ne) + 1);
-        hipLaunchKernelGGL(k_cm_flag, dim3(nblk(ne, 256)), dim3(256), 0, s, mask, ne, max_pc, flag);
+        int32_t *flag = cm.pc.as<int32_t>();
+        int32_t *fpos = cm.incoff.as<int32_t>();
+        hipLaunchKernelGGL(k_cm_flag, dim3(nblk(ne, 256)), dim3(256), 0, s, in.mask, ne, in.max_pc, flag);
         STK_CHECK_LAUNCH();
-        scan_exclusive_i32(flag, fpos, ne, t.s_scan, s);
-        hipLaunchKernelGGL(k_cm_compact, dim3(nblk(ne, 256)), dim3(256), 0, s, node, mask, ne, max_pc, fpos, keys, ent);
+        scan_exclusive_i32(flag, fpos, ne, cm.s_scan, s);
+        hipLaunchKernelGGL(k_cm_compact, dim3(nblk(ne, 256)), dim3(256), 0, s, in.node, in.mask, ne, in.max_pc, fpos,
+                           keys, ent);
         STK_CHECK_LAUNCH();
         const PeekSrc src{fpos + ne, 4};
-        peek(t.peek, s, 1, &src, &nk);
-        radix_sort_pairs(t, keys, ent, nk, bits, s);
+        peek_start(cm.peek, s, 1, &src);
+        cm.nk_pending = true;
     } else if (ne > 0) {
-        hipLaunchKernelGGL(k_cm_keys, dim3(nblk(ne, 256)), dim3(256), 0, s, node, mask, ne, nn, max_pc, keys, ent);
+        hipLaunchKernelGGL(k_cm_keys, dim3(nblk(ne, 256)), dim3(256), 0, s, in.node, in.mask, ne, nn, in.max_pc, keys,
+                           ent);
         STK_CHECK_LAUNCH();
-        radix_sort_pairs(t, keys, ent, ne, bits, s);
     }
+}
+
+// stage 2: the sort, each sorted entry's incidences, per-target and per-node offsets; the
+// totals are requested
+void cm_stage2(Tree &t, ClusterMajor &cm, const CmInput &in, hipStream_t s) {
+    const int32_t nn = int32_t(t.nnodes);
+    const int64_t m = in.m;
+    if (cm.nk_pending) {
+        peek_wait(cm.peek, s, 1, &cm.nk);
+        cm.nk_pending = false;
+    }
+    const int64_t nk = cm.nk;
+    uint64_t *keys = cm.keys.as<uint64_t>();
+    int32_t *ent = cm.ent.as<int32_t>();
+    int32_t *pc = cm.pc.as<int32_t>();
+    int32_t *pos = cm.pos.as<int32_t>();
+    int32_t *incoff = cm.incoff.as<int32_t>();
+    // kept entries sorted by node (stable: group order within a node), the others last
+    radix_sort_pairs(cm.s_keys2, cm.s_vals2, cm.s_hist, keys, ent, nk, cm_key_bits(nn), s);
     if (nk > 0) {
-        hipLaunchKernelGGL(k_cm_pos, dim3(nblk(nk, 256)), dim3(256), 0, s, ent, mask, nk, max_pc, pc, pos);
+        hipLaunchKernelGGL(k_cm_pos, dim3(nblk(nk, 256)), dim3(256), 0, s, ent, in.mask, nk, in.max_pc, pc, pos);
         STK_CHECK_LAUNCH();
     }
-    scan_exclusive_i32(pc, incoff, nk, t.s_scan, s);
+    scan_exclusive_i32(pc, incoff, nk, cm.s_scan, s);
     // per target: first slot (exclusive scan of its kept-entry count, sorted order)
+    const int32_t *tcount = in.tcount;
     if (!tcount) {
         int32_t *tc = reserve<int32_t>(cm.tcnt, size_t(m) + 1);
-        if (ng > 0) {
-            hipLaunchKernelGGL(k_cm_tcount, dim3(ng), dim3(64), 0, s, off, mask, m, max_pc, tc);
+        if (in.ng > 0) {
+            hipLaunchKernelGGL(k_cm_tcount, dim3(in.ng), dim3(64), 0, s, in.off, in.mask, m, in.max_pc, tc);
             STK_CHECK_LAUNCH();
         }
         tcount = tc;
     }
     int32_t *toff = reserve<int32_t>(cm.toff, size_t(m) + 1);
-    scan_exclusive_i32(tcount, toff, m, t.s_scan, s);
+    scan_exclusive_i32(tcount, toff, m, cm.s_scan, s);
     // per node: entry range, incidence range, items of up to 64 incidences
     int32_t *eoff = reserve<int32_t>(cm.eoff, size_t(nn) + 1);
     int32_t *loff = reserve<int32_t>(cm.loff, size_t(nn) + 1);
@@ -658,38 +695,46 @@ void cluster_major(Tree &t, ClusterMajor &cm, const int32_t *off, const int32_t 
     STK_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_item_count, dim3(nblk(nn, 256)), dim3(256), 0, s, loff, nn, 64, icnt);
     STK_CHECK_LAUNCH();
-    scan_exclusive_i32(icnt, ioff, nn, t.s_scan, s);
+    scan_exclusive_i32(icnt, ioff, nn, cm.s_scan, s);
+    const PeekSrc src[3] = {{incoff + nk, 4}, {ioff + nn, 4}, {toff + m, 4}};
+    peek_start(cm.peek, s, 3, src);
+}
+
+// stage 3: the totals; the incidence and item arrays
+void cm_stage3(Tree &t, ClusterMajor &cm, const CmInput &in, hipStream_t s) {
+    const int32_t nn = int32_t(t.nnodes);
     int64_t tot[3];
-    {
-        const PeekSrc src[3] = {{incoff + nk, 4}, {ioff + nn, 4}, {toff + m, 4}};
-        peek(t.peek, s, 3, src, tot);
-    }
+    peek_wait(cm.peek, s, 3, tot);
     if (tot[0] != tot[2]) throw Error(STK_EDEVICE, "lists: incidence count differs from the per-target counts");
     cm.n_inc = tot[0];
-    cm.n_items = tot[1];
+    cm.n_items = int32_t(tot[1]);
     int32_t *inc_tgt = reserve<int32_t>(cm.inc_tgt, size_t(cm.n_inc) + 1);
     int32_t *inc_slot = reserve<int32_t>(cm.inc_slot, size_t(cm.n_inc) + 1);
     int32_t *inode = reserve<int32_t>(cm.item_node, size_t(cm.n_items) + 1);
     int32_t *i0 = reserve<int32_t>(cm.item_i0, size_t(cm.n_items) + 1);
     int32_t *i1 = reserve<int32_t>(cm.item_i1, size_t(cm.n_items) + 1);
     if (cm.n_items > 0) {
-        hipLaunchKernelGGL(k_item_fill, dim3(nblk(cm.n_items, 256)), dim3(256), 0, s, loff, ioff, nn, 64, cm.n_items,
-                           inode, i0, i1);
+        hipLaunchKernelGGL(k_item_fill, dim3(nblk(cm.n_items, 256)), dim3(256), 0, s, cm.loff.as<int32_t>(),
+                           cm.ioff.as<int32_t>(), nn, 64, cm.n_items, inode, i0, i1);
         STK_CHECK_LAUNCH();
     }
-    if (ng > 0) {
-        hipLaunchKernelGGL(k_cm_fill, dim3(ng), dim3(64), 0, s, off, mask, max_pc, pos, incoff, toff, m, inc_tgt,
-                           inc_slot);
+    if (in.ng > 0) {
+        hipLaunchKernelGGL(k_cm_fill, dim3(in.ng), dim3(64), 0, s, in.off, in.mask, in.max_pc, cm.pos.as<int32_t>(),
+                           cm.incoff.as<int32_t>(), cm.toff.as<int32_t>(), in.m, inc_tgt, inc_slot);
         STK_CHECK_LAUNCH();
     }
 }
 
 void near_field(Tree &t, Plan &pl, double *unear, hipStream_t s, bool reduce) {
+    cluster_major(t, pl.ncm, pl.near_off.as<int32_t>(), pl.near_node.as<int32_t>(), pl.near_mask.as<uint64_t>(),
+                  pl.n_near_entries, pl.ngroups, pl.m, 64, pl.cnt_near.as<int32_t>(), s);
+    prof_mark(STK_PHASE_LISTS, s);
+    near_kernels(t, pl, unear, s, reduce);
+}
+
+void near_kernels(Tree &t, Plan &pl, double *unear, hipStream_t s, bool reduce) {
     const int64_t m = pl.m;
     ClusterMajor &cm = pl.ncm;
-    cluster_major(t, cm, pl.near_off.as<int32_t>(), pl.near_node.as<int32_t>(), pl.near_mask.as<uint64_t>(),
-                  pl.n_near_entries, pl.ngroups, m, 64, pl.cnt_near.as<int32_t>(), s);
-    prof_mark(STK_PHASE_LISTS, s);
     // source records computed beside the lists (on another stream) must be complete from
     // here on
     if (pl.records_ready) {

@@ -347,6 +347,11 @@ void peek_wait(HostPeek &pk, hipStream_t s, int n, int64_t *out) {
 }
 
 void peek(HostPeek &pk, hipStream_t s, int n, const PeekSrc *src, int64_t *out) {
+    peek_start(pk, s, n, src);
+    peek_wait(pk, s, n, out);
+}
+
+void peek_start(HostPeek &pk, hipStream_t s, int n, const PeekSrc *src) {
     if (n < 1 || n > PEEK_MAX) throw Error(STK_EINVAL, "peek: 1 to PEEK_MAX values");
     peek_slots(pk);
     PeekArgs a{};
@@ -358,7 +363,6 @@ void peek(HostPeek &pk, hipStream_t s, int n, const PeekSrc *src, int64_t *out) 
     }
     hipLaunchKernelGGL(k_peek, dim3(1), dim3(64), 0, s, a, pk.d);
     STK_CHECK_LAUNCH();
-    peek_wait(pk, s, n, out);
 }
 
 void scan2_stats(const int32_t *a, int32_t *oa, const int32_t *b, int32_t *ob, const int32_t *c, const int32_t *d,
@@ -375,12 +379,17 @@ void scan2_stats(const int32_t *a, int32_t *oa, const int32_t *b, int32_t *ob, c
 }
 
 void radix_sort_pairs(Tree &t, uint64_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t s) {
+    radix_sort_pairs(t.s_keys2, t.s_vals2, t.s_hist, keys, vals, n, bits, s);
+}
+
+void radix_sort_pairs(DBuf &keys2, DBuf &vals2, DBuf &hbuf, uint64_t *keys, int32_t *vals, int64_t n, int bits,
+                      hipStream_t s) {
     if (n <= 1) return;
     const int32_t ntiles = int32_t((n + TILE - 1) / TILE);
-    uint64_t *k2 = reserve<uint64_t>(t.s_keys2, size_t(n));
-    int32_t *v2 = reserve<int32_t>(t.s_vals2, size_t(n));
+    uint64_t *k2 = reserve<uint64_t>(keys2, size_t(n));
+    int32_t *v2 = reserve<int32_t>(vals2, size_t(n));
     const int64_t hn = int64_t(RADIX) * ntiles;
-    int32_t *hist = reserve<int32_t>(t.s_hist, size_t(hn + RADIX));
+    int32_t *hist = reserve<int32_t>(hbuf, size_t(hn + RADIX));
     int32_t *dbase = hist + hn;
     uint64_t *ka = keys, *kb = k2;
     int32_t *va = vals, *vb = v2;

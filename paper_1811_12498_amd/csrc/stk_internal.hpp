@@ -85,8 +85,9 @@ struct PeekSrc {
     int bytes;      // 4: int32 (sign-extended); 8: int64 or double (raw bits)
 };
 // Enqueue the copy of src[0..n) (1 <= n <= PEEK_MAX) on s, synchronise s, and return the
-// values in out[0..n).
+// values in out[0..n).  peek_start only enqueues the copy (peek_wait completes it).
 void peek(HostPeek &pk, hipStream_t s, int n, const PeekSrc *src, int64_t *out);
+void peek_start(HostPeek &pk, hipStream_t s, int n, const PeekSrc *src);
 // The slots as the device sees them (allocated if needed), for a kernel that writes its
 // results there itself; peek_wait then synchronises s and returns slots [0, n).
 int64_t *peek_slots(HostPeek &pk);
@@ -179,6 +180,12 @@ struct ClusterMajor {
     DBuf part;                     // T (incidences, K, 3): per-incidence partial velocities
     int64_t n_inc = 0;
     int32_t n_items = 0;
+    // the build's own sort and scan scratch and readback slots, so that two views can be
+    // built at once on two streams; nk = entries in the sorted array
+    DBuf s_keys2, s_vals2, s_hist, s_scan;
+    HostPeek peek;
+    int64_t nk = 0;
+    bool nk_pending = false;
 };
 
 // scratch of the adjoint, kept with the plan for repeated backward calls
@@ -237,6 +244,10 @@ struct Plan {
     // before the near field (which reads the source records) and on moments_ready before
     // the far field (which reads the clusters' streams)
     hipEvent_t records_ready = nullptr, moments_ready = nullptr;
+    // if set, a stream on which the evaluation builds the sparse far entries' view while
+    // its own stream builds the near field's; ev: the events that order the two
+    hipStream_t aux = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
     double reg_eps = -1.0;            // >= 0: the last evaluation used the regularized kernels with this eps
     Tiles force;
     AdjScratch adj;
@@ -254,6 +265,9 @@ constexpr int CHUNK = 512;   // particles per reduction work item
 // radix sort of (uint64 key, int32 value) pairs; sorts keys[0..n) in place using
 // scratch buffers owned by `t`.  Stable.  `bits` = number of low key bits to sort.
 void radix_sort_pairs(Tree &t, uint64_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t s);
+// the same with explicit scratch (keys2: n uint64, vals2: n int32, hist: the tile histograms)
+void radix_sort_pairs(DBuf &keys2, DBuf &vals2, DBuf &hist, uint64_t *keys, int32_t *vals, int64_t n, int bits,
+                      hipStream_t s);
 // exclusive scan of int32 in[0..n) into out[0..n]; out[n] = total.  Long inputs use
 // `scratch` for per-tile sums (in and out must not overlap).
 void scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, DBuf &scratch, hipStream_t s);
@@ -294,21 +308,40 @@ Tiles autotune(int p, int K, stk_precision prec, int64_t n, double theta, int32_
 
 // Build cm from group-major lists (off: ngroups + 1 offsets, node/mask: ne entries), keeping
 // the entries whose lane mask has at most max_pc bits (64: all).  tcount: per-target number
-// of kept entries if known (sorted order), else NULL (counted here).  Synchronises s once.
+// of kept entries if known (sorted order), else NULL (counted here).  Synchronises s once
+// or twice.  The build in three stages, each ending at (the request of) a host readback, so
+// that a caller can interleave two builds on two streams: cm_stage1, cm_stage2, cm_stage3
+// with the same arguments, in order.
+struct CmInput {
+    const int32_t *off, *node;
+    const uint64_t *mask;
+    int64_t ne;
+    int32_t ng;
+    int64_t m;
+    int max_pc;
+    const int32_t *tcount;
+};
 void cluster_major(Tree &t, ClusterMajor &cm, const int32_t *off, const int32_t *node, const uint64_t *mask,
                    int64_t ne, int32_t ng, int64_t m, int max_pc, const int32_t *tcount, hipStream_t s);
+void cm_stage1(Tree &t, ClusterMajor &cm, const CmInput &in, hipStream_t s);
+void cm_stage2(Tree &t, ClusterMajor &cm, const CmInput &in, hipStream_t s);
+void cm_stage3(Tree &t, ClusterMajor &cm, const CmInput &in, hipStream_t s);
 // near field of a plan whose group-major near lists are filled: unear (m,K,3), sorted
 // target order, K = the tree's right-hand sides
 // reduce = false leaves the per-target sums of the partials to a later pass (the partials
-// stay in plan.ncm.part)
+// stay in plan.ncm.part).  near_field = the leaf-major view (cluster_major of the near lists)
+// then near_kernels.
 void near_field(Tree &t, Plan &plan, double *unear, hipStream_t s, bool reduce = true);
+void near_kernels(Tree &t, Plan &plan, double *unear, hipStream_t s, bool reduce);
 // far entries with at most max_pc targets, cluster major: adds their velocities (every
 // right-hand side) to unear (m,K,3); the group-major far kernel then skips entries of at
 // most max_pc targets.  FAR_SPARSE_MAX is the split used by default with one right-hand
 // side; max_pc = 64 takes every far entry.
 constexpr int FAR_SPARSE_MAX = 32;
-// add = false leaves the per-target sums to a later pass (the partials stay in plan.fcm.part)
+// add = false leaves the per-target sums to a later pass (the partials stay in plan.fcm.part).
+// far_sparse_run: the kernels on a view plan.fcm already built.
 void far_sparse(Tree &t, Plan &plan, double *unear, int max_pc, hipStream_t s, bool add = true);
+void far_sparse_run(Tree &t, Plan &plan, double *unear, int max_pc, hipStream_t s, bool add);
 // FP64 direct sum: k_direct sums `chunk` consecutive sources per wave for 64 targets into
 // partial velocities (3 m nch doubles), k_direct_reduce adds them in chunk order; the shape
 // depends only on (m, n)
