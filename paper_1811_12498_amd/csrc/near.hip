@@ -239,12 +239,29 @@ __global__ __launch_bounds__(64) void k_cm_tcount(const int32_t *__restrict__ of
     if (t < m) tcnt[t] = c;
 }
 
-// loff[c] = first incidence of node c, c in [0, nn]
-__global__ void k_cm_loff(const int32_t *__restrict__ eoff, const int32_t *__restrict__ incoff, int32_t nn,
-                          int32_t *__restrict__ loff) {
+// per node c in [0, nn]: its first sorted entry eoff[c] (the first key >= c) and first
+// incidence loff[c]; for c < nn also its number of items of up to `per` incidences
+__global__ void k_cm_nodes(const uint64_t *__restrict__ keys, int64_t nk, int32_t nn,
+                           const int32_t *__restrict__ incoff, int32_t per, int32_t *__restrict__ eoff,
+                           int32_t *__restrict__ loff, int32_t *__restrict__ icnt) {
     const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c > nn) return;
-    loff[c] = incoff[eoff[c]];
+    auto first = [&](int32_t v) {
+        int64_t lo = 0, hi = nk;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (keys[mid] < uint64_t(v))
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        return lo;
+    };
+    const int64_t e0 = first(c);
+    const int32_t l0 = incoff[e0];
+    eoff[c] = int32_t(e0);
+    loff[c] = l0;
+    if (c < nn) icnt[c] = (incoff[first(c + 1)] - l0 + per - 1) / per;
 }
 
 // one wave per group: lane l walks the group's kept entries that include its target, in
@@ -689,11 +706,8 @@ void cm_stage2(Tree &t, ClusterMajor &cm, const CmInput &in, hipStream_t s) {
     int32_t *loff = reserve<int32_t>(cm.loff, size_t(nn) + 1);
     int32_t *icnt = reserve<int32_t>(cm.icnt, size_t(nn) + 1);
     int32_t *ioff = reserve<int32_t>(cm.ioff, size_t(nn) + 1);
-    hipLaunchKernelGGL(k_node_off, dim3(nblk(int64_t(nn) + 1, 256)), dim3(256), 0, s, keys, nk, nn, eoff);
-    STK_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_cm_loff, dim3(nblk(int64_t(nn) + 1, 256)), dim3(256), 0, s, eoff, incoff, nn, loff);
-    STK_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_item_count, dim3(nblk(nn, 256)), dim3(256), 0, s, loff, nn, 64, icnt);
+    hipLaunchKernelGGL(k_cm_nodes, dim3(nblk(int64_t(nn) + 1, 256)), dim3(256), 0, s, keys, nk, nn, incoff, 64, eoff,
+                       loff, icnt);
     STK_CHECK_LAUNCH();
     scan_exclusive_i32(icnt, ioff, nn, cm.s_scan, s);
     const PeekSrc src[3] = {{incoff + nk, 4}, {ioff + nn, 4}, {toff + m, 4}};

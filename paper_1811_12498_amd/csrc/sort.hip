@@ -1,11 +1,11 @@
 // Stable LSD radix sort of (uint64 key, int32 value) pairs and a single-block scan.
 //
 // Each pass handles 8 key bits: (1) per-tile digit histograms, (2) an exclusive scan of
-// each digit's row of tile counts plus a scan of the digit totals, (3) a stable scatter
-// in which every tile ranks its keys round by round (256 keys per round, wave64 ballots
-// find the lanes sharing a digit, wave counts are combined in LDS in wave order), lays
-// the tile out in digit order in LDS and writes each digit's run contiguously.  Ties keep
-// their input order, so sorting (key, index) pairs yields the order of a
+// each digit's row of tile counts, (3) a stable scatter in which every tile first scans the
+// 256 digit totals itself, then ranks its keys round by round (256 keys per round, wave64
+// ballots find the lanes sharing a digit, wave counts are combined in LDS in wave order),
+// lays the tile out in digit order in LDS and writes each digit's run contiguously.  Ties
+// keep their input order, so sorting (key, index) pairs yields the order of a
 // lexicographic (key, index) sort.
 #include "stk_internal.hpp"
 
@@ -56,7 +56,7 @@ __device__ inline int32_t block_excl_radix(int32_t v, int32_t *ws) {
 __global__ __launch_bounds__(ST) void k_scatter(const uint64_t *__restrict__ kin, const int32_t *__restrict__ vin,
                                                 uint64_t *__restrict__ kout, int32_t *__restrict__ vout, int64_t n,
                                                 int shift, const int32_t *__restrict__ off, int32_t ntiles,
-                                                const int32_t *__restrict__ dbase) {
+                                                const int32_t *__restrict__ dtot) {
     static_assert(RADIX == ST, "one thread per digit");
     __shared__ uint64_t lk[TILE];
     __shared__ int32_t lv[TILE];
@@ -64,23 +64,21 @@ __global__ __launch_bounds__(ST) void k_scatter(const uint64_t *__restrict__ kin
     __shared__ int32_t tstart[RADIX];  // start of each digit's run within the tile
     __shared__ int32_t run[RADIX];     // keys of each digit placed so far
     __shared__ int32_t wcnt[NWAVE][RADIX];
-    __shared__ int32_t ws[NWAVE];
+    __shared__ int32_t ws[NWAVE], ws2[NWAVE];
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
     const int32_t tile = blockIdx.x;
     const int64_t tbase = int64_t(tile) * TILE;
     const int32_t tn = int32_t(n - tbase < TILE ? n - tbase : TILE);
-    // this tile's count of digit tid: the difference of the scanned histogram row, the
-    // last tile against the digit's total
+    // digit tid: its total over all tiles, their exclusive scan (every block scans the 256
+    // totals itself), and this tile's count, the difference of the scanned histogram row
+    // (the last tile against the digit's total)
+    const int32_t total_d = dtot[tid];
+    const int32_t dbase = block_excl_radix(total_d, ws2);
     const int32_t o = off[int64_t(tid) * ntiles + tile];
-    int32_t total_d;
-    if (tid + 1 < RADIX)
-        total_d = dbase[tid + 1] - dbase[tid];
-    else
-        total_d = int32_t(n) - dbase[tid];
     const int32_t cnt = (tile + 1 < ntiles ? off[int64_t(tid) * ntiles + tile + 1] : total_d) - o;
-    gbase[tid] = dbase[tid] + o;
+    gbase[tid] = dbase + o;
     tstart[tid] = block_excl_radix(cnt, ws);
     run[tid] = 0;
     for (int w = 0; w < NWAVE; ++w) wcnt[w][tid] = 0;
@@ -274,23 +272,6 @@ __global__ __launch_bounds__(256) void k_scan_rows(int32_t *__restrict__ hist, i
     if (threadIdx.x == 0) tot[blockIdx.x] = t;
 }
 
-// exclusive scan of the RADIX row totals, added to every row
-__global__ __launch_bounds__(RADIX) void k_scan_digits(int32_t *__restrict__ tot) {
-    __shared__ int32_t s[RADIX];
-    s[threadIdx.x] = tot[threadIdx.x];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int32_t run = 0;
-        for (int d = 0; d < RADIX; ++d) {
-            const int32_t t = s[d];
-            s[d] = run;
-            run += t;
-        }
-    }
-    __syncthreads();
-    tot[threadIdx.x] = s[threadIdx.x];
-}
-
 }  // namespace
 
 void scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, DBuf &scratch, hipStream_t s) {
@@ -390,7 +371,7 @@ void radix_sort_pairs(DBuf &keys2, DBuf &vals2, DBuf &hbuf, uint64_t *keys, int3
     int32_t *v2 = reserve<int32_t>(vals2, size_t(n));
     const int64_t hn = int64_t(RADIX) * ntiles;
     int32_t *hist = reserve<int32_t>(hbuf, size_t(hn + RADIX));
-    int32_t *dbase = hist + hn;
+    int32_t *dtot = hist + hn;  // the digits' totals
     uint64_t *ka = keys, *kb = k2;
     int32_t *va = vals, *vb = v2;
     const int passes = (bits + RB - 1) / RB;
@@ -398,11 +379,9 @@ void radix_sort_pairs(DBuf &keys2, DBuf &vals2, DBuf &hbuf, uint64_t *keys, int3
         const int shift = ps * RB;
         hipLaunchKernelGGL(k_hist, dim3(ntiles), dim3(ST), 0, s, ka, n, shift, hist, ntiles);
         STK_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_scan_rows, dim3(RADIX), dim3(256), 0, s, hist, ntiles, dbase);
+        hipLaunchKernelGGL(k_scan_rows, dim3(RADIX), dim3(256), 0, s, hist, ntiles, dtot);
         STK_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_scan_digits, dim3(1), dim3(RADIX), 0, s, dbase);
-        STK_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_scatter, dim3(ntiles), dim3(ST), 0, s, ka, va, kb, vb, n, shift, hist, ntiles, dbase);
+        hipLaunchKernelGGL(k_scatter, dim3(ntiles), dim3(ST), 0, s, ka, va, kb, vb, n, shift, hist, ntiles, dtot);
         STK_CHECK_LAUNCH();
         std::swap(ka, kb);
         std::swap(va, vb);
