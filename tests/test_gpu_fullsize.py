@@ -87,3 +87,43 @@ def test_cube500k_k16_sampled_rhs(nat, orc):
         ref = orc.treecode(T, w.src, w.f[r], w.h[r], w.nu, M, Mt, w.p, w.theta, w.src[S])
         assert _rel(u64[r][S], ref.u) < 1e-12, r
         assert _rel(umx[r][S], ref.u) < 1e-5, r
+
+
+def test_more_than_65536_groups_lists(nat, orc):
+    """4,300,000 targets (= sources) in the unit cube, N0 400, theta 0.5: 67,188 groups of 64,
+    so the list build's group offsets, pair totals and longest-list maxima take the
+    multi-tile scans.  For 1,500 seeded targets the per-target far/near counts and near pairs
+    equal the oracle's (Algorithm 1 at those targets), and for 24 seeded groups the group
+    lists (entries and their order-free sets) equal the union of the oracle's lists of the
+    group's 64 targets."""
+    w = W.cube(4_300_000, seed=21, n0=400)
+    theta = 0.5
+    X = _t(w.src)
+    _, plan = nat.evaluate(X, X, _t(w.f[0]), _t(w.h[0]), _t(w.nu), 2, theta, w.n0, "mixed", keep_plan=True)
+    info = nat.plan_info(plan)
+    assert info["groups"] == (w.n + 63) // 64 > 65536
+    T = orc.build_tree(w.src, w.n0)
+    rng = np.random.default_rng(8)
+    S = np.sort(rng.choice(w.n, 1500, replace=False))
+    L = orc.lists(T, theta, w.src[S])
+    nfar, nnear, npair = nat.plan_counts(plan)
+    cnt = np.asarray(T.count)
+    assert np.array_equal(nfar[S], np.diff(L.far_ptr))
+    assert np.array_equal(nnear[S], np.diff(L.near_ptr))
+    csum = np.concatenate([[0], np.cumsum(cnt[np.asarray(L.near_nodes[: int(L.near_ptr[-1])])])])
+    ptr = np.asarray(L.near_ptr)
+    assert np.array_equal(npair[S], csum[ptr[1:]] - csum[ptr[:-1]])
+    for kind in ("far", "near"):
+        lists = nat.plan_lists(plan, kind)
+        off, node, tperm = lists["off"], lists["node"], lists["tperm"]
+        assert off[-1] == info[kind + "_entries"]
+        for g in np.sort(rng.choice(info["groups"], 24, replace=False)):
+            tg = tperm[64 * g: min(64 * g + 64, w.n)]
+            Lg = orc.lists(T, theta, w.src[tg])
+            ref = Lg.far_nodes if kind == "far" else Lg.near_nodes
+            ptr = Lg.far_ptr if kind == "far" else Lg.near_ptr
+            want = np.unique(ref[: int(ptr[-1])])
+            got = node[off[g]:off[g + 1]]
+            assert len(got) == len(np.unique(got)) == len(want), (kind, g)
+            assert np.array_equal(np.sort(got), want), (kind, g)
+    del plan
