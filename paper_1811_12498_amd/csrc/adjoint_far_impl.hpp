@@ -67,7 +67,7 @@ template <int PB, typename T, class Visit> struct Coefs {
 // x + (x of lane ^ o) in every lane, o = 16 or 32, through the VALU's lane-half swaps (the
 // two outputs of a swap of x with itself hold x and its partner in opposite halves, so their
 // sum is the pair sum whatever the orientation)
-STK_HD inline float pair_sum(float x, int o) {
+STK_HD float pair_sum(float x, int o) {
 #if defined(__HIP_DEVICE_COMPILE__)
     const unsigned u = __float_as_uint(x);
     const auto r = o == 32 ? __builtin_amdgcn_permlane32_swap(u, u, false, false)
@@ -77,7 +77,7 @@ STK_HD inline float pair_sum(float x, int o) {
     return x + __shfl_xor(x, o);
 #endif
 }
-STK_HD inline double pair_sum(double x, int o) {
+STK_HD double pair_sum(double x, int o) {
 #if defined(__HIP_DEVICE_COMPILE__)
     const unsigned long long b = __double_as_longlong(x);
     const unsigned lo = unsigned(b), hi = unsigned(b >> 32);

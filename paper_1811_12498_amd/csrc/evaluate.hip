@@ -302,9 +302,11 @@ template <typename T>
 __global__ void k_finish(const T *__restrict__ npart, const int32_t *__restrict__ ntoff, const T *__restrict__ spart,
                          const int32_t *__restrict__ stoff, const double *__restrict__ fpart, int32_t nsplit,
                          const int32_t *__restrict__ tperm, int64_t m, int32_t K, double *__restrict__ u_out) {
+    // right-hand side fastest, so the lanes of a wave read the partials of a target's K
+    // right-hand sides, which lie side by side
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= m * K) return;
-    const int64_t r = i / m, t = i - r * m;
+    const int64_t t = i / K, r = i - t * K;
     double un[3];
     {
         Comp<T> acc[3];

@@ -204,18 +204,27 @@ __global__ __launch_bounds__(MT) void k_m2m(const double *__restrict__ center, c
 
 // grid (nnodes, K): each cluster's far-field stream (stk_math.hpp) in the evaluation
 // precision, wblk[(node * K + r) * 6 nG + pos], nG = nidx(p + 1)
+// The cluster's 12 nm moments of this right-hand side are staged in LDS first (every
+// value is read by many outputs).
 template <typename T>
 __global__ __launch_bounds__(MT) void k_channels(const double *__restrict__ mom, const double *__restrict__ rho, int p,
                                                  int nm, int ng, T *__restrict__ wblk) {
+    extern __shared__ double ms[];  // [nm][12]
     const int32_t node = blockIdx.x;
     const int r = blockIdx.y, K = gridDim.y;
+    const double *src = mom + size_t(node) * nm * 12 * K + 12 * r;
+    for (int i = threadIdx.x; i < 12 * nm; i += MT) {
+        const int a = i / 12;
+        ms[i] = src[size_t(a) * 12 * K + (i - 12 * a)];
+    }
+    __syncthreads();
     const double inv = 1.0 / rho[node];  // a power of two: exact
     T *out = wblk + (size_t(node) * K + r) * 6 * ng;
     for (int a = threadIdx.x; a < ng; a += MT) {
         int q[3];
         kof(a, q);
         double ge[6];
-        phi_ge(mom + size_t(node) * nm * 12 * K + 12 * r, 12 * K, p, q, ge);
+        phi_ge(ms, 12, p, q, ge);
         double s = 1.0;
         for (int e = 0; e < q[0] + q[1] + q[2]; ++e) s *= inv;
         int pg, pe;
@@ -314,10 +323,10 @@ void compute_moments(Tree &t, const double *f, const double *h, const double *nu
         }
     }
     if (prec == STK_FP64)
-        hipLaunchKernelGGL(k_channels<double>, dim3(nn, K), dim3(MT), 0, s, mom, t.nrho.as<double>(), p, nm, ng,
+        hipLaunchKernelGGL(k_channels<double>, dim3(nn, K), dim3(MT), sizeof(double) * 12 * nm, s, mom, t.nrho.as<double>(), p, nm, ng,
                            t.wblk.as<double>());
     else
-        hipLaunchKernelGGL(k_channels<float>, dim3(nn, K), dim3(MT), 0, s, mom, t.nrho.as<double>(), p, nm, ng,
+        hipLaunchKernelGGL(k_channels<float>, dim3(nn, K), dim3(MT), sizeof(double) * 12 * nm, s, mom, t.nrho.as<double>(), p, nm, ng,
                            t.wblk.as<float>());
     STK_CHECK_LAUNCH();
     prof_mark(STK_PHASE_MOMENTS, s);
