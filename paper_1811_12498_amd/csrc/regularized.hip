@@ -20,13 +20,18 @@
 namespace stk {
 namespace {
 
-// grid (nnodes): each cluster's stream (reg_math.hpp), reg_stream_len(p) values per node
+// grid (nnodes): each cluster's stream (reg_math.hpp), reg_stream_len(p) values per node,
+// from the node's 12 nm moments staged in LDS (every moment feeds many stream values)
 __global__ __launch_bounds__(64) void k_reg_stream(const double *__restrict__ mom, int p, int nm,
                                                    double *__restrict__ wreg) {
+    extern __shared__ double ms[];  // [nm][12]
     const int32_t node = blockIdx.x;
+    const double *src = mom + size_t(node) * nm * 12;
+    for (int i = threadIdx.x; i < 12 * nm; i += 64) ms[i] = src[i];
+    __syncthreads();
     double *out = wreg + size_t(node) * reg_stream_len(p);
     for (int a = nidx(1) + threadIdx.x; a < nidx(p + 3); a += 64)
-        reg_stream_fill(mom + size_t(node) * nm * 12, 12, p, a, out);
+        reg_stream_fill(ms, 12, p, a, out);
 }
 
 void dispatch_reg_far(int p, const RegFarArgs &a, hipStream_t s) {
@@ -85,8 +90,8 @@ void evaluate_regularized(Tree &t, Plan &pl, const double *tgt, int64_t m, doubl
         pl.moments_ready = nullptr;
     }
     if (t.nnodes > 0) {
-        hipLaunchKernelGGL(k_reg_stream, dim3(unsigned(t.nnodes)), dim3(64), 0, s, t.mom.as<double>(), t.p,
-                           nidx(t.p), wreg);
+        hipLaunchKernelGGL(k_reg_stream, dim3(unsigned(t.nnodes)), dim3(64), sizeof(double) * 12 * nidx(t.p), s,
+                           t.mom.as<double>(), t.p, nidx(t.p), wreg);
         STK_CHECK_LAUNCH();
     }
     prof_mark(STK_PHASE_MOMENTS, s);  // the clusters' streams, like the channel blocks
