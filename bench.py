@@ -668,7 +668,7 @@ def main():
                     help="run only this secondary measurement and print its JSON object (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the treecode would shard over targets with replicated sources)",
               file=sys.stderr)
         sys.exit(2)
