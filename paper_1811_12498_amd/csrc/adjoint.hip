@@ -45,9 +45,11 @@ __device__ inline void pgrad_f64(const double d[3], const double f[3], const dou
     const double wd = w[0] * d[0] + w[1] * d[1] + w[2] * d[2];
     const double wf = w[0] * f[0] + w[1] * f[1] + w[2] * f[2];
     const double s = df * r3i, tt = dh * dn * r5i;
-    for (int q = 0; q < 3; ++q)
-        gx[q] = -wf * d[q] * r3i + w[q] * (s + tt) +
-                wd * (f[q] * r3i - 3.0 * s * d[q] * r2i + (h[q] * dn + dh * nu[q]) * r5i - 5.0 * tt * d[q] * r2i);
+    // gx = -wf d r3i + w (s + tt) + wd (f r3i - 3 s d r2i + (h dn + dh nu) r5i - 5 tt d r2i),
+    // gathered per vector: five pair scalars, then five multiply-adds per component
+    const double A = -(wf * r3i + (wd * r2i) * (3.0 * s + 5.0 * tt)), B = s + tt, C = wd * r3i;
+    const double W5 = wd * r5i, D = W5 * dn, E = W5 * dh;
+    for (int q = 0; q < 3; ++q) gx[q] = d[q] * A + w[q] * B + f[q] * C + h[q] * D + nu[q] * E;
 }
 
 // mixed precision: d and d.nu arrive in FP64, the rest in FP32
@@ -64,9 +66,10 @@ __device__ inline void pgrad_mixed(const double dd[3], double dnd, const float f
     const float wd = w[0] * d[0] + w[1] * d[1] + w[2] * d[2];
     const float wf = w[0] * f[0] + w[1] * f[1] + w[2] * f[2];
     const float s = df * r3i, tt = dh * dn * r5i;
-    for (int q = 0; q < 3; ++q)
-        gx[q] = -wf * d[q] * r3i + w[q] * (s + tt) +
-                wd * (f[q] * r3i - 3.0f * s * d[q] * r2i + (h[q] * dn + dh * nu[q]) * r5i - 5.0f * tt * d[q] * r2i);
+    // the expression of pgrad_f64, gathered the same way
+    const float A = -(wf * r3i + (wd * r2i) * (3.0f * s + 5.0f * tt)), B = s + tt, C = wd * r3i;
+    const float W5 = wd * r5i, D = W5 * dn, E = W5 * dh;
+    for (int q = 0; q < 3; ++q) gx[q] = d[q] * A + w[q] * B + f[q] * C + h[q] * D + nu[q] * E;
 }
 
 struct NearAdjArgs {
