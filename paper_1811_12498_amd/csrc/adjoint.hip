@@ -221,9 +221,11 @@ template <typename T> __global__ __launch_bounds__(64 * SG_WAVES) void k_near_sg
             }
             const T r3i = ri * ri * ri, r5i = r3i * ri * ri;
             const T wdot = wv[0] * dt[0] + wv[1] * dt[1] + wv[2] * dt[2];
+            // dL/df: w ri + (w.d) r3i d; dL/dh: (w.d)(d.nu) r5i d, as multiply-adds per component
+            const T a3 = wdot * r3i, a5 = wdot * T(dn) * r5i;
             for (int q = 0; q < 3; ++q) {
-                sf[q] += wv[q] * ri + wdot * dt[q] * r3i;
-                sh[q] += wdot * dt[q] * T(dn) * r5i;
+                sf[q] += wv[q] * ri + a3 * dt[q];
+                sh[q] += a5 * dt[q];
             }
             T gx[3];
             if constexpr (sizeof(T) == 8) {
