@@ -243,6 +243,7 @@ template <int P, typename T> struct TgradVisit {
     T dh[3], wl[3];
     T a1[3], a2[3], a3[3];
     T lag;        // the sums as they stood one layer back
+    T zb[2][P + 3];  // zh of the two newest layers of the order below, by layer parity and k_1
 
     template <int Q, int N> STK_HD void coef(T) {}
     template <int N> STK_HD void order_done(const T (&)[nidx(P + 3)]) {}
@@ -252,15 +253,32 @@ template <int P, typename T> struct TgradVisit {
     //  term 3 for k of order N-1 in layer J-1 (<= P+1): Ehat_s^k zh^k
     //  term 2 for k of order N-2 in layer J-2 (<= P+1):
     //      (dh.Ehat^k) sum_i w_i (k_i+1)(k_s+1+delta_is) bt^{k+e_i+e_s}
-    // so each layer of order N is last read two layers later and the coefficients alive
-    // at a time are three layers of the current order plus those the recurrence keeps
+    //    = (dh.Ehat^k) (k_s+1) zh^{k+e_s}   ((k_i+1)(k_s+1+delta_is) = (k_s+1)(m_i+1) with
+    //      m = k + e_s), so it reads the zh of layers J-2 and J-1 of order N-1, which the
+    //      term-3 walk has just formed (for order P+2 they are formed for this use alone)
+    // so each layer of order N is last read one layer later
     template <int N, int J> STK_HD void layer_done(const T (&b)[nidx(P + 3)]) {
         // the fence pins this layer's scalar loads after the sums of two layers back, so they
         // can be in flight while the previous layer is consumed
         const T *__restrict__ Wf = W + FarEval<P, T>::fence(lag);
         lag = a1[0] + a2[0] + a3[0];
         if constexpr (J >= 1 && N - 1 <= P + 1) walk13<N - 1, J - 1, N - J>(b, Wf);
-        if constexpr (J >= 2 && N - 2 <= P + 1) walk2<N - 2, J - 2, N - J>(b, Wf);
+        if constexpr (J >= 1 && N - 1 == P + 2) walkz<N - 1, J - 1, N - J>(b);
+        if constexpr (J >= 2 && N - 2 <= P + 1) walk2<N - 2, J - 2, N - J>(Wf);
+    }
+
+    // zh^k = sum_i w_i (k_i+1) bt^{k+e_i}, kept for term 2
+    template <int M, int K3, int K1> STK_HD T zh(const T (&b)[nidx(P + 3)]) {
+        constexpr int K2 = M - K3 - K1;
+        const T z = wl[0] * (T(K1 + 1) * b[gidx(K1 + 1, K2, K3)]) + wl[1] * (T(K2 + 1) * b[gidx(K1, K2 + 1, K3)]) +
+                    wl[2] * (T(K3 + 1) * b[gidx(K1, K2, K3 + 1)]);
+        zb[K3 & 1][K1] = z;
+        return z;
+    }
+
+    template <int M, int K3, int K1> STK_HD void walkz(const T (&b)[nidx(P + 3)]) {
+        (void)zh<M, K3, K1>(b);
+        if constexpr (K1 > 0) walkz<M, K3, K1 - 1>(b);
     }
 
     // k of order M in layer k3 = K3, k1 = K1 .. 0
@@ -274,35 +292,25 @@ template <int P, typename T> struct TgradVisit {
         a1[0] += g * (T(K1 + 1) * bx);
         a1[1] += g * (T(K2 + 1) * by);
         a1[2] += g * (T(K3 + 1) * bz);
-        const T z = wl[0] * (T(K1 + 1) * bx) + wl[1] * (T(K2 + 1) * by) + wl[2] * (T(K3 + 1) * bz);
+        const T z = zh<M, K3, K1>(b);
         a3[0] += W[pe] * z;
         a3[1] += W[pe + 1] * z;
         a3[2] += W[pe + 2] * z;
         if constexpr (K1 > 0) walk13<M, K3, K1 - 1>(b, W);
     }
 
-    template <int M, int K3, int K1> STK_HD void walk2(const T (&b)[nidx(P + 3)], const T *__restrict__ W) {
+    template <int M, int K3, int K1> STK_HD void walk2(const T *__restrict__ W) {
         constexpr int K2 = M - K3 - K1;
         constexpr int kk[3] = {K1, K2, K3};
         int pg = 0, pe = 0;
         stream_pos_c(kk, pg, pe);
         const T sig = dh[0] * W[pe] + dh[1] * W[pe + 1] + dh[2] * W[pe + 2];
-        // h_s = sum_i w_i (k_i+1)(k_s+1+delta_is) bt^{k+e_i+e_s}; every product takes a
-        // coefficient before the lane's weight, so no weight-times-constant product is
-        // invariant over the entry loop (hoisted, such products fill the register file)
-        const T hx = wl[0] * (T((K1 + 1) * (K1 + 2)) * b[gidx(K1 + 2, K2, K3)]) +
-                     wl[1] * (T((K2 + 1) * (K1 + 1)) * b[gidx(K1 + 1, K2 + 1, K3)]) +
-                     wl[2] * (T((K3 + 1) * (K1 + 1)) * b[gidx(K1 + 1, K2, K3 + 1)]);
-        const T hy = wl[0] * (T((K1 + 1) * (K2 + 1)) * b[gidx(K1 + 1, K2 + 1, K3)]) +
-                     wl[1] * (T((K2 + 1) * (K2 + 2)) * b[gidx(K1, K2 + 2, K3)]) +
-                     wl[2] * (T((K3 + 1) * (K2 + 1)) * b[gidx(K1, K2 + 1, K3 + 1)]);
-        const T hz = wl[0] * (T((K1 + 1) * (K3 + 1)) * b[gidx(K1 + 1, K2, K3 + 1)]) +
-                     wl[1] * (T((K2 + 1) * (K3 + 1)) * b[gidx(K1, K2 + 1, K3 + 1)]) +
-                     wl[2] * (T((K3 + 1) * (K3 + 2)) * b[gidx(K1, K2, K3 + 2)]);
-        a2[0] += sig * hx;
-        a2[1] += sig * hy;
-        a2[2] += sig * hz;
-        if constexpr (K1 > 0) walk2<M, K3, K1 - 1>(b, W);
+        // h_s = (k_s+1) zh^{k+e_s}: k+e_1 and k+e_2 lie in layer K3 of order M+1, k+e_3 in
+        // layer K3+1
+        a2[0] += sig * (T(K1 + 1) * zb[K3 & 1][K1 + 1]);
+        a2[1] += sig * (T(K2 + 1) * zb[K3 & 1][K1]);
+        a2[2] += sig * (T(K3 + 1) * zb[(K3 + 1) & 1][K1]);
+        if constexpr (K1 > 0) walk2<M, K3, K1 - 1>(W);
     }
 
     STK_HD static constexpr void stream_pos_c(const int (&k)[3], int &g, int &e) {
